@@ -1,0 +1,69 @@
+"""Host-side estimators of the oracle (TEST INFRASTRUCTURE ONLY).
+
+Written from their definitions, in numpy, for a reader to check by eye:
+  * Binder cumulant U = <M^4> / <M^2>^2 (Sec. IV.A, Eq. Def-Binder-Cum), the
+    averages being plain means over the retained samples (App. B, Eq.
+    ensemble-average-calculation with the time integral as a sample mean).
+  * Integrated autocorrelation time and error of a time-series mean (App. B,
+    Eqs. Autocorrelation-Function, Autocorrelation-Time, Time-Series-Var):
+    tau = 1/2 + sum_{t>=1} rho(t) in units of the sampling interval and
+    var(mean) = 2 tau sigma^2 / n.  The sum is cut by the automatic window of
+    Madras and Sokal (the reference the paper cites for this), the smallest M
+    with M >= c tau(M), c = 6.
+  * Second-moment correlation length from the structure factor at k = 0 and
+    at the smallest nonzero wave number (the Lorentzian of App. C, Eq.
+    Lorentzian-Peak, evaluated at those two points).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def discard_count(n: int, discard_fraction: float) -> int:
+    return int(np.floor(discard_fraction * n))
+
+
+def binder(m, discard_fraction: float = 0.2) -> float:
+    m = np.asarray(m, dtype=np.float64)
+    m = m[discard_count(len(m), discard_fraction):]
+    m2 = np.mean(m ** 2)
+    m4 = np.mean(m ** 4)
+    return m4 / (m2 * m2)
+
+
+def autocorrelation(f) -> np.ndarray:
+    f = np.asarray(f, dtype=np.float64)
+    n = len(f)
+    d = f - f.mean()
+    c0 = np.dot(d, d) / n
+    rho = np.empty(n)
+    for t in range(n):
+        rho[t] = np.dot(d[: n - t], d[t:]) / n / c0 if c0 > 0 else 0.0
+    return rho
+
+
+def tau_int(f, c: float = 6.0) -> float:
+    rho = autocorrelation(f)
+    n = len(rho)
+    tau = 0.5
+    for M in range(1, n):
+        tau += rho[M]
+        if M >= c * tau:
+            return max(tau, 0.5)
+    return max(tau, 0.5)
+
+
+def mean_and_error(f, discard_fraction: float = 0.0):
+    f = np.asarray(f, dtype=np.float64)
+    f = f[discard_count(len(f), discard_fraction):]
+    n = len(f)
+    tau = tau_int(f)
+    var = np.var(f)
+    return float(f.mean()), float(np.sqrt(2.0 * tau * var / n)), float(tau)
+
+
+def xi_second_moment(F0_mean: float, Fk_mean: float, L: int) -> float:
+    r = F0_mean / Fk_mean - 1.0
+    if r <= 0:
+        return 0.0
+    return float(np.sqrt(r) / (2.0 * np.sin(np.pi / L)))

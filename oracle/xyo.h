@@ -1,0 +1,93 @@
+/*
+ * xyo — plain FP64 CPU oracle for Langevin dynamics of the symmetry-broken XY
+ * lattice (Weitzel, Schaller, Queisser, Schützhold, arXiv:2409.06412).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP product path.
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header, table or helper with the HIP library.
+ *
+ * Model (paper Sec. III.A, Eq. XY-Hamilton-Field, specialised to q = 1, p = 2
+ * and written with the sign convention used by this project):
+ *     H = sum_i [ Jx cos(th_i - th_{i+x}) + Jy cos(th_i - th_{i+y})
+ *                 - h cos(2 th_i) + omega_i^2 / 2 ]
+ * on an Lx x Ly periodic lattice, site (x, y) at linear index i = y*Lx + x.
+ * Dynamics: Langevin equations of Sec. III.D (Eq. Si-Langevin) with I = kB = 1,
+ * integrated by the three-stage BBK scheme of App. A.1 (Eqs. BBK-1, BBK-2).
+ * All arithmetic is IEEE binary64, round to nearest, no contraction.
+ */
+#ifndef XYO_H
+#define XYO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XYO_MAX_KNOTS 16
+#define XYO_NOBS 6
+
+typedef struct {
+    int32_t Lx, Ly;
+    double Jx, Jy, h, gamma, dt;
+    uint64_t seed;
+    uint32_t replica;
+    int32_t nknots;                      /* >= 1; one knot = constant T */
+    uint64_t knot_step[XYO_MAX_KNOTS];   /* strictly increasing */
+    double knot_T[XYO_MAX_KNOTS];        /* >= 0 */
+} xyo_model;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): one block. */
+void xyo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Uniform in (0,1): ((r >> 9) + 1/2) * 2^-23. */
+double xyo_uniform(uint32_t r);
+/* Gaussian draw n_i^k of site i at step k (Box-Muller on the Philox block
+ * with counter (i>>2, replica, k_lo, k_hi) and key (seed_lo, seed_hi)). */
+double xyo_normal(const xyo_model* m, uint64_t k, int64_t i);
+void xyo_normals(const xyo_model* m, uint64_t k, double* n);
+/* Temperature T_k: piecewise linear in the step index, held outside the knots. */
+double xyo_temperature(const xyo_model* m, uint64_t k);
+
+/* Initial states.  Random: th_i = pi (2U - 1) from the reserved init stream
+ * (step counter 2^64 - 1), omega = 0.  Ordered: staggered ground state. */
+void xyo_init_random(const xyo_model* m, double* theta, double* omega);
+void xyo_init_ordered(const xyo_model* m, int32_t sign, double* theta, double* omega);
+/* Staggering sign eps_i in {+1,-1}. */
+int32_t xyo_stagger(const xyo_model* m, int64_t i);
+
+/* Potential energy (total) and force F_i = -dH/dth_i. */
+double xyo_energy_pot(const xyo_model* m, const double* theta);
+void xyo_force(const xyo_model* m, const double* theta, double* F);
+
+/* Advance (theta, omega) at step k0 by nsteps BBK steps.  Returns 0, or -1 on a
+ * numeric fault (non-finite omega or |theta| > 3 pi after the wrap). */
+int32_t xyo_run(const xyo_model* m, double* theta, double* omega, uint64_t k0, uint64_t nsteps);
+/* Same, recording observables at k0 + j*every for j*every <= nsteps into
+ * out[j*XYO_NOBS ...].  Returns the number of samples or -1. */
+int64_t xyo_run_measured(const xyo_model* m, double* theta, double* omega, uint64_t k0,
+                         uint64_t nsteps, uint64_t every, double* out);
+
+/* Observables of a synchronized state, per site where noted:
+ * out = {E_pot/N, E_kin/N, m_s, F(0), F(kx_min), F(ky_min)}. */
+void xyo_observables(const xyo_model* m, const double* theta, const double* omega, double* out);
+/* Staggered rotor correlation C_axis(r), r = 0..rmax (axis 0 = x, 1 = y). */
+void xyo_correlation(const xyo_model* m, const double* theta, int32_t axis, int32_t rmax, double* C);
+/* Frozen domains: labels[i] = smallest linear index of the 4-connected periodic
+ * cluster of equal staggered spin.  Spin threshold is pi_p / 2 with pi_p the
+ * value of pi in the state precision (precision_bits 32 or 64).
+ * Returns the number of domains. */
+int64_t xyo_domains(const xyo_model* m, const double* theta, int32_t precision_bits, int32_t* labels);
+
+/* Pathwise reverse-mode gradient of L = (1/W) sum_{k=N-W+1}^{N} m_s(theta^k)^2
+ * with the Gaussian draws held fixed.  grad = dL/d{Jx, Jy, h, gamma};
+ * dtheta0, domega0 = dL/d(initial state) (may be NULL).  Returns L, or NaN on a
+ * numeric fault / allocation failure. */
+double xyo_adjoint(const xyo_model* m, const double* theta0, const double* omega0,
+                   uint64_t nsteps, uint64_t window, double* grad, double* dtheta0, double* domega0);
+/* The same loss by a plain forward run (for finite differences). */
+double xyo_loss(const xyo_model* m, const double* theta0, const double* omega0,
+                uint64_t nsteps, uint64_t window);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,116 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module holds no arithmetic of the method: only the parameter sets of the
+lattices that are simulated and numpy-seeded arbitrary states for tests that
+need a state other than the method's own initial conditions.  Both the HIP
+path and the oracle receive what this module produces as plain inputs.
+
+Parameter sets (all with J_x = +1 along the dimer rows, J_y = -0.1 across
+them, the two-fold field h and damping gamma, dt = 0.01):
+  * ``small_fp64``  64 x 64, FP64, T = 0.5, seed 0, 10,000 steps, sampled
+    every 100 steps (the size the oracle finishes in seconds).
+  * ``large_fp32``  4096 x 4096, FP32 state, eight temperatures evenly spaced
+    in [0.3, 1.2], seed 1, sampled every 500 steps.
+  * ``fss_ensemble`` 288 replicas: L in {32, ..., 512} x 16 temperatures in
+    [0.3, 1.2] x 2 seeds, 50,000 steps.
+  * ``kz_quench``   60 replicas of 2048 x 2048: tau_Q in {1e3, 1e4, 1e5}
+    steps x gamma in {0.1, 1} x h in {0.25, 0.5} x 5 seeds; T ramps linearly
+    from 1.5 to 0 over tau_Q steps, then holds at 0 for 1000 steps.
+  * ``adjoint_512`` 512 x 512, FP32, T = 0.6, seed 7, 5000 steps, loss window
+    1000, checkpoints every 100 steps.
+The paper runs on synthetic lattices only (no dataset), so nothing here stands
+in for external data.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+JX, JY, H, GAMMA, DT = 1.0, -0.1, 0.5, 1.0, 0.01
+
+
+@dataclass
+class LatticeSpec:
+    Lx: int
+    Ly: int
+    Jx: float = JX
+    Jy: float = JY
+    h: float = H
+    gamma: float = GAMMA
+    dt: float = DT
+    schedule: Sequence[Tuple[int, float]] = ((0, 0.5),)
+    seed: int = 0
+    replica: int = 0
+    nsteps: int = 0
+
+    def params(self):
+        return dict(Jx=self.Jx, Jy=self.Jy, h=self.h, gamma=self.gamma, dt=self.dt)
+
+    def oracle_kwargs(self):
+        return dict(Lx=self.Lx, Ly=self.Ly, Jx=self.Jx, Jy=self.Jy, h=self.h, gamma=self.gamma,
+                    dt=self.dt, schedule=list(self.schedule), seed=self.seed, replica=self.replica)
+
+
+def small_fp64() -> LatticeSpec:
+    return LatticeSpec(64, 64, schedule=((0, 0.5),), seed=0, replica=0, nsteps=10_000)
+
+
+def large_temperatures() -> List[float]:
+    return [0.3 + 0.9 * j / 7 for j in range(8)]
+
+
+def large_fp32(j: int = 0, L: int = 4096) -> LatticeSpec:
+    return LatticeSpec(L, L, schedule=((0, large_temperatures()[j]),), seed=1, replica=j,
+                       nsteps=100_000)
+
+
+FSS_SIZES = (32, 48, 64, 96, 128, 192, 256, 384, 512)
+
+
+def fss_ensemble(sizes: Sequence[int] = FSS_SIZES, ntemps: int = 16, seeds=(0, 1),
+                 nsteps: int = 50_000) -> List[LatticeSpec]:
+    out = []
+    temps = [0.3 + 0.06 * t for t in range(ntemps)]
+    for iL, L in enumerate(sizes):
+        for iT, T in enumerate(temps):
+            for iS, s in enumerate(seeds):
+                r = (iL * ntemps + iT) * len(seeds) + iS
+                out.append(LatticeSpec(L, L, schedule=((0, T),), seed=s, replica=r, nsteps=nsteps))
+    return out
+
+
+def kz_quench(L: int = 2048, taus=(1_000, 10_000, 100_000), gammas=(0.1, 1.0), hs=(0.25, 0.5),
+              seeds=range(5), hold: int = 1000) -> List[LatticeSpec]:
+    out = []
+    r = 0
+    for tq in taus:
+        for g in gammas:
+            for hh in hs:
+                for s in seeds:
+                    out.append(LatticeSpec(L, L, h=hh, gamma=g, schedule=((0, 1.5), (tq, 0.0)),
+                                           seed=s, replica=r, nsteps=tq + hold))
+                    r += 1
+    return out
+
+
+def adjoint_512(L: int = 512) -> LatticeSpec:
+    return LatticeSpec(L, L, schedule=((0, 0.6),), seed=7, replica=0, nsteps=5000)
+
+
+def random_state(Lx: int, Ly: int, seed: int, omega_scale: float = 1.0, dtype=np.float64):
+    """Arbitrary (theta, omega): theta uniform in [-pi, pi), omega ~ N(0, omega_scale^2)."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-np.pi, np.pi, size=(Ly, Lx)).astype(dtype)
+    om = (omega_scale * rng.standard_normal((Ly, Lx))).astype(dtype)
+    return th.astype(np.float64), om.astype(np.float64)
+
+
+def perturbed_ground_state(Lx: int, Ly: int, stagger: np.ndarray, amplitude: float, seed: int):
+    """Staggered ground state (theta = 0 where the stagger sign is +1, -pi where it
+    is -1) plus uniform noise of the given amplitude, omega = 0."""
+    rng = np.random.default_rng(seed)
+    th = np.where(stagger > 0, 0.0, -np.pi) + rng.uniform(-amplitude, amplitude, size=(Ly, Lx))
+    th = np.where(th < -np.pi, th + 2 * np.pi, th)
+    return th, np.zeros((Ly, Lx))
