@@ -1,0 +1,241 @@
+/*
+ * xyl.h — C-ABI of the MI355X (gfx950) Langevin-XY library.
+ *
+ * The library time-steps the underdamped Langevin equations of the angles
+ * th_i and angular velocities w_i of a periodic Lx x Ly lattice under the
+ * symmetry-broken XY Hamiltonian of Weitzel, Schaller, Queisser, Schützhold,
+ * "Continuous Dimer Angles on the Silicon Surface" (arXiv:2409.06412),
+ * Sec. III.A, Eq. XY-Hamilton-Field, taken at q = 1, p = 2 and written as
+ *
+ *     H = sum_i [ Jx cos(th_i - th_{i+x}) + Jy cos(th_i - th_{i+y})
+ *                 - h cos(2 th_i) + w_i^2 / 2 ]                          (1)
+ *
+ * (kinetic term of Eq. XY-Hamilton-Kinetic with I = 1; every bond counted
+ * once).  Jx > 0 favours antiparallel neighbours along x (the dimer rows).
+ * The dynamics is Eq. Si-Langevin (Sec. III.D),
+ *     d th/dt = w,   d w/dt = -gamma w - dH/dth + sqrt(2 gamma T(t)) G(t),
+ * integrated with the three-stage Brünger-Brooks-Karplus scheme of App. A.1
+ * (Eqs. BBK-1, BBK-2): half-kick, drift, half-kick, the Gaussian draw of a
+ * step's second half-kick being the draw of the next step's first half-kick,
+ * and the angle wrapped to [-pi_p, pi_p) after every step (Sec. III.D), pi_p
+ * being pi rounded to the state precision.
+ *
+ * Noise.  The draw n_i^k of site i = y*Lx + x at step k comes from
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (i>>2, replica, k_lo,
+ * k_hi) and key (seed_lo, seed_hi): words (2p, 2p+1), p = (i&3)>>1, give
+ * U1, U2 with U(r) = ((r>>9) + 1/2) 2^-23, and n = sqrt(-2 ln U1) cos(2 pi U2)
+ * for even i, sin(2 pi U2) for odd i.  Results are a pure function of
+ * (parameters, schedule, seed, replica, step, lattice size, precision); they
+ * do not depend on launch shape, batching or steps per launch.
+ *
+ * Layout.  Every per-site array is row-major, x fastest: element (x, y) at
+ * y*Lx + x.  Host arrays passed to the library are float64 regardless of the
+ * state precision; device states are float32 (XYL_F32) or float64 (XYL_F64).
+ *
+ * Errors.  Every call returns XYL_OK (0) or a negative status and records a
+ * message for xyl_last_error().  No exception or abort crosses the ABI.
+ * Calls are asynchronous on the handle's stream unless they write host memory,
+ * in which case they synchronise that stream first.  A handle is used by one
+ * host thread at a time.
+ */
+#ifndef XYL_H
+#define XYL_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XYL_ABI_VERSION 1
+
+enum {
+    XYL_OK = 0,
+    XYL_EINVAL = -1,       /* invalid argument */
+    XYL_ENOMEM = -2,       /* device or host allocation failed */
+    XYL_EDEVICE = -3,      /* HIP runtime error or no gfx950 device */
+    XYL_ESTATE = -4,       /* call not valid in the handle's current state */
+    XYL_EUNSUPPORTED = -5, /* shape or mode not supported */
+    XYL_ENUMERIC = -6      /* non-finite value detected */
+};
+
+enum { XYL_F32 = 0, XYL_F64 = 1 };
+
+#define XYL_MAX_KNOTS 16
+
+/* One measurement at a synchronized step k (App. B; Sec. IV.A; App. C):
+ *   e_pot = (1/N) sum of the potential terms of (1)
+ *   e_kin = (1/N) sum w_i^2 / 2
+ *   m_s   = (1/N) sum eps_i cos th_i         (staggered order parameter)
+ *   f0, fkx, fky = F(q) = (1/N) sum_{kappa} |sum_i eps_i s^kappa_i e^{-i q.r_i}|^2
+ *           at q = 0, (2 pi/Lx, 0), (0, 2 pi/Ly); s^0 = cos th, s^1 = sin th
+ * with eps_i = (-1)^(x [Jx > 0] + y [Jy > 0]). */
+typedef struct {
+    double e_pot, e_kin, m_s, f0, fkx, fky;
+} xyl_obs;
+
+typedef struct xyl_lattice xyl_lattice;
+typedef struct xyl_ensemble xyl_ensemble;
+
+/* ---------------------------------------------------------------- library */
+int xyl_abi_version(void);
+/* Message of the last failing call on this thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char* xyl_last_error(void);
+/* Number of visible gfx950 devices (0 if none).  Never fails. */
+int xyl_device_count(void);
+
+/* ---------------------------------------------------------------- lattice */
+/* Creates an Lx x Ly lattice on HIP device `device` with library-owned device
+ * buffers (two angle buffers and one velocity buffer of the given precision).
+ * Lx, Ly >= 2, Lx*Ly < 2^34.  Default parameters: Jx = 1, Jy = -0.1, h = 0.5,
+ * gamma = 1, dt = 0.01, constant T = 0, seed 0, replica 0.  The state is
+ * undefined until an init or set_state call (ESTATE before that). */
+int xyl_create(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype, int32_t device);
+/* Same, on caller-owned device buffers of Lx*Ly elements of the given
+ * precision (e.g. torch tensors): theta_a, theta_b, vel must be distinct, stay
+ * alive and unaliased until xyl_destroy.  The current angles live in the
+ * buffer reported by xyl_state_buffers. */
+int xyl_create_wrapped(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype, int32_t device,
+                       void* theta_a, void* theta_b, void* vel);
+int xyl_destroy(xyl_lattice* h); /* NULL is a no-op */
+/* HIP stream (hipStream_t) for all later work; NULL = the null stream. */
+int xyl_set_stream(xyl_lattice* h, void* stream);
+/* Model and integrator parameters (Eq. (1), Eq. Si-Langevin, App. A.1).
+ * dt > 0, gamma >= 0, all finite.  Takes effect at the next step. */
+int xyl_set_params(xyl_lattice* h, double Jx, double Jy, double hfield, double gamma, double dt);
+/* Temperature schedule T(k), piecewise linear in the step index between knots
+ * (k_j, T_j) and held outside them (Sec. II.B, Eq. Linear-Quench, with the
+ * reduced temperature written as T).  1 <= n <= XYL_MAX_KNOTS, knot steps
+ * strictly increasing, T_j >= 0 and finite. */
+int xyl_set_schedule(xyl_lattice* h, const uint64_t* knot_step, const double* knot_T, int32_t n);
+int xyl_set_seed(xyl_lattice* h, uint64_t seed, uint32_t replica);
+/* th_i = pi (2 U(w_{i&3}) - 1) from the Philox block of counter
+ * (i>>2, replica, 2^32-1, 2^32-1) (the reserved step 2^64 - 1), computed in
+ * float64 and rounded to the state precision; w = 0; step k = 0. */
+int xyl_init_random(xyl_lattice* h);
+/* Staggered ground state: th_i = 0 where sign*eps_i = +1, else -pi_p; w = 0; k = 0. */
+int xyl_init_ordered(xyl_lattice* h, int32_t sign);
+/* Copies a host state (float64, Lx*Ly each; converted to the state precision)
+ * and sets the step index.  theta entries must be finite with |th| <= 3 pi. */
+int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint64_t step);
+/* Copies the synchronized state (th^k, w^k) at the current step to host
+ * float64 arrays (either may be NULL) and the step index (may be NULL). */
+int xyl_get_state(xyl_lattice* h, double* theta, double* omega, uint64_t* step);
+/* Device pointers of the current angle buffer and of the velocity buffer and
+ * whether the velocity buffer holds w^k ("fresh", 1) or w^{k-1/2} (0). */
+int xyl_state_buffers(xyl_lattice* h, void** theta, void** vel, int32_t* fresh);
+/* Advances nsteps BBK steps (stream-ordered, asynchronous). */
+int xyl_step(xyl_lattice* h, uint64_t nsteps);
+/* Advances nsteps steps and records observables at the current step k0 and at
+ * k0 + j*every for j*every <= nsteps (every >= 1).  out has room for cap
+ * samples; *nout receives the count (nsteps/every + 1; EINVAL if cap is
+ * smaller).  Synchronises. */
+int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap,
+                      uint64_t* nout);
+/* Observables at the current step.  Synchronises. */
+int xyl_measure(xyl_lattice* h, xyl_obs* out);
+/* Staggered rotor correlation along axis (0 = x, 1 = y) at the current step
+ * (App. C, two-point function of the rotors, lattice average):
+ * C(r) = (1/N) sum_i eps_i eps_j cos(th_i - th_j), j = i + r along the axis,
+ * r = 0..rmax, 0 <= rmax <= L_axis/2.  C has rmax+1 entries.  Synchronises. */
+int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C);
+/* Frozen domains of the current angles (Abstract; Figs. 1 and 6): spin
+ * s_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1), clusters of equal spin under
+ * 4-neighbour periodic connectivity.  labels (nullable, Lx*Ly) receives for
+ * each site the smallest linear index of its cluster.  The size distribution
+ * is returned as pairs (sizes[j], counts[j]) sorted by size, j < *n_sizes;
+ * sizes/counts (nullable) have room for cap pairs (EINVAL if too few).
+ * n_domains and max_size are nullable.  Synchronises. */
+int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
+                uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size);
+/* Blocks until all work issued on the handle's stream has finished. */
+int xyl_sync(xyl_lattice* h);
+
+/* ------------------------------------------------------ tuning and graphs */
+/* Launch shape of the step kernels: rows per strip (>= 1) and waves per
+ * workgroup (1, 2, 4 or 8); 0 keeps the current value.  Results do not
+ * depend on it.  xyl_autotune times candidates on this lattice and keeps the
+ * fastest; the choice is cached per (shape, precision) for the process. */
+int xyl_set_launch(xyl_lattice* h, int32_t rows_per_strip, int32_t waves_per_block);
+int xyl_get_launch(xyl_lattice* h, int32_t* rows_per_strip, int32_t* waves_per_block);
+int xyl_autotune(xyl_lattice* h);
+/* Steps per captured HIP graph used by xyl_step (0 or 1 disables graphs). */
+int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
+
+/* -------------------------------------------------------------- test hooks */
+/* Raw Philox4x32-10 blocks computed on the device: for j < n, counter
+ * ctr[4j..4j+3] and key (seed_lo, seed_hi) -> out[4j..4j+3]. */
+int xyl_philox_blocks(int32_t device, uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n);
+/* The Gaussian draws n_i^k of every site at step k as the step kernel of this
+ * lattice computes them (in its precision), converted to float64. */
+int xyl_noise(xyl_lattice* h, uint64_t k, double* out);
+
+/* --------------------------------------------------------------- analysis */
+/* Binder cumulant U = <m^4>/<m^2>^2 (Sec. IV.A, Eq. Def-Binder-Cum) of the
+ * samples m[discard..n-1], and its standard error from blocks longer than
+ * twice the integrated autocorrelation time (App. B); U_se may be NULL.
+ * Pure host computation. */
+int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double* U_se);
+/* Integrated autocorrelation time (in samples; automatic window of Madras and
+ * Sokal, c = 6) and standard error of the mean of f[discard..n-1] (App. B,
+ * Eqs. Autocorrelation-Time and Time-Series-Var).  Pure host computation. */
+int xyl_mean_error(const double* f, uint64_t n, uint64_t discard, double* mean, double* se, double* tau);
+
+/* --------------------------------------------------------------- ensemble */
+/* One replica of a batched ensemble: its own lattice size, parameters,
+ * schedule, noise key and number of steps to run. */
+typedef struct {
+    int32_t Lx, Ly;
+    double Jx, Jy, h, gamma, dt;
+    uint64_t seed;
+    uint32_t replica;
+    int32_t nknots;
+    uint64_t knot_step[XYL_MAX_KNOTS];
+    double knot_T[XYL_MAX_KNOTS];
+    uint64_t nsteps;
+} xyl_replica_desc;
+
+/* Creates n >= 1 replicas on one device in one state allocation, indexed by a
+ * per-replica offset table (App. B packs independent subsystems into one
+ * simulation; here their sizes and parameters may differ).  Every replica
+ * starts from xyl_init_random's state for its own (seed, replica). */
+int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_t n, int32_t dtype,
+                        int32_t device);
+int xyl_ensemble_destroy(xyl_ensemble* e); /* NULL is a no-op */
+int xyl_ensemble_set_stream(xyl_ensemble* e, void* stream);
+/* Advances every replica by up to nsteps steps without passing its own nsteps
+ * (replicas that have finished stay where they are), in batched launches.
+ * With every >= 1, replica r records observables at its steps that are
+ * multiples of `every` (its step 0 included, at most one sample per step)
+ * into out[r*cap + j], nout[r] receiving the running count (EINVAL on
+ * overflow of cap).  every = 0 records nothing (out, nout may be NULL).
+ * Synchronises when recording. */
+int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap,
+                      uint64_t* nout);
+/* Mode 0: all replicas in one launch per step (tiles of every replica in one
+ * grid).  Mode 1: one launch per replica per step (the reference loop the
+ * batched mode is measured against).  Default 0. */
+int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
+int xyl_ensemble_get_state(xyl_ensemble* e, int32_t r, double* theta, double* omega, uint64_t* step);
+int xyl_ensemble_set_state(xyl_ensemble* e, int32_t r, const double* theta, const double* omega,
+                           uint64_t step);
+int xyl_ensemble_domains(xyl_ensemble* e, int32_t r, int32_t* labels, uint64_t* sizes, uint64_t* counts,
+                         uint64_t cap, uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size);
+int xyl_ensemble_sync(xyl_ensemble* e);
+
+/* ---------------------------------------------------------------- adjoint */
+/* Pathwise gradients with the Gaussian draws held fixed (a training-style
+ * reverse mode of the discrete BBK map of App. A.1; the wrap has derivative
+ * 1).  Loss L = (1/W) sum_{k=k0+N-W+1}^{k0+N} m_s(th^k)^2.
+ * xyl_adjoint_forward runs N steps from the current state, keeping a
+ * checkpoint every `ckpt_every` steps, and returns L; the lattice advances.
+ * xyl_adjoint_backward then returns dL/d(Jx, Jy, h, gamma) in grad[4] (gamma
+ * must be > 0 when T > 0) and writes dL/d th^{k0} and dL/d w^{k0} as float64
+ * host arrays (nullable).  1 <= W <= N. */
+int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss);
+int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* domega0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,1 +1,423 @@
-"""Python binding of the MI355X Langevin-XY library (placeholder, filled in below)."""
+"""Python binding of ``libxyl.so``, the MI355X (gfx950) Langevin-XY library.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C-ABI declared in ``include/xyl.h``.  PyTorch provides the
+device memory of the state (three tensors per lattice) and the stream.  There
+is no CPU fallback: if the library or a gfx950 device is missing, every call
+raises.
+
+    import paper_2409_06412_amd as xyl
+    lat = xyl.Lattice(4096, 4096, dtype="f32", schedule=[(0, 0.5)], seed=1)
+    lat.init_random()
+    lat.step(1000)
+    samples = lat.step_measured(10_000, every=500)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxyl.so")
+
+F32, F64 = 0, 1
+MAX_KNOTS = 16
+OBS_FIELDS = ("e_pot", "e_kin", "m_s", "f0", "fkx", "fky")
+
+_ERRORS = {-1: "XYL_EINVAL", -2: "XYL_ENOMEM", -3: "XYL_EDEVICE", -4: "XYL_ESTATE",
+           -5: "XYL_EUNSUPPORTED", -6: "XYL_ENUMERIC"}
+
+
+class XylError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_ERRORS.get(code, str(code)), msg))
+        self.code = code
+
+
+class ReplicaDesc(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+        ("Jx", ctypes.c_double), ("Jy", ctypes.c_double), ("h", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("replica", ctypes.c_uint32),
+        ("nknots", ctypes.c_int32),
+        ("knot_step", ctypes.c_uint64 * MAX_KNOTS),
+        ("knot_T", ctypes.c_double * MAX_KNOTS),
+        ("nsteps", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+P = ctypes.POINTER
+_d, _u64, _u32, _i32, _vp = ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p
+
+_SIGS = {
+    "xyl_abi_version": (_i32, []),
+    "xyl_last_error": (ctypes.c_char_p, []),
+    "xyl_device_count": (_i32, []),
+    "xyl_create": (_i32, [P(_vp), _i32, _i32, _i32, _i32]),
+    "xyl_create_wrapped": (_i32, [P(_vp), _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "xyl_destroy": (_i32, [_vp]),
+    "xyl_set_stream": (_i32, [_vp, _vp]),
+    "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
+    "xyl_set_schedule": (_i32, [_vp, P(_u64), P(_d), _i32]),
+    "xyl_set_seed": (_i32, [_vp, _u64, _u32]),
+    "xyl_init_random": (_i32, [_vp]),
+    "xyl_init_ordered": (_i32, [_vp, _i32]),
+    "xyl_set_state": (_i32, [_vp, P(_d), P(_d), _u64]),
+    "xyl_get_state": (_i32, [_vp, P(_d), P(_d), P(_u64)]),
+    "xyl_state_buffers": (_i32, [_vp, P(_vp), P(_vp), P(_i32)]),
+    "xyl_step": (_i32, [_vp, _u64]),
+    "xyl_step_measured": (_i32, [_vp, _u64, _u64, P(_d), _u64, P(_u64)]),
+    "xyl_measure": (_i32, [_vp, P(_d)]),
+    "xyl_correlation": (_i32, [_vp, _i32, _i32, P(_d)]),
+    "xyl_domains": (_i32, [_vp, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
+    "xyl_sync": (_i32, [_vp]),
+    "xyl_set_launch": (_i32, [_vp, _i32, _i32]),
+    "xyl_get_launch": (_i32, [_vp, P(_i32), P(_i32)]),
+    "xyl_autotune": (_i32, [_vp]),
+    "xyl_set_graph_steps": (_i32, [_vp, _i32]),
+    "xyl_philox_blocks": (_i32, [_i32, _u64, P(_u32), P(_u32), _u64]),
+    "xyl_noise": (_i32, [_vp, _u64, P(_d)]),
+    "xyl_binder": (_i32, [P(_d), _u64, _u64, P(_d), P(_d)]),
+    "xyl_mean_error": (_i32, [P(_d), _u64, _u64, P(_d), P(_d), P(_d)]),
+    "xyl_ensemble_create": (_i32, [P(_vp), P(ReplicaDesc), _i32, _i32, _i32]),
+    "xyl_ensemble_destroy": (_i32, [_vp]),
+    "xyl_ensemble_set_stream": (_i32, [_vp, _vp]),
+    "xyl_ensemble_step": (_i32, [_vp, _u64, _u64, P(_d), _u64, P(_u64)]),
+    "xyl_ensemble_set_mode": (_i32, [_vp, _i32]),
+    "xyl_ensemble_get_state": (_i32, [_vp, _i32, P(_d), P(_d), P(_u64)]),
+    "xyl_ensemble_set_state": (_i32, [_vp, _i32, P(_d), P(_d), _u64]),
+    "xyl_ensemble_domains": (_i32, [_vp, _i32, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
+    "xyl_ensemble_sync": (_i32, [_vp]),
+    "xyl_adjoint_forward": (_i32, [_vp, _u64, _u64, _u64, P(_d)]),
+    "xyl_adjoint_backward": (_i32, [_vp, P(_d), P(_d), P(_d)]),
+}
+
+
+def load():
+    """Loads ``libxyl.so`` (built in-tree by ``build.py``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libxyl.so is not built: run `python -m paper_2409_06412_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise XylError(rc, load().xyl_last_error().decode())
+
+
+def _pd(a: np.ndarray):
+    return a.ctypes.data_as(P(_d))
+
+
+def _f64(a, shape) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+def _sched_arrays(schedule):
+    sched = list(schedule)
+    ks = (_u64 * len(sched))(*[int(k) for k, _ in sched])
+    Ts = (_d * len(sched))(*[float(T) for _, T in sched])
+    return ks, Ts, len(sched)
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in ("f32", "float32", F32):
+        return F32
+    if dtype in ("f64", "float64", F64):
+        return F64
+    raise ValueError("dtype must be 'f32' or 'f64'")
+
+
+def device_count() -> int:
+    return load().xyl_device_count()
+
+
+class Lattice:
+    """One periodic Lx x Ly lattice whose state lives in three torch tensors on
+    ``cuda:device`` (two angle buffers and the velocity buffer)."""
+
+    def __init__(self, Lx: int, Ly: int, dtype="f32", device: int = 0, *, Jx=1.0, Jy=-0.1, h=0.5,
+                 gamma=1.0, dt=0.01, schedule: Sequence[Tuple[int, float]] = ((0, 0.0),), seed=0,
+                 replica=0, stream=None, torch_buffers: bool = True):
+        import torch
+        lib = load()
+        self.Lx, self.Ly, self.N = int(Lx), int(Ly), int(Lx) * int(Ly)
+        self.dtype = _dtype_code(dtype)
+        self.device = int(device)
+        self._h = _vp()
+        self._bufs = None
+        if torch_buffers:
+            tdt = torch.float32 if self.dtype == F32 else torch.float64
+            dev = torch.device("cuda", self.device)
+            self._bufs = [torch.zeros(self.N, dtype=tdt, device=dev) for _ in range(3)]
+            _check(lib.xyl_create_wrapped(ctypes.byref(self._h), self.Lx, self.Ly, self.dtype, self.device,
+                                          *[_vp(b.data_ptr()) for b in self._bufs]))
+        else:
+            _check(lib.xyl_create(ctypes.byref(self._h), self.Lx, self.Ly, self.dtype, self.device))
+        if stream is not None:
+            _check(lib.xyl_set_stream(self._h, _vp(int(stream))))
+        self.set_params(Jx, Jy, h, gamma, dt)
+        self.set_schedule(schedule)
+        self.set_seed(seed, replica)
+
+    # -- lifetime --------------------------------------------------------------
+    def close(self):
+        if self._h:
+            _check(load().xyl_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- configuration -----------------------------------------------------------
+    def set_params(self, Jx, Jy, h, gamma, dt):
+        self.params = dict(Jx=float(Jx), Jy=float(Jy), h=float(h), gamma=float(gamma), dt=float(dt))
+        _check(load().xyl_set_params(self._h, float(Jx), float(Jy), float(h), float(gamma), float(dt)))
+
+    def set_schedule(self, schedule):
+        ks, Ts, n = _sched_arrays(schedule)
+        _check(load().xyl_set_schedule(self._h, ks, Ts, n))
+
+    def set_seed(self, seed, replica=0):
+        _check(load().xyl_set_seed(self._h, int(seed), int(replica)))
+
+    def set_stream(self, stream):
+        _check(load().xyl_set_stream(self._h, _vp(int(stream) if stream is not None else 0)))
+
+    def set_launch(self, rows_per_strip=0, waves_per_block=0):
+        _check(load().xyl_set_launch(self._h, int(rows_per_strip), int(waves_per_block)))
+
+    def launch(self):
+        r, w = _i32(), _i32()
+        _check(load().xyl_get_launch(self._h, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
+
+    def autotune(self):
+        _check(load().xyl_autotune(self._h))
+        return self.launch()
+
+    def set_graph_steps(self, steps: int):
+        _check(load().xyl_set_graph_steps(self._h, int(steps)))
+
+    # -- state -------------------------------------------------------------------
+    def init_random(self):
+        _check(load().xyl_init_random(self._h))
+
+    def init_ordered(self, sign=1):
+        _check(load().xyl_init_ordered(self._h, int(sign)))
+
+    def set_state(self, theta, omega, step: int = 0):
+        th = _f64(theta, (self.Ly, self.Lx))
+        om = _f64(omega, (self.Ly, self.Lx))
+        _check(load().xyl_set_state(self._h, _pd(th), _pd(om), int(step)))
+
+    def get_state(self):
+        th = np.empty((self.Ly, self.Lx))
+        om = np.empty((self.Ly, self.Lx))
+        k = _u64()
+        _check(load().xyl_get_state(self._h, _pd(th), _pd(om), ctypes.byref(k)))
+        return th, om, k.value
+
+    @property
+    def step_index(self) -> int:
+        k = _u64()
+        _check(load().xyl_get_state(self._h, None, None, ctypes.byref(k)))
+        return k.value
+
+    def state_buffers(self):
+        """(theta_ptr, vel_ptr, fresh): device pointers of the current angles and
+        of the velocity buffer (w^k if fresh, else w^{k-1/2})."""
+        t, v, f = _vp(), _vp(), _i32()
+        _check(load().xyl_state_buffers(self._h, ctypes.byref(t), ctypes.byref(v), ctypes.byref(f)))
+        return t.value, v.value, bool(f.value)
+
+    def theta_tensor(self):
+        """The current angles as a (Ly, Lx) torch view (torch-backed lattices only)."""
+        if self._bufs is None:
+            raise RuntimeError("lattice was created without torch buffers")
+        ptr = self.state_buffers()[0]
+        for b in self._bufs[:2]:
+            if b.data_ptr() == ptr:
+                return b.view(self.Ly, self.Lx)
+        raise RuntimeError("current angle buffer not found")
+
+    # -- stepping and measurement ------------------------------------------------------
+    def step(self, nsteps: int):
+        _check(load().xyl_step(self._h, int(nsteps)))
+
+    def step_measured(self, nsteps: int, every: int) -> np.ndarray:
+        ns = int(nsteps) // int(every) + 1
+        out = np.empty((ns, 6))
+        nout = _u64()
+        _check(load().xyl_step_measured(self._h, int(nsteps), int(every), _pd(out), ns, ctypes.byref(nout)))
+        return out[: nout.value]
+
+    def measure(self) -> np.ndarray:
+        out = np.empty(6)
+        _check(load().xyl_measure(self._h, _pd(out)))
+        return out
+
+    def correlation(self, axis: int, rmax: int) -> np.ndarray:
+        C = np.empty(int(rmax) + 1)
+        _check(load().xyl_correlation(self._h, int(axis), int(rmax), _pd(C)))
+        return C
+
+    def domains(self, want_labels: bool = True):
+        """Returns (labels or None, sizes, counts, n_domains, max_size)."""
+        return _domains(lambda *a: load().xyl_domains(self._h, *a), self.N, (self.Ly, self.Lx), want_labels)
+
+    def noise(self, k: int) -> np.ndarray:
+        out = np.empty((self.Ly, self.Lx))
+        _check(load().xyl_noise(self._h, int(k), _pd(out)))
+        return out
+
+    def sync(self):
+        _check(load().xyl_sync(self._h))
+
+    # -- gradients ---------------------------------------------------------------------
+    def adjoint_forward(self, nsteps: int, ckpt_every: int, window: int) -> float:
+        L = _d()
+        _check(load().xyl_adjoint_forward(self._h, int(nsteps), int(ckpt_every), int(window), ctypes.byref(L)))
+        return L.value
+
+    def adjoint_backward(self):
+        g = np.empty(4)
+        dth = np.empty((self.Ly, self.Lx))
+        dom = np.empty((self.Ly, self.Lx))
+        _check(load().xyl_adjoint_backward(self._h, _pd(g), _pd(dth), _pd(dom)))
+        return g, dth, dom
+
+
+def _domains(call, N, shape, want_labels):
+    labels = np.empty(shape, dtype=np.int32) if want_labels else None
+    ns, nd, mx = _u64(), _u64(), _u64()
+    lab_p = labels.ctypes.data_as(P(_i32)) if want_labels else None
+    _check(call(lab_p, None, None, 0, ctypes.byref(ns), ctypes.byref(nd), ctypes.byref(mx)))
+    cap = max(ns.value, 1)
+    sizes = np.empty(cap, dtype=np.uint64)
+    counts = np.empty(cap, dtype=np.uint64)
+    _check(call(None, sizes.ctypes.data_as(P(_u64)), counts.ctypes.data_as(P(_u64)), cap,
+                ctypes.byref(ns), ctypes.byref(nd), ctypes.byref(mx)))
+    return labels, sizes[: ns.value], counts[: ns.value], nd.value, mx.value
+
+
+class Ensemble:
+    """Replicas of possibly different size, parameters, schedule, seed and step
+    count, stepped together in batched launches."""
+
+    def __init__(self, specs, dtype="f32", device: int = 0, stream=None):
+        self.specs = list(specs)
+        n = len(self.specs)
+        arr = (ReplicaDesc * n)()
+        for d, s in zip(arr, self.specs):
+            d.Lx, d.Ly = s.Lx, s.Ly
+            d.Jx, d.Jy, d.h, d.gamma, d.dt = s.Jx, s.Jy, s.h, s.gamma, s.dt
+            d.seed, d.replica = s.seed, s.replica
+            sched = list(s.schedule)
+            d.nknots = len(sched)
+            for j, (k, T) in enumerate(sched):
+                d.knot_step[j] = int(k)
+                d.knot_T[j] = float(T)
+            d.nsteps = int(s.nsteps)
+        self.dtype = _dtype_code(dtype)
+        self._h = _vp()
+        _check(load().xyl_ensemble_create(ctypes.byref(self._h), arr, n, self.dtype, int(device)))
+        if stream is not None:
+            _check(load().xyl_ensemble_set_stream(self._h, _vp(int(stream))))
+        self.n = n
+
+    def close(self):
+        if self._h:
+            _check(load().xyl_ensemble_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mode(self, mode: int):
+        _check(load().xyl_ensemble_set_mode(self._h, int(mode)))
+
+    def step(self, nsteps: int, every: int = 0, cap: int = 0):
+        """Advances; with every > 0 returns a list of (n_r, 6) sample arrays."""
+        if not every:
+            _check(load().xyl_ensemble_step(self._h, int(nsteps), 0, None, 0, None))
+            return None
+        cap = cap or int(nsteps) // int(every) + 2
+        out = np.empty((self.n, cap, 6))
+        nout = np.zeros(self.n, dtype=np.uint64)
+        _check(load().xyl_ensemble_step(self._h, int(nsteps), int(every), _pd(out), cap,
+                                        nout.ctypes.data_as(P(_u64))))
+        return [out[r, : int(nout[r])] for r in range(self.n)]
+
+    def get_state(self, r: int):
+        s = self.specs[r]
+        th = np.empty((s.Ly, s.Lx))
+        om = np.empty((s.Ly, s.Lx))
+        k = _u64()
+        _check(load().xyl_ensemble_get_state(self._h, int(r), _pd(th), _pd(om), ctypes.byref(k)))
+        return th, om, k.value
+
+    def set_state(self, r: int, theta, omega, step: int = 0):
+        s = self.specs[r]
+        th = _f64(theta, (s.Ly, s.Lx))
+        om = _f64(omega, (s.Ly, s.Lx))
+        _check(load().xyl_ensemble_set_state(self._h, int(r), _pd(th), _pd(om), int(step)))
+
+    def domains(self, r: int, want_labels: bool = True):
+        s = self.specs[r]
+        return _domains(lambda *a: load().xyl_ensemble_domains(self._h, int(r), *a), s.Lx * s.Ly,
+                        (s.Ly, s.Lx), want_labels)
+
+    def sync(self):
+        _check(load().xyl_ensemble_sync(self._h))
+
+
+def philox_blocks(counters: np.ndarray, seed: int, device: int = 0) -> np.ndarray:
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(c)
+    _check(load().xyl_philox_blocks(int(device), int(seed), c.ctypes.data_as(P(_u32)),
+                                    out.ctypes.data_as(P(_u32)), c.shape[0]))
+    return out
+
+
+def binder(m, discard: int = 0):
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    U, se = _d(), _d()
+    _check(load().xyl_binder(_pd(m), m.size, int(discard), ctypes.byref(U), ctypes.byref(se)))
+    return U.value, se.value
+
+
+def mean_error(f, discard: int = 0):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    mu, se, tau = _d(), _d(), _d()
+    _check(load().xyl_mean_error(_pd(f), f.size, int(discard), ctypes.byref(mu), ctypes.byref(se),
+                                 ctypes.byref(tau)))
+    return mu.value, se.value, tau.value

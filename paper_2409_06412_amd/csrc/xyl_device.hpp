@@ -1,0 +1,194 @@
+// Device primitives of the Langevin-XY step: counter-based noise, the
+// temperature schedule, precision traits and the per-lattice launch view.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xyl_internal.hpp"
+
+namespace xyl {
+
+// ----------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// -> 64 bit products of words 0 and 2 with fixed multipliers, whose halves are
+// mixed with words 1, 3 and the round key; the key advances by the Weyl
+// constants between rounds.  The key is wave-uniform, so its schedule lives
+// in scalar registers.
+struct U32x4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t ka = k0 + (uint32_t)r * kWeylA;
+        const uint32_t kb = k1 + (uint32_t)r * kWeylB;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ ka;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ kb;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+    }
+    U32x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+// --------------------------------------------------------------- schedule
+// T(k), piecewise linear in the step index, held outside the knots; FP64 with
+// the operation order fixed so that every caller gets the same bits.
+__host__ __device__ __forceinline__ double schedule_T(const Schedule& s, uint64_t k) {
+    double T;
+    if (k <= s.step[0]) {
+        T = s.T[0];
+    } else if (k >= s.step[s.n - 1]) {
+        T = s.T[s.n - 1];
+    } else {
+        int j = 0;
+        while (!(k >= s.step[j] && k < s.step[j + 1])) ++j;
+        const double ka = (double)s.step[j], kb = (double)s.step[j + 1];
+        const double frac = ((double)k - ka) / (kb - ka);
+        T = s.T[j] + (s.T[j + 1] - s.T[j]) * frac;
+    }
+    return T < 0.0 ? 0.0 : T;
+}
+
+// Noise amplitude of one half-kick, (1/2) sqrt(2 gamma T_k dt), in FP64.
+__host__ __device__ __forceinline__ double half_sigma(const Schedule& s, double gamma, double dt, uint64_t k) {
+    return 0.5 * sqrt(2.0 * gamma * schedule_T(s, k) * dt);
+}
+
+// -------------------------------------------------------- precision traits
+template <typename R>
+struct Prec;
+
+template <>
+struct Prec<float> {
+    static constexpr float kPi = 3.14159274101257324e+00f;    // pi rounded to binary32
+    static constexpr float kTwoPi = 6.28318548202514648e+00f;
+    static constexpr float kHalfPi = 1.57079637050628662e+00f;
+    // Native sine/cosine take revolutions; angles here lie in [-pi_p, pi_p].
+    __device__ static __forceinline__ void sincos(float t, float& s, float& c) {
+        const float x = t * 0.159154943091895336f;
+        s = __builtin_amdgcn_sinf(x);
+        c = __builtin_amdgcn_cosf(x);
+    }
+    __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    // ((r >> 9) + 1/2) 2^-23, exactly: [1, 2) from the top 23 bits, minus (1 - 2^-24).
+    __device__ static __forceinline__ float uniform(uint32_t r) {
+        return __uint_as_float((r >> 9) | 0x3f800000u) - 0x1.fffffep-1f;
+    }
+    // One Box-Muller pair: radius sqrt(-2 ln u1) (ln via the native log2),
+    // angle 2 pi u2 (native sine/cosine in revolutions, no multiplication).
+    __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, float& nc, float& ns) {
+        const float u1 = uniform(r1), u2 = uniform(r2);
+        const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989062f * __builtin_amdgcn_logf(u1));
+        nc = rad * __builtin_amdgcn_cosf(u2);
+        ns = rad * __builtin_amdgcn_sinf(u2);
+    }
+};
+
+template <>
+struct Prec<double> {
+    static constexpr double kPi = 3.14159265358979311600e+00;
+    static constexpr double kTwoPi = 6.28318530717958623200e+00;
+    static constexpr double kHalfPi = 1.57079632679489655800e+00;
+    __device__ static __forceinline__ void sincos(double t, double& s, double& c) { ::sincos(t, &s, &c); }
+    __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    __device__ static __forceinline__ double uniform(uint32_t r) { return ((double)(r >> 9) + 0.5) * 0x1p-23; }
+    __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, double& nc, double& ns) {
+        const double u1 = uniform(r1), u2 = uniform(r2);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double phi = kTwoPi * u2;
+        nc = rad * cos(phi);
+        ns = rad * sin(phi);
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ R wrap_angle(R t) {
+    // exact by Sterbenz's lemma while |dt * u| < pi
+    if (t >= Prec<R>::kPi)
+        t -= Prec<R>::kTwoPi;
+    else if (t < -Prec<R>::kPi)
+        t += Prec<R>::kTwoPi;
+    return t;
+}
+
+// Four Gaussian draws of the sites 4q..4q+3 (q = i >> 2) at step k.
+template <typename R>
+__device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k, uint32_t s0, uint32_t s1, R n[4]) {
+    const U32x4 r = philox4x32_10(q, replica, (uint32_t)k, (uint32_t)(k >> 32), s0, s1);
+    Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1]);
+    Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3]);
+}
+
+// ---------------------------------------------------- lane exchange (DPP)
+// wave_shr:1 moves a value to the next lane up, wave_shl:1 to the next lane
+// down; lanes at the ends receive `old`.
+__device__ __forceinline__ float from_lane_below(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_lane_above(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_lane_below(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_lane_above(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename R>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using T = float4;
+};
+template <>
+struct Vec4<double> {
+    using T = double4;
+};
+
+template <typename R>
+__device__ __forceinline__ void load4(const R* p, R o[4]) {
+    const typename Vec4<R>::T v = *reinterpret_cast<const typename Vec4<R>::T*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+template <typename R>
+__device__ __forceinline__ void store4(R* p, const R o[4]) {
+    typename Vec4<R>::T v;
+    v.x = o[0];
+    v.y = o[1];
+    v.z = o[2];
+    v.w = o[3];
+    *reinterpret_cast<typename Vec4<R>::T*>(p) = v;
+}
+
+// Bijective remap of workgroup ids so that each of the eight XCDs (which
+// receive workgroups round-robin) processes a contiguous range of logical
+// workgroups: neighbouring strips, whose halo rows overlap, share one L2.
+__device__ __forceinline__ int xcd_contiguous_block(int b, int nb) {
+    constexpr int kXcd = 8;
+    const int per = nb / kXcd, rem = nb % kXcd;
+    const int xcd = b % kXcd, idx = b / kXcd;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+}  // namespace xyl

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+
+namespace xyl {
+
+constexpr int kWave = 64;                  // CDNA wavefront width
+constexpr int kLaneSites = 4;              // sites per lane = sites per Philox block
+constexpr int kWaveSites = kWave * kLaneSites;
+constexpr int kMaxKnots = 16;
+constexpr int kNPart = 12;                 // measurement partial sums per (row, wave chunk)
+constexpr uint64_t kInitStep = ~(uint64_t)0;  // reserved step counter of the init stream
+
+struct Schedule {
+    int32_t n;
+    uint64_t step[kMaxKnots];
+    double T[kMaxKnots];
+};
+
+// Everything a step kernel needs to know about one lattice (or one replica of
+// an ensemble).  Buffers: two angle buffers (ping-pong) and one velocity
+// buffer updated in place.
+template <typename R>
+struct Lat {
+    R* th[2];
+    R* u;
+    int32_t cur;           // index of the angle buffer holding th^k at the view's base step
+    int32_t Lx, Ly;
+    int32_t nxw;           // wave chunks per row: ceil(Lx / 256)
+    int32_t stag_x, stag_y;
+    R Jx, Jy, h4, a, c, hdt, dt;   // state-precision coefficients
+    double Jxd, Jyd, hd;           // FP64 copies for the energy
+    double gamma, dtd;             // FP64 for the noise amplitude
+    Schedule sched;
+    uint32_t seed_lo, seed_hi, replica;
+    uint64_t k_base;       // step index at launch-step 0
+    uint64_t fresh_k;      // step at which u holds w^k itself
+    uint64_t k_end;        // the replica does not step at k >= k_end
+    double* part;          // measurement partials [Ly][nxw][kNPart]
+    R* omega_out;          // destination of w^k (omega mode)
+};
+
+// Step-kernel modes (bit flags).
+enum : int { kStore = 1, kMeasure = 2, kOmega = 4 };
+
+struct Launch {
+    int rows = 16;     // rows per strip
+    int wpb = 4;       // waves per workgroup
+};
+
+// One wave's work item inside a batched launch.
+struct Task {
+    int32_t rep, xw, strip, pad;
+};
+
+// ------------------------------------------------------------- launchers
+template <typename R>
+void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j,
+                 hipStream_t s);
+template <typename R>
+void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int rows, int wpb,
+                          const uint64_t* kdev, uint64_t j, hipStream_t s);
+template <typename R>
+void launch_init_random(const Lat<R>& v, hipStream_t s);
+template <typename R>
+void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s);
+void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s);
+void launch_finalize_obs_batched(const Lat<float>* reps_f, const Lat<double>* reps_d, const int* rep_ids,
+                                 int nrep, double* const* outs, hipStream_t s);
+void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
+void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
+template <typename R>
+void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int axis, int rmax, double* part,
+                        double* out, hipStream_t s);
+template <typename R>
+void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent, uint32_t* size,
+                    uint32_t* hist, uint32_t* stats, hipStream_t s);
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void check_hip(hipError_t e, const char* what);
+
+}  // namespace xyl

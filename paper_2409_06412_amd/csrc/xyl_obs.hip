@@ -1,0 +1,178 @@
+// Measurements outside the step: the staggered rotor correlation function and
+// the frozen-domain labelling.
+#include "xyl_device.hpp"
+
+namespace xyl {
+
+// --------------------------------------------------------- correlation
+// C(r) = (1/N) sum_i eps_i eps_j cos(th_i - th_j), j = i + r along one axis
+// (App. C, two-point function of the rotors averaged over the lattice).  One
+// workgroup per line (row for axis 0, column for axis 1) stages the line's
+// staggered rotors (eps cos th, eps sin th) in LDS in FP64; thread r sums the
+// line's products in index order.  A second pass sums the lines in order.
+template <typename R>
+__global__ __launch_bounds__(256) void k_corr_lines(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
+                                                    int axis, int rmax, double* __restrict__ part) {
+    extern __shared__ double lds[];
+    const int line = blockIdx.x;
+    const int L = axis == 0 ? Lx : Ly;
+    double* cs = lds;
+    double* sn = lds + L;
+    for (int p = threadIdx.x; p < L; p += blockDim.x) {
+        const int x = axis == 0 ? p : line;
+        const int y = axis == 0 ? line : p;
+        const double t = (double)th[(size_t)y * Lx + x];
+        const double e = (((x * sx) + (y * sy)) & 1) ? -1.0 : 1.0;
+        double s, c;
+        sincos(t, &s, &c);
+        cs[p] = e * c;
+        sn[p] = e * s;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r <= rmax; r += blockDim.x) {
+        double acc = 0.0;
+        for (int p = 0; p < L; ++p) {
+            int q = p + r;
+            if (q >= L) q -= L;
+            acc += cs[p] * cs[q] + sn[p] * sn[q];
+        }
+        part[(size_t)line * (rmax + 1) + r] = acc;
+    }
+}
+
+__global__ void k_corr_sum(const double* __restrict__ part, int nlines, int rmax, double N, double* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > rmax) return;
+    double acc = 0.0;
+    for (int l = 0; l < nlines; ++l) acc += part[(size_t)l * (rmax + 1) + r];
+    out[r] = acc / N;
+}
+
+template <typename R>
+void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int axis, int rmax, double* part, double* out,
+                        hipStream_t s) {
+    const int nlines = axis == 0 ? Ly : Lx;
+    const int L = axis == 0 ? Lx : Ly;
+    const size_t lds = 2 * sizeof(double) * (size_t)L;
+    k_corr_lines<R><<<nlines, 256, lds, s>>>(th, Lx, Ly, sx, sy, axis, rmax, part);
+    check_hip(hipGetLastError(), "correlation kernel launch");
+    k_corr_sum<<<(rmax + 256) / 256, 256, 0, s>>>(part, nlines, rmax, (double)Lx * (double)Ly, out);
+    check_hip(hipGetLastError(), "correlation sum launch");
+}
+
+// -------------------------------------------------------------- domains
+// Spin of site (x, y): eps * (|th| <= pi_p / 2 ? +1 : -1), decided in the
+// state precision.
+template <typename R>
+__device__ __forceinline__ int spin_of(const R* th, int Lx, int x, int y, int sx, int sy) {
+    const R t = th[(size_t)y * Lx + x];
+    const int s = (t <= Prec<R>::kHalfPi && t >= -Prec<R>::kHalfPi) ? 1 : -1;
+    return (((x * sx) + (y * sy)) & 1) ? -s : s;
+}
+
+__device__ __forceinline__ int32_t uf_load(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t uf_find(const int32_t* parent, int32_t a) {
+    int32_t p = uf_load(parent + a);
+    while (p != a) {
+        a = p;
+        p = uf_load(parent + a);
+    }
+    return a;
+}
+
+// Union with monotone links (the larger root is hooked under the smaller by
+// atomicMin; parent[i] <= i always, so every find terminates).  When the hook
+// finds that another thread re-parented the root first, the loop unites the
+// value it displaced, so no connection is lost (Playne and Hawick, IEEE TPDS
+// 2018).  The surviving root of a cluster is its smallest index.
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+    while (true) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicMin(parent + a, b);
+        if (old == a) return;
+        b = old;
+    }
+}
+
+__global__ void k_uf_init(int32_t* parent, uint32_t* size, size_t N) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        parent[i] = (int32_t)i;
+        size[i] = 0u;
+    }
+}
+
+template <typename R>
+__global__ void k_uf_merge(const R* __restrict__ th, int Lx, int Ly, int sx, int sy, int32_t* parent) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)Lx * Ly) return;
+    const int x = (int)(i % Lx), y = (int)(i / Lx);
+    const int s = spin_of(th, Lx, x, y, sx, sy);
+    const int xp = x + 1 == Lx ? 0 : x + 1;
+    const int yp = y + 1 == Ly ? 0 : y + 1;
+    if (spin_of(th, Lx, xp, y, sx, sy) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)y * Lx + xp));
+    if (spin_of(th, Lx, x, yp, sx, sy) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)yp * Lx + x));
+}
+
+__global__ void k_uf_flatten(int32_t* parent, uint32_t* size, size_t N) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t r = uf_find(parent, (int32_t)i);
+    atomicAdd(size + r, 1u);
+}
+
+// After the flatten pass every find is settled: write the roots and histogram
+// the cluster sizes; stats = {number of clusters, largest cluster}.
+__global__ void k_uf_finish(int32_t* parent, const uint32_t* size, uint32_t* hist, uint32_t* stats, size_t N) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t r = uf_find(parent, (int32_t)i);
+    if (r == (int32_t)i) {
+        const uint32_t sz = size[i];
+        atomicAdd(hist + sz, 1u);
+        atomicAdd(stats, 1u);
+        atomicMax(stats + 1, sz);
+    }
+}
+
+__global__ void k_uf_label(int32_t* parent, size_t N) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    parent[i] = uf_find(parent, (int32_t)i);
+}
+
+template <typename R>
+void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent, uint32_t* size, uint32_t* hist,
+                    uint32_t* stats, hipStream_t s) {
+    const size_t N = (size_t)Lx * Ly;
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    k_uf_init<<<nb, 256, 0, s>>>(parent, size, N);
+    check_hip(hipGetLastError(), "uf init launch");
+    k_uf_merge<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, parent);
+    check_hip(hipGetLastError(), "uf merge launch");
+    k_uf_flatten<<<nb, 256, 0, s>>>(parent, size, N);
+    check_hip(hipGetLastError(), "uf flatten launch");
+    k_uf_finish<<<nb, 256, 0, s>>>(parent, size, hist, stats, N);
+    check_hip(hipGetLastError(), "uf finish launch");
+    k_uf_label<<<nb, 256, 0, s>>>(parent, N);
+    check_hip(hipGetLastError(), "uf label launch");
+}
+
+template void launch_correlation<float>(const float*, int, int, int, int, int, int, double*, double*, hipStream_t);
+template void launch_correlation<double>(const double*, int, int, int, int, int, int, double*, double*, hipStream_t);
+template void launch_domains<float>(const float*, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                    hipStream_t);
+template void launch_domains<double>(const double*, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                     hipStream_t);
+
+}  // namespace xyl

@@ -1,0 +1,1266 @@
+// Host runtime behind the C-ABI of include/xyl.h: parameter validation,
+// device buffers, streams, captured step graphs, the launch-shape autotuner,
+// the batched ensemble and the host-side estimators.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/xyl.h"
+#include "xyl_device.hpp"
+#include "xyl_internal.hpp"
+
+namespace xyl {
+
+void launch_finalize_jobs(const void* jobs, int njobs, hipStream_t s);
+void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
+
+struct FinalizeJobHost {
+    const double* part;
+    int nrp;
+    double N;
+    double* out;
+};
+
+thread_local std::string g_err;
+
+void check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Error(XYL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static void require(bool ok, int code, const std::string& msg) {
+    if (!ok) throw Error(code, msg);
+}
+
+static void check_alloc(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        throw Error(XYL_ENOMEM, std::string(what) + ": out of device memory");
+    check_hip(e, what);
+}
+
+// ------------------------------------------------------------- devices
+static bool is_gfx950(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    return std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+}
+
+static void select_device(int dev) {
+    int n = 0;
+    check_hip(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    require(dev >= 0 && dev < n, XYL_EINVAL, "device index out of range");
+    require(is_gfx950(dev), XYL_EDEVICE, "device is not gfx950 (MI355X)");
+    check_hip(hipSetDevice(dev), "hipSetDevice");
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        (void)hipGetDevice(&prev);
+        check_hip(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void reserve(size_t count) {
+        if (count <= n && p) return;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        check_alloc(hipMalloc(reinterpret_cast<void**>(&p), sizeof(T) * std::max<size_t>(count, 1)), "hipMalloc");
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { release(); }
+};
+
+// ------------------------------------------------------------ parameters
+struct Params {
+    double Jx = 1.0, Jy = -0.1, h = 0.5, gamma = 1.0, dt = 0.01;
+};
+
+static void validate_params(const Params& p) {
+    require(std::isfinite(p.Jx) && std::isfinite(p.Jy) && std::isfinite(p.h) && std::isfinite(p.gamma) &&
+                std::isfinite(p.dt),
+            XYL_EINVAL, "parameters must be finite");
+    require(p.dt > 0.0, XYL_EINVAL, "dt must be > 0");
+    require(p.gamma >= 0.0, XYL_EINVAL, "gamma must be >= 0");
+}
+
+static Schedule make_schedule(const uint64_t* ks, const double* Ts, int32_t n) {
+    require(n >= 1 && n <= kMaxKnots, XYL_EINVAL, "schedule needs 1..16 knots");
+    require(ks != nullptr && Ts != nullptr, XYL_EINVAL, "schedule arrays are NULL");
+    Schedule s{};
+    s.n = n;
+    for (int j = 0; j < n; ++j) {
+        require(std::isfinite(Ts[j]) && Ts[j] >= 0.0, XYL_EINVAL, "schedule temperatures must be finite and >= 0");
+        if (j > 0) require(ks[j] > ks[j - 1], XYL_EINVAL, "schedule steps must be strictly increasing");
+        s.step[j] = ks[j];
+        s.T[j] = Ts[j];
+    }
+    return s;
+}
+
+template <typename R>
+static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule& s, uint64_t seed, uint32_t replica) {
+    v.Lx = Lx;
+    v.Ly = Ly;
+    v.nxw = (Lx + kWaveSites - 1) / kWaveSites;
+    v.stag_x = p.Jx > 0.0 ? 1 : 0;
+    v.stag_y = p.Jy > 0.0 ? 1 : 0;
+    v.Jx = (R)p.Jx;
+    v.Jy = (R)p.Jy;
+    v.h4 = (R)(4.0 * p.h);
+    v.a = (R)(1.0 - 0.5 * p.gamma * p.dt);
+    v.c = (R)(1.0 / (1.0 + 0.5 * p.gamma * p.dt));
+    v.hdt = (R)(0.5 * p.dt);
+    v.dt = (R)p.dt;
+    v.Jxd = p.Jx;
+    v.Jyd = p.Jy;
+    v.hd = p.h;
+    v.gamma = p.gamma;
+    v.dtd = p.dt;
+    v.sched = s;
+    v.seed_lo = (uint32_t)seed;
+    v.seed_hi = (uint32_t)(seed >> 32);
+    v.replica = replica;
+}
+
+static void validate_shape(int Lx, int Ly) {
+    require(Lx >= 2 && Ly >= 2, XYL_EINVAL, "Lx and Ly must be >= 2");
+    require((double)Lx * (double)Ly < 17179869184.0, XYL_EINVAL, "Lx*Ly must be < 2^34");
+    require(Lx % 4 == 0, XYL_EUNSUPPORTED, "Lx must be a multiple of 4 (one Philox block per 4 sites of a row)");
+    require((double)Lx * (double)Ly < 2147483647.0, XYL_EUNSUPPORTED, "Lx*Ly must fit int32 labels");
+}
+
+static size_t elem_size(int dtype) { return dtype == XYL_F64 ? sizeof(double) : sizeof(float); }
+
+// -------------------------------------------------------- launch tuning
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, Launch> g_tuned;
+
+static void validate_launch(const Launch& l) {
+    require(l.rows >= 1, XYL_EINVAL, "rows per strip must be >= 1");
+    require(l.wpb == 1 || l.wpb == 2 || l.wpb == 4 || l.wpb == 8, XYL_EINVAL, "waves per block must be 1, 2, 4 or 8");
+}
+
+// ------------------------------------------------------------- host stats
+static double tau_int(const double* f, size_t n) {
+    if (n < 2) return 0.5;
+    double mean = 0.0;
+    for (size_t i = 0; i < n; ++i) mean += f[i];
+    mean /= (double)n;
+    double c0 = 0.0;
+    for (size_t i = 0; i < n; ++i) c0 += (f[i] - mean) * (f[i] - mean);
+    c0 /= (double)n;
+    if (!(c0 > 0.0)) return 0.5;
+    double tau = 0.5;
+    for (size_t M = 1; M < n; ++M) {
+        double c = 0.0;
+        for (size_t i = 0; i + M < n; ++i) c += (f[i] - mean) * (f[i + M] - mean);
+        tau += c / (double)n / c0;
+        if ((double)M >= 6.0 * tau) break;
+    }
+    return std::max(tau, 0.5);
+}
+
+}  // namespace xyl
+
+using namespace xyl;
+
+// ===================================================================== lattice
+struct xyl_lattice {
+    int dtype = XYL_F32;
+    int device = 0;
+    int Lx = 0, Ly = 0;
+    size_t N = 0;
+    bool owns = true;
+    void* th[2] = {nullptr, nullptr};
+    void* u = nullptr;
+    int cur = 0;                  // th^k lives in th[(k + cur) & 1]
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Params p;
+    Schedule sched{};
+    uint64_t seed = 0;
+    uint32_t replica = 0;
+    uint64_t k = 0;
+    uint64_t fresh_k = 0;
+    bool initialized = false;
+    Launch launch;
+    int graph_steps = 32;
+    // graphs
+    hipGraphExec_t graph = nullptr;
+    int graph_n = 0;
+    uint64_t graph_version = ~(uint64_t)0;
+    uint64_t version = 0;
+    bool counter_valid = false;
+    // device scratch
+    DevBuf<uint64_t> kdev;
+    DevBuf<double> part;
+    DevBuf<double> obs;
+    DevBuf<double> dscratch;
+    DevBuf<char> omega_buf;
+    DevBuf<int32_t> parent;
+    DevBuf<uint32_t> usz;
+    DevBuf<uint32_t> hist;
+    DevBuf<uint32_t> stats;
+    // adjoint state (see xyl_adjoint.hip)
+    void* adj = nullptr;
+
+    template <typename R>
+    Lat<R> view() {
+        Lat<R> v{};
+        v.th[0] = static_cast<R*>(th[0]);
+        v.th[1] = static_cast<R*>(th[1]);
+        v.u = static_cast<R*>(u);
+        v.cur = cur;
+        fill_lat(v, Lx, Ly, p, sched, seed, replica);
+        v.k_base = 0;
+        v.fresh_k = fresh_k;
+        v.k_end = ~(uint64_t)0;
+        v.part = part.p;
+        v.omega_out = reinterpret_cast<R*>(omega_buf.p);
+        return v;
+    }
+    void* cur_theta() { return th[(int)((k + (uint64_t)cur) & 1)]; }
+    int nrowparts() const { return Ly * ((Lx + kWaveSites - 1) / kWaveSites); }
+    void touch() { ++version; }
+};
+
+namespace xyl {
+void adjoint_release(xyl_lattice* h);  // defined in xyl_adjoint.hip
+}
+
+static void destroy_graph(xyl_lattice* h) {
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_n = 0;
+}
+
+template <typename R>
+static void lattice_launch_one(xyl_lattice* h, int mode) {
+    Lat<R> v = h->view<R>();
+    launch_step<R>(v, mode, h->launch, nullptr, h->k, h->stream);
+}
+
+template <typename R>
+static void build_graph(xyl_lattice* h, int S) {
+    destroy_graph(h);
+    Lat<R> v = h->view<R>();
+    hipGraph_t g = nullptr;
+    check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        for (int j = 0; j < S; ++j) launch_step<R>(v, kStore, h->launch, h->kdev.p, (uint64_t)j, h->cap_stream);
+        launch_bump(h->kdev.p, (uint64_t)S, h->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(e, "hipGraphInstantiate");
+    h->graph = ex;
+    h->graph_n = S;
+    h->graph_version = h->version;
+}
+
+template <typename R>
+static void lattice_steps(xyl_lattice* h, uint64_t n) {
+    while (n > 0) {
+        const int S = h->graph_steps;
+        if (S > 1 && n >= (uint64_t)S) {
+            if (!h->graph || h->graph_n != S || h->graph_version != h->version) build_graph<R>(h, S);
+            if (!h->counter_valid) {
+                launch_set_counter(h->kdev.p, h->k, h->stream);
+                h->counter_valid = true;
+            }
+            check_hip(hipGraphLaunch(h->graph, h->stream), "hipGraphLaunch");
+            h->k += (uint64_t)S;
+            n -= (uint64_t)S;
+        } else {
+            lattice_launch_one<R>(h, kStore);
+            h->k += 1;
+            h->counter_valid = false;
+            n -= 1;
+        }
+    }
+}
+
+template <typename R>
+static void lattice_measure_into(xyl_lattice* h, bool advance, double* obs_dev) {
+    lattice_launch_one<R>(h, advance ? (kStore | kMeasure) : kMeasure);
+    launch_finalize_obs(h->part.p, h->nrowparts(), (double)h->N, obs_dev, h->stream);
+    if (advance) {
+        h->k += 1;
+        h->counter_valid = false;
+    }
+}
+
+static void require_init(xyl_lattice* h) {
+    require(h != nullptr, XYL_EINVAL, "NULL handle");
+    require(h->initialized, XYL_ESTATE, "lattice state not initialised (call an init or set_state first)");
+}
+
+template <typename R>
+static void to_host(const void* dev, double* host, size_t n, hipStream_t s) {
+    std::vector<R> tmp(n);
+    check_hip(hipMemcpyAsync(tmp.data(), dev, sizeof(R) * n, hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (size_t i = 0; i < n; ++i) host[i] = (double)tmp[i];
+}
+
+template <typename R>
+static void to_device(void* dev, const double* host, size_t n, hipStream_t s) {
+    std::vector<R> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (R)host[i];
+    check_hip(hipMemcpyAsync(dev, tmp.data(), sizeof(R) * n, hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+template <typename R>
+static void lattice_omega(xyl_lattice* h, double* omega) {
+    if (h->k == h->fresh_k) {
+        to_host<R>(h->u, omega, h->N, h->stream);
+        return;
+    }
+    h->omega_buf.reserve(sizeof(R) * h->N);
+    lattice_launch_one<R>(h, kOmega);
+    to_host<R>(h->omega_buf.p, omega, h->N, h->stream);
+}
+
+template <typename R>
+static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, DevBuf<int32_t>& parent, DevBuf<uint32_t>& usz,
+                        DevBuf<uint32_t>& hist, DevBuf<uint32_t>& stats, hipStream_t s, int32_t* labels,
+                        uint64_t* sizes, uint64_t* counts, uint64_t cap, uint64_t* n_sizes, uint64_t* n_domains,
+                        uint64_t* max_size) {
+    const size_t N = (size_t)Lx * Ly;
+    parent.reserve(N);
+    usz.reserve(N);
+    hist.reserve(N + 1);
+    stats.reserve(2);
+    check_hip(hipMemsetAsync(hist.p, 0, sizeof(uint32_t) * (N + 1), s), "hipMemsetAsync");
+    check_hip(hipMemsetAsync(stats.p, 0, sizeof(uint32_t) * 2, s), "hipMemsetAsync");
+    launch_domains<R>(th, Lx, Ly, sx, sy, parent.p, usz.p, hist.p, stats.p, s);
+    std::vector<uint32_t> hh(N + 1);
+    uint32_t st[2];
+    check_hip(hipMemcpyAsync(hh.data(), hist.p, sizeof(uint32_t) * (N + 1), hipMemcpyDeviceToHost, s), "D2H");
+    check_hip(hipMemcpyAsync(st, stats.p, sizeof(st), hipMemcpyDeviceToHost, s), "D2H");
+    if (labels) check_hip(hipMemcpyAsync(labels, parent.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s), "D2H");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    uint64_t ns = 0;
+    for (size_t sz = 1; sz <= N; ++sz)
+        if (hh[sz]) ++ns;
+    if (sizes || counts) require(cap >= ns, XYL_EINVAL, "size-distribution capacity too small");
+    uint64_t j = 0;
+    for (size_t sz = 1; sz <= N; ++sz)
+        if (hh[sz]) {
+            if (sizes) sizes[j] = sz;
+            if (counts) counts[j] = hh[sz];
+            ++j;
+        }
+    if (n_sizes) *n_sizes = ns;
+    if (n_domains) *n_domains = st[0];
+    if (max_size) *max_size = st[1];
+}
+
+// ============================================================ error wrapper
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        g_err.clear();
+        f();
+        return XYL_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return XYL_ENOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return XYL_EDEVICE;
+    } catch (...) {
+        g_err = "unknown error";
+        return XYL_EDEVICE;
+    }
+}
+
+#define DISPATCH(dt, FN, ...) ((dt) == XYL_F64 ? FN<double>(__VA_ARGS__) : FN<float>(__VA_ARGS__))
+
+extern "C" {
+
+int xyl_abi_version(void) { return XYL_ABI_VERSION; }
+
+const char* xyl_last_error(void) { return g_err.c_str(); }
+
+int xyl_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    int m = 0;
+    for (int d = 0; d < n; ++d)
+        if (is_gfx950(d)) ++m;
+    return m;
+}
+
+static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype, int32_t device, void* ta, void* tb,
+                       void* vel) {
+    return guarded([&] {
+        require(out != nullptr, XYL_EINVAL, "out is NULL");
+        *out = nullptr;
+        require(dtype == XYL_F32 || dtype == XYL_F64, XYL_EINVAL, "dtype must be XYL_F32 or XYL_F64");
+        validate_shape(Lx, Ly);
+        select_device(device);
+        std::unique_ptr<xyl_lattice> h(new xyl_lattice());
+        h->dtype = dtype;
+        h->device = device;
+        h->Lx = Lx;
+        h->Ly = Ly;
+        h->N = (size_t)Lx * Ly;
+        const uint64_t k0[1] = {0};
+        const double T0[1] = {0.0};
+        h->sched = make_schedule(k0, T0, 1);
+        if (ta) {
+            require(tb && vel && ta != tb && ta != vel && tb != vel, XYL_EINVAL, "wrapped buffers must be distinct");
+            h->owns = false;
+            h->th[0] = ta;
+            h->th[1] = tb;
+            h->u = vel;
+        } else {
+            const size_t bytes = elem_size(dtype) * h->N;
+            for (int b = 0; b < 2; ++b) check_alloc(hipMalloc(&h->th[b], bytes), "hipMalloc theta");
+            check_alloc(hipMalloc(&h->u, bytes), "hipMalloc velocity");
+        }
+        check_hip(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+        h->kdev.reserve(1);
+        h->part.reserve((size_t)h->nrowparts() * kNPart);
+        h->obs.reserve(16 * 6);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find({Lx, Ly, dtype});
+            if (it != g_tuned.end()) h->launch = it->second;
+        }
+        *out = h.release();
+    });
+}
+
+int xyl_create(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype, int32_t device) {
+    return create_impl(out, Lx, Ly, dtype, device, nullptr, nullptr, nullptr);
+}
+
+int xyl_create_wrapped(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype, int32_t device, void* theta_a,
+                       void* theta_b, void* vel) {
+    if (!theta_a || !theta_b || !vel) {
+        g_err = "wrapped buffers must be non-NULL";
+        return XYL_EINVAL;
+    }
+    return create_impl(out, Lx, Ly, dtype, device, theta_a, theta_b, vel);
+}
+
+int xyl_destroy(xyl_lattice* h) {
+    if (!h) return XYL_OK;
+    return guarded([&] {
+        DeviceGuard g(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        destroy_graph(h);
+        adjoint_release(h);
+        if (h->owns) {
+            for (int b = 0; b < 2; ++b)
+                if (h->th[b]) (void)hipFree(h->th[b]);
+            if (h->u) (void)hipFree(h->u);
+        }
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        delete h;
+    });
+}
+
+int xyl_set_stream(xyl_lattice* h, void* stream) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        h->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int xyl_set_params(xyl_lattice* h, double Jx, double Jy, double hf, double gamma, double dt) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        Params p{Jx, Jy, hf, gamma, dt};
+        validate_params(p);
+        h->p = p;
+        h->touch();
+    });
+}
+
+int xyl_set_schedule(xyl_lattice* h, const uint64_t* ks, const double* Ts, int32_t n) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        h->sched = make_schedule(ks, Ts, n);
+        h->touch();
+    });
+}
+
+int xyl_set_seed(xyl_lattice* h, uint64_t seed, uint32_t replica) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        h->seed = seed;
+        h->replica = replica;
+        h->touch();
+    });
+}
+
+int xyl_init_random(xyl_lattice* h) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        DeviceGuard g(h->device);
+        h->k = 0;
+        h->fresh_k = 0;
+        h->cur = 0;
+        h->counter_valid = false;
+        h->touch();
+        if (h->dtype == XYL_F64) launch_init_random<double>(h->view<double>(), h->stream);
+        else launch_init_random<float>(h->view<float>(), h->stream);
+        h->initialized = true;
+    });
+}
+
+int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint64_t step) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
+        for (size_t i = 0; i < h->N; ++i) {
+            require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI, XYL_EINVAL,
+                    "theta entries must be finite with |theta| <= 3 pi");
+            require(std::isfinite(omega[i]), XYL_EINVAL, "omega entries must be finite");
+        }
+        DeviceGuard g(h->device);
+        h->k = step;
+        h->fresh_k = step;
+        h->counter_valid = false;
+        h->touch();
+        if (h->dtype == XYL_F64) {
+            to_device<double>(h->cur_theta(), theta, h->N, h->stream);
+            to_device<double>(h->u, omega, h->N, h->stream);
+        } else {
+            to_device<float>(h->cur_theta(), theta, h->N, h->stream);
+            to_device<float>(h->u, omega, h->N, h->stream);
+        }
+        h->initialized = true;
+    });
+}
+
+int xyl_init_ordered(xyl_lattice* h, int32_t sign) {
+    if (!h) {
+        g_err = "NULL handle";
+        return XYL_EINVAL;
+    }
+    std::vector<double> th(h->N), om(h->N, 0.0);
+    const double pi_p = h->dtype == XYL_F64 ? Prec<double>::kPi : (double)Prec<float>::kPi;
+    const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
+    for (int y = 0; y < h->Ly; ++y)
+        for (int x = 0; x < h->Lx; ++x) {
+            int e = ((x * sx + y * sy) & 1) ? -1 : 1;
+            if (sign < 0) e = -e;
+            th[(size_t)y * h->Lx + x] = e > 0 ? 0.0 : -pi_p;
+        }
+    return xyl_set_state(h, th.data(), om.data(), 0);
+}
+
+int xyl_get_state(xyl_lattice* h, double* theta, double* omega, uint64_t* step) {
+    return guarded([&] {
+        require_init(h);
+        DeviceGuard g(h->device);
+        if (theta) {
+            if (h->dtype == XYL_F64) to_host<double>(h->cur_theta(), theta, h->N, h->stream);
+            else to_host<float>(h->cur_theta(), theta, h->N, h->stream);
+        }
+        if (omega) {
+            if (h->dtype == XYL_F64) lattice_omega<double>(h, omega);
+            else lattice_omega<float>(h, omega);
+        }
+        if (step) *step = h->k;
+    });
+}
+
+int xyl_state_buffers(xyl_lattice* h, void** theta, void** vel, int32_t* fresh) {
+    return guarded([&] {
+        require_init(h);
+        if (theta) *theta = h->cur_theta();
+        if (vel) *vel = h->u;
+        if (fresh) *fresh = h->k == h->fresh_k ? 1 : 0;
+    });
+}
+
+int xyl_step(xyl_lattice* h, uint64_t nsteps) {
+    return guarded([&] {
+        require_init(h);
+        DeviceGuard g(h->device);
+        if (h->dtype == XYL_F64) lattice_steps<double>(h, nsteps);
+        else lattice_steps<float>(h, nsteps);
+    });
+}
+
+int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap, uint64_t* nout) {
+    return guarded([&] {
+        require_init(h);
+        require(every >= 1, XYL_EINVAL, "every must be >= 1");
+        require(out != nullptr, XYL_EINVAL, "out is NULL");
+        const uint64_t ns = nsteps / every + 1;
+        require(cap >= ns, XYL_EINVAL, "sample capacity too small");
+        DeviceGuard g(h->device);
+        h->obs.reserve(6 * ns);
+        for (uint64_t j = 0; j < ns; ++j) {
+            const bool last = j * every == nsteps;
+            if (h->dtype == XYL_F64) lattice_measure_into<double>(h, !last, h->obs.p + 6 * j);
+            else lattice_measure_into<float>(h, !last, h->obs.p + 6 * j);
+            if (!last) {
+                const uint64_t rest = std::min<uint64_t>(every - 1, nsteps - j * every - 1);
+                if (h->dtype == XYL_F64) lattice_steps<double>(h, rest);
+                else lattice_steps<float>(h, rest);
+                if (j + 1 == ns) {
+                    // nsteps not a multiple of every: finish the remaining steps
+                    const uint64_t done = j * every + 1 + rest;
+                    if (done < nsteps) {
+                        if (h->dtype == XYL_F64) lattice_steps<double>(h, nsteps - done);
+                        else lattice_steps<float>(h, nsteps - done);
+                    }
+                }
+            }
+        }
+        check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6 * ns, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (nout) *nout = ns;
+    });
+}
+
+int xyl_measure(xyl_lattice* h, xyl_obs* out) {
+    return guarded([&] {
+        require_init(h);
+        require(out != nullptr, XYL_EINVAL, "out is NULL");
+        DeviceGuard g(h->device);
+        h->obs.reserve(6);
+        if (h->dtype == XYL_F64) lattice_measure_into<double>(h, false, h->obs.p);
+        else lattice_measure_into<float>(h, false, h->obs.p);
+        check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    });
+}
+
+int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C) {
+    return guarded([&] {
+        require_init(h);
+        require(axis == 0 || axis == 1, XYL_EINVAL, "axis must be 0 or 1");
+        const int L = axis == 0 ? h->Lx : h->Ly;
+        require(rmax >= 0 && rmax <= L / 2, XYL_EINVAL, "rmax must be in [0, L/2]");
+        require(L <= 4096, XYL_EUNSUPPORTED, "correlation needs the axis length <= 4096");
+        require(C != nullptr, XYL_EINVAL, "C is NULL");
+        DeviceGuard g(h->device);
+        const int nlines = axis == 0 ? h->Ly : h->Lx;
+        h->dscratch.reserve((size_t)nlines * (rmax + 1) + (rmax + 1));
+        double* part = h->dscratch.p;
+        double* outd = h->dscratch.p + (size_t)nlines * (rmax + 1);
+        const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
+        if (h->dtype == XYL_F64)
+            launch_correlation<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, axis, rmax,
+                                       part, outd, h->stream);
+        else
+            launch_correlation<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, axis, rmax,
+                                      part, outd, h->stream);
+        check_hip(hipMemcpyAsync(C, outd, sizeof(double) * (rmax + 1), hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    });
+}
+
+int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap, uint64_t* n_sizes,
+                uint64_t* n_domains, uint64_t* max_size) {
+    return guarded([&] {
+        require_init(h);
+        DeviceGuard g(h->device);
+        const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
+        if (h->dtype == XYL_F64)
+            run_domains<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->parent, h->usz,
+                                h->hist, h->stats, h->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+        else
+            run_domains<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->parent, h->usz,
+                               h->hist, h->stats, h->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+    });
+}
+
+int xyl_sync(xyl_lattice* h) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        DeviceGuard g(h->device);
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    });
+}
+
+int xyl_set_launch(xyl_lattice* h, int32_t rows, int32_t wpb) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        Launch l = h->launch;
+        if (rows) l.rows = rows;
+        if (wpb) l.wpb = wpb;
+        validate_launch(l);
+        h->launch = l;
+        h->touch();
+    });
+}
+
+int xyl_get_launch(xyl_lattice* h, int32_t* rows, int32_t* wpb) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        if (rows) *rows = h->launch.rows;
+        if (wpb) *wpb = h->launch.wpb;
+    });
+}
+
+}  // extern "C"
+
+template <typename R>
+static Launch autotune_impl(xyl_lattice* h) {
+    // time candidates on scratch copies so the lattice state is untouched
+    const size_t bytes = sizeof(R) * h->N;
+    DevBuf<char> tmp;
+    tmp.reserve(3 * bytes);
+    Lat<R> v = h->view<R>();
+    v.th[0] = reinterpret_cast<R*>(tmp.p);
+    v.th[1] = reinterpret_cast<R*>(tmp.p + bytes);
+    v.u = reinterpret_cast<R*>(tmp.p + 2 * bytes);
+    check_hip(hipMemcpyAsync(v.th[0], h->cur_theta(), bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+    check_hip(hipMemcpyAsync(v.th[1], h->cur_theta(), bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+    check_hip(hipMemcpyAsync(v.u, h->u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+    v.fresh_k = ~(uint64_t)0;
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    const int rows_c[] = {4, 8, 16, 32, 64};
+    const int wpb_c[] = {1, 2, 4, 8};
+    const int reps = h->N >= (1u << 22) ? 10 : 50;
+    Launch best = h->launch;
+    float best_ms = 1e30f;
+    for (int r : rows_c) {
+        if (r > h->Ly && r != rows_c[0]) continue;
+        for (int w : wpb_c) {
+            Launch l;
+            l.rows = r;
+            l.wpb = w;
+            for (int i = 0; i < 2; ++i) launch_step<R>(v, kStore, l, nullptr, (uint64_t)i, h->stream);
+            check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+            for (int i = 0; i < reps; ++i) launch_step<R>(v, kStore, l, nullptr, (uint64_t)i, h->stream);
+            check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+            check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = l;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+extern "C" {
+
+int xyl_autotune(xyl_lattice* h) {
+    return guarded([&] {
+        require_init(h);
+        DeviceGuard g(h->device);
+        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h) : autotune_impl<float>(h);
+        h->launch = l;
+        h->touch();
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[{h->Lx, h->Ly, h->dtype}] = l;
+    });
+}
+
+int xyl_set_graph_steps(xyl_lattice* h, int32_t steps) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(steps >= 0 && steps <= 4096, XYL_EINVAL, "graph steps must be in [0, 4096]");
+        h->graph_steps = steps;
+        h->touch();
+    });
+}
+
+int xyl_philox_blocks(int32_t device, uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n) {
+    return guarded([&] {
+        require(ctr != nullptr && out != nullptr, XYL_EINVAL, "NULL array");
+        require(n >= 1 && n <= (1ull << 26), XYL_EINVAL, "n out of range");
+        select_device(device);
+        DevBuf<uint32_t> dc, dout;
+        dc.reserve(4 * n);
+        dout.reserve(4 * n);
+        check_hip(hipMemcpy(dc.p, ctr, sizeof(uint32_t) * 4 * n, hipMemcpyHostToDevice), "H2D");
+        launch_philox_blocks(seed, dc.p, dout.p, n, nullptr);
+        check_hip(hipMemcpy(out, dout.p, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost), "D2H");
+    });
+}
+
+int xyl_noise(xyl_lattice* h, uint64_t k, double* out) {
+    return guarded([&] {
+        require(h != nullptr && out != nullptr, XYL_EINVAL, "NULL argument");
+        DeviceGuard g(h->device);
+        h->dscratch.reserve(h->N);
+        if (h->dtype == XYL_F64) launch_noise<double>(h->view<double>(), k, h->dscratch.p, h->stream);
+        else launch_noise<float>(h->view<float>(), k, h->dscratch.p, h->stream);
+        check_hip(hipMemcpyAsync(out, h->dscratch.p, sizeof(double) * h->N, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    });
+}
+
+int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double* U_se) {
+    return guarded([&] {
+        require(m != nullptr && U != nullptr, XYL_EINVAL, "NULL argument");
+        require(discard < n, XYL_EINVAL, "discard must be < n");
+        const double* x = m + discard;
+        const size_t cnt = n - discard;
+        double m2 = 0.0, m4 = 0.0;
+        for (size_t i = 0; i < cnt; ++i) {
+            const double q = x[i] * x[i];
+            m2 += q;
+            m4 += q * q;
+        }
+        m2 /= (double)cnt;
+        m4 /= (double)cnt;
+        require(m2 > 0.0, XYL_ENUMERIC, "<m^2> is zero");
+        *U = m4 / (m2 * m2);
+        if (U_se) {
+            // jackknife over blocks longer than twice the autocorrelation time of m^2
+            std::vector<double> sq(cnt);
+            for (size_t i = 0; i < cnt; ++i) sq[i] = x[i] * x[i];
+            const double tau = tau_int(sq.data(), cnt);
+            const size_t B = (size_t)std::ceil(2.0 * tau) + 1;
+            const size_t nb = cnt / B;
+            if (nb < 2) {
+                *U_se = NAN;
+            } else {
+                std::vector<double> s2(nb, 0.0), s4(nb, 0.0);
+                double t2 = 0.0, t4 = 0.0;
+                for (size_t b = 0; b < nb; ++b) {
+                    for (size_t i = b * B; i < (b + 1) * B; ++i) {
+                        s2[b] += sq[i];
+                        s4[b] += sq[i] * sq[i];
+                    }
+                    t2 += s2[b];
+                    t4 += s4[b];
+                }
+                const double nn = (double)(nb - 1) * (double)B;
+                double mean = 0.0;
+                std::vector<double> ub(nb);
+                for (size_t b = 0; b < nb; ++b) {
+                    const double a2 = (t2 - s2[b]) / nn, a4 = (t4 - s4[b]) / nn;
+                    ub[b] = a4 / (a2 * a2);
+                    mean += ub[b];
+                }
+                mean /= (double)nb;
+                double var = 0.0;
+                for (size_t b = 0; b < nb; ++b) var += (ub[b] - mean) * (ub[b] - mean);
+                *U_se = std::sqrt(var * (double)(nb - 1) / (double)nb);
+            }
+        }
+    });
+}
+
+int xyl_mean_error(const double* f, uint64_t n, uint64_t discard, double* mean, double* se, double* tau) {
+    return guarded([&] {
+        require(f != nullptr, XYL_EINVAL, "NULL argument");
+        require(discard < n, XYL_EINVAL, "discard must be < n");
+        const double* x = f + discard;
+        const size_t cnt = n - discard;
+        double mu = 0.0;
+        for (size_t i = 0; i < cnt; ++i) mu += x[i];
+        mu /= (double)cnt;
+        double var = 0.0;
+        for (size_t i = 0; i < cnt; ++i) var += (x[i] - mu) * (x[i] - mu);
+        var /= (double)cnt;
+        const double t = tau_int(x, cnt);
+        if (mean) *mean = mu;
+        if (se) *se = std::sqrt(2.0 * t * var / (double)cnt);
+        if (tau) *tau = t;
+    });
+}
+
+}  // extern "C"
+
+// ==================================================================== ensemble
+struct xyl_ensemble {
+    int dtype = XYL_F32;
+    int device = 0;
+    int n = 0;
+    int mode = 0;
+    hipStream_t stream = nullptr;
+    std::vector<xyl_replica_desc> desc;
+    std::vector<size_t> off;        // element offset of each replica
+    std::vector<size_t> poff;       // partial-sum offset of each replica
+    size_t total = 0, ptotal = 0;
+    void* th[2] = {nullptr, nullptr};
+    void* u = nullptr;
+    std::vector<uint64_t> k;        // current step of each replica
+    std::vector<uint64_t> fresh_k;
+    std::vector<uint64_t> last_sample;  // step of the last recorded sample (+1), 0 = none
+    uint64_t j = 0;                 // batched launches issued
+    Launch launch;
+    DevBuf<char> reps;              // Lat<R>[n]
+    DevBuf<Task> tasks;
+    int ntasks = 0;
+    std::vector<int> task_active;   // replica ids the task list was built for
+    DevBuf<double> part;
+    DevBuf<double> obs;
+    DevBuf<FinalizeJobHost> jobs;
+    DevBuf<double> dscratch;
+    DevBuf<char> omega_buf;
+    DevBuf<int32_t> parent;
+    DevBuf<uint32_t> usz, hist, stats;
+
+    template <typename R>
+    Lat<R> view(int r, uint64_t jbase) {
+        const xyl_replica_desc& d = desc[r];
+        Lat<R> v{};
+        R* t0 = static_cast<R*>(th[0]) + off[r];
+        R* t1 = static_cast<R*>(th[1]) + off[r];
+        v.th[0] = t0;
+        v.th[1] = t1;
+        v.u = static_cast<R*>(u) + off[r];
+        v.cur = 0;
+        Params p{d.Jx, d.Jy, d.h, d.gamma, d.dt};
+        Schedule s{};
+        s.n = d.nknots;
+        for (int q = 0; q < d.nknots; ++q) {
+            s.step[q] = d.knot_step[q];
+            s.T[q] = d.knot_T[q];
+        }
+        fill_lat(v, d.Lx, d.Ly, p, s, d.seed, d.replica);
+        v.k_base = k[r] - jbase;   // k = k_base + j for the launches numbered from jbase
+        v.fresh_k = fresh_k[r];
+        v.k_end = d.nsteps;
+        v.part = part.p + poff[r];
+        v.omega_out = reinterpret_cast<R*>(omega_buf.p);
+        return v;
+    }
+    void* cur_theta(int r) {
+        const size_t es = elem_size(dtype);
+        return static_cast<char*>(th[(int)(k[r] & 1)]) + es * off[r];
+    }
+    int nrp(int r) const { return desc[r].Ly * ((desc[r].Lx + kWaveSites - 1) / kWaveSites); }
+};
+
+template <typename R>
+static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<int>& active) {
+    std::vector<Lat<R>> tab(e->n);
+    for (int r = 0; r < e->n; ++r) tab[r] = e->view<R>(r, jbase);
+    e->reps.reserve(sizeof(Lat<R>) * e->n);
+    check_hip(hipMemcpyAsync(e->reps.p, tab.data(), sizeof(Lat<R>) * e->n, hipMemcpyHostToDevice, e->stream), "H2D");
+    std::vector<Task> tk;
+    for (int r : active) {
+        const int nxw = (e->desc[r].Lx + kWaveSites - 1) / kWaveSites;
+        const int nstrips = (e->desc[r].Ly + e->launch.rows - 1) / e->launch.rows;
+        for (int s = 0; s < nstrips; ++s)
+            for (int x = 0; x < nxw; ++x) tk.push_back(Task{r, x, s, 0});
+    }
+    e->ntasks = (int)tk.size();
+    e->tasks.reserve(std::max<size_t>(tk.size(), 1));
+    if (!tk.empty())
+        check_hip(hipMemcpyAsync(e->tasks.p, tk.data(), sizeof(Task) * tk.size(), hipMemcpyHostToDevice, e->stream),
+                  "H2D");
+    // the host vectors must outlive the copies
+    check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    e->task_active = active;
+}
+
+template <typename R>
+static void ens_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap, uint64_t* nout) {
+    // samples are gathered in device memory and copied out at the end
+    std::vector<std::pair<int, uint64_t>> sample_slots;   // (replica, slot index)
+    std::vector<uint64_t> cnt(e->n, 0);
+    if (every && nout)
+        for (int r = 0; r < e->n; ++r) cnt[r] = nout[r];
+    size_t nsamp_dev = 0;
+    std::vector<std::pair<size_t, size_t>> copies;   // (device sample index, host index)
+    auto want_sample = [&](int r) {
+        return every && e->k[r] <= e->desc[r].nsteps && e->k[r] % every == 0 && e->last_sample[r] != e->k[r] + 1;
+    };
+    std::vector<FinalizeJobHost> jobs;
+    auto flush_jobs = [&]() {
+        if (jobs.empty()) return;
+        e->jobs.reserve(jobs.size());
+        check_hip(hipMemcpyAsync(e->jobs.p, jobs.data(), sizeof(FinalizeJobHost) * jobs.size(), hipMemcpyHostToDevice,
+                                 e->stream),
+                  "H2D");
+        launch_finalize_jobs(e->jobs.p, (int)jobs.size(), e->stream);
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+        jobs.clear();
+    };
+    auto reserve_obs = [&](size_t need) {
+        if (need * 6 > e->obs.n) {
+            // grow: keep what was gathered so far
+            DevBuf<double> nb;
+            nb.reserve(std::max(need * 6, e->obs.n * 2));
+            if (e->obs.p && nsamp_dev)
+                check_hip(hipMemcpyAsync(nb.p, e->obs.p, sizeof(double) * 6 * nsamp_dev, hipMemcpyDeviceToDevice,
+                                         e->stream),
+                          "D2D");
+            check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+            std::swap(e->obs.p, nb.p);
+            std::swap(e->obs.n, nb.n);
+        }
+    };
+    for (uint64_t it = 0; it <= nsteps; ++it) {
+        std::vector<int> active, measuring;
+        for (int r = 0; r < e->n; ++r) {
+            if (want_sample(r)) measuring.push_back(r);
+            if (it < nsteps && e->k[r] < e->desc[r].nsteps) active.push_back(r);
+        }
+        if (it == nsteps && measuring.empty()) break;
+        if (active.empty() && measuring.empty()) break;
+        for (int r : measuring) {
+            require(cnt[r] < cap, XYL_EINVAL, "ensemble sample capacity too small");
+        }
+        reserve_obs(nsamp_dev + measuring.size());
+        if (e->mode == 0) {
+            // one launch for every replica: advancing ones in store mode (plus
+            // measurement when any replica samples), sampling-only ones measured
+            std::vector<int> set = active;
+            for (int r : measuring)
+                if (std::find(active.begin(), active.end(), r) == active.end()) set.push_back(r);
+            std::sort(set.begin(), set.end());
+            if (set != e->task_active) ens_upload_table<R>(e, e->j, set);
+            const bool meas = !measuring.empty();
+            // replicas that only measure (finished) must not store: give them
+            // their own launch in measure-only mode
+            std::vector<int> only_meas;
+            for (int r : measuring)
+                if (std::find(active.begin(), active.end(), r) == active.end()) only_meas.push_back(r);
+            if (only_meas.empty()) {
+                if (!set.empty())
+                    launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(e->reps.p), e->tasks.p, e->ntasks,
+                                            meas ? (kStore | kMeasure) : kStore, e->launch.rows, e->launch.wpb, nullptr,
+                                            e->j, e->stream);
+            } else {
+                for (int r : set) {
+                    Lat<R> v = e->view<R>(r, e->j);
+                    const bool adv = std::find(active.begin(), active.end(), r) != active.end();
+                    const bool m = std::find(measuring.begin(), measuring.end(), r) != measuring.end();
+                    const int mode = (adv ? kStore : 0) | (m ? kMeasure : 0);
+                    launch_step<R>(v, mode, e->launch, nullptr, e->j, e->stream);
+                }
+            }
+        } else {
+            for (int r = 0; r < e->n; ++r) {
+                const bool adv = std::find(active.begin(), active.end(), r) != active.end();
+                const bool m = std::find(measuring.begin(), measuring.end(), r) != measuring.end();
+                if (!adv && !m) continue;
+                Lat<R> v = e->view<R>(r, e->j);
+                launch_step<R>(v, (adv ? kStore : 0) | (m ? kMeasure : 0), e->launch, nullptr, e->j, e->stream);
+            }
+        }
+        for (int r : measuring) {
+            const size_t slot = nsamp_dev++;
+            jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
+                                           (double)e->desc[r].Lx * (double)e->desc[r].Ly, e->obs.p + 6 * slot});
+            copies.push_back({slot, (size_t)r * cap + cnt[r]});
+            cnt[r] += 1;
+            e->last_sample[r] = e->k[r] + 1;
+        }
+        flush_jobs();
+        for (int r : active) e->k[r] += 1;
+        if (!active.empty()) e->j += 1;
+        if (it == nsteps) break;
+    }
+    if (every) {
+        std::vector<double> host(6 * nsamp_dev);
+        if (nsamp_dev)
+            check_hip(hipMemcpyAsync(host.data(), e->obs.p, sizeof(double) * 6 * nsamp_dev, hipMemcpyDeviceToHost,
+                                     e->stream),
+                      "D2H");
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+        for (auto& c : copies) std::memcpy(&out[c.second], &host[6 * c.first], sizeof(double) * 6);
+        if (nout)
+            for (int r = 0; r < e->n; ++r) nout[r] = cnt[r];
+    }
+}
+
+extern "C" {
+
+int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_t n, int32_t dtype, int32_t device) {
+    return guarded([&] {
+        require(out != nullptr && desc != nullptr, XYL_EINVAL, "NULL argument");
+        *out = nullptr;
+        require(n >= 1, XYL_EINVAL, "need at least one replica");
+        require(dtype == XYL_F32 || dtype == XYL_F64, XYL_EINVAL, "dtype must be XYL_F32 or XYL_F64");
+        select_device(device);
+        std::unique_ptr<xyl_ensemble> e(new xyl_ensemble());
+        e->dtype = dtype;
+        e->device = device;
+        e->n = n;
+        e->desc.assign(desc, desc + n);
+        for (int r = 0; r < n; ++r) {
+            const xyl_replica_desc& d = desc[r];
+            validate_shape(d.Lx, d.Ly);
+            validate_params(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt});
+            (void)make_schedule(d.knot_step, d.knot_T, d.nknots);
+            e->off.push_back(e->total);
+            // keep every replica's base 256-byte aligned
+            const size_t N = (size_t)d.Lx * d.Ly;
+            e->total += (N + 63) / 64 * 64;
+            e->poff.push_back(e->ptotal);
+            e->ptotal += (size_t)e->nrp(r) * kNPart;
+        }
+        const size_t bytes = elem_size(dtype) * e->total;
+        for (int b = 0; b < 2; ++b) check_alloc(hipMalloc(&e->th[b], bytes), "hipMalloc theta");
+        check_alloc(hipMalloc(&e->u, bytes), "hipMalloc velocity");
+        e->part.reserve(e->ptotal);
+        e->k.assign(n, 0);
+        e->fresh_k.assign(n, 0);
+        e->last_sample.assign(n, 0);
+        for (int r = 0; r < n; ++r) {
+            if (dtype == XYL_F64) launch_init_random<double>(e->view<double>(r, 0), e->stream);
+            else launch_init_random<float>(e->view<float>(r, 0), e->stream);
+        }
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+        *out = e.release();
+    });
+}
+
+int xyl_ensemble_destroy(xyl_ensemble* e) {
+    if (!e) return XYL_OK;
+    return guarded([&] {
+        DeviceGuard g(e->device);
+        (void)hipStreamSynchronize(e->stream);
+        for (int b = 0; b < 2; ++b)
+            if (e->th[b]) (void)hipFree(e->th[b]);
+        if (e->u) (void)hipFree(e->u);
+        delete e;
+    });
+}
+
+int xyl_ensemble_set_stream(xyl_ensemble* e, void* stream) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        e->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        require(mode == 0 || mode == 1, XYL_EINVAL, "mode must be 0 or 1");
+        e->mode = mode;
+    });
+}
+
+int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap, uint64_t* nout) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        if (every) require(out != nullptr && nout != nullptr, XYL_EINVAL, "out/nout are NULL");
+        DeviceGuard g(e->device);
+        if (e->dtype == XYL_F64) ens_step<double>(e, nsteps, every, out, cap, nout);
+        else ens_step<float>(e, nsteps, every, out, cap, nout);
+    });
+}
+
+int xyl_ensemble_get_state(xyl_ensemble* e, int32_t r, double* theta, double* omega, uint64_t* step) {
+    return guarded([&] {
+        require(e != nullptr && r >= 0 && r < e->n, XYL_EINVAL, "bad handle or replica");
+        DeviceGuard g(e->device);
+        const size_t N = (size_t)e->desc[r].Lx * e->desc[r].Ly;
+        if (theta) {
+            if (e->dtype == XYL_F64) to_host<double>(e->cur_theta(r), theta, N, e->stream);
+            else to_host<float>(e->cur_theta(r), theta, N, e->stream);
+        }
+        if (omega) {
+            const size_t es = elem_size(e->dtype);
+            if (e->k[r] == e->fresh_k[r]) {
+                void* up = static_cast<char*>(e->u) + es * e->off[r];
+                if (e->dtype == XYL_F64) to_host<double>(up, omega, N, e->stream);
+                else to_host<float>(up, omega, N, e->stream);
+            } else {
+                e->omega_buf.reserve(es * N);
+                if (e->dtype == XYL_F64) {
+                    Lat<double> v = e->view<double>(r, 0);
+                    v.k_end = ~(uint64_t)0;
+                    launch_step<double>(v, kOmega, e->launch, nullptr, e->k[r] - v.k_base, e->stream);
+                    to_host<double>(e->omega_buf.p, omega, N, e->stream);
+                } else {
+                    Lat<float> v = e->view<float>(r, 0);
+                    v.k_end = ~(uint64_t)0;
+                    launch_step<float>(v, kOmega, e->launch, nullptr, e->k[r] - v.k_base, e->stream);
+                    to_host<float>(e->omega_buf.p, omega, N, e->stream);
+                }
+            }
+        }
+        if (step) *step = e->k[r];
+    });
+}
+
+int xyl_ensemble_set_state(xyl_ensemble* e, int32_t r, const double* theta, const double* omega, uint64_t step) {
+    return guarded([&] {
+        require(e != nullptr && r >= 0 && r < e->n, XYL_EINVAL, "bad handle or replica");
+        require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
+        const size_t N = (size_t)e->desc[r].Lx * e->desc[r].Ly;
+        for (size_t i = 0; i < N; ++i)
+            require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI && std::isfinite(omega[i]), XYL_EINVAL,
+                    "state entries must be finite with |theta| <= 3 pi");
+        DeviceGuard g(e->device);
+        e->k[r] = step;
+        e->fresh_k[r] = step;
+        e->last_sample[r] = 0;
+        e->task_active.clear();   // force a table rebuild
+        const size_t es = elem_size(e->dtype);
+        void* up = static_cast<char*>(e->u) + es * e->off[r];
+        if (e->dtype == XYL_F64) {
+            to_device<double>(e->cur_theta(r), theta, N, e->stream);
+            to_device<double>(up, omega, N, e->stream);
+        } else {
+            to_device<float>(e->cur_theta(r), theta, N, e->stream);
+            to_device<float>(up, omega, N, e->stream);
+        }
+    });
+}
+
+int xyl_ensemble_domains(xyl_ensemble* e, int32_t r, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
+                         uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size) {
+    return guarded([&] {
+        require(e != nullptr && r >= 0 && r < e->n, XYL_EINVAL, "bad handle or replica");
+        DeviceGuard g(e->device);
+        const xyl_replica_desc& d = e->desc[r];
+        const int sx = d.Jx > 0.0, sy = d.Jy > 0.0;
+        if (e->dtype == XYL_F64)
+            run_domains<double>(static_cast<const double*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, e->parent, e->usz,
+                                e->hist, e->stats, e->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+        else
+            run_domains<float>(static_cast<const float*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, e->parent, e->usz,
+                               e->hist, e->stats, e->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+    });
+}
+
+int xyl_ensemble_sync(xyl_ensemble* e) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        DeviceGuard g(e->device);
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,375 @@
+// Fused Langevin step of the symmetry-broken XY lattice on gfx950.
+//
+// One pass per step does, for every site: stencil force at th^k, completion of
+// the previous step's second half-kick (App. A.1, Eq. BBK-2) giving w^k, the
+// next first half-kick (Eq. BBK-1) giving w^{k+1/2}, the drift and the wrap
+// (Sec. III.D).  Both half-kicks around time k share the Gaussian draw n^k,
+// generated in registers from Philox4x32-10 keyed on (seed, replica, k, site);
+// no noise is stored.  State: two angle buffers (ping-pong, th^k in
+// th[(k + p0) & 1]) and the velocity buffer u, which holds w^{k-1/2}, or w^k
+// itself at the step `fresh_k` after an initialisation.
+//
+// Work decomposition: a wave owns 256 consecutive sites of a row (4 per lane,
+// one Philox block per lane) and walks down a strip of rows, keeping the
+// sine/cosine of rows y-1, y, y+1 in registers, so every angle is loaded once
+// per strip and its sine/cosine evaluated once.  x-neighbours inside the wave
+// come from the adjacent lanes through DPP; the two wave-edge lanes load their
+// outer neighbour.  Bytes per site-update: read th and u, write th' and u'.
+#include "xyl_device.hpp"
+
+namespace xyl {
+
+template <typename R, int MODE>
+__device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
+    const int Lx = v.Lx, Ly = v.Ly;
+    const uint64_t k = v.k_base + j;
+    if (k >= v.k_end) return;
+    const int y0 = strip * rows;
+    if (y0 >= Ly) return;
+    const int y1 = min(y0 + rows, Ly);
+    const int x0 = xw * kWaveSites;
+    const int nact = min(kWave, (Lx - x0) >> 2);
+    const bool act = lane < nact;
+    const int x = x0 + kLaneSites * lane;
+    const int par = (int)((k + (uint64_t)v.cur) & 1);
+    const R* __restrict__ thi = v.th[par];
+    R* __restrict__ tho = v.th[par ^ 1];
+    R* uu = v.u;
+    const R hs = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
+    const bool fresh = (k == v.fresh_k);
+    const uint32_t qrow = (uint32_t)(Lx >> 2);
+
+    R sp[4], cp[4], sc[4], cc[4], sn[4], cn[4], thc[4], thn[4], uc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) thc[q] = thn[q] = uc[q] = R(0);
+    {
+        R t[4] = {R(0), R(0), R(0), R(0)};
+        const int ym = (y0 == 0) ? Ly - 1 : y0 - 1;
+        if (act) load4(thi + (size_t)ym * Lx + x, t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Prec<R>::sincos(t[q], sp[q], cp[q]);
+        if (act) {
+            load4(thi + (size_t)y0 * Lx + x, thc);
+            load4(thi + (size_t)((y0 + 1 == Ly) ? 0 : y0 + 1) * Lx + x, thn);
+            load4(uu + (size_t)y0 * Lx + x, uc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Prec<R>::sincos(thc[q], sc[q], cc[q]);
+    }
+
+    double rowphase_s = 0.0, rowphase_c = 1.0;
+    for (int y = y0; y < y1; ++y) {
+        const size_t row = (size_t)y * Lx;
+        // prefetch the rows of the next iteration
+        R thnn[4] = {R(0), R(0), R(0), R(0)}, un[4] = {R(0), R(0), R(0), R(0)};
+        if (y + 1 < y1 && act) {
+            const int ynn = (y + 2) % Ly;
+            load4(thi + (size_t)ynn * Lx + x, thnn);
+            load4(uu + row + Lx + x, un);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Prec<R>::sincos(thn[q], sn[q], cn[q]);
+
+        // x-neighbours of the lane's first and last site
+        R sL = from_lane_below(sc[3]), cL = from_lane_below(cc[3]);
+        R sR = from_lane_above(sc[0]), cR = from_lane_above(cc[0]);
+        if (lane == 0 && act) {
+            const R t = thi[row + (x == 0 ? Lx - 1 : x - 1)];
+            Prec<R>::sincos(t, sL, cL);
+        }
+        if (lane == nact - 1) {
+            const R t = thi[row + (x + 4 == Lx ? 0 : x + 4)];
+            Prec<R>::sincos(t, sR, cR);
+        }
+
+        R n[4];
+        noise4<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, n);
+
+        R tho4[4], uo4[4], w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const R sxm = q == 0 ? sL : sc[q - 1], cxm = q == 0 ? cL : cc[q - 1];
+            const R sxp = q == 3 ? sR : sc[q + 1], cxp = q == 3 ? cR : cc[q + 1];
+            // F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [...] - 4 h s c  (= -dH/dth)
+            const R fx = Prec<R>::fma(sc[q], cxp + cxm, -(cc[q] * (sxp + sxm)));
+            const R fy = Prec<R>::fma(sc[q], cn[q] + cp[q], -(cc[q] * (sn[q] + sp[q])));
+            R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
+            f = Prec<R>::fma(-v.h4, sc[q] * cc[q], f);
+            R ww;
+            if (fresh) {
+                ww = uc[q];
+            } else {
+                R t = Prec<R>::fma(v.hdt, f, uc[q]);
+                t = Prec<R>::fma(hs, n[q], t);
+                ww = v.c * t;
+            }
+            w[q] = ww;
+            R t2 = v.hdt * f;
+            t2 = Prec<R>::fma(hs, n[q], t2);
+            const R unew = Prec<R>::fma(v.a, ww, t2);
+            uo4[q] = unew;
+            tho4[q] = wrap_angle<R>(Prec<R>::fma(v.dt, unew, thc[q]));
+        }
+        if ((MODE & kStore) && act) {
+            store4(tho + row + x, tho4);
+            store4(uu + row + x, uo4);
+        }
+        if ((MODE & kOmega) && act) store4(v.omega_out + row + x, w);
+
+        if (MODE & kMeasure) {
+            double acc[kNPart];
+#pragma unroll
+            for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
+            sincospi(2.0 * (double)y / (double)Ly, &rowphase_s, &rowphase_c);
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double s = (double)sc[q], c = (double)cc[q];
+                    const double sxp = (double)(q == 3 ? sR : sc[q + 1]);
+                    const double cxp = (double)(q == 3 ? cR : cc[q + 1]);
+                    const double syp = (double)sn[q], cyp = (double)cn[q];
+                    acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) - v.hd * (c * c - s * s);
+                    acc[1] += 0.5 * (double)w[q] * (double)w[q];
+                    const int xs = x + q;
+                    const double e = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
+                    const double ec = e * c, es = e * s;
+                    acc[2] += ec;
+                    acc[3] += es;
+                    double pxs, pxc;
+                    sincospi(2.0 * (double)xs / (double)Lx, &pxs, &pxc);
+                    acc[4] += ec * pxc;
+                    acc[5] -= ec * pxs;
+                    acc[6] += es * pxc;
+                    acc[7] -= es * pxs;
+                    acc[8] += ec * rowphase_c;
+                    acc[9] -= ec * rowphase_s;
+                    acc[10] += es * rowphase_c;
+                    acc[11] -= es * rowphase_s;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < kNPart; ++p) {
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, kWave);
+            }
+            if (lane == 0) {
+                double* dst = v.part + ((size_t)y * v.nxw + xw) * kNPart;
+#pragma unroll
+                for (int p = 0; p < kNPart; ++p) dst[p] = acc[p];
+            }
+        }
+
+        // rotate the register window down one row
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sp[q] = sc[q];
+            cp[q] = cc[q];
+            sc[q] = sn[q];
+            cc[q] = cn[q];
+            thc[q] = thn[q];
+            thn[q] = thnn[q];
+            uc[q] = un[q];
+        }
+    }
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(512) void k_step(Lat<R> v, const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
+    const int wpb = blockDim.x / kWave;
+    const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int t = b * wpb + (int)(threadIdx.x / kWave);
+    if (t >= ntasks) return;
+    const uint64_t j = j0 + (kdev ? *kdev : 0);
+    run_strip<R, MODE>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(512) void k_ensemble_step(const Lat<R>* __restrict__ reps, const Task* __restrict__ tasks,
+                                                       const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
+    const int wpb = blockDim.x / kWave;
+    const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int t = b * wpb + (int)(threadIdx.x / kWave);
+    if (t >= ntasks) return;
+    const Task task = tasks[t];
+    const uint64_t j = j0 + (kdev ? *kdev : 0);
+    run_strip<R, MODE>(reps[task.rep], task.xw, task.strip, rows, j, threadIdx.x & (kWave - 1));
+}
+
+template <typename R>
+static void dispatch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    const int nstrips = (v.Ly + l.rows - 1) / l.rows;
+    const int ntasks = nstrips * v.nxw;
+    const int nblocks = (ntasks + l.wpb - 1) / l.wpb;
+    const dim3 grid(nblocks), block(l.wpb * kWave);
+    switch (mode) {
+        case kStore: k_step<R, kStore><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kStore | kMeasure: k_step<R, kStore | kMeasure><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kMeasure: k_step<R, kMeasure><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kOmega: k_step<R, kOmega><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        default: throw Error(-5, "unsupported step mode");
+    }
+    check_hip(hipGetLastError(), "step kernel launch");
+}
+
+template <typename R>
+void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    dispatch_step<R>(v, mode, l, kdev, j, s);
+}
+
+template <typename R>
+void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int rows, int wpb,
+                          const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    const int nblocks = (ntasks + wpb - 1) / wpb;
+    const dim3 grid(nblocks), block(wpb * kWave);
+    switch (mode) {
+        case kStore: k_ensemble_step<R, kStore><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
+        case kStore | kMeasure:
+            k_ensemble_step<R, kStore | kMeasure><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks);
+            break;
+        case kMeasure: k_ensemble_step<R, kMeasure><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
+        case kOmega: k_ensemble_step<R, kOmega><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
+        default: throw Error(-5, "unsupported step mode");
+    }
+    check_hip(hipGetLastError(), "ensemble step kernel launch");
+}
+
+// ------------------------------------------------------------------ init
+template <typename R>
+__global__ void k_init_random(Lat<R> v) {
+    const size_t N = (size_t)v.Lx * v.Ly;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // one Philox block per thread
+    if (q * 4 >= N) return;
+    const U32x4 r = philox4x32_10((uint32_t)q, v.replica, 0xFFFFFFFFu, 0xFFFFFFFFu, v.seed_lo, v.seed_hi);
+    R* th = v.th[(int)((v.k_base + (uint64_t)v.cur) & 1)];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const size_t i = q * 4 + p;
+        if (i < N) {
+            const double uni = ((double)(r.v[p] >> 9) + 0.5) * 0x1p-23;
+            th[i] = (R)(Prec<double>::kPi * (2.0 * uni - 1.0));
+            v.u[i] = R(0);
+        }
+    }
+}
+
+template <typename R>
+void launch_init_random(const Lat<R>& v, hipStream_t s) {
+    const size_t nq = ((size_t)v.Lx * v.Ly + 3) / 4;
+    k_init_random<R><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(v);
+    check_hip(hipGetLastError(), "init kernel launch");
+}
+
+// ------------------------------------------------------------ test hooks
+template <typename R>
+__global__ void k_noise(Lat<R> v, uint64_t k, double* out) {
+    const size_t N = (size_t)v.Lx * v.Ly;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q * 4 >= N) return;
+    R n[4];
+    noise4<R>((uint32_t)q, v.replica, k, v.seed_lo, v.seed_hi, n);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        if (q * 4 + p < N) out[q * 4 + p] = (double)n[p];
+}
+
+template <typename R>
+void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s) {
+    const size_t nq = ((size_t)v.Lx * v.Ly + 3) / 4;
+    k_noise<R><<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(v, k, out);
+    check_hip(hipGetLastError(), "noise kernel launch");
+}
+
+__global__ void k_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U32x4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], (uint32_t)seed,
+                                  (uint32_t)(seed >> 32));
+    for (int p = 0; p < 4; ++p) out[4 * i + p] = r.v[p];
+}
+
+void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s) {
+    k_philox_blocks<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(seed, ctr, out, n);
+    check_hip(hipGetLastError(), "philox kernel launch");
+}
+
+// --------------------------------------------------- measurement finalize
+// Sums the per-(row, wave chunk) partials in a fixed order (strided per
+// thread, then a fixed tree), so a measurement is bit-reproducible for a
+// given lattice shape whatever the strip height or workgroup size.
+__device__ void finalize_block(const double* part, int nrp, double N, double* out) {
+    __shared__ double red[256][kNPart];
+    double acc[kNPart];
+    for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
+    for (int e = threadIdx.x; e < nrp; e += blockDim.x)
+        for (int p = 0; p < kNPart; ++p) acc[p] += part[(size_t)e * kNPart + p];
+    for (int p = 0; p < kNPart; ++p) red[threadIdx.x][p] = acc[p];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int p = 0; p < kNPart; ++p) red[threadIdx.x][p] += red[threadIdx.x + w][p];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double* P = red[0];
+        out[0] = P[0] / N;
+        out[1] = P[1] / N;
+        out[2] = P[2] / N;
+        out[3] = (P[2] * P[2] + P[3] * P[3]) / N;
+        out[4] = (P[4] * P[4] + P[5] * P[5] + P[6] * P[6] + P[7] * P[7]) / N;
+        out[5] = (P[8] * P[8] + P[9] * P[9] + P[10] * P[10] + P[11] * P[11]) / N;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_obs(const double* part, int nrp, double N, double* out) {
+    finalize_block(part, nrp, N, out);
+}
+
+void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s) {
+    k_finalize_obs<<<1, 256, 0, s>>>(part, nrowparts, N, out);
+    check_hip(hipGetLastError(), "finalize kernel launch");
+}
+
+struct FinalizeJob {
+    const double* part;
+    int nrp;
+    double N;
+    double* out;
+};
+
+__global__ __launch_bounds__(256) void k_finalize_obs_batched(const FinalizeJob* jobs) {
+    const FinalizeJob jb = jobs[blockIdx.x];
+    if (jb.out == nullptr) return;
+    finalize_block(jb.part, jb.nrp, jb.N, jb.out);
+}
+
+void launch_finalize_jobs(const void* jobs, int njobs, hipStream_t s) {
+    k_finalize_obs_batched<<<njobs, 256, 0, s>>>(reinterpret_cast<const FinalizeJob*>(jobs));
+    check_hip(hipGetLastError(), "batched finalize kernel launch");
+}
+
+__global__ void k_counter(uint64_t* p, uint64_t add, uint64_t set, int mode) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = mode ? set : *p + add;
+}
+
+void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s) {
+    k_counter<<<1, 64, 0, s>>>(kdev, by, 0, 0);
+    check_hip(hipGetLastError(), "counter kernel launch");
+}
+
+void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s) {
+    k_counter<<<1, 64, 0, s>>>(kdev, 0, value, 1);
+    check_hip(hipGetLastError(), "counter kernel launch");
+}
+
+template void launch_step<float>(const Lat<float>&, int, const Launch&, const uint64_t*, uint64_t, hipStream_t);
+template void launch_step<double>(const Lat<double>&, int, const Launch&, const uint64_t*, uint64_t, hipStream_t);
+template void launch_ensemble_step<float>(const Lat<float>*, const Task*, int, int, int, int, const uint64_t*,
+                                          uint64_t, hipStream_t);
+template void launch_ensemble_step<double>(const Lat<double>*, const Task*, int, int, int, int, const uint64_t*,
+                                           uint64_t, hipStream_t);
+template void launch_init_random<float>(const Lat<float>&, hipStream_t);
+template void launch_init_random<double>(const Lat<double>&, hipStream_t);
+template void launch_noise<float>(const Lat<float>&, uint64_t, double*, hipStream_t);
+template void launch_noise<double>(const Lat<double>&, uint64_t, double*, hipStream_t);
+
+}  // namespace xyl

@@ -1,0 +1,78 @@
+"""The C-ABI library (CPU-only checks): it loads, exports every function that
+include/xyl.h declares, rejects invalid arguments before touching a device and
+its pure-host estimators agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import estimators
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xyl.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xyl_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2409_06412_amd as xyl
+    return xyl.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 40
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version(lib):
+    assert lib.xyl_abi_version() == 1
+
+
+def test_invalid_arguments_are_rejected_without_a_device(lib):
+    import paper_2409_06412_amd as xyl
+    h = ctypes.c_void_p()
+    assert lib.xyl_create(ctypes.byref(h), 1, 8, 0, 0) == -1        # L < 2
+    assert b"Lx and Ly" in lib.xyl_last_error()
+    assert lib.xyl_create(ctypes.byref(h), 8, 8, 7, 0) == -1        # unknown dtype
+    assert lib.xyl_create(ctypes.byref(h), 6, 8, 0, 0) == -5        # Lx not a multiple of 4
+    assert lib.xyl_create(None, 8, 8, 0, 0) == -1
+    assert lib.xyl_destroy(None) == 0
+    assert lib.xyl_step(None, 1) == -1
+    with pytest.raises(xyl.XylError):
+        xyl.binder(np.zeros(10))                                    # <m^2> = 0
+
+
+def test_binder_and_errors_match_oracle_estimators():
+    import paper_2409_06412_amd as xyl
+    rng = np.random.default_rng(3)
+    m = np.empty(4000)
+    m[0] = 0.3
+    for t in range(1, m.size):
+        m[t] = 0.9 * m[t - 1] + 0.1 * rng.standard_normal() + 0.03
+    U, se = xyl.binder(m, 800)
+    assert U == pytest.approx(estimators.binder(m, 0.2), rel=1e-13)
+    assert np.isfinite(se) and se > 0
+    mu, e, tau = xyl.mean_error(m, 800)
+    mo, eo, to = estimators.mean_and_error(m, 0.2)
+    assert mu == pytest.approx(mo, rel=1e-13)
+    assert tau == pytest.approx(to, rel=1e-12)
+    assert e == pytest.approx(eo, rel=1e-12)
+
+
+def test_oracle_library_is_independent_of_product():
+    """The oracle neither links nor imports the HIP library."""
+    for f in ("xyo.c", "xyo.h", "__init__.py", "estimators.py"):
+        src = open(os.path.join(ROOT, "oracle", f)).read()
+        assert not re.search(r"^\s*(import|from)\s+paper_2409_06412_amd", src, flags=re.M), f
+        assert "#include" not in src or "xyl" not in "".join(re.findall(r"#include.*", src)), f
+    assert oracle.lib() is not None

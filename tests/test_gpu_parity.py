@@ -1,0 +1,328 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Tolerances (the acceptance bar of the method's hot path):
+  * integer work (Philox words, domain labels): bit-exact;
+  * FP64 state vs oracle: max wrapped |d theta| <= 1e-12 over 1000 steps with
+    shared noise (the two sides differ only by ulps of sin/cos/log and by the
+    force being evaluated as sin/cos products instead of sines of differences);
+  * FP32 state vs FP64 oracle started from the same FP32-representable state:
+    max wrapped |d theta| <= 1e-4 over 100 steps;
+  * observables of an FP64 state: relative 1e-10 (summation order differs).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_06412_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def wrapped_diff(a, b):
+    return np.abs(np.remainder(np.asarray(a) - np.asarray(b) + np.pi, 2 * np.pi) - np.pi)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_pair(xyl, Lx, Ly, dtype, **kw):
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.5)], seed=0, replica=0)
+    spec.update(kw)
+    lat = xyl.Lattice(Lx, Ly, dtype=dtype, **spec)
+    o = oracle.Oracle(Lx, Ly, **spec)
+    return lat, o
+
+
+# ------------------------------------------------------------------ noise
+def test_philox_blocks_bit_exact(xyl):
+    rng = np.random.default_rng(7)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = [0, 0, 0, 0]
+    ctr[1] = [0xFFFFFFFF] * 4
+    for seed in (0, 1, 0xDEADBEEFCAFEF00D):
+        got = xyl.philox_blocks(ctr, seed)
+        key = (seed & 0xFFFFFFFF, seed >> 32)
+        for i in range(0, 4096, 97):
+            np.testing.assert_array_equal(got[i], oracle.philox(ctr[i], key))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_noise_matches_oracle(xyl, dtype):
+    lat, o = make_pair(xyl, 256, 64, dtype, seed=0x1234567890, replica=5)
+    for k in (0, 1, 77, 2 ** 40 + 3):
+        g = lat.noise(k)
+        r = o.normals(k)
+        err = np.abs(g - r) / np.maximum(1.0, np.abs(r))
+        say(dtype, "k", k, "max rel noise err", err.max())
+        if dtype == "f64":
+            assert err.max() < 1e-13
+        else:
+            assert err.max() < 1e-5
+            assert np.mean(err) < 5e-7
+    lat.close()
+
+
+# ------------------------------------------------------------------- init
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_init_random_bit_exact(xyl, dtype):
+    lat, o = make_pair(xyl, 68, 10, dtype, seed=99, replica=3)
+    lat.init_random()
+    th, om, k = lat.get_state()
+    tr, _ = o.init_random()
+    if dtype == "f32":
+        tr = tr.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(th, tr)
+    assert np.all(om == 0) and k == 0
+    lat.close()
+
+
+# ----------------------------------------------------------------- stepping
+@pytest.mark.parametrize("Lx,Ly,nsteps,rows,wpb", [
+    (64, 64, 1000, 16, 4),      # small lattice at the oracle's size, full acceptance run
+    (260, 37, 200, 16, 4),      # two wave chunks, the second one lane wide; ragged strips
+    (4, 2, 300, 1, 1),          # one lane, both x edges explicit; Ly = 2
+    (516, 9, 150, 4, 2),
+])
+def test_fp64_parity(xyl, Lx, Ly, nsteps, rows, wpb):
+    say("fp64 parity", Lx, Ly, nsteps)
+    lat, o = make_pair(xyl, Lx, Ly, "f64", schedule=[(0, 1.2), (nsteps, 0.3)], seed=11, replica=2)
+    lat.set_launch(rows, wpb)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    lat.step(nsteps)
+    th, om, k = lat.get_state()
+    tr, wr = o.run(th0, om0, 0, nsteps)
+    assert k == nsteps
+    dth = wrapped_diff(th, tr).max()
+    dom = np.abs(om - wr).max()
+    say("  max|dtheta|", dth, "max|domega|", dom)
+    assert dth <= 1e-12
+    assert dom <= 1e-11
+    lat.close()
+
+
+def test_fp64_parity_small_acceptance_config(xyl):
+    """64 x 64, T = 0.5, seed 0: max wrapped |d theta| <= 1e-12 over 1000 steps."""
+    spec = workloads.small_fp64()
+    lat = xyl.Lattice(spec.Lx, spec.Ly, dtype="f64", schedule=spec.schedule, seed=spec.seed, **spec.params())
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    lat.init_random()
+    th0, om0 = o.init_random()
+    lat.step(1000)
+    th, om, _ = lat.get_state()
+    tr, wr = o.run(th0, om0, 0, 1000)
+    dth = wrapped_diff(th, tr).max()
+    say("small config fp64 1000 steps max|dtheta|", dth)
+    assert dth <= 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("Lx,Ly", [(64, 64), (300, 20)])
+def test_fp32_parity(xyl, Lx, Ly):
+    lat, o = make_pair(xyl, Lx, Ly, "f32", schedule=[(0, 0.5)], seed=3)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()          # FP32-representable start
+    lat.step(100)
+    th, om, _ = lat.get_state()
+    tr, wr = o.run(th0, om0, 0, 100)
+    dth = wrapped_diff(th, tr).max()
+    say("fp32 parity", Lx, Ly, "max|dtheta|", dth, "max|domega|", np.abs(om - wr).max())
+    assert dth <= 1e-4
+    assert np.abs(om - wr).max() <= 1e-3
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_set_state_fresh_velocity(xyl, dtype):
+    """A state set with nonzero omega at step k0 continues exactly like the oracle."""
+    Lx, Ly = 32, 12
+    lat, o = make_pair(xyl, Lx, Ly, dtype, schedule=[(0, 0.9)], seed=4)
+    th0, om0 = workloads.random_state(Lx, Ly, seed=8, omega_scale=0.7)
+    if dtype == "f32":
+        th0 = th0.astype(np.float32).astype(np.float64)
+        om0 = om0.astype(np.float32).astype(np.float64)
+    lat.set_state(th0, om0, step=12345)
+    lat.step(50)
+    th, om, k = lat.get_state()
+    tr, wr = o.run(th0, om0, 12345, 50)
+    assert k == 12345 + 50
+    tol = 1e-12 if dtype == "f64" else 1e-4
+    assert wrapped_diff(th, tr).max() <= tol
+    assert np.abs(om - wr).max() <= 10 * tol
+    lat.close()
+
+
+def test_launch_shape_and_graph_invariance(xyl):
+    """Bitwise-identical states whatever the strip height, workgroup size or graph use."""
+    ref = None
+    for rows, wpb, graph in ((16, 4, 0), (4, 1, 0), (64, 8, 0), (16, 4, 8), (7, 2, 5)):
+        lat = xyl.Lattice(300, 21, dtype="f32", schedule=[(0, 1.0), (40, 0.2)], seed=5)
+        lat.set_launch(rows, wpb)
+        lat.set_graph_steps(graph)
+        lat.init_random()
+        lat.step(41)
+        th, om, k = lat.get_state()
+        lat.close()
+        if ref is None:
+            ref = (th, om)
+        else:
+            np.testing.assert_array_equal(th, ref[0])
+            np.testing.assert_array_equal(om, ref[1])
+
+
+def test_split_stepping_is_exact(xyl):
+    """step(a); step(b) equals step(a + b) bitwise (noise is keyed on the step index)."""
+    out = []
+    for parts in ((100,), (1, 38, 61), (64, 36)):
+        lat = xyl.Lattice(128, 16, dtype="f32", schedule=[(0, 0.8)], seed=6)
+        lat.init_random()
+        for p in parts:
+            lat.step(p)
+        out.append(lat.get_state())
+        lat.close()
+    for th, om, k in out[1:]:
+        np.testing.assert_array_equal(th, out[0][0])
+        np.testing.assert_array_equal(om, out[0][1])
+
+
+# -------------------------------------------------------------- observables
+def test_measured_samples_match_oracle(xyl):
+    Lx, Ly = 68, 40
+    lat, o = make_pair(xyl, Lx, Ly, "f64", schedule=[(0, 0.7)], seed=12)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    s = lat.step_measured(230, 50)
+    _, _, so = o.run(th0, om0, 0, 230, every=50)
+    assert s.shape == so.shape == (5, 6)
+    np.testing.assert_allclose(s, so, rtol=1e-10, atol=1e-13)
+    # and the state after measured stepping equals plain stepping
+    th1, om1, k = lat.get_state()
+    tr, wr = o.run(th0, om0, 0, 230)
+    assert k == 230 and wrapped_diff(th1, tr).max() < 1e-12
+    m = lat.measure()
+    np.testing.assert_allclose(m, o.observables(tr, wr), rtol=1e-10, atol=1e-13)
+    lat.close()
+
+
+def test_measure_fp32_matches_oracle_on_same_state(xyl):
+    Lx, Ly = 1024, 24
+    lat, o = make_pair(xyl, Lx, Ly, "f32", schedule=[(0, 0.7)], seed=13)
+    lat.init_random()
+    lat.step(20)
+    th, om, _ = lat.get_state()
+    m = lat.measure()
+    r = o.observables(th, om)
+    np.testing.assert_allclose(m, r, rtol=2e-5, atol=2e-6)
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_correlation_matches_oracle(xyl, dtype):
+    Lx, Ly = 48, 36
+    lat, o = make_pair(xyl, Lx, Ly, dtype, schedule=[(0, 0.6)], seed=14)
+    lat.init_random()
+    lat.step(300)
+    th, _, _ = lat.get_state()
+    for axis, rmax in ((0, 24), (1, 18), (0, 0)):
+        C = lat.correlation(axis, rmax)
+        Cr = o.correlation(th, axis, rmax)
+        tol = 1e-12 if dtype == "f64" else 1e-6
+        np.testing.assert_allclose(C, Cr, atol=tol)
+    lat.close()
+
+
+# ------------------------------------------------------------------ domains
+@pytest.mark.parametrize("dtype,L", [("f32", 128), ("f64", 64), ("f32", 260)])
+def test_domains_bit_exact(xyl, dtype, L):
+    lat, o = make_pair(xyl, L, L // 2 + 2, dtype, schedule=[(0, 1.5), (400, 0.0)], seed=21)
+    lat.init_random()
+    lat.step(500)
+    th, _, _ = lat.get_state()
+    labels, sizes, counts, nd, mx = lat.domains()
+    lab_o, nd_o = o.domains(th, 32 if dtype == "f32" else 64)
+    np.testing.assert_array_equal(labels, lab_o)
+    assert nd == nd_o
+    u, c = np.unique(lab_o, return_counts=True)
+    su, sc = np.unique(c, return_counts=True)
+    np.testing.assert_array_equal(sizes, su)
+    np.testing.assert_array_equal(counts, sc)
+    assert mx == c.max()
+    assert int(np.sum(sizes * counts)) == th.size
+    lat.close()
+
+
+def test_domains_degenerate_states(xyl):
+    lat = xyl.Lattice(64, 8, dtype="f32")
+    lat.init_ordered(1)
+    labels, sizes, counts, nd, mx = lat.domains()
+    assert nd == 1 and mx == 512 and np.all(labels == 0)
+    # alternating spins in both directions: every site its own domain
+    eps = np.where(np.arange(64) % 2 == 0, 1, -1)[None, :] * np.ones((8, 1))
+    chk = np.where((np.add.outer(np.arange(8), np.arange(64)) % 2) == 0, 1, -1)
+    th = np.where(chk * eps > 0, 0.2, 2.9)
+    lat.set_state(th, np.zeros_like(th))
+    labels, sizes, counts, nd, mx = lat.domains()
+    assert nd == 512 and mx == 1
+    np.testing.assert_array_equal(labels.ravel(), np.arange(512))
+    lat.close()
+
+
+# ---------------------------------------------------------------- ensemble
+def ensemble_specs():
+    S = workloads.LatticeSpec
+    return [S(32, 32, schedule=((0, 0.5),), seed=1, replica=0, nsteps=37),
+            S(48, 20, schedule=((0, 1.1),), seed=1, replica=1, nsteps=60),
+            S(260, 12, h=0.25, gamma=0.1, schedule=((0, 1.5), (30, 0.0)), seed=2, replica=7, nsteps=45),
+            S(64, 64, schedule=((0, 0.8),), seed=3, replica=9, nsteps=0)]
+
+
+def test_ensemble_matches_single_lattices(xyl):
+    specs = ensemble_specs()
+    results = {}
+    for mode in (0, 1):
+        ens = xyl.Ensemble(specs, dtype="f32")
+        ens.set_mode(mode)
+        s1 = ens.step(25, every=10)
+        s2 = ens.step(40, every=10)
+        results[mode] = ([ens.get_state(r) for r in range(len(specs))], s1, s2)
+        ens.close()
+    for r, sp in enumerate(specs):
+        lat = xyl.Lattice(sp.Lx, sp.Ly, dtype="f32", schedule=sp.schedule, seed=sp.seed, replica=sp.replica,
+                          **sp.params())
+        lat.init_random()
+        n = min(sp.nsteps, 65)
+        samples = lat.step_measured(n, 10) if n else lat.step_measured(0, 10)
+        th, om, k = lat.get_state()
+        for mode in (0, 1):
+            eth, eom, ek = results[mode][0][r]
+            assert ek == k == n
+            np.testing.assert_array_equal(eth, th)
+            np.testing.assert_array_equal(eom, om)
+            got = np.concatenate([results[mode][1][r], results[mode][2][r]])
+            np.testing.assert_allclose(got, samples, rtol=1e-12, atol=1e-14)
+        lat.close()
+
+
+# ------------------------------------------------------------------ thermal
+def test_thermal_averages_fp32_vs_oracle(xyl):
+    """Small-config physics, 64 x 64 at T = 0.5 for 10,000 steps: FP32 GPU and FP64
+    oracle thermal averages of E_pot, E_kin and m_s^2 agree within 3 combined
+    standard errors (errors from the integrated autocorrelation time)."""
+    from oracle import estimators
+    spec = workloads.small_fp64()
+    lat = xyl.Lattice(spec.Lx, spec.Ly, dtype="f32", schedule=spec.schedule, seed=spec.seed, **spec.params())
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    sg = lat.step_measured(10_000, 100)
+    _, _, so = o.run(th0, om0, 0, 10_000, every=100)
+    for col, f in ((0, lambda x: x), (1, lambda x: x), (2, lambda x: x * x)):
+        mg, eg, _ = estimators.mean_and_error(f(sg[:, col]), 0.2)
+        mo, eo, _ = estimators.mean_and_error(f(so[:, col]), 0.2)
+        say("col", col, "gpu", mg, "+-", eg, "oracle", mo, "+-", eo)
+        assert abs(mg - mo) <= 3 * math.hypot(eg, eo) + 1e-6
+    lat.close()
