@@ -317,11 +317,12 @@ def _domains(call, N, shape, want_labels):
     labels = np.empty(shape, dtype=np.int32) if want_labels else None
     ns, nd, mx = _u64(), _u64(), _u64()
     lab_p = labels.ctypes.data_as(P(_i32)) if want_labels else None
-    _check(call(lab_p, None, None, 0, ctypes.byref(ns), ctypes.byref(nd), ctypes.byref(mx)))
-    cap = max(ns.value, 1)
+    # distinct cluster sizes s_1 < s_2 < ... sum to at most N, so there are
+    # fewer than sqrt(2 N) + 1 of them
+    cap = int(np.sqrt(2.0 * N)) + 2
     sizes = np.empty(cap, dtype=np.uint64)
     counts = np.empty(cap, dtype=np.uint64)
-    _check(call(None, sizes.ctypes.data_as(P(_u64)), counts.ctypes.data_as(P(_u64)), cap,
+    _check(call(lab_p, sizes.ctypes.data_as(P(_u64)), counts.ctypes.data_as(P(_u64)), cap,
                 ctypes.byref(ns), ctypes.byref(nd), ctypes.byref(mx)))
     return labels, sizes[: ns.value], counts[: ns.value], nd.value, mx.value
 

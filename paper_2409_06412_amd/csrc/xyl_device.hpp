@@ -28,8 +28,9 @@ __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         const uint64_t pb = (uint64_t)kMulB * c2;
         const uint32_t ka = k0 + (uint32_t)r * kWeylA;
         const uint32_t kb = k1 + (uint32_t)r * kWeylB;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ ka;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ kb;
+        // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, ka, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, kb, 0x96);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -83,9 +84,11 @@ struct Prec<float> {
         c = __builtin_amdgcn_cosf(x);
     }
     __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-    // ((r >> 9) + 1/2) 2^-23, exactly: [1, 2) from the top 23 bits, minus (1 - 2^-24).
+    // ((r >> 9) + 1/2) 2^-23, exactly: the top 23 bits under the exponent of
+    // 1.0 (one v_alignbit: (0x7f << 23) | (r >> 9)) give 1 + (r >> 9) 2^-23 in
+    // [1, 2); subtracting 1 - 2^-24 is exact.
     __device__ static __forceinline__ float uniform(uint32_t r) {
-        return __uint_as_float((r >> 9) | 0x3f800000u) - 0x1.fffffep-1f;
+        return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, r, 9u)) - 0x1.fffffep-1f;
     }
     // One Box-Muller pair: radius sqrt(-2 ln u1) (ln via the native log2),
     // angle 2 pi u2 (native sine/cosine in revolutions, no multiplication).
@@ -114,14 +117,16 @@ struct Prec<double> {
     }
 };
 
+// Wrap to [-pi_p, pi_p): exact by Sterbenz's lemma while |dt * u| < pi.  Two
+// selects instead of branches; same result as "if t >= pi: t -= 2 pi, else if
+// t < -pi: t += 2 pi" for every input (after the first select t < pi holds,
+// and a value that the first select moved is >= -pi).
 template <typename R>
 __device__ __forceinline__ R wrap_angle(R t) {
-    // exact by Sterbenz's lemma while |dt * u| < pi
-    if (t >= Prec<R>::kPi)
-        t -= Prec<R>::kTwoPi;
-    else if (t < -Prec<R>::kPi)
-        t += Prec<R>::kTwoPi;
-    return t;
+    const R lo = t - Prec<R>::kTwoPi;
+    t = t >= Prec<R>::kPi ? lo : t;
+    const R hi = t + Prec<R>::kTwoPi;
+    return t < -Prec<R>::kPi ? hi : t;
 }
 
 // Four Gaussian draws of the sites 4q..4q+3 (q = i >> 2) at step k.

@@ -84,10 +84,12 @@ __device__ __forceinline__ int32_t uf_find(const int32_t* parent, int32_t a) {
 }
 
 // Union with monotone links (the larger root is hooked under the smaller by
-// atomicMin; parent[i] <= i always, so every find terminates).  When the hook
-// finds that another thread re-parented the root first, the loop unites the
-// value it displaced, so no connection is lost (Playne and Hawick, IEEE TPDS
-// 2018).  The surviving root of a cluster is its smallest index.
+// atomicMin; parent[i] <= i always, so every find terminates).  If the hook
+// finds that another thread re-parented that root first (to `old`), atomicMin
+// may have replaced the link to `old` by the link to the other root, so the
+// loop goes on uniting `old` with the other root: no connection is lost
+// (Playne and Hawick, IEEE TPDS 2018).  The surviving root of a cluster is its
+// smallest index.
 __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
     while (true) {
         a = uf_find(parent, a);
@@ -98,9 +100,10 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
             a = b;
             b = t;
         }
+        // a > b: hook root a under b
         const int32_t old = atomicMin(parent + a, b);
         if (old == a) return;
-        b = old;
+        a = old;
     }
 }
 

@@ -19,6 +19,16 @@
 
 namespace xyl {
 
+// Register window of one row: raw angles and the two outer x-neighbours
+// (used by the wave's edge lanes), their sine/cosine and the velocities.
+template <typename R>
+struct RowSet {
+    R th[4];
+    R eL, eR;
+    R s[4], c[4];
+    R u[4];
+};
+
 template <typename R, int MODE>
 __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
     const int Lx = v.Lx, Ly = v.Ly;
@@ -30,7 +40,11 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const int x0 = xw * kWaveSites;
     const int nact = min(kWave, (Lx - x0) >> 2);
     const bool act = lane < nact;
+    const bool edgeL = act && lane == 0;
+    const bool edgeR = lane == nact - 1;
     const int x = x0 + kLaneSites * lane;
+    const int xm = x == 0 ? Lx - 1 : x - 1;          // outer neighbours of the lane's 4 sites
+    const int xp = x + 4 == Lx ? 0 : x + 4;
     const int par = (int)((k + (uint64_t)v.cur) & 1);
     const R* __restrict__ thi = v.th[par];
     R* __restrict__ tho = v.th[par ^ 1];
@@ -39,48 +53,44 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const bool fresh = (k == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
 
-    R sp[4], cp[4], sc[4], cc[4], sn[4], cn[4], thc[4], thn[4], uc[4];
+    auto load_theta = [&](RowSet<R>& S, int y) {
+        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
+        if (act) load4(thi + row + x, S.th);
+        if (edgeL) S.eL = thi[row + xm];
+        if (edgeR) S.eR = thi[row + xp];
+    };
+    auto trig = [&](RowSet<R>& S) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) thc[q] = thn[q] = uc[q] = R(0);
-    {
-        R t[4] = {R(0), R(0), R(0), R(0)};
-        const int ym = (y0 == 0) ? Ly - 1 : y0 - 1;
-        if (act) load4(thi + (size_t)ym * Lx + x, t);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Prec<R>::sincos(t[q], sp[q], cp[q]);
-        if (act) {
-            load4(thi + (size_t)y0 * Lx + x, thc);
-            load4(thi + (size_t)((y0 + 1 == Ly) ? 0 : y0 + 1) * Lx + x, thn);
-            load4(uu + (size_t)y0 * Lx + x, uc);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Prec<R>::sincos(thc[q], sc[q], cc[q]);
-    }
+        for (int q = 0; q < 4; ++q) Prec<R>::sincos(S.th[q], S.s[q], S.c[q]);
+    };
 
-    double rowphase_s = 0.0, rowphase_c = 1.0;
-    for (int y = y0; y < y1; ++y) {
-        const size_t row = (size_t)y * Lx;
-        // prefetch the rows of the next iteration
-        R thnn[4] = {R(0), R(0), R(0), R(0)}, un[4] = {R(0), R(0), R(0), R(0)};
-        if (y + 1 < y1 && act) {
-            const int ynn = (y + 2) % Ly;
-            load4(thi + (size_t)ynn * Lx + x, thnn);
-            load4(uu + row + Lx + x, un);
+    // One row y with the window (P = y-1, C = y, N = y+1).  At entry N.th is
+    // loaded (sin/cos not yet taken) and C.u is loaded.  The row issues the
+    // loads of row y+2 into P's raw-angle slots (dead since row y-1 was
+    // stored; P's sin/cos, still needed here, are not touched) and of the
+    // velocities of row y+1.
+    auto do_row = [&](RowSet<R>& P, RowSet<R>& C, RowSet<R>& N, int y) {
+        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
+        trig(N);
+        if (y + 2 <= y1) {   // row y+1 will be processed: it needs row y+2 and its velocities
+            int y2 = y + 2;
+            if (y2 >= Ly) y2 -= Ly;
+            load_theta(P, y2);
+            if (act) load4(uu + row + (uint32_t)Lx + x, N.u);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Prec<R>::sincos(thn[q], sn[q], cn[q]);
-
         // x-neighbours of the lane's first and last site
-        R sL = from_lane_below(sc[3]), cL = from_lane_below(cc[3]);
-        R sR = from_lane_above(sc[0]), cR = from_lane_above(cc[0]);
-        if (lane == 0 && act) {
-            const R t = thi[row + (x == 0 ? Lx - 1 : x - 1)];
-            Prec<R>::sincos(t, sL, cL);
-        }
-        if (lane == nact - 1) {
-            const R t = thi[row + (x + 4 == Lx ? 0 : x + 4)];
-            Prec<R>::sincos(t, sR, cR);
-        }
+        // (the wave's first lane takes its left neighbour, the last active lane
+        // its right one, from the extra angle loaded with the row; a wave with
+        // a single active lane needs both)
+        R se, ce;
+        Prec<R>::sincos(edgeL ? C.eL : C.eR, se, ce);
+        R sL = from_lane_below(C.s[3]), cL = from_lane_below(C.c[3]);
+        R sR = from_lane_above(C.s[0]), cR = from_lane_above(C.c[0]);
+        sL = edgeL ? se : sL;
+        cL = edgeL ? ce : cL;
+        sR = edgeR ? se : sR;
+        cR = edgeR ? ce : cR;
+        if (nact == 1) Prec<R>::sincos(C.eR, sR, cR);
 
         R n[4];
         noise4<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, n);
@@ -88,18 +98,18 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         R tho4[4], uo4[4], w[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const R sxm = q == 0 ? sL : sc[q - 1], cxm = q == 0 ? cL : cc[q - 1];
-            const R sxp = q == 3 ? sR : sc[q + 1], cxp = q == 3 ? cR : cc[q + 1];
+            const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
+            const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
             // F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [...] - 4 h s c  (= -dH/dth)
-            const R fx = Prec<R>::fma(sc[q], cxp + cxm, -(cc[q] * (sxp + sxm)));
-            const R fy = Prec<R>::fma(sc[q], cn[q] + cp[q], -(cc[q] * (sn[q] + sp[q])));
+            const R fx = Prec<R>::fma(C.s[q], cxp + cxm, -(C.c[q] * (sxp + sxm)));
+            const R fy = Prec<R>::fma(C.s[q], N.c[q] + P.c[q], -(C.c[q] * (N.s[q] + P.s[q])));
             R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
-            f = Prec<R>::fma(-v.h4, sc[q] * cc[q], f);
+            f = Prec<R>::fma(-v.h4, C.s[q] * C.c[q], f);
             R ww;
             if (fresh) {
-                ww = uc[q];
+                ww = C.u[q];
             } else {
-                R t = Prec<R>::fma(v.hdt, f, uc[q]);
+                R t = Prec<R>::fma(v.hdt, f, C.u[q]);
                 t = Prec<R>::fma(hs, n[q], t);
                 ww = v.c * t;
             }
@@ -108,7 +118,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             t2 = Prec<R>::fma(hs, n[q], t2);
             const R unew = Prec<R>::fma(v.a, ww, t2);
             uo4[q] = unew;
-            tho4[q] = wrap_angle<R>(Prec<R>::fma(v.dt, unew, thc[q]));
+            tho4[q] = wrap_angle<R>(Prec<R>::fma(v.dt, unew, C.th[q]));
         }
         if ((MODE & kStore) && act) {
             store4(tho + row + x, tho4);
@@ -120,14 +130,15 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             double acc[kNPart];
 #pragma unroll
             for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
-            sincospi(2.0 * (double)y / (double)Ly, &rowphase_s, &rowphase_c);
+            double rps, rpc;
+            sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
             if (act) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double s = (double)sc[q], c = (double)cc[q];
-                    const double sxp = (double)(q == 3 ? sR : sc[q + 1]);
-                    const double cxp = (double)(q == 3 ? cR : cc[q + 1]);
-                    const double syp = (double)sn[q], cyp = (double)cn[q];
+                    const double s = (double)C.s[q], c = (double)C.c[q];
+                    const double sxp = (double)(q == 3 ? sR : C.s[q + 1]);
+                    const double cxp = (double)(q == 3 ? cR : C.c[q + 1]);
+                    const double syp = (double)N.s[q], cyp = (double)N.c[q];
                     acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) - v.hd * (c * c - s * s);
                     acc[1] += 0.5 * (double)w[q] * (double)w[q];
                     const int xs = x + q;
@@ -141,10 +152,10 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                     acc[5] -= ec * pxs;
                     acc[6] += es * pxc;
                     acc[7] -= es * pxs;
-                    acc[8] += ec * rowphase_c;
-                    acc[9] -= ec * rowphase_s;
-                    acc[10] += es * rowphase_c;
-                    acc[11] -= es * rowphase_s;
+                    acc[8] += ec * rpc;
+                    acc[9] -= ec * rps;
+                    acc[10] += es * rpc;
+                    acc[11] -= es * rps;
                 }
             }
 #pragma unroll
@@ -158,18 +169,33 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                 for (int p = 0; p < kNPart; ++p) dst[p] = acc[p];
             }
         }
+    };
 
-        // rotate the register window down one row
+    RowSet<R> A, B, C;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            sp[q] = sc[q];
-            cp[q] = cc[q];
-            sc[q] = sn[q];
-            cc[q] = cn[q];
-            thc[q] = thn[q];
-            thn[q] = thnn[q];
-            uc[q] = un[q];
-        }
+    for (int q = 0; q < 4; ++q) {
+        A.th[q] = B.th[q] = C.th[q] = R(0);
+        A.u[q] = B.u[q] = C.u[q] = R(0);
+    }
+    A.eL = A.eR = B.eL = B.eR = C.eL = C.eR = R(0);
+    // prologue: A = row y0-1 (sin/cos), B = row y0 (sin/cos, velocities),
+    // C = row y0+1 (raw angles)
+    load_theta(A, y0 == 0 ? Ly - 1 : y0 - 1);
+    load_theta(B, y0);
+    load_theta(C, y0 + 1 == Ly ? 0 : y0 + 1);
+    if (act) load4(uu + (uint32_t)y0 * (uint32_t)Lx + x, B.u);
+    trig(A);
+    trig(B);
+
+    int y = y0;
+    for (; y + 3 <= y1; y += 3) {
+        do_row(A, B, C, y);
+        do_row(B, C, A, y + 1);
+        do_row(C, A, B, y + 2);
+    }
+    if (y < y1) {
+        do_row(A, B, C, y);
+        if (y + 1 < y1) do_row(B, C, A, y + 1);
     }
 }
 
