@@ -422,3 +422,47 @@ def mean_error(f, discard: int = 0):
     _check(load().xyl_mean_error(_pd(f), f.size, int(discard), ctypes.byref(mu), ctypes.byref(se),
                                  ctypes.byref(tau)))
     return mu.value, se.value, tau.value
+
+
+def _langevin_loss_class():
+    import torch
+
+    class LangevinLoss(torch.autograd.Function):
+        """Pathwise loss L = (1/W) sum over the last W steps of m_s^2 after
+        `nsteps` BBK steps from (theta0, omega0), with the lattice's noise held
+        fixed; differentiable in params = [Jx, Jy, h, gamma] (float64 tensor)
+        and in the initial state.  The backward pass is the library's adjoint
+        (checkpoints every `ckpt_every` steps, segments recomputed on the GPU)."""
+
+        @staticmethod
+        def forward(ctx, params, theta0, omega0, lattice, nsteps, ckpt_every, window):
+            p = [float(v) for v in params.detach().cpu().double().tolist()]
+            lattice.set_params(p[0], p[1], p[2], p[3], lattice.params["dt"])
+            lattice.set_state(theta0.detach().cpu().double().numpy(), omega0.detach().cpu().double().numpy(), 0)
+            L = lattice.adjoint_forward(int(nsteps), int(ckpt_every), int(window))
+            ctx.lattice = lattice
+            ctx.meta = (params.dtype, params.device, theta0.dtype, theta0.device, theta0.shape)
+            return torch.tensor(L, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gL):
+            g, dth, dom = ctx.lattice.adjoint_backward()
+            pdt, pdev, tdt, tdev, shape = ctx.meta
+            s = float(gL)
+            gp = torch.tensor(g * s, dtype=pdt, device=pdev)
+            gth = torch.from_numpy(dth * s).to(dtype=tdt, device=tdev).reshape(shape)
+            gom = torch.from_numpy(dom * s).to(dtype=tdt, device=tdev).reshape(shape)
+            return gp, gth, gom, None, None, None, None
+
+    return LangevinLoss
+
+
+_LL = None
+
+
+def langevin_loss(params, theta0, omega0, lattice: "Lattice", nsteps: int, ckpt_every: int, window: int):
+    """Functional form of ``LangevinLoss.apply``."""
+    global _LL
+    if _LL is None:
+        _LL = _langevin_loss_class()
+    return _LL.apply(params, theta0, omega0, lattice, nsteps, ckpt_every, window)

@@ -39,10 +39,20 @@ struct Lat {
     uint32_t seed_lo, seed_hi, replica;
     uint64_t k_base;       // step index at launch-step 0
     uint64_t fresh_k;      // step at which u holds w^k itself
-    uint64_t k_end;        // the replica does not step at k >= k_end
-    double* part;          // measurement partials [Ly][nxw][kNPart]
+    uint64_t k_end;        // steps while k < k_end; may be measured at k_end
+    double* part;          // measurement partials [Ly][nxw][kNPart] (+ stage-1 room)
     R* omega_out;          // destination of w^k (omega mode)
+    int32_t pingpong;      // 1: th[(k+cur)&1] -> th[(k+cur+1)&1]; 0: th[0] -> th[1]
+    R* u_out;              // velocities written here instead of in place (or NULL)
 };
+
+// Measurements of lattices with more than kFinalizeSplit partial rows are
+// reduced in two stages (kFinalizeBlocks blocks, then one).
+constexpr int kFinalizeSplit = 4096;
+constexpr int kFinalizeBlocks = 256;
+inline size_t part_elems(int nrowparts) {
+    return ((size_t)nrowparts + (size_t)kFinalizeBlocks) * kNPart;
+}
 
 // Step-kernel modes (bit flags).
 enum : int { kStore = 1, kMeasure = 2, kOmega = 4 };
@@ -69,8 +79,6 @@ void launch_init_random(const Lat<R>& v, hipStream_t s);
 template <typename R>
 void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s);
 void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s);
-void launch_finalize_obs_batched(const Lat<float>* reps_f, const Lat<double>* reps_d, const int* rep_ids,
-                                 int nrep, double* const* outs, hipStream_t s);
 void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
 void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
 template <typename R>
@@ -79,6 +87,15 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int axis, i
 template <typename R>
 void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent, uint32_t* size,
                     uint32_t* hist, uint32_t* stats, hipStream_t s);
+
+template <typename R>
+int adjoint_tasks(const Lat<R>& v, int rows);
+template <typename R>
+void launch_adjoint_step(const Lat<R>& v, const R* th, const R* u, const R* lt_in, const R* lu_in, R* lt_out,
+                         R* lu_out, const double* cm, uint64_t cm_base, double* gacc, const uint64_t* kdev,
+                         uint64_t koff, const Launch& l, hipStream_t s);
+template <typename R>
+void launch_adjoint_seed(const Lat<R>& v, const R* th, R* lt, R* lu, double cmN, hipStream_t s);
 
 struct Error : std::runtime_error {
     int code;

@@ -238,6 +238,8 @@ struct xyl_lattice {
         v.k_end = ~(uint64_t)0;
         v.part = part.p;
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
+        v.pingpong = 1;
+        v.u_out = nullptr;
         return v;
     }
     void* cur_theta() { return th[(int)((k + (uint64_t)cur) & 1)]; }
@@ -245,8 +247,20 @@ struct xyl_lattice {
     void touch() { ++version; }
 };
 
-namespace xyl {
-void adjoint_release(xyl_lattice* h);  // defined in xyl_adjoint.hip
+// State of a pathwise-gradient run between xyl_adjoint_forward and
+// xyl_adjoint_backward: checkpoints every K steps, the loss samples and the
+// device buffers of the reverse sweep.
+struct AdjState {
+    uint64_t k0 = 0, N = 0, K = 0, W = 0;
+    double loss = 0.0;
+    std::vector<double> m;       // m_s at steps k0+N-W+1 .. k0+N
+    DevBuf<char> ckpt, seg, lam;
+    DevBuf<double> cm, gacc, obs;
+};
+
+static void adjoint_release(xyl_lattice* h) {
+    delete static_cast<AdjState*>(h->adj);
+    h->adj = nullptr;
 }
 
 static void destroy_graph(xyl_lattice* h) {
@@ -453,7 +467,7 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
         }
         check_hip(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
         h->kdev.reserve(1);
-        h->part.reserve((size_t)h->nrowparts() * kNPart);
+        h->part.reserve(part_elems(h->nrowparts()));
         h->obs.reserve(16 * 6);
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -957,6 +971,8 @@ struct xyl_ensemble {
         v.k_end = d.nsteps;
         v.part = part.p + poff[r];
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
+        v.pingpong = 1;
+        v.u_out = nullptr;
         return v;
     }
     void* cur_theta(int r) {
@@ -1125,7 +1141,7 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
             const size_t N = (size_t)d.Lx * d.Ly;
             e->total += (N + 63) / 64 * 64;
             e->poff.push_back(e->ptotal);
-            e->ptotal += (size_t)e->nrp(r) * kNPart;
+            e->ptotal += part_elems(e->nrp(r));
         }
         const size_t bytes = elem_size(dtype) * e->total;
         for (int b = 0; b < 2; ++b) check_alloc(hipMalloc(&e->th[b], bytes), "hipMalloc theta");
@@ -1260,6 +1276,150 @@ int xyl_ensemble_sync(xyl_ensemble* e) {
         require(e != nullptr, XYL_EINVAL, "NULL handle");
         DeviceGuard g(e->device);
         check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    });
+}
+
+}  // extern "C"
+
+// ===================================================================== adjoint
+template <typename R>
+static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_t W, double* loss) {
+    adjoint_release(h);
+    std::unique_ptr<AdjState> a(new AdjState());
+    const size_t bytes = sizeof(R) * h->N;
+    a->k0 = h->k;
+    a->N = N;
+    a->K = K;
+    a->W = W;
+    const uint64_t S = (N + K - 1) / K;
+    a->ckpt.reserve(S * 2 * bytes);
+    a->obs.reserve(6 * W);
+    const uint64_t kw = a->k0 + N - W + 1;   // first step of the loss window
+    for (uint64_t s = 0; s < S; ++s) {
+        char* slot = a->ckpt.p + s * 2 * bytes;
+        check_hip(hipMemcpyAsync(slot, h->cur_theta(), bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+        check_hip(hipMemcpyAsync(slot + bytes, h->u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+        const uint64_t len = std::min<uint64_t>(K, N - s * K);
+        uint64_t j = 0;
+        while (j < len) {
+            if (h->k >= kw) {
+                lattice_measure_into<R>(h, true, a->obs.p + 6 * (h->k - kw));
+                ++j;
+            } else {
+                const uint64_t run = std::min<uint64_t>(len - j, kw - h->k);
+                lattice_steps<R>(h, run);
+                j += run;
+            }
+        }
+    }
+    lattice_measure_into<R>(h, false, a->obs.p + 6 * (W - 1));
+    std::vector<double> o(6 * W);
+    check_hip(hipMemcpyAsync(o.data(), a->obs.p, sizeof(double) * 6 * W, hipMemcpyDeviceToHost, h->stream), "D2H");
+    check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    a->m.resize(W);
+    double L = 0.0;
+    for (uint64_t i = 0; i < W; ++i) {
+        a->m[i] = o[6 * i + 2];
+        L += a->m[i] * a->m[i];
+    }
+    a->loss = L / (double)W;
+    if (loss) *loss = a->loss;
+    h->adj = a.release();
+}
+
+template <typename R>
+static void adjoint_backward_impl(xyl_lattice* h, double* grad, double* dth0, double* dom0) {
+    AdjState* a = static_cast<AdjState*>(h->adj);
+    const size_t bytes = sizeof(R) * h->N;
+    const uint64_t N = a->N, K = a->K, W = a->W, k0 = a->k0;
+    const uint64_t S = (N + K - 1) / K;
+    // direct loss coefficients dL/dm_k * dm_k/d(eps cos th) = (2 m_k / W) / Nsites
+    std::vector<double> cmh(N + 1, 0.0);
+    for (uint64_t i = 0; i < W; ++i) cmh[N - W + 1 + i] = 2.0 * a->m[i] / (double)W / (double)h->N;
+    a->cm.reserve(N + 1);
+    check_hip(hipMemcpyAsync(a->cm.p, cmh.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice, h->stream), "H2D");
+    Launch l = h->launch;
+    l.wpb = std::min(l.wpb, 4);
+    Lat<R> v = h->view<R>();
+    const int ntasks = adjoint_tasks<R>(v, l.rows);
+    a->gacc.reserve((size_t)ntasks * 4);
+    check_hip(hipMemsetAsync(a->gacc.p, 0, sizeof(double) * ntasks * 4, h->stream), "hipMemsetAsync");
+    a->lam.reserve(4 * bytes);
+    R* lt[2] = {reinterpret_cast<R*>(a->lam.p), reinterpret_cast<R*>(a->lam.p + bytes)};
+    R* lu[2] = {reinterpret_cast<R*>(a->lam.p + 2 * bytes), reinterpret_cast<R*>(a->lam.p + 3 * bytes)};
+    launch_adjoint_seed<R>(v, static_cast<const R*>(h->cur_theta()), lt[0], lu[0], cmh[N], h->stream);
+    int li = 0;
+    a->seg.reserve((K + 1) * 2 * bytes);
+    auto slot_th = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes); };
+    auto slot_u = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes + bytes); };
+    for (uint64_t s = S; s-- > 0;) {
+        const uint64_t ks = k0 + s * K;
+        const uint64_t len = std::min<uint64_t>(K, k0 + N - ks);
+        const char* ck = a->ckpt.p + s * 2 * bytes;
+        check_hip(hipMemcpyAsync(slot_th(0), ck, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+        check_hip(hipMemcpyAsync(slot_u(0), ck + bytes, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+        // recompute the segment's states, each into its own slot
+        for (uint64_t j = 0; j < len; ++j) {
+            Lat<R> w = v;
+            w.pingpong = 0;
+            w.th[0] = slot_th(j);
+            w.th[1] = slot_th(j + 1);
+            w.u = slot_u(j);
+            w.u_out = slot_u(j + 1);
+            launch_step<R>(w, kStore, h->launch, nullptr, ks + j, h->stream);
+        }
+        for (uint64_t j = len; j-- > 0;) {
+            launch_adjoint_step<R>(v, slot_th(j), slot_u(j), lt[li], lu[li], lt[li ^ 1], lu[li ^ 1], a->cm.p, k0,
+                                   a->gacc.p, nullptr, ks + j, l, h->stream);
+            li ^= 1;
+        }
+    }
+    std::vector<double> g((size_t)ntasks * 4);
+    check_hip(hipMemcpyAsync(g.data(), a->gacc.p, sizeof(double) * ntasks * 4, hipMemcpyDeviceToHost, h->stream),
+              "D2H");
+    if (dth0) {
+        std::vector<R> t(h->N);
+        check_hip(hipMemcpyAsync(t.data(), lt[li], bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        for (size_t i = 0; i < h->N; ++i) dth0[i] = (double)t[i];
+    }
+    if (dom0) {
+        std::vector<R> t(h->N);
+        check_hip(hipMemcpyAsync(t.data(), lu[li], bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        for (size_t i = 0; i < h->N; ++i) dom0[i] = (double)t[i];
+    }
+    check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (grad) {
+        for (int p = 0; p < 4; ++p) grad[p] = 0.0;
+        for (int t = 0; t < ntasks; ++t)
+            for (int p = 0; p < 4; ++p) grad[p] += g[(size_t)t * 4 + p];
+    }
+}
+
+extern "C" {
+
+int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss) {
+    return guarded([&] {
+        require_init(h);
+        require(nsteps >= 1, XYL_EINVAL, "nsteps must be >= 1");
+        require(window >= 1 && window <= nsteps, XYL_EINVAL, "window must be in [1, nsteps]");
+        require(ckpt_every >= 1, XYL_EINVAL, "ckpt_every must be >= 1");
+        DeviceGuard g(h->device);
+        if (h->dtype == XYL_F64) adjoint_forward_impl<double>(h, nsteps, ckpt_every, window, loss);
+        else adjoint_forward_impl<float>(h, nsteps, ckpt_every, window, loss);
+    });
+}
+
+int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* domega0) {
+    return guarded([&] {
+        require_init(h);
+        AdjState* a = static_cast<AdjState*>(h->adj);
+        require(a != nullptr, XYL_ESTATE, "no adjoint forward run to differentiate");
+        require(h->k == a->k0 + a->N, XYL_ESTATE, "lattice was stepped or reset after xyl_adjoint_forward");
+        DeviceGuard g(h->device);
+        if (h->dtype == XYL_F64) adjoint_backward_impl<double>(h, grad, dtheta0, domega0);
+        else adjoint_backward_impl<float>(h, grad, dtheta0, domega0);
     });
 }
 

@@ -33,7 +33,8 @@ template <typename R, int MODE>
 __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
     const int Lx = v.Lx, Ly = v.Ly;
     const uint64_t k = v.k_base + j;
-    if (k >= v.k_end) return;
+    // a replica steps while k < k_end and can still be measured at k_end
+    if ((MODE & kStore) ? k >= v.k_end : k > v.k_end) return;
     const int y0 = strip * rows;
     if (y0 >= Ly) return;
     const int y1 = min(y0 + rows, Ly);
@@ -46,9 +47,10 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const int xm = x == 0 ? Lx - 1 : x - 1;          // outer neighbours of the lane's 4 sites
     const int xp = x + 4 == Lx ? 0 : x + 4;
     const int par = (int)((k + (uint64_t)v.cur) & 1);
-    const R* __restrict__ thi = v.th[par];
-    R* __restrict__ tho = v.th[par ^ 1];
-    R* uu = v.u;
+    const R* __restrict__ thi = v.pingpong ? v.th[par] : v.th[0];
+    R* __restrict__ tho = v.pingpong ? v.th[par ^ 1] : v.th[1];
+    const R* uu = v.u;
+    R* uw = v.u_out ? v.u_out : v.u;
     const R hs = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
     const bool fresh = (k == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
@@ -122,7 +124,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         }
         if ((MODE & kStore) && act) {
             store4(tho + row + x, tho4);
-            store4(uu + row + x, uo4);
+            store4(uw + row + x, uo4);
         }
         if ((MODE & kOmega) && act) store4(v.omega_out + row + x, w);
 
@@ -350,8 +352,39 @@ __global__ __launch_bounds__(256) void k_finalize_obs(const double* part, int nr
     finalize_block(part, nrp, N, out);
 }
 
+// First stage for large lattices: block b sums the contiguous range
+// [b * chunk, (b + 1) * chunk) of partial rows (same fixed pattern), writing
+// one partial row per block.
+__global__ __launch_bounds__(256) void k_finalize_stage1(const double* part, int nrp, int chunk, double* out) {
+    __shared__ double red[256][kNPart];
+    const int b0 = blockIdx.x * chunk;
+    const int b1 = min(b0 + chunk, nrp);
+    double acc[kNPart];
+    for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
+    for (int e = b0 + (int)threadIdx.x; e < b1; e += blockDim.x)
+        for (int p = 0; p < kNPart; ++p) acc[p] += part[(size_t)e * kNPart + p];
+    for (int p = 0; p < kNPart; ++p) red[threadIdx.x][p] = acc[p];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int p = 0; p < kNPart; ++p) red[threadIdx.x][p] += red[threadIdx.x + w][p];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNPart) out[(size_t)blockIdx.x * kNPart + threadIdx.x] = red[0][threadIdx.x];
+}
+
 void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s) {
-    k_finalize_obs<<<1, 256, 0, s>>>(part, nrowparts, N, out);
+    if (nrowparts > kFinalizeSplit) {
+        // stage-1 output goes after the row partials (the buffer is sized for it)
+        const int nb = kFinalizeBlocks;
+        const int chunk = (nrowparts + nb - 1) / nb;
+        double* tmp = const_cast<double*>(part) + (size_t)nrowparts * kNPart;
+        k_finalize_stage1<<<nb, 256, 0, s>>>(part, nrowparts, chunk, tmp);
+        check_hip(hipGetLastError(), "finalize stage-1 launch");
+        k_finalize_obs<<<1, 256, 0, s>>>(tmp, nb, N, out);
+    } else {
+        k_finalize_obs<<<1, 256, 0, s>>>(part, nrowparts, N, out);
+    }
     check_hip(hipGetLastError(), "finalize kernel launch");
 }
 

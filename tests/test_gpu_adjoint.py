@@ -1,0 +1,117 @@
+"""GPU adjoint (pathwise gradients with the noise held fixed) against the FP64
+oracle adjoint and against central finite differences with common random
+numbers, through the C-ABI and through the torch.autograd.Function."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("Jx", "Jy", "h", "gamma")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_fp64_adjoint_matches_oracle(xyl):
+    """64 x 64, 500 steps, loss window 100, checkpoints every 100."""
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=7, replica=0)
+    lat = xyl.Lattice(64, 64, dtype="f64", **spec)
+    o = oracle.Oracle(64, 64, **spec)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    L = lat.adjoint_forward(500, 100, 100)
+    g, dth, dom = lat.adjoint_backward()
+    Lo, go, dtho, domo = o.adjoint(th0, om0, 500, 100)
+    say("loss gpu", L, "oracle", Lo, "grad gpu", g, "oracle", go)
+    assert L == pytest.approx(Lo, rel=1e-11)
+    np.testing.assert_allclose(g, go, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(dth, dtho, rtol=1e-7, atol=1e-11 * np.abs(dtho).max())
+    np.testing.assert_allclose(dom, domo, rtol=1e-7, atol=1e-11 * np.abs(domo).max())
+    lat.close()
+
+
+@pytest.mark.parametrize("Lx,Ly,K", [(68, 20, 7), (12, 5, 50)])
+def test_fp64_adjoint_ragged_and_partial_segments(xyl, Lx, Ly, K):
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=0.7, dt=0.01, schedule=[(0, 1.0), (90, 0.3)], seed=3, replica=1)
+    lat = xyl.Lattice(Lx, Ly, dtype="f64", **spec)
+    lat.init_random()
+    lat.step(13)                      # start from a non-fresh state
+    L = lat.adjoint_forward(90, K, 25)
+    g, dth, dom = lat.adjoint_backward()
+    # from a non-fresh state the independent velocity is the stored half-step
+    # one, so the reference is central differences of the GPU's own FP64 loss
+    def loss_at(**kw):
+        # the 13 lead-in steps use the base parameters: the state at step 13
+        # is the independent variable
+        p = dict(spec)
+        p.update(kw)
+        l2 = xyl.Lattice(Lx, Ly, dtype="f64", **spec)
+        l2.init_random()
+        l2.step(13)
+        l2.set_params(p["Jx"], p["Jy"], p["h"], p["gamma"], p["dt"])
+        val = l2.adjoint_forward(90, K, 25)
+        l2.close()
+        return val
+    assert loss_at() == L
+    for j, n in enumerate(NAMES):
+        e = 1e-6 * abs(spec[n])
+        fd = (loss_at(**{n: spec[n] + e}) - loss_at(**{n: spec[n] - e})) / (2 * e)
+        assert g[j] == pytest.approx(fd, rel=1e-5, abs=1e-10), n
+    lat.close()
+
+
+def test_fp32_adjoint_512_against_finite_differences(xyl):
+    """512 x 512, T = 0.6, 5000 steps, window 1000, checkpoints every 100; FP32
+    adjoint within 1e-3 relative of central differences (relative step 1e-4,
+    common random numbers) evaluated with the FP64 path."""
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=7, replica=0)
+    lat = xyl.Lattice(512, 512, dtype="f32", **spec)
+    lat.init_random()
+    L = lat.adjoint_forward(5000, 100, 1000)
+    g, dth, dom = lat.adjoint_backward()
+    lat.close()
+
+    def loss64(**kw):
+        p = dict(spec)
+        p.update(kw)
+        l2 = xyl.Lattice(512, 512, dtype="f64", **p)
+        l2.init_random()
+        th, om, _ = l2.get_state()
+        # start from the FP32-rounded initial angles, like the FP32 run
+        l2.set_state(th.astype(np.float32).astype(np.float64), om, 0)
+        val = l2.adjoint_forward(5000, 5000, 1000)
+        l2.close()
+        return val
+
+    L64 = loss64()
+    say("loss fp32", L, "fp64", L64)
+    assert L == pytest.approx(L64, rel=1e-3)
+    for j, n in enumerate(NAMES):
+        e = 1e-4 * abs(spec[n])
+        fd = (loss64(**{n: spec[n] + e}) - loss64(**{n: spec[n] - e})) / (2 * e)
+        say(n, "adjoint", g[j], "fd", fd)
+        assert g[j] == pytest.approx(fd, rel=1e-3, abs=1e-3 * max(abs(fd), 1e-3 * abs(L)))
+
+
+def test_autograd_function(xyl):
+    import torch
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=5, replica=0)
+    lat = xyl.Lattice(64, 32, dtype="f64", **spec)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    params = torch.tensor([1.0, -0.1, 0.5, 1.0], dtype=torch.float64, requires_grad=True)
+    th = torch.tensor(th0, device="cuda", requires_grad=True)
+    om = torch.tensor(om0, device="cuda", requires_grad=True)
+    L = xyl.langevin_loss(params, th, om, lat, 200, 50, 40)
+    L.backward()
+    o = oracle.Oracle(64, 32, **spec)
+    Lo, go, dtho, domo = o.adjoint(th0, om0, 200, 40)
+    assert float(L) == pytest.approx(Lo, rel=1e-11)
+    np.testing.assert_allclose(params.grad.numpy(), go, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(th.grad.cpu().numpy(), dtho, rtol=1e-7, atol=1e-11 * np.abs(dtho).max())
+    lat.close()
