@@ -120,12 +120,14 @@ def bench_adjoint(torch, xyl, workloads):
     lat.init_random()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    lat.step_measured(spec.nsteps, 1) if False else lat.step(spec.nsteps)
+    lat.step(spec.nsteps)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     lat.close()
-    return {"L": spec.Lx, "steps": spec.nsteps, "forward_with_loss_s": t1 - t0, "backward_s": t2 - t1,
-            "plain_forward_s": t4 - t3, "adjoint_over_forward": (t2 - t1) / (t1 - t0)}
+    return {"L": spec.Lx, "steps": spec.nsteps, "checkpoint_every": 100, "window": 1000,
+            "forward_with_loss_s": t1 - t0, "backward_s": t2 - t1, "plain_forward_s": t4 - t3,
+            "adjoint_over_forward": (t2 - t1) / (t1 - t0),
+            "adjoint_over_plain_forward": (t2 - t1) / (t4 - t3)}
 
 
 def bench_domains(torch, xyl):
@@ -156,6 +158,92 @@ def cpu_baseline(L, nsteps):
             "sample": "FP64 oracle, %dx%d lattice, %d BBK steps (%.1f s)" % (L, L, nsteps, dt)}
 
 
+# ----------------------------------------------------------- profile summaries
+STEP_KERNEL = "xyl::k_step<float, 1>"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def summarize_trace(d, out_md, command):
+    """Kernel statistics of a `rocprofv3 --kernel-trace --stats` run as markdown."""
+    import csv
+    files = _csvs(d, "kernel_stats.csv")
+    if not files:
+        raise SystemExit("no kernel_stats.csv under %s" % d)
+    rows = list(csv.DictReader(open(files[0])))
+    lines = ["# Kernel statistics: %s" % os.path.basename(out_md).replace(".md", ""), "",
+             "Command (from the repository root):", "", "    " + command, "",
+             "| kernel | calls | total (ms) | average (us) | min (us) | max (us) | share |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[:12]:
+        name = r["Name"].replace("|", "/")
+        lines.append("| %s | %s | %.3f | %.2f | %.2f | %.2f | %.1f%% |" % (
+            name[:80], r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter_means(d, counter, L):
+    """Mean counter value (KiB) of the step kernel at its most frequent grid and
+    of plain device copies of one lattice array (L*L*4 bytes)."""
+    import csv
+    from collections import defaultdict
+    files = _csvs(d, "counter_collection.csv")
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    step = defaultdict(list)
+    copy = []
+    for r in csv.DictReader(open(files[0])):
+        if r.get("Counter_Name") != counter:
+            continue
+        v = float(r["Counter_Value"])
+        name = r["Kernel_Name"]
+        if name.startswith(STEP_KERNEL):
+            step[(r["Grid_Size"], r["Workgroup_Size"])].append(v)
+        elif name.startswith(COPY_KERNEL):
+            copy.append(v)
+    key = max(step, key=lambda k: len(step[k]))
+    return sum(step[key]) / len(step[key]), max(copy) if copy else None, key
+
+
+def summarize_traffic(fetch_dir, write_dir, out_json, out_md, L, commands):
+    """HBM traffic of one step launch from FETCH_SIZE and WRITE_SIZE, each scaled
+    by what it reads for a plain copy of one 4*L*L-byte array."""
+    nbytes = 4 * L * L
+    f_step, f_copy, key = _counter_means(fetch_dir, "FETCH_SIZE", L)
+    w_step, w_copy, _ = _counter_means(write_dir, "WRITE_SIZE", L)
+    f_scale = nbytes / (f_copy * 1024.0)
+    w_scale = nbytes / (w_copy * 1024.0)
+    fetch_b = f_step * 1024.0 * f_scale
+    write_b = w_step * 1024.0 * w_scale
+    alg = BYTES_PER_SITE_F32 * L * L
+    res = {"kernel": STEP_KERNEL, "L": L, "kernel_hash": kernel_source_hash(), "grid_workgroup": list(key),
+           "fetch_kib_per_launch": f_step, "write_kib_per_launch": w_step,
+           "copy_fetch_kib": f_copy, "copy_write_kib": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes": fetch_b, "write_bytes": write_b, "bytes_per_launch": fetch_b + write_b,
+           "algorithmic_bytes": alg, "traffic_over_algorithmic": (fetch_b + write_b) / alg,
+           "commands": commands}
+    json.dump(res, open(out_json, "w"), indent=1)
+    md = ["# HBM traffic of the FP32 step kernel, %dx%d lattice" % (L, L), "",
+          "Commands (from the repository root):", ""] + ["    " + c for c in commands] + [
+          "", "| quantity | value |", "|---|---|",
+          "| step FETCH_SIZE per launch (KiB) | %.0f |" % f_step,
+          "| step WRITE_SIZE per launch (KiB) | %.0f |" % w_step,
+          "| copy of %d B: FETCH_SIZE / WRITE_SIZE (KiB) | %.0f / %.0f |" % (nbytes, f_copy, w_copy),
+          "| scale factors fetch / write | %.4f / %.4f |" % (f_scale, w_scale),
+          "| scaled fetch + write per launch (MB) | %.1f + %.1f = %.1f |" % (fetch_b / 1e6, write_b / 1e6,
+                                                                            (fetch_b + write_b) / 1e6),
+          "| algorithmic bytes per launch (MB) | %.1f |" % (alg / 1e6),
+          "| traffic / algorithmic | %.3f |" % ((fetch_b + write_b) / alg), ""]
+    open(out_md, "w").write("\n".join(md))
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,7 +254,19 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--launch", type=str, default="",
+                    help="rows,waves: fixed launch shape of the step kernel instead of autotuning")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"))
+    ap.add_argument("--summarize-traffic", nargs=6,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "OUT_MD", "FETCH_CMD", "WRITE_CMD"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        a = args.summarize_traffic
+        summarize_traffic(a[0], a[1], a[2], a[3], args.L, [a[4], a[5]])
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
@@ -183,7 +283,12 @@ def main():
     lat = xyl.Lattice(L, L, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
                       stream=stream, **spec.params())
     lat.init_random()
-    launch = lat.autotune()
+    if args.launch:
+        r, w = (int(v) for v in args.launch.split(","))
+        lat.set_launch(r, w)
+        launch = lat.launch()
+    else:
+        launch = lat.autotune()
     log("launch shape (rows per strip, waves per workgroup):", launch)
     lat.step(args.warmup)
     torch.cuda.synchronize()

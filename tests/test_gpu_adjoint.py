@@ -65,14 +65,19 @@ def test_fp64_adjoint_ragged_and_partial_segments(xyl, Lx, Ly, K):
     lat.close()
 
 
-def test_fp32_adjoint_512_against_finite_differences(xyl):
-    """512 x 512, T = 0.6, 5000 steps, window 1000, checkpoints every 100; FP32
-    adjoint within 1e-3 relative of central differences (relative step 1e-4,
-    common random numbers) evaluated with the FP64 path."""
+@pytest.mark.parametrize("nsteps,window", [(1000, 200)])
+def test_fp32_adjoint_512_against_finite_differences(xyl, nsteps, window):
+    """512 x 512, T = 0.6, checkpoints every 100: the FP32 adjoint agrees within
+    1e-3 relative with central differences (relative step 1e-4, common random
+    numbers) of the loss evaluated on the FP64 path from the same FP32 start.
+    The horizon is 1000 steps: at T = 0.6 the pathwise derivative over 5000
+    steps is dominated by chaotic growth and no finite-difference step
+    converges (shown on the oracle in test_oracle_physics), so 5000 steps are
+    used for timing only."""
     spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=7, replica=0)
     lat = xyl.Lattice(512, 512, dtype="f32", **spec)
     lat.init_random()
-    L = lat.adjoint_forward(5000, 100, 1000)
+    L = lat.adjoint_forward(nsteps, 100, window)
     g, dth, dom = lat.adjoint_backward()
     lat.close()
 
@@ -82,9 +87,8 @@ def test_fp32_adjoint_512_against_finite_differences(xyl):
         l2 = xyl.Lattice(512, 512, dtype="f64", **p)
         l2.init_random()
         th, om, _ = l2.get_state()
-        # start from the FP32-rounded initial angles, like the FP32 run
         l2.set_state(th.astype(np.float32).astype(np.float64), om, 0)
-        val = l2.adjoint_forward(5000, 5000, 1000)
+        val = l2.adjoint_forward(nsteps, nsteps, window)
         l2.close()
         return val
 
@@ -95,7 +99,7 @@ def test_fp32_adjoint_512_against_finite_differences(xyl):
         e = 1e-4 * abs(spec[n])
         fd = (loss64(**{n: spec[n] + e}) - loss64(**{n: spec[n] - e})) / (2 * e)
         say(n, "adjoint", g[j], "fd", fd)
-        assert g[j] == pytest.approx(fd, rel=1e-3, abs=1e-3 * max(abs(fd), 1e-3 * abs(L)))
+        assert g[j] == pytest.approx(fd, rel=1e-3), n
 
 
 def test_autograd_function(xyl):

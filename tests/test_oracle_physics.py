@@ -380,3 +380,24 @@ def test_adjoint_matches_central_differences():
             else:
                 fd = (o.loss(th0, a.reshape(arr.shape), nsteps, window) - o.loss(th0, b.reshape(arr.shape), nsteps, window)) / (2 * e)
             assert grad.ravel()[i] == pytest.approx(fd, rel=1e-5, abs=1e-11)
+
+
+@pytest.mark.slow
+def test_pathwise_gradient_conditioning_horizon():
+    """At T = 0.6 (64 x 64) the pathwise derivative of the windowed m_s^2 loss is
+    well conditioned over 1000 steps (finite differences converge to the adjoint)
+    but not over 5000 steps, where chaotic growth makes finite differences at
+    relative steps 1e-3 .. 1e-6 disagree wildly with each other."""
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=7)
+    o = oracle.Oracle(64, 64, **spec)
+    th, om = o.init_random()
+
+    def fd(N, rel):
+        W = N // 5
+        return (o.with_params(Jx=1 + rel).loss(th, om, N, W) - o.with_params(Jx=1 - rel).loss(th, om, N, W)) / (2 * rel)
+
+    _, g, _, _ = o.adjoint(th, om, 1000, 200)
+    for rel in (1e-4, 1e-5, 1e-6):
+        assert fd(1000, rel) == pytest.approx(g[0], rel=1e-3)
+    long = [fd(5000, rel) for rel in (1e-3, 1e-4, 1e-5, 1e-6)]
+    assert max(long) - min(long) > 10 * max(abs(v) for v in long[:1])
