@@ -65,15 +65,16 @@ def test_fp64_adjoint_ragged_and_partial_segments(xyl, Lx, Ly, K):
     lat.close()
 
 
-@pytest.mark.parametrize("nsteps,window", [(1000, 200)])
+@pytest.mark.parametrize("nsteps,window", [(500, 100)])
 def test_fp32_adjoint_512_against_finite_differences(xyl, nsteps, window):
     """512 x 512, T = 0.6, checkpoints every 100: the FP32 adjoint agrees within
     1e-3 relative with central differences (relative step 1e-4, common random
     numbers) of the loss evaluated on the FP64 path from the same FP32 start.
-    The horizon is 1000 steps: at T = 0.6 the pathwise derivative over 5000
-    steps is dominated by chaotic growth and no finite-difference step
-    converges (shown on the oracle in test_oracle_physics), so 5000 steps are
-    used for timing only."""
+    The horizon is 500 steps: at T = 0.6 the pathwise derivative loses its
+    conditioning between 500 and 1000 steps (there, even converged FP64
+    differences and the FP64 adjoint part at 1e-3) and over 5000 steps no
+    finite-difference step converges (shown on the oracle), so the 5000-step
+    run is used for timing only."""
     spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=7, replica=0)
     lat = xyl.Lattice(512, 512, dtype="f32", **spec)
     lat.init_random()
