@@ -44,6 +44,8 @@ struct Lat {
     R* omega_out;          // destination of w^k (omega mode)
     int32_t pingpong;      // 1: th[(k+cur)&1] -> th[(k+cur+1)&1]; 0: th[0] -> th[1]
     R* u_out;              // velocities written here instead of in place (or NULL)
+    uint64_t part_k0;      // with part_stride > 0, step k writes its partials at
+    uint64_t part_stride;  //   part + (k - part_k0) * part_stride
 };
 
 // Measurements of lattices with more than kFinalizeSplit partial rows are
@@ -79,6 +81,10 @@ void launch_init_random(const Lat<R>& v, hipStream_t s);
 template <typename R>
 void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s);
 void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s);
+// count measurements whose partials lie stride apart: out[6 j ...] for j < count
+void launch_finalize_many(const double* part, int nrowparts, uint64_t stride, double N, double* out, int count,
+                          hipStream_t s);
+void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
 void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
 void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
 template <typename R>

@@ -20,7 +20,6 @@
 namespace xyl {
 
 void launch_finalize_jobs(const void* jobs, int njobs, hipStream_t s);
-void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
 
 struct FinalizeJobHost {
     const double* part;
@@ -206,10 +205,15 @@ struct xyl_lattice {
     bool initialized = false;
     Launch launch;
     int graph_steps = 32;
-    // graphs
-    hipGraphExec_t graph = nullptr;
-    int graph_n = 0;
-    uint64_t graph_version = ~(uint64_t)0;
+    // captured step sequences, keyed by what their kernel arguments bake in
+    struct GraphEntry {
+        int mode = 0, S = 0;
+        double* part = nullptr;
+        uint64_t part_k0 = 0, part_stride = 0;
+        uint64_t version = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
     uint64_t version = 0;
     bool counter_valid = false;
     // device scratch
@@ -240,6 +244,8 @@ struct xyl_lattice {
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
         v.pingpong = 1;
         v.u_out = nullptr;
+        v.part_k0 = 0;
+        v.part_stride = 0;
         return v;
     }
     void* cur_theta() { return th[(int)((k + (uint64_t)cur) & 1)]; }
@@ -255,7 +261,13 @@ struct AdjState {
     double loss = 0.0;
     std::vector<double> m;       // m_s at steps k0+N-W+1 .. k0+N
     DevBuf<char> ckpt, seg, lam;
-    DevBuf<double> cm, gacc, obs;
+    DevBuf<double> cm, gacc, obs, win;
+    DevBuf<uint64_t> kseg;
+    hipGraphExec_t seg_graph = nullptr;   // recompute + reverse of one full segment
+    int seg_graph_li = -1;                // adjoint buffer parity it was captured for
+    ~AdjState() {
+        if (seg_graph) (void)hipGraphExecDestroy(seg_graph);
+    }
 };
 
 static void adjoint_release(xyl_lattice* h) {
@@ -264,9 +276,9 @@ static void adjoint_release(xyl_lattice* h) {
 }
 
 static void destroy_graph(xyl_lattice* h) {
-    if (h->graph) (void)hipGraphExecDestroy(h->graph);
-    h->graph = nullptr;
-    h->graph_n = 0;
+    for (auto& g : h->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
 }
 
 template <typename R>
@@ -275,14 +287,14 @@ static void lattice_launch_one(xyl_lattice* h, int mode) {
     launch_step<R>(v, mode, h->launch, nullptr, h->k, h->stream);
 }
 
+// Captures S consecutive steps whose step index comes from the device counter
+// (node j runs step *kdev + j), followed by a node that advances the counter.
 template <typename R>
-static void build_graph(xyl_lattice* h, int S) {
-    destroy_graph(h);
-    Lat<R> v = h->view<R>();
+static hipGraphExec_t capture_steps(xyl_lattice* h, const Lat<R>& v, int mode, int S) {
     hipGraph_t g = nullptr;
     check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        for (int j = 0; j < S; ++j) launch_step<R>(v, kStore, h->launch, h->kdev.p, (uint64_t)j, h->cap_stream);
+        for (int j = 0; j < S; ++j) launch_step<R>(v, mode, h->launch, h->kdev.p, (uint64_t)j, h->cap_stream);
         launch_bump(h->kdev.p, (uint64_t)S, h->cap_stream);
     } catch (...) {
         (void)hipStreamEndCapture(h->cap_stream, &g);
@@ -294,31 +306,65 @@ static void build_graph(xyl_lattice* h, int S) {
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     check_hip(e, "hipGraphInstantiate");
-    h->graph = ex;
-    h->graph_n = S;
-    h->graph_version = h->version;
+    return ex;
 }
 
+// Advances n steps in the given mode.  With part_stride > 0 every step writes
+// its measurement partials to part + (k - part_k0) * part_stride.
 template <typename R>
-static void lattice_steps(xyl_lattice* h, uint64_t n) {
+static void lattice_steps_mode(xyl_lattice* h, uint64_t n, int mode, double* part, uint64_t part_k0,
+                               uint64_t part_stride) {
+    Lat<R> v = h->view<R>();
+    if (part_stride) {
+        v.part = part;
+        v.part_k0 = part_k0;
+        v.part_stride = part_stride;
+    }
     while (n > 0) {
         const int S = h->graph_steps;
         if (S > 1 && n >= (uint64_t)S) {
-            if (!h->graph || h->graph_n != S || h->graph_version != h->version) build_graph<R>(h, S);
+            xyl_lattice::GraphEntry* ge = nullptr;
+            for (auto& g : h->graphs)
+                if (g.mode == mode && g.S == S && g.part == v.part && g.part_k0 == v.part_k0 &&
+                    g.part_stride == v.part_stride)
+                    ge = &g;
+            if (ge && ge->version != h->version) {
+                (void)hipGraphExecDestroy(ge->exec);
+                ge->exec = nullptr;
+            }
+            if (!ge) {
+                if (h->graphs.size() >= 8) destroy_graph(h);   // bound the cache
+                h->graphs.push_back(xyl_lattice::GraphEntry());
+                ge = &h->graphs.back();
+                ge->mode = mode;
+                ge->S = S;
+                ge->part = v.part;
+                ge->part_k0 = v.part_k0;
+                ge->part_stride = v.part_stride;
+            }
+            if (!ge->exec) {
+                ge->exec = capture_steps<R>(h, v, mode, S);
+                ge->version = h->version;
+            }
             if (!h->counter_valid) {
                 launch_set_counter(h->kdev.p, h->k, h->stream);
                 h->counter_valid = true;
             }
-            check_hip(hipGraphLaunch(h->graph, h->stream), "hipGraphLaunch");
+            check_hip(hipGraphLaunch(ge->exec, h->stream), "hipGraphLaunch");
             h->k += (uint64_t)S;
             n -= (uint64_t)S;
         } else {
-            lattice_launch_one<R>(h, kStore);
+            launch_step<R>(v, mode, h->launch, nullptr, h->k, h->stream);
             h->k += 1;
             h->counter_valid = false;
             n -= 1;
         }
     }
+}
+
+template <typename R>
+static void lattice_steps(xyl_lattice* h, uint64_t n) {
+    lattice_steps_mode<R>(h, n, kStore, nullptr, 0, 0);
 }
 
 template <typename R>
@@ -973,6 +1019,8 @@ struct xyl_ensemble {
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
         v.pingpong = 1;
         v.u_out = nullptr;
+        v.part_k0 = 0;
+        v.part_stride = 0;
         return v;
     }
     void* cur_theta(int r) {
@@ -1295,24 +1343,39 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
     a->ckpt.reserve(S * 2 * bytes);
     a->obs.reserve(6 * W);
     const uint64_t kw = a->k0 + N - W + 1;   // first step of the loss window
+    // the window's measurement partials, one block per step, reduced together
+    // at the end (falls back to one reduction per step for huge lattices)
+    const uint64_t stride = (uint64_t)h->nrowparts() * kNPart;
+    const bool batched = (double)W * (double)stride * 8.0 <= 1.0e9;
+    if (batched) a->win.reserve(W * stride);
     for (uint64_t s = 0; s < S; ++s) {
         char* slot = a->ckpt.p + s * 2 * bytes;
         check_hip(hipMemcpyAsync(slot, h->cur_theta(), bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
         check_hip(hipMemcpyAsync(slot + bytes, h->u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
-        const uint64_t len = std::min<uint64_t>(K, N - s * K);
-        uint64_t j = 0;
-        while (j < len) {
+        const uint64_t kend = a->k0 + std::min<uint64_t>((s + 1) * K, N);
+        while (h->k < kend) {
             if (h->k >= kw) {
-                lattice_measure_into<R>(h, true, a->obs.p + 6 * (h->k - kw));
-                ++j;
+                if (batched) {
+                    lattice_steps_mode<R>(h, kend - h->k, kStore | kMeasure, a->win.p, kw, stride);
+                } else {
+                    lattice_measure_into<R>(h, true, a->obs.p + 6 * (h->k - kw));
+                }
             } else {
-                const uint64_t run = std::min<uint64_t>(len - j, kw - h->k);
-                lattice_steps<R>(h, run);
-                j += run;
+                lattice_steps<R>(h, std::min(kend, kw) - h->k);
             }
         }
     }
-    lattice_measure_into<R>(h, false, a->obs.p + 6 * (W - 1));
+    if (batched) {
+        // the last sample (step k0 + N) is a measurement without a step
+        Lat<R> v = h->view<R>();
+        v.part = a->win.p;
+        v.part_k0 = kw;
+        v.part_stride = stride;
+        launch_step<R>(v, kMeasure, h->launch, nullptr, h->k, h->stream);
+        launch_finalize_many(a->win.p, h->nrowparts(), stride, (double)h->N, a->obs.p, (int)W, h->stream);
+    } else {
+        lattice_measure_into<R>(h, false, a->obs.p + 6 * (W - 1));
+    }
     std::vector<double> o(6 * W);
     check_hip(hipMemcpyAsync(o.data(), a->obs.p, sizeof(double) * 6 * W, hipMemcpyDeviceToHost, h->stream), "D2H");
     check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -1352,26 +1415,64 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, double* dth0, do
     a->seg.reserve((K + 1) * 2 * bytes);
     auto slot_th = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes); };
     auto slot_u = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes + bytes); };
+    a->kseg.reserve(1);
+    auto recompute_node = [&](uint64_t j, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
+        Lat<R> w = v;
+        w.pingpong = 0;
+        w.th[0] = slot_th(j);
+        w.th[1] = slot_th(j + 1);
+        w.u = slot_u(j);
+        w.u_out = slot_u(j + 1);
+        launch_step<R>(w, kStore, h->launch, kdev, kj, st);
+    };
+    auto reverse_node = [&](uint64_t j, int parity, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
+        launch_adjoint_step<R>(v, slot_th(j), slot_u(j), lt[parity], lu[parity], lt[parity ^ 1], lu[parity ^ 1],
+                               a->cm.p, k0, a->gacc.p, kdev, kj, l, st);
+    };
+    // Full segments of even length replay one captured graph (K recompute
+    // steps into the slots, then K reverse steps) whose step indices come
+    // from a device counter set to the segment's first step.
+    const bool use_graph = h->graph_steps > 1 && K % 2 == 0 && K <= 4096;
     for (uint64_t s = S; s-- > 0;) {
         const uint64_t ks = k0 + s * K;
         const uint64_t len = std::min<uint64_t>(K, k0 + N - ks);
         const char* ck = a->ckpt.p + s * 2 * bytes;
         check_hip(hipMemcpyAsync(slot_th(0), ck, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
         check_hip(hipMemcpyAsync(slot_u(0), ck + bytes, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
-        // recompute the segment's states, each into its own slot
-        for (uint64_t j = 0; j < len; ++j) {
-            Lat<R> w = v;
-            w.pingpong = 0;
-            w.th[0] = slot_th(j);
-            w.th[1] = slot_th(j + 1);
-            w.u = slot_u(j);
-            w.u_out = slot_u(j + 1);
-            launch_step<R>(w, kStore, h->launch, nullptr, ks + j, h->stream);
-        }
-        for (uint64_t j = len; j-- > 0;) {
-            launch_adjoint_step<R>(v, slot_th(j), slot_u(j), lt[li], lu[li], lt[li ^ 1], lu[li ^ 1], a->cm.p, k0,
-                                   a->gacc.p, nullptr, ks + j, l, h->stream);
-            li ^= 1;
+        if (use_graph && len == K) {
+            if (!a->seg_graph || a->seg_graph_li != li) {
+                if (a->seg_graph) (void)hipGraphExecDestroy(a->seg_graph);
+                a->seg_graph = nullptr;
+                hipGraph_t gr = nullptr;
+                check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal),
+                          "hipStreamBeginCapture");
+                try {
+                    for (uint64_t j = 0; j < K; ++j) recompute_node(j, a->kseg.p, j, h->cap_stream);
+                    int p = li;
+                    for (uint64_t j = K; j-- > 0;) {
+                        reverse_node(j, p, a->kseg.p, j, h->cap_stream);
+                        p ^= 1;
+                    }
+                } catch (...) {
+                    (void)hipStreamEndCapture(h->cap_stream, &gr);
+                    if (gr) (void)hipGraphDestroy(gr);
+                    throw;
+                }
+                check_hip(hipStreamEndCapture(h->cap_stream, &gr), "hipStreamEndCapture");
+                hipError_t e = hipGraphInstantiate(&a->seg_graph, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                check_hip(e, "hipGraphInstantiate");
+                a->seg_graph_li = li;
+            }
+            launch_set_counter(a->kseg.p, ks, h->stream);
+            check_hip(hipGraphLaunch(a->seg_graph, h->stream), "hipGraphLaunch");
+            // K even: the adjoint state ends in the buffer it started from
+        } else {
+            for (uint64_t j = 0; j < len; ++j) recompute_node(j, nullptr, ks + j, h->stream);
+            for (uint64_t j = len; j-- > 0;) {
+                reverse_node(j, li, nullptr, ks + j, h->stream);
+                li ^= 1;
+            }
         }
     }
     std::vector<double> g((size_t)ntasks * 4);

@@ -166,7 +166,8 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                 for (int off = 32; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, kWave);
             }
             if (lane == 0) {
-                double* dst = v.part + ((size_t)y * v.nxw + xw) * kNPart;
+                double* base = v.part + (v.part_stride ? (k - v.part_k0) * v.part_stride : 0);
+                double* dst = base + ((size_t)y * v.nxw + xw) * kNPart;
 #pragma unroll
                 for (int p = 0; p < kNPart; ++p) dst[p] = acc[p];
             }
@@ -386,6 +387,18 @@ void launch_finalize_obs(const double* part, int nrowparts, double N, double* ou
         k_finalize_obs<<<1, 256, 0, s>>>(part, nrowparts, N, out);
     }
     check_hip(hipGetLastError(), "finalize kernel launch");
+}
+
+__global__ __launch_bounds__(256) void k_finalize_many(const double* part, int nrp, uint64_t stride, double N,
+                                                       double* out) {
+    finalize_block(part + (size_t)blockIdx.x * stride, nrp, N, out + 6 * (size_t)blockIdx.x);
+}
+
+void launch_finalize_many(const double* part, int nrowparts, uint64_t stride, double N, double* out, int count,
+                          hipStream_t s) {
+    if (count <= 0) return;
+    k_finalize_many<<<count, 256, 0, s>>>(part, nrowparts, stride, N, out);
+    check_hip(hipGetLastError(), "finalize-many launch");
 }
 
 struct FinalizeJob {
