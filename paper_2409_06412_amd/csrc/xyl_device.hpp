@@ -137,6 +137,42 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
     Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3]);
 }
 
+// ------------------------------------------------------ per-site BBK math
+// Shared by every kernel that advances sites, so that their states agree bit
+// for bit.  F = -dH/dth from the sine/cosine of the site and its neighbours
+// (x-1, x+1, y-1, y+1):
+//   F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [s (cy+ + cy-) - c (sy+ + sy-)] - 4 h s c
+template <typename R>
+__device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm, R sxp, R cxp, R sym, R cym, R syp,
+                                        R cyp) {
+    const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
+    const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
+    const R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
+    return Prec<R>::fma(-v.h4, s * c, f);
+}
+
+// Completes the previous step's second half-kick (w^k; skipped at the fresh
+// step, where u already holds w^k), then the next first half-kick, the drift
+// and the wrap (App. A.1, Eqs. BBK-2 and BBK-1), with the fma order the
+// oracle uses.
+template <typename R>
+__device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
+                                            R& thnew) {
+    R ww;
+    if (fresh) {
+        ww = u;
+    } else {
+        R t = Prec<R>::fma(v.hdt, f, u);
+        t = Prec<R>::fma(hs, n, t);
+        ww = v.c * t;
+    }
+    w = ww;
+    R t2 = v.hdt * f;
+    t2 = Prec<R>::fma(hs, n, t2);
+    unew = Prec<R>::fma(v.a, ww, t2);
+    thnew = wrap_angle<R>(Prec<R>::fma(v.dt, unew, th));
+}
+
 // ---------------------------------------------------- lane exchange (DPP)
 // wave_shr:1 moves a value to the next lane up, wave_shl:1 to the next lane
 // down; lanes at the ends receive `old`.

@@ -103,6 +103,17 @@ void launch_adjoint_step(const Lat<R>& v, const R* th, const R* u, const R* lt_i
 template <typename R>
 void launch_adjoint_seed(const Lat<R>& v, const R* th, R* lt, R* lu, double cmN, hipStream_t s);
 
+// Whole-replica-in-LDS stepping of small FP32 replicas.
+constexpr int kLdsMaxGroups = 4;      // Philox blocks (4 sites) per thread
+constexpr int kLdsMaxSites = 16384;   // 128 x 128: 128 KB of sine/cosine tables
+struct LdsJobHost {
+    int32_t rep, measure, nsteps, pad;
+    double* obs;
+};
+int lds_threads(int N);
+void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites,
+                         uint64_t j0, hipStream_t s);
+
 struct Error : std::runtime_error {
     int code;
     Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}

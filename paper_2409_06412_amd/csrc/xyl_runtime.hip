@@ -155,6 +155,18 @@ static size_t elem_size(int dtype) { return dtype == XYL_F64 ? sizeof(double) : 
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Launch> g_tuned;
 
+// Launch shape before any autotuning: enough waves to occupy every SIMD of
+// the 256 CUs (strips of up to 16 rows while there are >= 4096 wave-rows,
+// down to single-row strips and one-wave workgroups for small lattices).
+static Launch default_launch(int Lx, int Ly) {
+    const long wave_rows = (long)Ly * ((Lx + kWaveSites - 1) / kWaveSites);
+    Launch l;
+    l.rows = (int)std::max<long>(1, std::min<long>(16, wave_rows / 4096));
+    const long waves = wave_rows / l.rows;
+    l.wpb = waves >= 8192 ? 4 : (waves >= 2048 ? 2 : 1);
+    return l;
+}
+
 static void validate_launch(const Launch& l) {
     require(l.rows >= 1, XYL_EINVAL, "rows per strip must be >= 1");
     require(l.wpb == 1 || l.wpb == 2 || l.wpb == 4 || l.wpb == 8, XYL_EINVAL, "waves per block must be 1, 2, 4 or 8");
@@ -515,6 +527,7 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
         h->kdev.reserve(1);
         h->part.reserve(part_elems(h->nrowparts()));
         h->obs.reserve(16 * 6);
+        h->launch = default_launch(Lx, Ly);
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find({Lx, Ly, dtype});
@@ -993,6 +1006,14 @@ struct xyl_ensemble {
     DevBuf<char> omega_buf;
     DevBuf<int32_t> parent;
     DevBuf<uint32_t> usz, hist, stats;
+    // small FP32 replicas stepped whole-in-LDS on a second stream
+    std::vector<char> lds;          // per replica: 1 = LDS path
+    int lds_max_sites = 0, lds_threads = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    DevBuf<char> lds_reps;
+    DevBuf<LdsJobHost> lds_jobs;
+    std::vector<LdsJobHost> lds_jobs_host;
 
     template <typename R>
     Lat<R> view(int r, uint64_t jbase) {
@@ -1053,115 +1074,193 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
     e->task_active = active;
 }
 
-template <typename R>
-static void ens_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs* out, uint64_t cap, uint64_t* nout) {
-    // samples are gathered in device memory and copied out at the end
-    std::vector<std::pair<int, uint64_t>> sample_slots;   // (replica, slot index)
-    std::vector<uint64_t> cnt(e->n, 0);
-    if (every && nout)
-        for (int r = 0; r < e->n; ++r) cnt[r] = nout[r];
-    size_t nsamp_dev = 0;
-    std::vector<std::pair<size_t, size_t>> copies;   // (device sample index, host index)
-    auto want_sample = [&](int r) {
-        return every && e->k[r] <= e->desc[r].nsteps && e->k[r] % every == 0 && e->last_sample[r] != e->k[r] + 1;
-    };
-    std::vector<FinalizeJobHost> jobs;
-    auto flush_jobs = [&]() {
-        if (jobs.empty()) return;
-        e->jobs.reserve(jobs.size());
-        check_hip(hipMemcpyAsync(e->jobs.p, jobs.data(), sizeof(FinalizeJobHost) * jobs.size(), hipMemcpyHostToDevice,
-                                 e->stream),
-                  "H2D");
-        launch_finalize_jobs(e->jobs.p, (int)jobs.size(), e->stream);
-        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-        jobs.clear();
-    };
-    auto reserve_obs = [&](size_t need) {
-        if (need * 6 > e->obs.n) {
-            // grow: keep what was gathered so far
-            DevBuf<double> nb;
-            nb.reserve(std::max(need * 6, e->obs.n * 2));
-            if (e->obs.p && nsamp_dev)
-                check_hip(hipMemcpyAsync(nb.p, e->obs.p, sizeof(double) * 6 * nsamp_dev, hipMemcpyDeviceToDevice,
-                                         e->stream),
-                          "D2D");
-            check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-            std::swap(e->obs.p, nb.p);
-            std::swap(e->obs.n, nb.n);
-        }
-    };
-    for (uint64_t it = 0; it <= nsteps; ++it) {
-        std::vector<int> active, measuring;
-        for (int r = 0; r < e->n; ++r) {
-            if (want_sample(r)) measuring.push_back(r);
-            if (it < nsteps && e->k[r] < e->desc[r].nsteps) active.push_back(r);
-        }
-        if (it == nsteps && measuring.empty()) break;
-        if (active.empty() && measuring.empty()) break;
-        for (int r : measuring) {
-            require(cnt[r] < cap, XYL_EINVAL, "ensemble sample capacity too small");
-        }
-        reserve_obs(nsamp_dev + measuring.size());
-        if (e->mode == 0) {
-            // one launch for every replica: advancing ones in store mode (plus
-            // measurement when any replica samples), sampling-only ones measured
-            std::vector<int> set = active;
-            for (int r : measuring)
-                if (std::find(active.begin(), active.end(), r) == active.end()) set.push_back(r);
-            std::sort(set.begin(), set.end());
-            if (set != e->task_active) ens_upload_table<R>(e, e->j, set);
-            const bool meas = !measuring.empty();
-            // replicas that only measure (finished) must not store: give them
-            // their own launch in measure-only mode
-            std::vector<int> only_meas;
-            for (int r : measuring)
-                if (std::find(active.begin(), active.end(), r) == active.end()) only_meas.push_back(r);
-            if (only_meas.empty()) {
-                if (!set.empty())
-                    launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(e->reps.p), e->tasks.p, e->ntasks,
-                                            meas ? (kStore | kMeasure) : kStore, e->launch.rows, e->launch.wpb, nullptr,
-                                            e->j, e->stream);
-            } else {
-                for (int r : set) {
-                    Lat<R> v = e->view<R>(r, e->j);
-                    const bool adv = std::find(active.begin(), active.end(), r) != active.end();
-                    const bool m = std::find(measuring.begin(), measuring.end(), r) != measuring.end();
-                    const int mode = (adv ? kStore : 0) | (m ? kMeasure : 0);
-                    launch_step<R>(v, mode, e->launch, nullptr, e->j, e->stream);
-                }
-            }
-        } else {
-            for (int r = 0; r < e->n; ++r) {
-                const bool adv = std::find(active.begin(), active.end(), r) != active.end();
-                const bool m = std::find(measuring.begin(), measuring.end(), r) != measuring.end();
-                if (!adv && !m) continue;
-                Lat<R> v = e->view<R>(r, e->j);
-                launch_step<R>(v, (adv ? kStore : 0) | (m ? kMeasure : 0), e->launch, nullptr, e->j, e->stream);
-            }
-        }
-        for (int r : measuring) {
-            const size_t slot = nsamp_dev++;
-            jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
-                                           (double)e->desc[r].Lx * (double)e->desc[r].Ly, e->obs.p + 6 * slot});
-            copies.push_back({slot, (size_t)r * cap + cnt[r]});
-            cnt[r] += 1;
-            e->last_sample[r] = e->k[r] + 1;
-        }
-        flush_jobs();
-        for (int r : active) e->k[r] += 1;
-        if (!active.empty()) e->j += 1;
-        if (it == nsteps) break;
+// Sample bookkeeping of one xyl_ensemble_step call: observables gathered in
+// device memory (slots), copied out at the end.
+struct EnsSamples {
+    xyl_ensemble* e;
+    uint64_t every, cap;
+    std::vector<uint64_t> cnt;
+    size_t nsamp = 0;
+    std::vector<std::pair<size_t, size_t>> copies;   // (device slot, host index)
+    EnsSamples(xyl_ensemble* e_, uint64_t every_, uint64_t cap_, const uint64_t* nout)
+        : e(e_), every(every_), cap(cap_), cnt(e_->n, 0) {
+        if (every && nout)
+            for (int r = 0; r < e->n; ++r) cnt[r] = nout[r];
     }
-    if (every) {
-        std::vector<double> host(6 * nsamp_dev);
-        if (nsamp_dev)
-            check_hip(hipMemcpyAsync(host.data(), e->obs.p, sizeof(double) * 6 * nsamp_dev, hipMemcpyDeviceToHost,
+    bool wants(int r) const {
+        return every && e->k[r] <= e->desc[r].nsteps && e->k[r] % every == 0 && e->last_sample[r] != e->k[r] + 1;
+    }
+    void reserve(size_t extra) {
+        const size_t need = nsamp + extra;
+        if (need * 6 <= e->obs.n) return;
+        // the side stream may still be writing samples into the old buffer
+        if (e->side) check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
+        DevBuf<double> nb;
+        nb.reserve(std::max(need * 6, e->obs.n * 2));
+        if (e->obs.p && nsamp)
+            check_hip(hipMemcpyAsync(nb.p, e->obs.p, sizeof(double) * 6 * nsamp, hipMemcpyDeviceToDevice, e->stream),
+                      "D2D");
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+        std::swap(e->obs.p, nb.p);
+        std::swap(e->obs.n, nb.n);
+    }
+    double* take(int r) {   // device slot of replica r's next sample
+        require(cnt[r] < cap, XYL_EINVAL, "ensemble sample capacity too small");
+        const size_t slot = nsamp++;
+        copies.push_back({slot, (size_t)r * cap + cnt[r]});
+        cnt[r] += 1;
+        e->last_sample[r] = e->k[r] + 1;
+        return e->obs.p + 6 * slot;
+    }
+    void finish(xyl_obs* out, uint64_t* nout) {
+        if (!every) return;
+        std::vector<double> host(6 * nsamp);
+        if (nsamp)
+            check_hip(hipMemcpyAsync(host.data(), e->obs.p, sizeof(double) * 6 * nsamp, hipMemcpyDeviceToHost,
                                      e->stream),
                       "D2H");
         check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
         for (auto& c : copies) std::memcpy(&out[c.second], &host[6 * c.first], sizeof(double) * 6);
         if (nout)
             for (int r = 0; r < e->n; ++r) nout[r] = cnt[r];
+    }
+};
+
+static void flush_finalize(xyl_ensemble* e, std::vector<FinalizeJobHost>& jobs) {
+    if (jobs.empty()) return;
+    e->jobs.reserve(jobs.size());
+    check_hip(hipMemcpyAsync(e->jobs.p, jobs.data(), sizeof(FinalizeJobHost) * jobs.size(), hipMemcpyHostToDevice,
+                             e->stream),
+              "H2D");
+    launch_finalize_jobs(e->jobs.p, (int)jobs.size(), e->stream);
+    check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    jobs.clear();
+}
+
+// Reference loop: every replica launched on its own, one step at a time.
+template <typename R>
+static void ens_step_per_replica(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) {
+    std::vector<FinalizeJobHost> jobs;
+    for (uint64_t it = 0; it <= nsteps; ++it) {
+        std::vector<int> active, measuring;
+        for (int r = 0; r < e->n; ++r) {
+            if (smp.wants(r)) measuring.push_back(r);
+            if (it < nsteps && e->k[r] < e->desc[r].nsteps) active.push_back(r);
+        }
+        if (active.empty() && measuring.empty()) break;
+        smp.reserve(measuring.size());
+        for (int r = 0; r < e->n; ++r) {
+            const bool adv = std::find(active.begin(), active.end(), r) != active.end();
+            const bool m = std::find(measuring.begin(), measuring.end(), r) != measuring.end();
+            if (!adv && !m) continue;
+            Lat<R> v = e->view<R>(r, e->j);
+            launch_step<R>(v, (adv ? kStore : 0) | (m ? kMeasure : 0), e->launch, nullptr, e->j, e->stream);
+            if (m)
+                jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
+                                               (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
+        }
+        flush_finalize(e, jobs);
+        for (int r : active) e->k[r] += 1;
+        if (!active.empty()) e->j += 1;
+    }
+}
+
+// Batched loop: the steps every active replica takes before the next sample
+// or end of any of them form a chunk; large replicas advance through one
+// tile-table launch per step, small FP32 replicas through one whole-in-LDS
+// launch per chunk on a second stream.
+template <typename R>
+static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) {
+    std::vector<FinalizeJobHost> jobs;
+    const bool have_lds = std::any_of(e->lds.begin(), e->lds.end(), [](char c) { return c != 0; });
+    if (have_lds) {
+        check_hip(hipEventRecord(e->ev_main, e->stream), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(e->side, e->ev_main, 0), "hipStreamWaitEvent");
+    }
+    uint64_t it = 0;
+    while (true) {
+        std::vector<int> active_g, meas_g, only_meas_g, lds_set;
+        std::vector<char> meas(e->n, 0), act(e->n, 0);
+        bool any = false;
+        for (int r = 0; r < e->n; ++r) {
+            meas[r] = smp.wants(r);
+            act[r] = it < nsteps && e->k[r] < e->desc[r].nsteps;
+            if (!meas[r] && !act[r]) continue;
+            any = true;
+            if (e->lds[r]) {
+                lds_set.push_back(r);
+            } else if (act[r]) {
+                active_g.push_back(r);
+                if (meas[r]) meas_g.push_back(r);
+            } else {
+                only_meas_g.push_back(r);
+            }
+        }
+        if (!any) break;
+        uint64_t chunk = 0;
+        bool any_active = false;
+        for (int r = 0; r < e->n; ++r) {
+            if (!act[r]) continue;
+            uint64_t c = std::min<uint64_t>(nsteps - it, e->desc[r].nsteps - e->k[r]);
+            if (smp.every) c = std::min<uint64_t>(c, smp.every - e->k[r] % smp.every);
+            chunk = any_active ? std::min(chunk, c) : c;
+            any_active = true;
+        }
+        size_t nmeas = 0;
+        for (int r = 0; r < e->n; ++r) nmeas += meas[r];
+        smp.reserve(nmeas);
+        // small replicas: one launch for the whole chunk
+        if (!lds_set.empty()) {
+            e->lds_jobs_host.clear();
+            for (int r : lds_set)
+                e->lds_jobs_host.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
+                                                      meas[r] ? smp.take(r) : nullptr});
+            e->lds_jobs.reserve(e->lds_jobs_host.size());
+            // the previous chunk's launch must have read its job table before it is rewritten
+            check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
+            check_hip(hipMemcpyAsync(e->lds_jobs.p, e->lds_jobs_host.data(), sizeof(LdsJobHost) * lds_set.size(),
+                                     hipMemcpyHostToDevice, e->side),
+                      "H2D");
+            std::vector<Lat<float>> tab(e->n);
+            for (int r = 0; r < e->n; ++r) tab[r] = e->view<float>(r, e->j);
+            e->lds_reps.reserve(sizeof(Lat<float>) * e->n);
+            check_hip(hipMemcpyAsync(e->lds_reps.p, tab.data(), sizeof(Lat<float>) * e->n, hipMemcpyHostToDevice,
+                                     e->side),
+                      "H2D");
+            check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
+            launch_ensemble_lds(reinterpret_cast<const Lat<float>*>(e->lds_reps.p), e->lds_jobs.p,
+                                (int)lds_set.size(), e->lds_threads, e->lds_max_sites, e->j, e->side);
+        }
+        // large replicas
+        if (!active_g.empty()) {
+            if (active_g != e->task_active) ens_upload_table<R>(e, e->j, active_g);
+            const Lat<R>* reps = reinterpret_cast<const Lat<R>*>(e->reps.p);
+            launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, meas_g.empty() ? kStore : (kStore | kMeasure),
+                                    e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
+            for (int r : meas_g)
+                jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
+                                               (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
+            flush_finalize(e, jobs);
+            for (uint64_t c = 1; c < chunk; ++c)
+                launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->launch.rows, e->launch.wpb, nullptr,
+                                        e->j + c, e->stream);
+        }
+        for (int r : only_meas_g) {
+            Lat<R> v = e->view<R>(r, e->j);
+            launch_step<R>(v, kMeasure, e->launch, nullptr, e->j, e->stream);
+            jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
+                                           (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
+        }
+        flush_finalize(e, jobs);
+        if (!any_active) break;
+        for (int r = 0; r < e->n; ++r)
+            if (act[r]) e->k[r] += chunk;
+        e->j += chunk;
+        it += chunk;
+    }
+    if (have_lds) {
+        check_hip(hipEventRecord(e->ev_side, e->side), "hipEventRecord");
+        check_hip(hipStreamWaitEvent(e->stream, e->ev_side, 0), "hipStreamWaitEvent");
     }
 }
 
@@ -1195,6 +1294,20 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
         for (int b = 0; b < 2; ++b) check_alloc(hipMalloc(&e->th[b], bytes), "hipMalloc theta");
         check_alloc(hipMalloc(&e->u, bytes), "hipMalloc velocity");
         e->part.reserve(e->ptotal);
+        e->lds.assign(n, 0);
+        for (int r = 0; r < n; ++r) {
+            const int N = desc[r].Lx * desc[r].Ly;
+            if (dtype == XYL_F32 && N <= kLdsMaxSites) {
+                e->lds[r] = 1;
+                e->lds_max_sites = std::max(e->lds_max_sites, N);
+            }
+        }
+        if (e->lds_max_sites) {
+            e->lds_threads = lds_threads(e->lds_max_sites);
+            check_hip(hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking), "hipStreamCreate");
+            check_hip(hipEventCreateWithFlags(&e->ev_main, hipEventDisableTiming), "hipEventCreate");
+            check_hip(hipEventCreateWithFlags(&e->ev_side, hipEventDisableTiming), "hipEventCreate");
+        }
         e->k.assign(n, 0);
         e->fresh_k.assign(n, 0);
         e->last_sample.assign(n, 0);
@@ -1212,9 +1325,13 @@ int xyl_ensemble_destroy(xyl_ensemble* e) {
     return guarded([&] {
         DeviceGuard g(e->device);
         (void)hipStreamSynchronize(e->stream);
+        if (e->side) (void)hipStreamSynchronize(e->side);
         for (int b = 0; b < 2; ++b)
             if (e->th[b]) (void)hipFree(e->th[b]);
         if (e->u) (void)hipFree(e->u);
+        if (e->side) (void)hipStreamDestroy(e->side);
+        if (e->ev_main) (void)hipEventDestroy(e->ev_main);
+        if (e->ev_side) (void)hipEventDestroy(e->ev_side);
         delete e;
     });
 }
@@ -1239,8 +1356,15 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
         require(e != nullptr, XYL_EINVAL, "NULL handle");
         if (every) require(out != nullptr && nout != nullptr, XYL_EINVAL, "out/nout are NULL");
         DeviceGuard g(e->device);
-        if (e->dtype == XYL_F64) ens_step<double>(e, nsteps, every, out, cap, nout);
-        else ens_step<float>(e, nsteps, every, out, cap, nout);
+        EnsSamples smp(e, every, cap, nout);
+        if (e->mode == 1) {
+            if (e->dtype == XYL_F64) ens_step_per_replica<double>(e, nsteps, smp);
+            else ens_step_per_replica<float>(e, nsteps, smp);
+        } else {
+            if (e->dtype == XYL_F64) ens_step_batched<double>(e, nsteps, smp);
+            else ens_step_batched<float>(e, nsteps, smp);
+        }
+        smp.finish(out, nout);
     });
 }
 

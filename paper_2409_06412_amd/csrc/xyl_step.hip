@@ -102,25 +102,8 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            // F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [...] - 4 h s c  (= -dH/dth)
-            const R fx = Prec<R>::fma(C.s[q], cxp + cxm, -(C.c[q] * (sxp + sxm)));
-            const R fy = Prec<R>::fma(C.s[q], N.c[q] + P.c[q], -(C.c[q] * (N.s[q] + P.s[q])));
-            R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
-            f = Prec<R>::fma(-v.h4, C.s[q] * C.c[q], f);
-            R ww;
-            if (fresh) {
-                ww = C.u[q];
-            } else {
-                R t = Prec<R>::fma(v.hdt, f, C.u[q]);
-                t = Prec<R>::fma(hs, n[q], t);
-                ww = v.c * t;
-            }
-            w[q] = ww;
-            R t2 = v.hdt * f;
-            t2 = Prec<R>::fma(hs, n[q], t2);
-            const R unew = Prec<R>::fma(v.a, ww, t2);
-            uo4[q] = unew;
-            tho4[q] = wrap_angle<R>(Prec<R>::fma(v.dt, unew, C.th[q]));
+            const R f = site_force<R>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q]);
+            site_update<R>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
         }
         if ((MODE & kStore) && act) {
             store4(tho + row + x, tho4);
@@ -260,6 +243,213 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
         default: throw Error(-5, "unsupported step mode");
     }
     check_hip(hipGetLastError(), "ensemble step kernel launch");
+}
+
+// -------------------------------------------- whole replica in LDS (FP32)
+// Small replicas of an ensemble: one workgroup holds the sine/cosine tables
+// of a whole lattice in LDS (8 B per site, 128 KB at 128 x 128) and its
+// angles and velocities in registers (up to 4 Philox blocks of 4 sites per
+// thread), and advances it several steps per launch with two barriers per
+// step and no HBM traffic between steps.  Per-site arithmetic is the shared
+// site_force / site_update / noise4, so states equal those of the strip
+// kernel bit for bit.
+struct LdsJob {
+    int32_t rep;        // replica index in the table
+    int32_t measure;    // 1: record observables at the launch's first step
+    int32_t nsteps;     // steps to advance (0: measure only)
+    int32_t pad;
+    double* obs;        // 6 doubles
+};
+
+__global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restrict__ reps,
+                                                       const LdsJob* __restrict__ jobs, uint64_t j0) {
+    extern __shared__ float lds[];
+    __shared__ double red[16][kNPart];
+    const LdsJob job = jobs[blockIdx.x];
+    const Lat<float>& v = reps[job.rep];
+    const int Lx = v.Lx, Ly = v.Ly;
+    const int N = Lx * Ly, ng = N >> 2;
+    float* S = lds;
+    float* C = lds + N;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint64_t k0 = v.k_base + j0;
+    float th[kLdsMaxGroups][4], u[kLdsMaxGroups][4];
+    {
+        const float* t0 = v.th[(int)((k0 + (uint64_t)v.cur) & 1)];
+#pragma unroll
+        for (int q = 0; q < kLdsMaxGroups; ++q) {
+            const int g = tid + q * nt;
+            if (g < ng) {
+                load4(t0 + 4 * g, th[q]);
+                load4(v.u + 4 * g, u[q]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) th[q][e] = u[q][e] = 0.f;
+            }
+        }
+    }
+    auto tables = [&]() {
+#pragma unroll
+        for (int q = 0; q < kLdsMaxGroups; ++q) {
+            const int g = tid + q * nt;
+            if (g < ng) {
+                float s4[4], c4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Prec<float>::sincos(th[q][e], s4[e], c4[e]);
+                store4(S + 4 * g, s4);
+                store4(C + 4 * g, c4);
+            }
+        }
+    };
+    // neighbours of group g from the tables; returns the force of its 4 sites
+    auto forces = [&](int g, float f[4], float s4[4], float c4[4], float& sR, float& cR, float sd[4],
+                      float cd[4]) {
+        const int i0 = 4 * g;
+        const int y = i0 / Lx, x = i0 - y * Lx;
+        const int ym = y == 0 ? Ly - 1 : y - 1, yp = y + 1 == Ly ? 0 : y + 1;
+        float su[4], cu[4];
+        load4(S + i0, s4);
+        load4(C + i0, c4);
+        load4(S + ym * Lx + x, su);
+        load4(C + ym * Lx + x, cu);
+        load4(S + yp * Lx + x, sd);
+        load4(C + yp * Lx + x, cd);
+        const int il = y * Lx + (x == 0 ? Lx - 1 : x - 1);
+        const int ir = y * Lx + (x + 4 == Lx ? 0 : x + 4);
+        const float sL = S[il], cL = C[il];
+        sR = S[ir];
+        cR = C[ir];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float sxm = e == 0 ? sL : s4[e - 1], cxm = e == 0 ? cL : c4[e - 1];
+            const float sxp = e == 3 ? sR : s4[e + 1], cxp = e == 3 ? cR : c4[e + 1];
+            f[e] = site_force<float>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e]);
+        }
+    };
+
+    tables();
+    __syncthreads();
+    if (job.measure) {
+        // observables of the synchronized state at k0 (same sums as the strip kernel)
+        const float hs = (float)half_sigma(v.sched, v.gamma, v.dtd, k0);
+        const bool fresh = (k0 == v.fresh_k);
+        double acc[kNPart];
+#pragma unroll
+        for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kLdsMaxGroups; ++q) {
+            const int g = tid + q * nt;
+            if (g < ng) {
+                float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
+                forces(g, f, s4, c4, sR, cR, sd, cd);
+                noise4<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, n);
+                const int i0 = 4 * g;
+                const int y = i0 / Lx, x = i0 - y * Lx;
+                double rps, rpc;
+                sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float w, un, tn;
+                    site_update<float>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, un, tn);
+                    const double sv = (double)s4[e], cv = (double)c4[e];
+                    const double sxp = (double)(e == 3 ? sR : s4[e + 1]);
+                    const double cxp = (double)(e == 3 ? cR : c4[e + 1]);
+                    acc[0] += v.Jxd * (cv * cxp + sv * sxp) + v.Jyd * (cv * (double)cd[e] + sv * (double)sd[e]) -
+                              v.hd * (cv * cv - sv * sv);
+                    acc[1] += 0.5 * (double)w * (double)w;
+                    const int xs = x + e;
+                    const double ep = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
+                    const double ec = ep * cv, es = ep * sv;
+                    acc[2] += ec;
+                    acc[3] += es;
+                    double pxs, pxc;
+                    sincospi(2.0 * (double)xs / (double)Lx, &pxs, &pxc);
+                    acc[4] += ec * pxc;
+                    acc[5] -= ec * pxs;
+                    acc[6] += es * pxc;
+                    acc[7] -= es * pxs;
+                    acc[8] += ec * rpc;
+                    acc[9] -= ec * rps;
+                    acc[10] += es * rpc;
+                    acc[11] -= es * rps;
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kNPart; ++p)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, kWave);
+        if ((tid & (kWave - 1)) == 0)
+            for (int p = 0; p < kNPart; ++p) red[tid / kWave][p] = acc[p];
+        __syncthreads();
+        if (tid == 0) {
+            double P[kNPart];
+            for (int p = 0; p < kNPart; ++p) {
+                P[p] = 0.0;
+                for (int w = 0; w < nt / kWave; ++w) P[p] += red[w][p];
+            }
+            const double Nd = (double)N;
+            job.obs[0] = P[0] / Nd;
+            job.obs[1] = P[1] / Nd;
+            job.obs[2] = P[2] / Nd;
+            job.obs[3] = (P[2] * P[2] + P[3] * P[3]) / Nd;
+            job.obs[4] = (P[4] * P[4] + P[5] * P[5] + P[6] * P[6] + P[7] * P[7]) / Nd;
+            job.obs[5] = (P[8] * P[8] + P[9] * P[9] + P[10] * P[10] + P[11] * P[11]) / Nd;
+        }
+    }
+    int done = 0;
+    for (int t = 0; t < job.nsteps; ++t) {
+        const uint64_t k = k0 + (uint64_t)t;
+        if (k >= v.k_end) break;
+        if (t > 0) {
+            tables();
+            __syncthreads();
+        }
+        const float hs = (float)half_sigma(v.sched, v.gamma, v.dtd, k);
+        const bool fresh = (k == v.fresh_k);
+#pragma unroll
+        for (int q = 0; q < kLdsMaxGroups; ++q) {
+            const int g = tid + q * nt;
+            if (g < ng) {
+                float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
+                forces(g, f, s4, c4, sR, cR, sd, cd);
+                noise4<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, n);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float w;
+                    site_update<float>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, u[q][e], th[q][e]);
+                }
+            }
+        }
+        ++done;
+        __syncthreads();   // every table read of this step precedes the next step's writes
+    }
+    float* t1 = v.th[(int)((k0 + (uint64_t)done + (uint64_t)v.cur) & 1)];
+#pragma unroll
+    for (int q = 0; q < kLdsMaxGroups; ++q) {
+        const int g = tid + q * nt;
+        if (g < ng) {
+            store4(t1 + 4 * g, th[q]);
+            store4(v.u + 4 * g, u[q]);
+        }
+    }
+}
+
+int lds_threads(int N) {
+    const int ng = N / 4;
+    int t = (ng + kLdsMaxGroups - 1) / kLdsMaxGroups;
+    t = (t + kWave - 1) / kWave * kWave;
+    return t < kWave ? kWave : t;
+}
+
+void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites,
+                         uint64_t j0, hipStream_t s) {
+    const size_t lds = 2 * sizeof(float) * (size_t)max_sites;
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble_lds),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+              "hipFuncSetAttribute");
+    k_ensemble_lds<<<njobs, threads, lds, s>>>(reps, reinterpret_cast<const LdsJob*>(jobs), j0);
+    check_hip(hipGetLastError(), "LDS ensemble kernel launch");
 }
 
 // ------------------------------------------------------------------ init

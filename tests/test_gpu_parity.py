@@ -280,18 +280,32 @@ def ensemble_specs():
             S(64, 64, schedule=((0, 0.8),), seed=3, replica=9, nsteps=0)]
 
 
-def test_ensemble_matches_single_lattices(xyl):
-    specs = ensemble_specs()
+def ensemble_specs_mixed():
+    """Small replicas (whole-in-LDS path) next to large ones (tile path)."""
+    S = workloads.LatticeSpec
+    return ensemble_specs() + [
+        S(260, 80, schedule=((0, 0.9),), seed=4, replica=11, nsteps=52),
+        S(516, 40, Jy=0.1, schedule=((0, 1.3), (20, 0.4)), seed=5, replica=12, nsteps=65),
+        S(128, 128, schedule=((0, 0.7),), seed=6, replica=13, nsteps=33)]
+
+
+@pytest.mark.parametrize("dtype,specs_fn", [("f32", "ensemble_specs"), ("f32", "ensemble_specs_mixed"),
+                                            ("f64", "ensemble_specs_mixed")])
+def test_ensemble_matches_single_lattices(xyl, dtype, specs_fn):
+    """Batched mode (tile table + whole-in-LDS launches) and the per-replica
+    reference loop give every replica exactly the state and samples it gets
+    when run alone."""
+    specs = globals()[specs_fn]()
     results = {}
     for mode in (0, 1):
-        ens = xyl.Ensemble(specs, dtype="f32")
+        ens = xyl.Ensemble(specs, dtype=dtype)
         ens.set_mode(mode)
         s1 = ens.step(25, every=10)
         s2 = ens.step(40, every=10)
         results[mode] = ([ens.get_state(r) for r in range(len(specs))], s1, s2)
         ens.close()
     for r, sp in enumerate(specs):
-        lat = xyl.Lattice(sp.Lx, sp.Ly, dtype="f32", schedule=sp.schedule, seed=sp.seed, replica=sp.replica,
+        lat = xyl.Lattice(sp.Lx, sp.Ly, dtype=dtype, schedule=sp.schedule, seed=sp.seed, replica=sp.replica,
                           **sp.params())
         lat.init_random()
         n = min(sp.nsteps, 65)
