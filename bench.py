@@ -105,6 +105,7 @@ def bench_adjoint(torch, xyl, workloads):
                       stream=torch.cuda.current_stream().cuda_stream, **spec.params())
     try:
         lat.init_random()
+        launch = lat.autotune()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat.adjoint_forward(spec.nsteps, 100, 1000)
@@ -124,7 +125,7 @@ def bench_adjoint(torch, xyl, workloads):
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     lat.close()
-    return {"L": spec.Lx, "steps": spec.nsteps, "checkpoint_every": 100, "window": 1000,
+    return {"L": spec.Lx, "steps": spec.nsteps, "checkpoint_every": 100, "window": 1000, "launch": list(launch),
             "forward_with_loss_s": t1 - t0, "backward_s": t2 - t1, "plain_forward_s": t4 - t3,
             "adjoint_over_forward": (t2 - t1) / (t1 - t0),
             "adjoint_over_plain_forward": (t2 - t1) / (t4 - t3)}

@@ -145,10 +145,17 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
 template <typename R>
 __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm, R sxp, R cxp, R sym, R cym, R syp,
                                         R cyp) {
-    const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
-    const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
-    const R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
-    return Prec<R>::fma(-v.h4, s * c, f);
+    if constexpr (sizeof(R) == 4) {
+        // FP32: grouped as s (Jx Cx + Jy Cy - 4h c) - c (Jx Sx + Jy Sy), 11 operations
+        const R P = Prec<R>::fma(-v.h4, c, Prec<R>::fma(v.Jx, cxp + cxm, v.Jy * (cyp + cym)));
+        const R Q = Prec<R>::fma(v.Jx, sxp + sxm, v.Jy * (syp + sym));
+        return Prec<R>::fma(s, P, -(c * Q));
+    } else {
+        const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
+        const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
+        const R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
+        return Prec<R>::fma(-v.h4, s * c, f);
+    }
 }
 
 // Completes the previous step's second half-kick (w^k; skipped at the fresh
@@ -158,18 +165,26 @@ __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm,
 template <typename R>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
-    R ww;
-    if (fresh) {
-        ww = u;
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the kick g = hdt F + hs n is formed once and used by both halves
+        const R g = Prec<R>::fma(v.hdt, f, hs * n);
+        const R ww = fresh ? u : v.c * (u + g);
+        w = ww;
+        unew = Prec<R>::fma(v.a, ww, g);
     } else {
-        R t = Prec<R>::fma(v.hdt, f, u);
-        t = Prec<R>::fma(hs, n, t);
-        ww = v.c * t;
+        R ww;
+        if (fresh) {
+            ww = u;
+        } else {
+            R t = Prec<R>::fma(v.hdt, f, u);
+            t = Prec<R>::fma(hs, n, t);
+            ww = v.c * t;
+        }
+        w = ww;
+        R t2 = v.hdt * f;
+        t2 = Prec<R>::fma(hs, n, t2);
+        unew = Prec<R>::fma(v.a, ww, t2);
     }
-    w = ww;
-    R t2 = v.hdt * f;
-    t2 = Prec<R>::fma(hs, n, t2);
-    unew = Prec<R>::fma(v.a, ww, t2);
     thnew = wrap_angle<R>(Prec<R>::fma(v.dt, unew, th));
 }
 
