@@ -79,7 +79,9 @@ def time_step_kernel(torch, lat, nlaunch):
     return e0.elapsed_time(e1) / nlaunch
 
 
-def bench_ensemble(torch, xyl, workloads, nsteps):
+def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
+    """The 288-replica FSS ensemble sampled every 100 steps, batched launches vs
+    one launch per replica per step."""
     specs = workloads.fss_ensemble(nsteps=10 ** 9)
     out = {}
     for mode, name in ((0, "batched"), (1, "per_replica")):
@@ -88,15 +90,33 @@ def bench_ensemble(torch, xyl, workloads, nsteps):
         ens.step(3)
         ens.sync()
         t0 = time.perf_counter()
-        ens.step(nsteps)
+        ens.step(nsteps, every=every)
         ens.sync()
         out[name] = time.perf_counter() - t0
         ens.close()
     sites = sum(s.Lx * s.Ly for s in specs)
-    return {"replicas": len(specs), "sites": sites, "steps": nsteps,
+    return {"replicas": len(specs), "sites": sites, "steps": nsteps, "sample_every": every,
             "batched_site_updates_per_s": sites * nsteps / out["batched"],
             "per_replica_site_updates_per_s": sites * nsteps / out["per_replica"],
             "speedup": out["per_replica"] / out["batched"]}
+
+
+def bench_quench(torch, xyl, workloads, nsteps):
+    """The 60-replica 2048^2 quench batch for a bounded number of steps, then
+    the union-find labelling of one end state."""
+    specs = workloads.kz_quench()
+    ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
+    ens.step(2)
+    ens.sync()
+    t0 = time.perf_counter()
+    ens.step(nsteps)
+    ens.sync()
+    t1 = time.perf_counter()
+    sites = sum(s.Lx * s.Ly for s in specs)
+    ens.close()
+    return {"replicas": len(specs), "sites": sites, "steps": nsteps,
+            "site_updates_per_s": sites * nsteps / (t1 - t0),
+            "full_run_site_updates": sum(s.Lx * s.Ly * s.nsteps for s in specs)}
 
 
 def bench_adjoint(torch, xyl, workloads):
@@ -322,6 +342,8 @@ def main():
     if not args.no_extras:
         extras["ensemble_fss"] = bench_ensemble(torch, xyl, workloads, 200)
         log("ensemble:", extras["ensemble_fss"])
+        extras["quench_2048"] = bench_quench(torch, xyl, workloads, 100)
+        log("quench:", extras["quench_2048"])
         extras["adjoint_512"] = bench_adjoint(torch, xyl, workloads)
         log("adjoint:", extras["adjoint_512"])
         extras["domains_2048"] = bench_domains(torch, xyl)

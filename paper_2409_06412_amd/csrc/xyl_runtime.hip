@@ -810,10 +810,14 @@ int xyl_get_launch(xyl_lattice* h, int32_t* rows, int32_t* wpb) {
 
 template <typename R>
 static Launch autotune_impl(xyl_lattice* h) {
-    // time candidates on scratch copies so the lattice state is untouched
+    // time candidates on scratch copies so the lattice state is untouched;
+    // each candidate runs as a captured graph of back-to-back steps, so the
+    // host's launch overhead does not mask kernel time on small lattices
     const size_t bytes = sizeof(R) * h->N;
     DevBuf<char> tmp;
     tmp.reserve(3 * bytes);
+    DevBuf<uint64_t> kc;
+    kc.reserve(1);
     Lat<R> v = h->view<R>();
     v.th[0] = reinterpret_cast<R*>(tmp.p);
     v.th[1] = reinterpret_cast<R*>(tmp.p + bytes);
@@ -822,25 +826,36 @@ static Launch autotune_impl(xyl_lattice* h) {
     check_hip(hipMemcpyAsync(v.th[1], h->cur_theta(), bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
     check_hip(hipMemcpyAsync(v.u, h->u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
     v.fresh_k = ~(uint64_t)0;
+    launch_set_counter(kc.p, 0, h->stream);
+    check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     hipEvent_t e0, e1;
     check_hip(hipEventCreate(&e0), "hipEventCreate");
     check_hip(hipEventCreate(&e1), "hipEventCreate");
-    const int rows_c[] = {4, 8, 16, 32, 64};
+    const int rows_c[] = {1, 2, 4, 8, 16, 32, 64};
     const int wpb_c[] = {1, 2, 4, 8};
-    const int reps = h->N >= (1u << 22) ? 10 : 50;
+    const int reps = h->N >= (1u << 22) ? 20 : 64;
     Launch best = h->launch;
     float best_ms = 1e30f;
     for (int r : rows_c) {
-        if (r > h->Ly && r != rows_c[0]) continue;
+        if (r > h->Ly) continue;
         for (int w : wpb_c) {
             Launch l;
             l.rows = r;
             l.wpb = w;
-            for (int i = 0; i < 2; ++i) launch_step<R>(v, kStore, l, nullptr, (uint64_t)i, h->stream);
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            for (int i = 0; i < reps; ++i) launch_step<R>(v, kStore, l, kc.p, (uint64_t)i, h->cap_stream);
+            check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+            hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            check_hip(err, "hipGraphInstantiate");
+            check_hip(hipGraphLaunch(ex, h->stream), "hipGraphLaunch");   // warm-up
             check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
-            for (int i = 0; i < reps; ++i) launch_step<R>(v, kStore, l, nullptr, (uint64_t)i, h->stream);
+            check_hip(hipGraphLaunch(ex, h->stream), "hipGraphLaunch");
             check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
             check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            (void)hipGraphExecDestroy(ex);
             float ms = 0.f;
             check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
             if (ms < best_ms) {
