@@ -151,6 +151,21 @@ def bench_adjoint(torch, xyl, workloads):
             "adjoint_over_plain_forward": (t2 - t1) / (t4 - t3)}
 
 
+def bench_control_8192(torch, xyl, workloads, nlaunch=200):
+    """Same kernel on an 8192^2 lattice (805 MB of state, larger than the
+    256 MB Infinity Cache): the HBM-resident rate."""
+    spec = workloads.large_fp32(0, 8192)
+    lat = xyl.Lattice(8192, 8192, dtype="f32", schedule=spec.schedule, seed=spec.seed,
+                      stream=torch.cuda.current_stream().cuda_stream, **spec.params())
+    lat.init_random()
+    launch = lat.autotune()
+    us = 1e3 * time_step_kernel(torch, lat, nlaunch)
+    lat.close()
+    gbs = BYTES_PER_SITE_F32 * 8192 * 8192 / (us * 1e-6) / 1e9
+    return {"L": 8192, "launch": list(launch), "avg_kernel_us": us, "site_updates_per_s": 8192 * 8192 / (us * 1e-6),
+            "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+
+
 def bench_domains(torch, xyl):
     lat = xyl.Lattice(2048, 2048, dtype="f32", schedule=[(0, 1.5), (1000, 0.0)], seed=0,
                       stream=torch.cuda.current_stream().cuda_stream)
@@ -274,7 +289,7 @@ def main():
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--launch", type=str, default="",
                     help="rows,waves: fixed launch shape of the step kernel instead of autotuning")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"))
@@ -342,6 +357,8 @@ def main():
     if not args.no_extras:
         extras["ensemble_fss"] = bench_ensemble(torch, xyl, workloads, 200)
         log("ensemble:", extras["ensemble_fss"])
+        extras["control_8192"] = bench_control_8192(torch, xyl, workloads)
+        log("8192^2 control:", extras["control_8192"])
         extras["quench_2048"] = bench_quench(torch, xyl, workloads, 100)
         log("quench:", extras["quench_2048"])
         extras["adjoint_512"] = bench_adjoint(torch, xyl, workloads)
