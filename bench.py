@@ -290,6 +290,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--only", type=str, default="",
+                    help="comma list of extras to run alone (ensemble, quench, adjoint, domains, control); "
+                         "prints their JSON and skips the headline measurement")
     ap.add_argument("--launch", type=str, default="",
                     help="rows,waves: fixed launch shape of the step kernel instead of autotuning")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"))
@@ -313,6 +316,14 @@ def main():
     from paper_2409_06412_amd import workloads
 
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.only:
+        runs = {"ensemble": lambda: bench_ensemble(torch, xyl, workloads, 200),
+                "quench": lambda: bench_quench(torch, xyl, workloads, 100),
+                "adjoint": lambda: bench_adjoint(torch, xyl, workloads),
+                "domains": lambda: bench_domains(torch, xyl),
+                "control": lambda: bench_control_8192(torch, xyl, workloads)}
+        print(json.dumps({k: runs[k]() for k in args.only.split(",")}), flush=True)
+        return
     L = args.L
     spec = workloads.large_fp32(0, L)
     stream = torch.cuda.current_stream().cuda_stream
