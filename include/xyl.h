@@ -34,6 +34,10 @@
  *
  * Errors.  Every call returns XYL_OK (0) or a negative status and records a
  * message for xyl_last_error().  No exception or abort crosses the ABI.
+ * A numeric fault (non-finite angles, velocities or observables, e.g. from a
+ * step size far too large) is reported as XYL_ENUMERIC by the calls that
+ * bring results to the host (xyl_get_state, xyl_measure, xyl_step_measured),
+ * after the values have been written.
  * Calls are asynchronous on the handle's stream unless they write host memory,
  * in which case they synchronise that stream first.  A handle is used by one
  * host thread at a time.

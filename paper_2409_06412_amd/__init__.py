@@ -202,9 +202,11 @@ class Lattice:
     def set_schedule(self, schedule):
         ks, Ts, n = _sched_arrays(schedule)
         _check(load().xyl_set_schedule(self._h, ks, Ts, n))
+        self._schedule = [(int(k), float(T)) for k, T in schedule]
 
     def set_seed(self, seed, replica=0):
         _check(load().xyl_set_seed(self._h, int(seed), int(replica)))
+        self._seed, self._replica = int(seed), int(replica)
 
     def set_stream(self, stream):
         _check(load().xyl_set_stream(self._h, _vp(int(stream) if stream is not None else 0)))
@@ -299,6 +301,32 @@ class Lattice:
     def sync(self):
         _check(load().xyl_sync(self._h))
 
+    # -- checkpoint --------------------------------------------------------------------
+    def save(self, path: str):
+        """Writes the synchronized state, step index, parameters, schedule and noise key to an
+        .npz file with a checksum of the state; resuming from it continues bit for bit."""
+        th, om, k = self.get_state()
+        payload = dict(theta=th, omega=om, step=np.uint64(k), Lx=self.Lx, Ly=self.Ly, dtype=self.dtype,
+                       params=np.array([self.params[n] for n in ("Jx", "Jy", "h", "gamma", "dt")]),
+                       schedule=np.array(self._schedule, dtype=np.float64),
+                       key=np.array([self._seed, self._replica], dtype=np.uint64))
+        payload["checksum"] = np.frombuffer(_checksum(payload), dtype=np.uint8)
+        np.savez(path, **payload)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0, stream=None) -> "Lattice":
+        with np.load(path, allow_pickle=False) as z:
+            d = {k: z[k] for k in z.files}
+        if bytes(d.pop("checksum")) != _checksum(d):
+            raise XylError(-1, "checkpoint %s is corrupt (checksum mismatch)" % path)
+        p = d["params"]
+        sched = [(int(k), float(T)) for k, T in d["schedule"]]
+        seed, rep = (int(v) for v in d["key"])
+        lat = cls(int(d["Lx"]), int(d["Ly"]), dtype=int(d["dtype"]), device=device, Jx=p[0], Jy=p[1], h=p[2],
+                  gamma=p[3], dt=p[4], schedule=sched, seed=seed, replica=rep, stream=stream)
+        lat.set_state(d["theta"], d["omega"], int(d["step"]))
+        return lat
+
     # -- gradients ---------------------------------------------------------------------
     def adjoint_forward(self, nsteps: int, ckpt_every: int, window: int) -> float:
         L = _d()
@@ -311,6 +339,17 @@ class Lattice:
         dom = np.empty((self.Ly, self.Lx))
         _check(load().xyl_adjoint_backward(self._h, _pd(g), _pd(dth), _pd(dom)))
         return g, dth, dom
+
+
+def _checksum(d) -> bytes:
+    import hashlib
+    h = hashlib.sha256()
+    for k in sorted(d):
+        a = np.ascontiguousarray(d[k])
+        h.update(k.encode())
+        h.update(str(a.dtype).encode())
+        h.update(a.tobytes())
+    return h.digest()
 
 
 def _domains(call, N, shape, want_labels):

@@ -389,6 +389,14 @@ static void lattice_measure_into(xyl_lattice* h, bool advance, double* obs_dev) 
     }
 }
 
+// A blown-up integration (dt far too large, say) shows up as non-finite
+// values; calls that bring results to the host report it as XYL_ENUMERIC
+// (the copied values are still written).
+static void require_finite(const double* x, size_t n, const char* what) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) throw Error(XYL_ENUMERIC, std::string("non-finite ") + what + " (numeric fault)");
+}
+
 static void require_init(xyl_lattice* h) {
     require(h != nullptr, XYL_EINVAL, "NULL handle");
     require(h->initialized, XYL_ESTATE, "lattice state not initialised (call an init or set_state first)");
@@ -671,6 +679,8 @@ int xyl_get_state(xyl_lattice* h, double* theta, double* omega, uint64_t* step) 
             else lattice_omega<float>(h, omega);
         }
         if (step) *step = h->k;
+        if (theta) require_finite(theta, h->N, "angles");
+        if (omega) require_finite(omega, h->N, "velocities");
     });
 }
 
@@ -722,6 +732,7 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
         check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6 * ns, hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         if (nout) *nout = ns;
+        require_finite(reinterpret_cast<const double*>(out), 6 * ns, "observables");
     });
 }
 
@@ -735,6 +746,7 @@ int xyl_measure(xyl_lattice* h, xyl_obs* out) {
         else lattice_measure_into<float>(h, false, h->obs.p);
         check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6, hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        require_finite(reinterpret_cast<const double*>(out), 6, "observables");
     });
 }
 

@@ -135,3 +135,59 @@ def test_graph_replays_across_state_resets(xyl):
     assert k == 1048
     assert np.abs(np.remainder(th - tr + np.pi, 2 * np.pi) - np.pi).max() < 1e-12
     lat.close()
+
+
+def test_checkpoint_resume_is_bitwise(xyl, tmp_path):
+    """get_state/set_state (and save/load) at step k, then continuing, equals the
+    uninterrupted run bit for bit; a corrupted checkpoint is rejected."""
+    for dtype in ("f32", "f64"):
+        kw = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 1.0), (300, 0.2)], seed=9, replica=4)
+        a = xyl.Lattice(96, 40, dtype=dtype, **kw)
+        a.init_random()
+        a.step(150)
+        a.save(str(tmp_path / "ck.npz"))
+        a.step(100)
+        ref = a.get_state()
+        b = xyl.Lattice.load(str(tmp_path / "ck.npz"))
+        b.step(100)
+        got = b.get_state()
+        np.testing.assert_array_equal(got[0], ref[0])
+        np.testing.assert_array_equal(got[1], ref[1])
+        assert got[2] == ref[2] == 250
+        a.close()
+        b.close()
+    z = dict(np.load(str(tmp_path / "ck.npz")))
+    z["theta"][3, 7] += 1e-3
+    np.savez(str(tmp_path / "bad.npz"), **z)
+    with pytest.raises(xyl.XylError):
+        xyl.Lattice.load(str(tmp_path / "bad.npz"))
+
+
+def test_numeric_fault_is_reported(xyl):
+    """A step size so large that the first drift overflows FP32 leaves
+    non-finite values, which the synchronizing calls report as XYL_ENUMERIC."""
+    lat = xyl.Lattice(32, 8, dtype="f32", dt=1e30, gamma=0.0, schedule=[(0, 0.0)])
+    lat.init_random()
+    lat.step(3)
+    with pytest.raises(xyl.XylError) as e:
+        lat.measure()
+    assert e.value.code == -6
+    with pytest.raises(xyl.XylError) as e:
+        lat.get_state()
+    assert e.value.code == -6
+    lat.close()
+
+
+def test_free_particle_equipartition_gpu(xyl):
+    """Jx = Jy = h = 0: the stationary velocity variance of the BBK map with
+    shared draws is exactly T/(1 + gamma dt/2) (0.8 T here); the FP32 GPU path
+    must reproduce it within sampling error on 1M sites."""
+    g, dt, T = 10.0, 0.05, 1.0
+    lat = xyl.Lattice(1024, 1024, dtype="f32", Jx=0.0, Jy=0.0, h=0.0, gamma=g, dt=dt, schedule=[(0, T)], seed=4)
+    lat.init_random()
+    lat.step(80)
+    _, om, _ = lat.get_state()
+    v = np.mean(om ** 2)
+    se = np.sqrt(2.0 / om.size) * v
+    assert abs(v - T / (1 + 0.5 * g * dt)) < 5 * se
+    lat.close()
