@@ -151,6 +151,25 @@ def bench_adjoint(torch, xyl, workloads):
             "adjoint_over_plain_forward": (t2 - t1) / (t4 - t3)}
 
 
+def bench_copy(torch, nbytes=1 << 30, reps=20):
+    """Plain device-to-device copy bandwidth (read + write bytes per second):
+    the practical streaming ceiling beside the 8 TB/s peak."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_copied": nbytes, "ms": ms, "GBs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def bench_control_8192(torch, xyl, workloads, nlaunch=200):
     """Same kernel on an 8192^2 lattice (805 MB of state, larger than the
     256 MB Infinity Cache): the HBM-resident rate."""
@@ -317,7 +336,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     if args.only:
-        runs = {"ensemble": lambda: bench_ensemble(torch, xyl, workloads, 200),
+        runs = {"copy": lambda: bench_copy(torch),
+                "ensemble": lambda: bench_ensemble(torch, xyl, workloads, 200),
                 "quench": lambda: bench_quench(torch, xyl, workloads, 100),
                 "adjoint": lambda: bench_adjoint(torch, xyl, workloads),
                 "domains": lambda: bench_domains(torch, xyl),
@@ -368,8 +388,12 @@ def main():
     if not args.no_extras:
         extras["ensemble_fss"] = bench_ensemble(torch, xyl, workloads, 200)
         log("ensemble:", extras["ensemble_fss"])
+        extras["copy_1GiB"] = bench_copy(torch)
+        log("copy:", extras["copy_1GiB"])
         extras["control_8192"] = bench_control_8192(torch, xyl, workloads)
-        log("8192^2 control:", extras["control_8192"])
+        c = extras["control_8192"]
+        c["frac_of_copy"] = c["algorithmic_GBs"] / extras["copy_1GiB"]["GBs_read_plus_write"]
+        log("8192^2 control:", c)
         extras["quench_2048"] = bench_quench(torch, xyl, workloads, 100)
         log("quench:", extras["quench_2048"])
         extras["adjoint_512"] = bench_adjoint(torch, xyl, workloads)
@@ -395,6 +419,8 @@ def main():
         line["adjoint_over_forward"] = extras["adjoint_512"]["adjoint_over_forward"]
     if "ensemble_fss" in extras:
         line["batched_over_per_replica"] = extras["ensemble_fss"]["speedup"]
+    if "copy_1GiB" in extras:
+        roofline["frac_of_measured_copy"] = achieved / extras["copy_1GiB"]["GBs_read_plus_write"]
     line["extras"] = extras
     print(json.dumps(line), flush=True)
 

@@ -66,19 +66,19 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         for (int q = 0; q < 4; ++q) Prec<R>::sincos(S.th[q], S.s[q], S.c[q]);
     };
 
-    // One row y with the window (P = y-1, C = y, N = y+1).  At entry N.th is
-    // loaded (sin/cos not yet taken) and C.u is loaded.  The row issues the
-    // loads of row y+2 into P's raw-angle slots (dead since row y-1 was
-    // stored; P's sin/cos, still needed here, are not touched) and of the
-    // velocities of row y+1.
-    auto do_row = [&](RowSet<R>& P, RowSet<R>& C, RowSet<R>& N, int y) {
+    // One row y with the window P = y-1, C = y, N = y+1 and F = y+2.  At entry
+    // N.th (loaded two rows ago) and C.u are in registers and F.th is in
+    // flight.  The row issues the loads of row y+3 into P's raw-angle slots
+    // (dead since row y-1 was stored; P's sin/cos, still needed here, are not
+    // touched) and of the velocities of row y+2 into F.
+    auto do_row = [&](RowSet<R>& P, RowSet<R>& C, RowSet<R>& N, RowSet<R>& F, int y) {
         const uint32_t row = (uint32_t)y * (uint32_t)Lx;
         trig(N);
-        if (y + 2 <= y1) {   // row y+1 will be processed: it needs row y+2 and its velocities
-            int y2 = y + 2;
-            if (y2 >= Ly) y2 -= Ly;
-            load_theta(P, y2);
-            if (act) load4(uu + row + (uint32_t)Lx + x, N.u);
+        if (y + 3 <= y1) {   // row y+2 will be processed: it needs row y+3 and its velocities
+            int y3 = y + 3;
+            if (y3 >= Ly) y3 -= Ly;
+            load_theta(P, y3);
+            if (act) load4(uu + row + 2u * (uint32_t)Lx + x, F.u);
         }
         // x-neighbours of the lane's first and last site
         // (the wave's first lane takes its left neighbour, the last active lane
@@ -157,31 +157,39 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         }
     };
 
-    RowSet<R> A, B, C;
+    RowSet<R> A, B, C, D;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        A.th[q] = B.th[q] = C.th[q] = R(0);
-        A.u[q] = B.u[q] = C.u[q] = R(0);
+        A.th[q] = B.th[q] = C.th[q] = D.th[q] = R(0);
+        A.u[q] = B.u[q] = C.u[q] = D.u[q] = R(0);
     }
-    A.eL = A.eR = B.eL = B.eR = C.eL = C.eR = R(0);
-    // prologue: A = row y0-1 (sin/cos), B = row y0 (sin/cos, velocities),
-    // C = row y0+1 (raw angles)
+    A.eL = A.eR = B.eL = B.eR = C.eL = C.eR = D.eL = D.eR = R(0);
+    // prologue: A = row y0-1, B = row y0 (with velocities), C = row y0+1
+    // (with velocities), D = row y0+2 in flight
     load_theta(A, y0 == 0 ? Ly - 1 : y0 - 1);
     load_theta(B, y0);
-    load_theta(C, y0 + 1 == Ly ? 0 : y0 + 1);
-    if (act) load4(uu + (uint32_t)y0 * (uint32_t)Lx + x, B.u);
+    load_theta(C, y0 + 1 >= Ly ? y0 + 1 - Ly : y0 + 1);
+    load_theta(D, y0 + 2 >= Ly ? y0 + 2 - Ly : y0 + 2);
+    if (act) {
+        load4(uu + (uint32_t)y0 * (uint32_t)Lx + x, B.u);
+        if (y0 + 1 < y1) load4(uu + (uint32_t)(y0 + 1) * (uint32_t)Lx + x, C.u);
+    }
     trig(A);
     trig(B);
 
     int y = y0;
-    for (; y + 3 <= y1; y += 3) {
-        do_row(A, B, C, y);
-        do_row(B, C, A, y + 1);
-        do_row(C, A, B, y + 2);
+    for (; y + 4 <= y1; y += 4) {
+        do_row(A, B, C, D, y);
+        do_row(B, C, D, A, y + 1);
+        do_row(C, D, A, B, y + 2);
+        do_row(D, A, B, C, y + 3);
     }
     if (y < y1) {
-        do_row(A, B, C, y);
-        if (y + 1 < y1) do_row(B, C, A, y + 1);
+        do_row(A, B, C, D, y);
+        if (y + 1 < y1) {
+            do_row(B, C, D, A, y + 1);
+            if (y + 2 < y1) do_row(C, D, A, B, y + 2);
+        }
     }
 }
 
