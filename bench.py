@@ -87,6 +87,8 @@ def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
     for mode, name in ((0, "batched"), (1, "per_replica")):
         ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
         ens.set_mode(mode)
+        if mode == 0:
+            ens.autotune()
         ens.step(3)
         ens.sync()
         t0 = time.perf_counter()
@@ -106,6 +108,7 @@ def bench_quench(torch, xyl, workloads, nsteps):
     the union-find labelling of one end state."""
     specs = workloads.kz_quench()
     ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
+    launch = ens.autotune()
     ens.step(2)
     ens.sync()
     t0 = time.perf_counter()
@@ -114,7 +117,7 @@ def bench_quench(torch, xyl, workloads, nsteps):
     t1 = time.perf_counter()
     sites = sum(s.Lx * s.Ly for s in specs)
     ens.close()
-    return {"replicas": len(specs), "sites": sites, "steps": nsteps,
+    return {"replicas": len(specs), "sites": sites, "steps": nsteps, "launch": list(launch),
             "site_updates_per_s": sites * nsteps / (t1 - t0),
             "full_run_site_updates": sum(s.Lx * s.Ly * s.nsteps for s in specs)}
 

@@ -220,6 +220,12 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
  * grid).  Mode 1: one launch per replica per step (the reference loop the
  * batched mode is measured against).  Default 0. */
 int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
+/* Launch shape (rows per strip, waves per workgroup) of the tile launches:
+ * xyl_ensemble_autotune times candidates on scratch copies of the replicas'
+ * state (the ensemble itself is not advanced) and keeps the fastest.
+ * Results do not depend on it. */
+int xyl_ensemble_autotune(xyl_ensemble* e);
+int xyl_ensemble_get_launch(xyl_ensemble* e, int32_t* rows, int32_t* wpb);
 int xyl_ensemble_get_state(xyl_ensemble* e, int32_t r, double* theta, double* omega, uint64_t* step);
 int xyl_ensemble_set_state(xyl_ensemble* e, int32_t r, const double* theta, const double* omega,
                            uint64_t step);

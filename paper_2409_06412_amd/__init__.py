@@ -89,6 +89,8 @@ _SIGS = {
     "xyl_ensemble_set_stream": (_i32, [_vp, _vp]),
     "xyl_ensemble_step": (_i32, [_vp, _u64, _u64, P(_d), _u64, P(_u64)]),
     "xyl_ensemble_set_mode": (_i32, [_vp, _i32]),
+    "xyl_ensemble_autotune": (_i32, [_vp]),
+    "xyl_ensemble_get_launch": (_i32, [_vp, P(_i32), P(_i32)]),
     "xyl_ensemble_get_state": (_i32, [_vp, _i32, P(_d), P(_d), P(_u64)]),
     "xyl_ensemble_set_state": (_i32, [_vp, _i32, P(_d), P(_d), _u64]),
     "xyl_ensemble_domains": (_i32, [_vp, _i32, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
@@ -404,6 +406,15 @@ class Ensemble:
 
     def set_mode(self, mode: int):
         _check(load().xyl_ensemble_set_mode(self._h, int(mode)))
+
+    def autotune(self):
+        _check(load().xyl_ensemble_autotune(self._h))
+        return self.launch()
+
+    def launch(self):
+        r, w = _i32(), _i32()
+        _check(load().xyl_ensemble_get_launch(self._h, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
 
     def step(self, nsteps: int, every: int = 0, cap: int = 0):
         """Advances; with every > 0 returns a list of (n_r, 6) sample arrays."""

@@ -1306,7 +1306,113 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
     }
 }
 
+// Launch shape of the tile launches, timed on scratch copies of the state of
+// the replicas that use the tile path (graph-captured steps, as for lattices).
+template <typename R>
+static Launch ensemble_autotune_impl(xyl_ensemble* e) {
+    std::vector<int> reps;
+    for (int r = 0; r < e->n; ++r)
+        if (!e->lds[r]) reps.push_back(r);
+    if (reps.empty()) return e->launch;
+    const size_t bytes = sizeof(R) * e->total;
+    DevBuf<char> tmp;
+    tmp.reserve(3 * bytes);
+    for (int b = 0; b < 2; ++b)
+        check_hip(hipMemcpyAsync(tmp.p + b * bytes, e->th[b], bytes, hipMemcpyDeviceToDevice, e->stream), "D2D");
+    check_hip(hipMemcpyAsync(tmp.p + 2 * bytes, e->u, bytes, hipMemcpyDeviceToDevice, e->stream), "D2D");
+    std::vector<Lat<R>> tab(e->n);
+    for (int r = 0; r < e->n; ++r) {
+        tab[r] = e->view<R>(r, 0);
+        tab[r].th[0] = reinterpret_cast<R*>(tmp.p) + e->off[r];
+        tab[r].th[1] = reinterpret_cast<R*>(tmp.p + bytes) + e->off[r];
+        tab[r].u = reinterpret_cast<R*>(tmp.p + 2 * bytes) + e->off[r];
+        tab[r].fresh_k = ~(uint64_t)0;
+        tab[r].k_end = ~(uint64_t)0;
+    }
+    DevBuf<char> dtab;
+    dtab.reserve(sizeof(Lat<R>) * e->n);
+    check_hip(hipMemcpyAsync(dtab.p, tab.data(), sizeof(Lat<R>) * e->n, hipMemcpyHostToDevice, e->stream), "H2D");
+    DevBuf<uint64_t> kc;
+    kc.reserve(1);
+    launch_set_counter(kc.p, 0, e->stream);
+    check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    size_t sites = 0;
+    for (int r : reps) sites += (size_t)e->desc[r].Lx * e->desc[r].Ly;
+    const int steps = (int)std::max<double>(4.0, std::min<double>(256.0, 2.0e11 * 2e-3 / (double)sites));
+    hipStream_t cap = nullptr;
+    check_hip(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    DevBuf<Task> dtasks;
+    Launch best = e->launch;
+    float best_ms = 1e30f;
+    const int rows_c[] = {1, 2, 4, 8, 16, 32};
+    const int wpb_c[] = {1, 2, 4, 8};
+    for (int rows : rows_c) {
+        std::vector<Task> tk;
+        for (int r : reps) {
+            const int nxw = (e->desc[r].Lx + kWaveSites - 1) / kWaveSites;
+            const int nstrips = (e->desc[r].Ly + rows - 1) / rows;
+            for (int st = 0; st < nstrips; ++st)
+                for (int x = 0; x < nxw; ++x) tk.push_back(Task{r, x, st, 0});
+        }
+        dtasks.reserve(tk.size());
+        check_hip(hipMemcpy(dtasks.p, tk.data(), sizeof(Task) * tk.size(), hipMemcpyHostToDevice), "H2D");
+        for (int w : wpb_c) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ex = nullptr;
+            check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            for (int i = 0; i < steps; ++i)
+                launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), dtasks.p, (int)tk.size(), kStore,
+                                        rows, w, kc.p, (uint64_t)i, cap);
+            check_hip(hipStreamEndCapture(cap, &g), "hipStreamEndCapture");
+            hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            check_hip(err, "hipGraphInstantiate");
+            check_hip(hipGraphLaunch(ex, e->stream), "hipGraphLaunch");
+            float t = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                check_hip(hipEventRecord(e0, e->stream), "hipEventRecord");
+                check_hip(hipGraphLaunch(ex, e->stream), "hipGraphLaunch");
+                check_hip(hipEventRecord(e1, e->stream), "hipEventRecord");
+                check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.f;
+                check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                t = std::min(t, ms);
+            }
+            (void)hipGraphExecDestroy(ex);
+            if (t < best_ms) {
+                best_ms = t;
+                best.rows = rows;
+                best.wpb = w;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(cap);
+    return best;
+}
+
 extern "C" {
+
+int xyl_ensemble_autotune(xyl_ensemble* e) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        DeviceGuard g(e->device);
+        e->launch = e->dtype == XYL_F64 ? ensemble_autotune_impl<double>(e) : ensemble_autotune_impl<float>(e);
+        e->task_active.clear();   // rebuild the tile table with the new strip height
+    });
+}
+
+int xyl_ensemble_get_launch(xyl_ensemble* e, int32_t* rows, int32_t* wpb) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        if (rows) *rows = e->launch.rows;
+        if (wpb) *wpb = e->launch.wpb;
+    });
+}
 
 int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_t n, int32_t dtype, int32_t device) {
     return guarded([&] {

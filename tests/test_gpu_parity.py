@@ -292,15 +292,23 @@ def ensemble_specs_mixed():
 @pytest.mark.parametrize("dtype,specs_fn", [("f32", "ensemble_specs"), ("f32", "ensemble_specs_mixed"),
                                             ("f64", "ensemble_specs_mixed")])
 def test_ensemble_matches_single_lattices(xyl, dtype, specs_fn):
-    """Batched mode (tile table + whole-in-LDS launches) and the per-replica
-    reference loop give every replica exactly the state and samples it gets
-    when run alone."""
+    """Batched mode (tile table + whole-in-LDS launches), batched mode re-tuned
+    halfway, and the per-replica reference loop give every replica exactly the
+    state and samples it gets when run alone (the tuner leaves the state alone
+    and the launch shape does not change results)."""
     specs = globals()[specs_fn]()
     results = {}
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         ens = xyl.Ensemble(specs, dtype=dtype)
-        ens.set_mode(mode)
+        ens.set_mode(min(mode, 1) if mode < 2 else 0)
         s1 = ens.step(25, every=10)
+        if mode == 2:
+            before = [ens.get_state(r) for r in range(len(specs))]
+            rows, wpb = ens.autotune()
+            assert rows >= 1 and wpb >= 1
+            for r in range(len(specs)):
+                for a, b in zip(before[r], ens.get_state(r)):
+                    np.testing.assert_array_equal(a, b)
         s2 = ens.step(40, every=10)
         results[mode] = ([ens.get_state(r) for r in range(len(specs))], s1, s2)
         ens.close()
@@ -311,7 +319,7 @@ def test_ensemble_matches_single_lattices(xyl, dtype, specs_fn):
         n = min(sp.nsteps, 65)
         samples = lat.step_measured(n, 10) if n else lat.step_measured(0, 10)
         th, om, k = lat.get_state()
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             eth, eom, ek = results[mode][0][r]
             assert ek == k == n
             np.testing.assert_array_equal(eth, th)
