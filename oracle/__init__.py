@@ -44,7 +44,12 @@ class Model(ctypes.Structure):
         ("nknots", ctypes.c_int32),
         ("knot_step", ctypes.c_uint64 * MAX_KNOTS),
         ("knot_T", ctypes.c_double * MAX_KNOTS),
+        ("model", ctypes.c_int32),
+        ("p", ctypes.c_double),
     ]
+
+
+MODELS = {"xy": 0, "si": 1}
 
 
 _lib = None
@@ -91,11 +96,17 @@ def _pd(a: np.ndarray):
 
 
 class Oracle:
-    """One lattice model: couplings, damping, step size, schedule and noise key."""
+    """One lattice model: couplings, damping, step size, schedule and noise key.
+
+    model "xy": q = 1, p = 2, angles in [-pi, pi); model "si": the Si(001)
+    mapping, q = 2 with field order p, angles in [-pi/2, pi/2)."""
 
     def __init__(self, Lx, Ly, Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01,
-                 schedule=((0, 0.5),), seed=0, replica=0):
+                 schedule=((0, 0.5),), seed=0, replica=0, model="xy", p=2.0):
         m = Model()
+        m.model = MODELS[model]
+        m.p = float(p)
+        self.model = model
         m.Lx, m.Ly = int(Lx), int(Ly)
         m.Jx, m.Jy, m.h, m.gamma, m.dt = float(Jx), float(Jy), float(h), float(gamma), float(dt)
         m.seed, m.replica = int(seed), int(replica)
@@ -210,7 +221,7 @@ class Oracle:
         m = self.m
         args = dict(Lx=m.Lx, Ly=m.Ly, Jx=m.Jx, Jy=m.Jy, h=m.h, gamma=m.gamma, dt=m.dt,
                     schedule=[(m.knot_step[j], m.knot_T[j]) for j in range(m.nknots)],
-                    seed=m.seed, replica=m.replica)
+                    seed=m.seed, replica=m.replica, model=self.model, p=m.p)
         args.update(kw)
         return Oracle(**args)
 

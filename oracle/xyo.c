@@ -3,15 +3,18 @@
  *
  * Everything here is the direct definition, written for a reader to check by
  * eye against the paper:
- *   - Hamiltonian: Sec. III.A, Eq. XY-Hamilton-Field (q = 1, p = 2) plus the
- *     kinetic term of Eq. XY-Hamilton-Kinetic with I = 1.
+ *   - Hamiltonian: Sec. III.A, Eq. XY-Hamilton-Field (q = 1, p = 2; or the
+ *     Si(001) mapping of Sec. III.C, q = 2 with real p) plus the kinetic term
+ *     of Eq. XY-Hamilton-Kinetic with I = 1.
  *   - Equations of motion: Sec. III.D, Eq. Si-Langevin; noise <G G'> = delta.
  *   - Integrator: App. A.1, three stages (Eq. BBK-1, drift, Eq. BBK-2); the
  *     Gaussian draw n(t+dt) of the second half-kick of one step is the n(t) of
  *     the first half-kick of the next step.
- *   - Wrap after every step (Sec. III.D), to [-pi, pi).
+ *   - Wrap after every step (Sec. III.D), to [-pi, pi) or, for the Si mapping,
+ *     to [-pi/2, pi/2) (Sec. III.C).
  *   - Order parameter and Binder cumulant: Sec. IV.A, Eqs. Def-Binder-Cum and
- *     lattice-average (staggered here, because Jx > 0 is antiferromagnetic).
+ *     lattice-average (staggered when a coupling is antiferromagnetic; the
+ *     site variable is cos th, or sin 2 th for the Si mapping).
  *   - Correlation function: App. C (rotor dot products, lattice average).
  *   - Linear quench: Sec. II.B, Eq. Linear-Quench, as a piecewise-linear T(k).
  * OpenMP parallelises the per-site loops only; every reduction is done per row
@@ -116,23 +119,35 @@ int32_t xyo_stagger(const xyo_model* m, int64_t i) {
     return (e & 1) ? -1 : 1;
 }
 
+/* Half-width W of the state space [-W, W): pi, or pi/2 for the Si mapping,
+ * whose rotors are half circles (Sec. III.C). */
+static double half_width(const xyo_model* m) {
+    return m->model == XYO_MODEL_SI ? PI64 / 2.0 : PI64;
+}
+
 void xyo_init_random(const xyo_model* m, double* theta, double* omega) {
     const int64_t N = (int64_t)m->Lx * m->Ly;
     const uint64_t kinit = ~(uint64_t)0;
+    const double W = half_width(m);
     for (int64_t i = 0; i < N; ++i) {
         uint32_t r[4];
         philox_block(m, kinit, i, r);
         double u = xyo_uniform(r[i & 3]);
-        theta[i] = PI64 * (2.0 * u - 1.0);
+        theta[i] = W * (2.0 * u - 1.0);
         omega[i] = 0.0;
     }
 }
 
 void xyo_init_ordered(const xyo_model* m, int32_t sign, double* theta, double* omega) {
     const int64_t N = (int64_t)m->Lx * m->Ly;
+    /* Si mapping: -h cos(p th) with h < 0 has its minima at th = +-pi/p */
+    const double th0 = (m->h < 0.0 && m->p > 2.0) ? PI64 / m->p : 0.0;
     for (int64_t i = 0; i < N; ++i) {
         int s = xyo_stagger(m, i) * (sign >= 0 ? 1 : -1);
-        theta[i] = (s > 0) ? 0.0 : -PI64;
+        if (m->model == XYO_MODEL_SI)
+            theta[i] = s > 0 ? th0 : -th0;
+        else
+            theta[i] = (s > 0) ? 0.0 : -PI64;
         omega[i] = 0.0;
     }
 }
@@ -141,14 +156,20 @@ void xyo_init_ordered(const xyo_model* m, int32_t sign, double* theta, double* o
  * neighbour and the on-site term; every bond is counted once. */
 double xyo_energy_pot(const xyo_model* m, const double* theta) {
     const int Lx = m->Lx, Ly = m->Ly;
+    const int si = m->model == XYO_MODEL_SI;
     double* row = (double*)calloc((size_t)Ly, sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < Ly; ++y) {
         double s = 0.0;
         for (int x = 0; x < Lx; ++x) {
             double t = theta[site(m, x, y)];
-            double e = m->Jx * cos(t - theta[site(m, x + 1, y)]) +
-                       m->Jy * cos(t - theta[site(m, x, y + 1)]) - m->h * cos(2.0 * t);
+            double e;
+            if (si)
+                e = m->Jx * cos(2.0 * (t - theta[site(m, x + 1, y)])) +
+                    m->Jy * cos(2.0 * (t - theta[site(m, x, y + 1)])) - m->h * cos(m->p * t);
+            else
+                e = m->Jx * cos(t - theta[site(m, x + 1, y)]) +
+                    m->Jy * cos(t - theta[site(m, x, y + 1)]) - m->h * cos(2.0 * t);
             s += e;
         }
         row[y] = s;
@@ -159,18 +180,29 @@ double xyo_energy_pot(const xyo_model* m, const double* theta) {
     return E;
 }
 
-/* F_i = -dH/dth_i = Jx [sin(th_i - th_{i+x}) + sin(th_i - th_{i-x})]
- *                 + Jy [sin(th_i - th_{i+y}) + sin(th_i - th_{i-y})]
- *                 - 2 h sin(2 th_i). */
+/* F_i = -dH/dth_i.  XY:
+ *   F_i = Jx [sin(th_i - th_{i+x}) + sin(th_i - th_{i-x})]
+ *       + Jy [sin(th_i - th_{i+y}) + sin(th_i - th_{i-y})] - 2 h sin(2 th_i);
+ * Si mapping (q = 2):
+ *   F_i = 2 Jx [sin(2 (th_i - th_{i+x})) + sin(2 (th_i - th_{i-x}))]
+ *       + 2 Jy [sin(2 (th_i - th_{i+y})) + sin(2 (th_i - th_{i-y}))]
+ *       - p h sin(p th_i). */
 void xyo_force(const xyo_model* m, const double* theta, double* F) {
     const int Lx = m->Lx, Ly = m->Ly;
+    const int si = m->model == XYO_MODEL_SI;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < Ly; ++y) {
         for (int x = 0; x < Lx; ++x) {
             double t = theta[site(m, x, y)];
-            double fx = sin(t - theta[site(m, x + 1, y)]) + sin(t - theta[site(m, x - 1, y)]);
-            double fy = sin(t - theta[site(m, x, y + 1)]) + sin(t - theta[site(m, x, y - 1)]);
-            F[site(m, x, y)] = m->Jx * fx + m->Jy * fy - 2.0 * m->h * sin(2.0 * t);
+            if (si) {
+                double fx = sin(2.0 * (t - theta[site(m, x + 1, y)])) + sin(2.0 * (t - theta[site(m, x - 1, y)]));
+                double fy = sin(2.0 * (t - theta[site(m, x, y + 1)])) + sin(2.0 * (t - theta[site(m, x, y - 1)]));
+                F[site(m, x, y)] = 2.0 * m->Jx * fx + 2.0 * m->Jy * fy - m->p * m->h * sin(m->p * t);
+            } else {
+                double fx = sin(t - theta[site(m, x + 1, y)]) + sin(t - theta[site(m, x - 1, y)]);
+                double fy = sin(t - theta[site(m, x, y + 1)]) + sin(t - theta[site(m, x, y - 1)]);
+                F[site(m, x, y)] = m->Jx * fx + m->Jy * fy - 2.0 * m->h * sin(2.0 * t);
+            }
         }
     }
 }
@@ -194,11 +226,12 @@ static double half_sigma(const xyo_model* m, uint64_t k) {
     return 0.5 * sqrt(2.0 * m->gamma * xyo_temperature(m, k) * m->dt);
 }
 
-static double wrap(double t) {
-    if (t >= PI64)
-        t -= TWO_PI64;
-    else if (t < -PI64)
-        t += TWO_PI64;
+/* Back into [-W, W) by one shift of 2W (Sec. III.D). */
+static double wrap(double t, double W) {
+    if (t >= W)
+        t -= 2.0 * W;
+    else if (t < -W)
+        t += 2.0 * W;
     return t;
 }
 
@@ -209,6 +242,7 @@ static int bbk_step(const xyo_model* m, const bbk_coef* b, uint64_t k, double* t
                     double* omega, double* F, double* n, double* whalf) {
     const int64_t N = (int64_t)m->Lx * m->Ly;
     const double hs0 = half_sigma(m, k);
+    const double W = half_width(m);
     int fault = 0;
     /* Eq. BBK-1 (half-kick), then the drift and the wrap. */
 #pragma omp parallel for schedule(static) reduction(| : fault)
@@ -217,8 +251,8 @@ static int bbk_step(const xyo_model* m, const bbk_coef* b, uint64_t k, double* t
         t = fma(hs0, n[i], t);
         double w = fma(b->a, omega[i], t);
         whalf[i] = w;
-        double th = wrap(fma(b->dt, w, theta[i]));
-        if (!(fabs(th) <= 3.0 * PI64)) fault = 1;
+        double th = wrap(fma(b->dt, w, theta[i]), W);
+        if (!(fabs(th) <= 3.0 * W)) fault = 1;
         theta[i] = th;
     }
     /* Eq. BBK-2 (second half-kick) with the force at the new angles. */
@@ -271,12 +305,14 @@ int32_t xyo_run(const xyo_model* m, double* theta, double* omega, uint64_t k0, u
 }
 
 /* ------------------------------------------------------------ observables */
-/* F(q) = (1/N) sum_{kappa} | sum_i eps_i s^kappa_i exp(-i q.r_i) |^2 with
- * s^0 = cos th, s^1 = sin th (the lattice Fourier transform of App. C at one
- * wave vector). */
+/* F(q) = (1/N) sum_{kappa} | sum_i eps_i s^kappa_i exp(-i q.r_i) |^2 over the
+ * two rotor components (the lattice Fourier transform of App. C at one wave
+ * vector).  XY: s^0 = cos th (the order-parameter component), s^1 = sin th;
+ * Si mapping: s^0 = sin 2 th (Sec. IV.A), s^1 = cos 2 th. */
 void xyo_observables(const xyo_model* m, const double* theta, const double* omega, double* out) {
     const int Lx = m->Lx, Ly = m->Ly;
     const double N = (double)Lx * (double)Ly;
+    const int si = m->model == XYO_MODEL_SI;
     double epot = xyo_energy_pot(m, theta);
     double ekin = 0.0, ms = 0.0, a0s = 0.0;
     double kxr[2] = {0, 0}, kxi[2] = {0, 0}, kyr[2] = {0, 0}, kyi[2] = {0, 0};
@@ -284,7 +320,14 @@ void xyo_observables(const xyo_model* m, const double* theta, const double* omeg
         for (int x = 0; x < Lx; ++x) {
             int64_t i = (int64_t)y * Lx + x;
             double e = (double)xyo_stagger(m, i);
-            double s[2] = {e * cos(theta[i]), e * sin(theta[i])};
+            double s[2];
+            if (si) {
+                s[0] = e * sin(2.0 * theta[i]);
+                s[1] = e * cos(2.0 * theta[i]);
+            } else {
+                s[0] = e * cos(theta[i]);
+                s[1] = e * sin(theta[i]);
+            }
             ekin += 0.5 * omega[i] * omega[i];
             ms += s[0];
             a0s += s[1];
@@ -306,24 +349,27 @@ void xyo_observables(const xyo_model* m, const double* theta, const double* omeg
     out[5] = (kyr[0] * kyr[0] + kyi[0] * kyi[0] + kyr[1] * kyr[1] + kyi[1] * kyi[1]) / N;
 }
 
-/* C(r) = (1/N) sum_i eps_i eps_j cos(th_i - th_j), j = i + r along the axis. */
+/* C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along the axis
+ * (q = 1 for XY, 2 for the Si mapping: the dot product of the rotors). */
 void xyo_correlation(const xyo_model* m, const double* theta, int32_t axis, int32_t rmax, double* C) {
     const int Lx = m->Lx, Ly = m->Ly;
     const double N = (double)Lx * (double)Ly;
+    const double q = m->model == XYO_MODEL_SI ? 2.0 : 1.0;
     for (int r = 0; r <= rmax; ++r) {
         double s = 0.0;
         for (int y = 0; y < Ly; ++y)
             for (int x = 0; x < Lx; ++x) {
                 int64_t i = site(m, x, y);
                 int64_t j = axis == 0 ? site(m, x + r, y) : site(m, x, y + r);
-                s += (double)(xyo_stagger(m, i) * xyo_stagger(m, j)) * cos(theta[i] - theta[j]);
+                s += (double)(xyo_stagger(m, i) * xyo_stagger(m, j)) * cos(q * (theta[i] - theta[j]));
             }
         C[r] = s / N;
     }
 }
 
 /* ---------------------------------------------------------------- domains */
-/* Spin sigma_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1).  Flood fill in order of
+/* Spin sigma_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1) (XY) or
+ * eps_i * (th_i >= 0 ? +1 : -1) (Si mapping).  Flood fill in order of
  * increasing linear index, so each cluster is labelled by its smallest index. */
 int64_t xyo_domains(const xyo_model* m, const double* theta, int32_t precision_bits, int32_t* labels) {
     const int Lx = m->Lx, Ly = m->Ly;
@@ -337,7 +383,8 @@ int64_t xyo_domains(const xyo_model* m, const double* theta, int32_t precision_b
         return -1;
     }
     for (int64_t i = 0; i < N; ++i) {
-        spin[i] = (int8_t)(xyo_stagger(m, i) * (fabs(theta[i]) <= half ? 1 : -1));
+        int up = m->model == XYO_MODEL_SI ? theta[i] >= 0.0 : fabs(theta[i]) <= half;
+        spin[i] = (int8_t)(xyo_stagger(m, i) * (up ? 1 : -1));
         labels[i] = -1;
     }
     int64_t ndom = 0;
@@ -376,6 +423,7 @@ static double order_parameter(const xyo_model* m, const double* theta) {
 double xyo_loss(const xyo_model* m, const double* theta0, const double* omega0, uint64_t nsteps,
                 uint64_t window) {
     const int64_t N = (int64_t)m->Lx * m->Ly;
+    if (m->model != XYO_MODEL_XY) return NAN;
     double* th = (double*)malloc(sizeof(double) * (size_t)N);
     double* om = (double*)malloc(sizeof(double) * (size_t)N);
     double* out = (double*)malloc(sizeof(double) * XYO_NOBS * (size_t)(nsteps + 1));
@@ -447,7 +495,7 @@ double xyo_adjoint(const xyo_model* m, const double* theta0, const double* omega
                    uint64_t window, double* grad, double* dtheta0, double* domega0) {
     const int64_t N = (int64_t)m->Lx * m->Ly;
     const size_t sz = sizeof(double) * (size_t)N;
-    if (window == 0 || window > nsteps) return NAN;
+    if (window == 0 || window > nsteps || m->model != XYO_MODEL_XY) return NAN;
     double* TH = (double*)malloc(sz * (size_t)(nsteps + 1));
     double* W = (double*)malloc(sz * (size_t)(nsteps + 1));
     double* WH = (double*)malloc(sz * (size_t)(nsteps + 1));

@@ -6,10 +6,16 @@
  * Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
  * load it.  It shares no code, header, table or helper with the HIP library.
  *
- * Model (paper Sec. III.A, Eq. XY-Hamilton-Field, specialised to q = 1, p = 2
- * and written with the sign convention used by this project):
+ * Models (paper Sec. III.A, Eq. XY-Hamilton-Field, written with the sign
+ * convention used by this project):
+ *   XYO_MODEL_XY (q = 1, p = 2, angles in [-pi, pi)):
  *     H = sum_i [ Jx cos(th_i - th_{i+x}) + Jy cos(th_i - th_{i+y})
  *                 - h cos(2 th_i) + omega_i^2 / 2 ]
+ *   XYO_MODEL_SI (the paper's Si(001) mapping of Sec. III.C: q = 2, real p,
+ *   angles in [-pi/2, pi/2)):
+ *     H = sum_i [ Jx cos(2 (th_i - th_{i+x})) + Jy cos(2 (th_i - th_{i+y}))
+ *                 - h cos(p th_i) + omega_i^2 / 2 ]
+ *   (the paper's J_par, J_perp, h are -Jx, -Jy, -h here).
  * on an Lx x Ly periodic lattice, site (x, y) at linear index i = y*Lx + x.
  * Dynamics: Langevin equations of Sec. III.D (Eq. Si-Langevin) with I = kB = 1,
  * integrated by the three-stage BBK scheme of App. A.1 (Eqs. BBK-1, BBK-2).
@@ -25,6 +31,8 @@ extern "C" {
 
 #define XYO_MAX_KNOTS 16
 #define XYO_NOBS 6
+#define XYO_MODEL_XY 0
+#define XYO_MODEL_SI 1
 
 typedef struct {
     int32_t Lx, Ly;
@@ -34,6 +42,8 @@ typedef struct {
     int32_t nknots;                      /* >= 1; one knot = constant T */
     uint64_t knot_step[XYO_MAX_KNOTS];   /* strictly increasing */
     double knot_T[XYO_MAX_KNOTS];        /* >= 0 */
+    int32_t model;                       /* XYO_MODEL_XY or XYO_MODEL_SI */
+    double p;                            /* field order of XYO_MODEL_SI (> 0) */
 } xyo_model;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): one block. */
@@ -47,8 +57,10 @@ void xyo_normals(const xyo_model* m, uint64_t k, double* n);
 /* Temperature T_k: piecewise linear in the step index, held outside the knots. */
 double xyo_temperature(const xyo_model* m, uint64_t k);
 
-/* Initial states.  Random: th_i = pi (2U - 1) from the reserved init stream
- * (step counter 2^64 - 1), omega = 0.  Ordered: staggered ground state. */
+/* Initial states.  Random: th_i = W (2U - 1) from the reserved init stream
+ * (step counter 2^64 - 1), omega = 0, with W = pi (XY) or pi/2 (SI).
+ * Ordered: XY: staggered ground state th in {0, -pi}; SI: th_i = +-eps_i th0
+ * with th0 = pi/p, the on-site minimum, when h < 0 and p > 2, else th0 = 0. */
 void xyo_init_random(const xyo_model* m, double* theta, double* omega);
 void xyo_init_ordered(const xyo_model* m, int32_t sign, double* theta, double* omega);
 /* Staggering sign eps_i in {+1,-1}. */
@@ -67,20 +79,23 @@ int64_t xyo_run_measured(const xyo_model* m, double* theta, double* omega, uint6
                          uint64_t nsteps, uint64_t every, double* out);
 
 /* Observables of a synchronized state, per site where noted:
- * out = {E_pot/N, E_kin/N, m_s, F(0), F(kx_min), F(ky_min)}. */
+ * out = {E_pot/N, E_kin/N, m_s, F(0), F(kx_min), F(ky_min)}.
+ * The rotor of a site is (cos q th, sin q th); the order parameter m_s is the
+ * staggered mean of cos th (XY) or of sin 2 th (SI, Sec. IV.A). */
 void xyo_observables(const xyo_model* m, const double* theta, const double* omega, double* out);
 /* Staggered rotor correlation C_axis(r), r = 0..rmax (axis 0 = x, 1 = y). */
 void xyo_correlation(const xyo_model* m, const double* theta, int32_t axis, int32_t rmax, double* C);
 /* Frozen domains: labels[i] = smallest linear index of the 4-connected periodic
- * cluster of equal staggered spin.  Spin threshold is pi_p / 2 with pi_p the
- * value of pi in the state precision (precision_bits 32 or 64).
- * Returns the number of domains. */
+ * cluster of equal staggered spin.  XY: the spin is +1 where |th| <= pi_p / 2
+ * with pi_p the value of pi in the state precision (precision_bits 32 or 64);
+ * SI: +1 where th >= 0 (the sign of sin 2 th).  Returns the number of domains. */
 int64_t xyo_domains(const xyo_model* m, const double* theta, int32_t precision_bits, int32_t* labels);
 
 /* Pathwise reverse-mode gradient of L = (1/W) sum_{k=N-W+1}^{N} m_s(theta^k)^2
  * with the Gaussian draws held fixed.  grad = dL/d{Jx, Jy, h, gamma};
  * dtheta0, domega0 = dL/d(initial state) (may be NULL).  Returns L, or NaN on a
- * numeric fault / allocation failure. */
+ * numeric fault / allocation failure, and for XYO_MODEL_SI (whose on-site force
+ * jumps at the wrap point, so the pathwise derivative does not exist). */
 double xyo_adjoint(const xyo_model* m, const double* theta0, const double* omega0,
                    uint64_t nsteps, uint64_t window, double* grad, double* dtheta0, double* domega0);
 /* The same loss by a plain forward run (for finite differences). */
