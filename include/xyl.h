@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define XYL_ABI_VERSION 1
+#define XYL_ABI_VERSION 2
 
 enum {
     XYL_OK = 0,
@@ -76,6 +76,20 @@ enum { XYL_F32 = 0, XYL_F64 = 1 };
 typedef struct {
     double e_pot, e_kin, m_s, f0, fkx, fky;
 } xyl_obs;
+
+/* Models (Sec. III.A, Eq. XY-Hamilton-Field, with H = sum Jx cos(q dth_x)
+ * + Jy cos(q dth_y) - h cos(p th) in this library's sign convention, so the
+ * paper's J_par, J_perp and h are -Jx, -Jy and -h):
+ *   XYL_MODEL_XY: q = 1, p = 2, angles in [-pi, pi); rotor (cos th, sin th),
+ *                 order-parameter component cos th.  The default.
+ *   XYL_MODEL_SI: the Si(001) dimer mapping of Sec. III.C: q = 2, real p
+ *                 (the paper uses 2.5), angles in [-pi/2, pi/2) (a modulo after
+ *                 every step, Sec. III.D); rotor (cos 2th, sin 2th),
+ *                 order-parameter component sin 2th (Sec. IV.A, Eq.
+ *                 lattice-average); domain spin eps_i * (th_i >= 0 ? +1 : -1).
+ *                 The field's force jumps at +-pi/2, so the adjoint calls
+ *                 refuse this model (XYL_EUNSUPPORTED). */
+enum { XYL_MODEL_XY = 0, XYL_MODEL_SI = 1 };
 
 typedef struct xyl_lattice xyl_lattice;
 typedef struct xyl_ensemble xyl_ensemble;
@@ -107,20 +121,28 @@ int xyl_set_stream(xyl_lattice* h, void* stream);
 /* Model and integrator parameters (Eq. (1), Eq. Si-Langevin, App. A.1).
  * dt > 0, gamma >= 0, all finite.  Takes effect at the next step. */
 int xyl_set_params(xyl_lattice* h, double Jx, double Jy, double hfield, double gamma, double dt);
+/* Selects the model (XYL_MODEL_*).  XYL_MODEL_XY needs p = 2; XYL_MODEL_SI
+ * takes any finite 0 < p <= 16.  The state becomes undefined (ESTATE until the
+ * next init or set_state call), because the two models' angle ranges differ. */
+int xyl_set_model(xyl_lattice* h, int32_t model, double p);
 /* Temperature schedule T(k), piecewise linear in the step index between knots
  * (k_j, T_j) and held outside them (Sec. II.B, Eq. Linear-Quench, with the
  * reduced temperature written as T).  1 <= n <= XYL_MAX_KNOTS, knot steps
  * strictly increasing, T_j >= 0 and finite. */
 int xyl_set_schedule(xyl_lattice* h, const uint64_t* knot_step, const double* knot_T, int32_t n);
 int xyl_set_seed(xyl_lattice* h, uint64_t seed, uint32_t replica);
-/* th_i = pi (2 U(w_{i&3}) - 1) from the Philox block of counter
- * (i>>2, replica, 2^32-1, 2^32-1) (the reserved step 2^64 - 1), computed in
- * float64 and rounded to the state precision; w = 0; step k = 0. */
+/* th_i = W (2 U(w_{i&3}) - 1) from the Philox block of counter
+ * (i>>2, replica, 2^32-1, 2^32-1) (the reserved step 2^64 - 1), with W = pi
+ * (XY) or pi/2 (SI), computed in float64 and rounded to the state precision;
+ * w = 0; step k = 0. */
 int xyl_init_random(xyl_lattice* h);
-/* Staggered ground state: th_i = 0 where sign*eps_i = +1, else -pi_p; w = 0; k = 0. */
+/* Ordered state; w = 0; k = 0.  XY: th_i = 0 where sign*eps_i = +1, else
+ * -pi_p (the staggered ground state).  SI: th_i = sign*eps_i*th0 with
+ * th0 = pi/p (the field's minimum) when h < 0 and p > 2, else th0 = 0. */
 int xyl_init_ordered(xyl_lattice* h, int32_t sign);
 /* Copies a host state (float64, Lx*Ly each; converted to the state precision)
- * and sets the step index.  theta entries must be finite with |th| <= 3 pi. */
+ * and sets the step index.  theta entries must be finite with |th| <= 3 pi
+ * (XY) or, after rounding to the state precision, in [-pi_p/2, pi_p/2) (SI). */
 int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint64_t step);
 /* Copies the synchronized state (th^k, w^k) at the current step to host
  * float64 arrays (either may be NULL) and the step index (may be NULL). */
@@ -140,11 +162,12 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
 int xyl_measure(xyl_lattice* h, xyl_obs* out);
 /* Staggered rotor correlation along axis (0 = x, 1 = y) at the current step
  * (App. C, two-point function of the rotors, lattice average):
- * C(r) = (1/N) sum_i eps_i eps_j cos(th_i - th_j), j = i + r along the axis,
+ * C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along the axis,
  * r = 0..rmax, 0 <= rmax <= L_axis/2.  C has rmax+1 entries.  Synchronises. */
 int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C);
 /* Frozen domains of the current angles (Abstract; Figs. 1 and 6): spin
- * s_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1), clusters of equal spin under
+ * s_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1) (XY; eps_i * (th_i >= 0 ? +1 : -1)
+ * for SI), clusters of equal spin under
  * 4-neighbour periodic connectivity.  labels (nullable, Lx*Ly) receives for
  * each site the smallest linear index of its cluster.  The size distribution
  * is returned as pairs (sizes[j], counts[j]) sorted by size, j < *n_sizes;
@@ -197,6 +220,8 @@ typedef struct {
     uint64_t knot_step[XYL_MAX_KNOTS];
     double knot_T[XYL_MAX_KNOTS];
     uint64_t nsteps;
+    int32_t model;    /* XYL_MODEL_*; every replica of an ensemble has the same */
+    double p;         /* field order, as for xyl_set_model */
 } xyl_replica_desc;
 
 /* Creates n >= 1 replicas on one device in one state allocation, indexed by a
@@ -241,7 +266,7 @@ int xyl_ensemble_sync(xyl_ensemble* e);
  * checkpoint every `ckpt_every` steps, and returns L; the lattice advances.
  * xyl_adjoint_backward then returns dL/d(Jx, Jy, h, gamma) in grad[4] (gamma
  * must be > 0 when T > 0) and writes dL/d th^{k0} and dL/d w^{k0} as float64
- * host arrays (nullable).  1 <= W <= N. */
+ * host arrays (nullable).  1 <= W <= N.  XYL_MODEL_XY only. */
 int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss);
 int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* domega0);
 

@@ -47,7 +47,18 @@ class ReplicaDesc(ctypes.Structure):
         ("knot_step", ctypes.c_uint64 * MAX_KNOTS),
         ("knot_T", ctypes.c_double * MAX_KNOTS),
         ("nsteps", ctypes.c_uint64),
+        ("model", ctypes.c_int32),
+        ("p", ctypes.c_double),
     ]
+
+
+# XYL_MODEL_*: the XY lattice with a two-fold field, and the paper's Si(001)
+# dimer mapping (q = 2, p-fold field, half-circle angles)
+MODELS = {"xy": 0, "si": 1}
+
+
+def _model_code(model) -> int:
+    return MODELS[model] if isinstance(model, str) else int(model)
 
 
 _lib = None
@@ -63,6 +74,7 @@ _SIGS = {
     "xyl_destroy": (_i32, [_vp]),
     "xyl_set_stream": (_i32, [_vp, _vp]),
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
+    "xyl_set_model": (_i32, [_vp, _i32, _d]),
     "xyl_set_schedule": (_i32, [_vp, P(_u64), P(_d), _i32]),
     "xyl_set_seed": (_i32, [_vp, _u64, _u32]),
     "xyl_init_random": (_i32, [_vp]),
@@ -156,7 +168,7 @@ class Lattice:
 
     def __init__(self, Lx: int, Ly: int, dtype="f32", device: int = 0, *, Jx=1.0, Jy=-0.1, h=0.5,
                  gamma=1.0, dt=0.01, schedule: Sequence[Tuple[int, float]] = ((0, 0.0),), seed=0,
-                 replica=0, stream=None, torch_buffers: bool = True):
+                 replica=0, stream=None, torch_buffers: bool = True, model="xy", p=2.0):
         import torch
         lib = load()
         self.Lx, self.Ly, self.N = int(Lx), int(Ly), int(Lx) * int(Ly)
@@ -175,6 +187,7 @@ class Lattice:
         if stream is not None:
             _check(lib.xyl_set_stream(self._h, _vp(int(stream))))
         self.set_params(Jx, Jy, h, gamma, dt)
+        self.set_model(model, p)
         self.set_schedule(schedule)
         self.set_seed(seed, replica)
 
@@ -200,6 +213,13 @@ class Lattice:
     def set_params(self, Jx, Jy, h, gamma, dt):
         self.params = dict(Jx=float(Jx), Jy=float(Jy), h=float(h), gamma=float(gamma), dt=float(dt))
         _check(load().xyl_set_params(self._h, float(Jx), float(Jy), float(h), float(gamma), float(dt)))
+
+    def set_model(self, model="xy", p=2.0):
+        """"xy" (q = 1, p = 2) or "si" (the Si(001) mapping: q = 2, field order p,
+        angles in [-pi/2, pi/2)).  The state must be initialised again afterwards."""
+        code = _model_code(model)
+        _check(load().xyl_set_model(self._h, code, float(p)))
+        self.model, self.p = code, float(p)
 
     def set_schedule(self, schedule):
         ks, Ts, n = _sched_arrays(schedule)
@@ -310,6 +330,7 @@ class Lattice:
         th, om, k = self.get_state()
         payload = dict(theta=th, omega=om, step=np.uint64(k), Lx=self.Lx, Ly=self.Ly, dtype=self.dtype,
                        params=np.array([self.params[n] for n in ("Jx", "Jy", "h", "gamma", "dt")]),
+                       model=np.int32(self.model), p=np.float64(self.p),
                        schedule=np.array(self._schedule, dtype=np.float64),
                        key=np.array([self._seed, self._replica], dtype=np.uint64))
         payload["checksum"] = np.frombuffer(_checksum(payload), dtype=np.uint8)
@@ -325,7 +346,8 @@ class Lattice:
         sched = [(int(k), float(T)) for k, T in d["schedule"]]
         seed, rep = (int(v) for v in d["key"])
         lat = cls(int(d["Lx"]), int(d["Ly"]), dtype=int(d["dtype"]), device=device, Jx=p[0], Jy=p[1], h=p[2],
-                  gamma=p[3], dt=p[4], schedule=sched, seed=seed, replica=rep, stream=stream)
+                  gamma=p[3], dt=p[4], schedule=sched, seed=seed, replica=rep, stream=stream,
+                  model=int(d["model"]), p=float(d["p"]))
         lat.set_state(d["theta"], d["omega"], int(d["step"]))
         return lat
 
@@ -386,6 +408,8 @@ class Ensemble:
                 d.knot_step[j] = int(k)
                 d.knot_T[j] = float(T)
             d.nsteps = int(s.nsteps)
+            d.model = _model_code(getattr(s, "model", "xy"))
+            d.p = float(getattr(s, "p", 2.0))
         self.dtype = _dtype_code(dtype)
         self._h = _vp()
         _check(load().xyl_ensemble_create(ctypes.byref(self._h), arr, n, self.dtype, int(device)))

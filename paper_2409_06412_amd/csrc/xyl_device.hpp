@@ -83,6 +83,14 @@ struct Prec<float> {
         s = __builtin_amdgcn_sinf(x);
         c = __builtin_amdgcn_cosf(x);
     }
+    // sin 2t, cos 2t: 2t / 2pi revolutions = t / pi
+    __device__ static __forceinline__ void sincos2(float t, float& s, float& c) {
+        const float x = t * 0.318309886183790672f;
+        s = __builtin_amdgcn_sinf(x);
+        c = __builtin_amdgcn_cosf(x);
+    }
+    // sin(p t) with f = p / 2pi (revolutions per radian)
+    __device__ static __forceinline__ float sin_scaled(float t, float f) { return __builtin_amdgcn_sinf(t * f); }
     __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     // ((r >> 9) + 1/2) 2^-23, exactly: the top 23 bits under the exponent of
     // 1.0 (one v_alignbit: (0x7f << 23) | (r >> 9)) give 1 + (r >> 9) 2^-23 in
@@ -106,6 +114,9 @@ struct Prec<double> {
     static constexpr double kTwoPi = 6.28318530717958623200e+00;
     static constexpr double kHalfPi = 1.57079632679489655800e+00;
     __device__ static __forceinline__ void sincos(double t, double& s, double& c) { ::sincos(t, &s, &c); }
+    __device__ static __forceinline__ void sincos2(double t, double& s, double& c) { ::sincos(2.0 * t, &s, &c); }
+    // sin(p t) with f = p
+    __device__ static __forceinline__ double sin_scaled(double t, double f) { return sin(f * t); }
     __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
     __device__ static __forceinline__ double uniform(uint32_t r) { return ((double)(r >> 9) + 0.5) * 0x1p-23; }
     __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, double& nc, double& ns) {
@@ -117,16 +128,26 @@ struct Prec<double> {
     }
 };
 
-// Wrap to [-pi_p, pi_p): exact by Sterbenz's lemma while |dt * u| < pi.  Two
-// selects instead of branches; same result as "if t >= pi: t -= 2 pi, else if
-// t < -pi: t += 2 pi" for every input (after the first select t < pi holds,
-// and a value that the first select moved is >= -pi).
-template <typename R>
+// Wrap to [-W, W) with W = pi_p (XY) or pi_p / 2 (SI, whose rotors are half
+// circles): exact by Sterbenz's lemma while |dt * u| < W.  Two selects
+// instead of branches; same result as "if t >= W: t -= 2W, else if t < -W:
+// t += 2W" for every input (after the first select t < W holds, and a value
+// that the first select moved is >= -W).
+template <typename R, int M>
 __device__ __forceinline__ R wrap_angle(R t) {
-    const R lo = t - Prec<R>::kTwoPi;
-    t = t >= Prec<R>::kPi ? lo : t;
-    const R hi = t + Prec<R>::kTwoPi;
-    return t < -Prec<R>::kPi ? hi : t;
+    constexpr R W = M == kModelSI ? Prec<R>::kHalfPi : Prec<R>::kPi;
+    constexpr R W2 = M == kModelSI ? Prec<R>::kPi : Prec<R>::kTwoPi;
+    const R lo = t - W2;
+    t = t >= W ? lo : t;
+    const R hi = t + W2;
+    return t < -W ? hi : t;
+}
+
+// Rotor of a site, (sin q t, cos q t): q = 1 (XY) or 2 (SI).
+template <typename R, int M>
+__device__ __forceinline__ void rotor(R t, R& s, R& c) {
+    if constexpr (M == kModelSI) Prec<R>::sincos2(t, s, c);
+    else Prec<R>::sincos(t, s, c);
 }
 
 // Four Gaussian draws of the sites 4q..4q+3 (q = i >> 2) at step k.
@@ -139,13 +160,26 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
 
 // ------------------------------------------------------ per-site BBK math
 // Shared by every kernel that advances sites, so that their states agree bit
-// for bit.  F = -dH/dth from the sine/cosine of the site and its neighbours
-// (x-1, x+1, y-1, y+1):
-//   F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [s (cy+ + cy-) - c (sy+ + sy-)] - 4 h s c
-template <typename R>
+// for bit.  F = -dH/dth from the rotors (s, c) = (sin q th, cos q th) of the
+// site and its neighbours (x-1, x+1, y-1, y+1) and, for SI, the raw angle:
+//   XY: F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [s (cy+ + cy-) - c (sy+ + sy-)] - 4 h s c
+//   SI: F = 2Jx [s (cx+ + cx-) - c (sx+ + sx-)] + 2Jy [...] - p h sin(p th)
+// (v.Jx, v.Jy hold q Jx, q Jy).
+template <typename R, int M>
 __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm, R sxp, R cxp, R sym, R cym, R syp,
-                                        R cyp) {
-    if constexpr (sizeof(R) == 4) {
+                                        R cyp, R th) {
+    if constexpr (M == kModelSI) {
+        const R sp = Prec<R>::sin_scaled(th, v.pf);
+        if constexpr (sizeof(R) == 4) {
+            const R P = Prec<R>::fma(v.Jx, cxp + cxm, v.Jy * (cyp + cym));
+            const R Q = Prec<R>::fma(v.Jx, sxp + sxm, v.Jy * (syp + sym));
+            return Prec<R>::fma(-v.ph, sp, Prec<R>::fma(s, P, -(c * Q)));
+        } else {
+            const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
+            const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
+            return Prec<R>::fma(-v.ph, sp, Prec<R>::fma(v.Jx, fx, v.Jy * fy));
+        }
+    } else if constexpr (sizeof(R) == 4) {
         // FP32: grouped as s (Jx Cx + Jy Cy - 4h c) - c (Jx Sx + Jy Sy), 11 operations
         const R P = Prec<R>::fma(-v.h4, c, Prec<R>::fma(v.Jx, cxp + cxm, v.Jy * (cyp + cym)));
         const R Q = Prec<R>::fma(v.Jx, sxp + sxm, v.Jy * (syp + sym));
@@ -158,11 +192,19 @@ __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm,
     }
 }
 
+// cos of the field's angle for the energy, in FP64: cos 2th = c^2 - s^2 from
+// the rotor (XY), cos(p th) of the raw angle (SI).
+template <typename R, int M>
+__device__ __forceinline__ double onsite_cos(const Lat<R>& v, R th, double s, double c) {
+    if constexpr (M == kModelSI) return cos(v.pd * (double)th);
+    else return c * c - s * s;
+}
+
 // Completes the previous step's second half-kick (w^k; skipped at the fresh
 // step, where u already holds w^k), then the next first half-kick, the drift
 // and the wrap (App. A.1, Eqs. BBK-2 and BBK-1), with the fma order the
 // oracle uses.
-template <typename R>
+template <typename R, int M>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
     if constexpr (sizeof(R) == 4) {
@@ -185,7 +227,7 @@ __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n
         t2 = Prec<R>::fma(hs, n, t2);
         unew = Prec<R>::fma(v.a, ww, t2);
     }
-    thnew = wrap_angle<R>(Prec<R>::fma(v.dt, unew, th));
+    thnew = wrap_angle<R, M>(Prec<R>::fma(v.dt, unew, th));
 }
 
 // ---------------------------------------------------- lane exchange (DPP)

@@ -32,8 +32,12 @@ struct Lat {
     int32_t Lx, Ly;
     int32_t nxw;           // wave chunks per row: ceil(Lx / 256)
     int32_t stag_x, stag_y;
-    R Jx, Jy, h4, a, c, hdt, dt;   // state-precision coefficients
-    double Jxd, Jyd, hd;           // FP64 copies for the energy
+    int32_t model;         // kModelXY or kModelSI (selects the kernel instance)
+    // state-precision coefficients: force couplings q Jx, q Jy; 4h (XY field
+    // force); p h and the field's angular factor (SI: p / 2pi revolutions in
+    // FP32, p in FP64)
+    R Jx, Jy, h4, ph, pf, a, c, hdt, dt;
+    double Jxd, Jyd, hd, pd;       // FP64 copies for the energy
     double gamma, dtd;             // FP64 for the noise amplitude
     Schedule sched;
     uint32_t seed_lo, seed_hi, replica;
@@ -59,6 +63,10 @@ inline size_t part_elems(int nrowparts) {
 // Step-kernel modes (bit flags).
 enum : int { kStore = 1, kMeasure = 2, kOmega = 4 };
 
+// Models: the XY lattice with a two-fold field (q = 1, p = 2, angles in
+// [-pi, pi)) and the Si(001) mapping (q = 2, real p, angles in [-pi/2, pi/2)).
+enum : int { kModelXY = 0, kModelSI = 1 };
+
 struct Launch {
     int rows = 16;     // rows per strip
     int wpb = 4;       // waves per workgroup
@@ -74,7 +82,7 @@ template <typename R>
 void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j,
                  hipStream_t s);
 template <typename R>
-void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int rows, int wpb,
+void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int model, int rows, int wpb,
                           const uint64_t* kdev, uint64_t j, hipStream_t s);
 template <typename R>
 void launch_init_random(const Lat<R>& v, hipStream_t s);
@@ -88,10 +96,10 @@ void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
 void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
 void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
 template <typename R>
-void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int axis, int rmax, double* part,
+void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,
                         double* out, hipStream_t s);
 template <typename R>
-void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent, uint32_t* size,
+void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
                     uint32_t* hist, uint32_t* stats, hipStream_t s);
 
 template <typename R>
@@ -111,7 +119,7 @@ struct LdsJobHost {
     double* obs;
 };
 int lds_threads(int N);
-void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites,
+void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites, int model,
                          uint64_t j0, hipStream_t s);
 
 struct Error : std::runtime_error {

@@ -5,14 +5,15 @@
 namespace xyl {
 
 // --------------------------------------------------------- correlation
-// C(r) = (1/N) sum_i eps_i eps_j cos(th_i - th_j), j = i + r along one axis
-// (App. C, two-point function of the rotors averaged over the lattice).  One
-// workgroup per line (row for axis 0, column for axis 1) stages the line's
-// staggered rotors (eps cos th, eps sin th) in LDS in FP64; thread r sums the
-// line's products in index order.  A second pass sums the lines in order.
+// C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along one
+// axis (App. C, two-point function of the rotors averaged over the lattice;
+// q = 1 for XY, 2 for the Si mapping).  One workgroup per line (row for axis
+// 0, column for axis 1) stages the line's staggered rotors (eps cos q th,
+// eps sin q th) in LDS in FP64; thread r sums the line's products in index
+// order.  A second pass sums the lines in order.
 template <typename R>
 __global__ __launch_bounds__(256) void k_corr_lines(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
-                                                    int axis, int rmax, double* __restrict__ part) {
+                                                    double q, int axis, int rmax, double* __restrict__ part) {
     extern __shared__ double lds[];
     const int line = blockIdx.x;
     const int L = axis == 0 ? Lx : Ly;
@@ -24,7 +25,7 @@ __global__ __launch_bounds__(256) void k_corr_lines(const R* __restrict__ th, in
         const double t = (double)th[(size_t)y * Lx + x];
         const double e = (((x * sx) + (y * sy)) & 1) ? -1.0 : 1.0;
         double s, c;
-        sincos(t, &s, &c);
+        sincos(q * t, &s, &c);
         cs[p] = e * c;
         sn[p] = e * s;
     }
@@ -49,24 +50,26 @@ __global__ void k_corr_sum(const double* __restrict__ part, int nlines, int rmax
 }
 
 template <typename R>
-void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int axis, int rmax, double* part, double* out,
-                        hipStream_t s) {
+void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,
+                        double* out, hipStream_t s) {
     const int nlines = axis == 0 ? Ly : Lx;
     const int L = axis == 0 ? Lx : Ly;
     const size_t lds = 2 * sizeof(double) * (size_t)L;
-    k_corr_lines<R><<<nlines, 256, lds, s>>>(th, Lx, Ly, sx, sy, axis, rmax, part);
+    k_corr_lines<R><<<nlines, 256, lds, s>>>(th, Lx, Ly, sx, sy, model == kModelSI ? 2.0 : 1.0, axis, rmax, part);
     check_hip(hipGetLastError(), "correlation kernel launch");
     k_corr_sum<<<(rmax + 256) / 256, 256, 0, s>>>(part, nlines, rmax, (double)Lx * (double)Ly, out);
     check_hip(hipGetLastError(), "correlation sum launch");
 }
 
 // -------------------------------------------------------------- domains
-// Spin of site (x, y): eps * (|th| <= pi_p / 2 ? +1 : -1), decided in the
-// state precision.
+// Spin of site (x, y), decided in the state precision: eps * (|th| <= pi_p/2
+// ? +1 : -1) (the sign of cos th, XY) or eps * (th >= 0 ? +1 : -1) (the sign
+// of sin 2th on the half circle, SI).
 template <typename R>
-__device__ __forceinline__ int spin_of(const R* th, int Lx, int x, int y, int sx, int sy) {
+__device__ __forceinline__ int spin_of(const R* th, int Lx, int x, int y, int sx, int sy, int model) {
     const R t = th[(size_t)y * Lx + x];
-    const int s = (t <= Prec<R>::kHalfPi && t >= -Prec<R>::kHalfPi) ? 1 : -1;
+    const bool up = model == kModelSI ? t >= R(0) : (t <= Prec<R>::kHalfPi && t >= -Prec<R>::kHalfPi);
+    const int s = up ? 1 : -1;
     return (((x * sx) + (y * sy)) & 1) ? -s : s;
 }
 
@@ -116,15 +119,15 @@ __global__ void k_uf_init(int32_t* parent, uint32_t* size, size_t N) {
 }
 
 template <typename R>
-__global__ void k_uf_merge(const R* __restrict__ th, int Lx, int Ly, int sx, int sy, int32_t* parent) {
+__global__ void k_uf_merge(const R* __restrict__ th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)Lx * Ly) return;
     const int x = (int)(i % Lx), y = (int)(i / Lx);
-    const int s = spin_of(th, Lx, x, y, sx, sy);
+    const int s = spin_of(th, Lx, x, y, sx, sy, model);
     const int xp = x + 1 == Lx ? 0 : x + 1;
     const int yp = y + 1 == Ly ? 0 : y + 1;
-    if (spin_of(th, Lx, xp, y, sx, sy) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)y * Lx + xp));
-    if (spin_of(th, Lx, x, yp, sx, sy) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)yp * Lx + x));
+    if (spin_of(th, Lx, xp, y, sx, sy, model) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)y * Lx + xp));
+    if (spin_of(th, Lx, x, yp, sx, sy, model) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)yp * Lx + x));
 }
 
 __global__ void k_uf_flatten(int32_t* parent, uint32_t* size, size_t N) {
@@ -155,13 +158,14 @@ __global__ void k_uf_label(int32_t* parent, size_t N) {
 }
 
 template <typename R>
-void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent, uint32_t* size, uint32_t* hist,
+void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
+                    uint32_t* hist,
                     uint32_t* stats, hipStream_t s) {
     const size_t N = (size_t)Lx * Ly;
     const unsigned nb = (unsigned)((N + 255) / 256);
     k_uf_init<<<nb, 256, 0, s>>>(parent, size, N);
     check_hip(hipGetLastError(), "uf init launch");
-    k_uf_merge<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, parent);
+    k_uf_merge<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, model, parent);
     check_hip(hipGetLastError(), "uf merge launch");
     k_uf_flatten<<<nb, 256, 0, s>>>(parent, size, N);
     check_hip(hipGetLastError(), "uf flatten launch");
@@ -171,11 +175,13 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int32_t* parent
     check_hip(hipGetLastError(), "uf label launch");
 }
 
-template void launch_correlation<float>(const float*, int, int, int, int, int, int, double*, double*, hipStream_t);
-template void launch_correlation<double>(const double*, int, int, int, int, int, int, double*, double*, hipStream_t);
-template void launch_domains<float>(const float*, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+template void launch_correlation<float>(const float*, int, int, int, int, int, int, int, double*, double*,
+                                        hipStream_t);
+template void launch_correlation<double>(const double*, int, int, int, int, int, int, int, double*, double*,
+                                         hipStream_t);
+template void launch_domains<float>(const float*, int, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
                                     hipStream_t);
-template void launch_domains<double>(const double*, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+template void launch_domains<double>(const double*, int, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
                                      hipStream_t);
 
 }  // namespace xyl

@@ -93,7 +93,15 @@ struct DevBuf {
 // ------------------------------------------------------------ parameters
 struct Params {
     double Jx = 1.0, Jy = -0.1, h = 0.5, gamma = 1.0, dt = 0.01;
+    int model = kModelXY;   // XYL_MODEL_XY / XYL_MODEL_SI
+    double p = 2.0;         // field order
 };
+
+static void validate_model(int model, double p) {
+    require(model == XYL_MODEL_XY || model == XYL_MODEL_SI, XYL_EINVAL, "model must be XYL_MODEL_XY or XYL_MODEL_SI");
+    if (model == XYL_MODEL_XY) require(p == 2.0, XYL_EINVAL, "the XY model has p = 2");
+    else require(std::isfinite(p) && p > 0.0 && p <= 16.0, XYL_EINVAL, "p must be in (0, 16]");
+}
 
 static void validate_params(const Params& p) {
     require(std::isfinite(p.Jx) && std::isfinite(p.Jy) && std::isfinite(p.h) && std::isfinite(p.gamma) &&
@@ -124,9 +132,15 @@ static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule&
     v.nxw = (Lx + kWaveSites - 1) / kWaveSites;
     v.stag_x = p.Jx > 0.0 ? 1 : 0;
     v.stag_y = p.Jy > 0.0 ? 1 : 0;
-    v.Jx = (R)p.Jx;
-    v.Jy = (R)p.Jy;
+    v.model = p.model;
+    const double q = p.model == kModelSI ? 2.0 : 1.0;
+    v.Jx = (R)(q * p.Jx);
+    v.Jy = (R)(q * p.Jy);
     v.h4 = (R)(4.0 * p.h);
+    v.ph = (R)(p.p * p.h);
+    // FP32 native sine takes revolutions: sin(p t) = sin_rev(t * p / 2pi)
+    v.pf = sizeof(R) == 4 ? (R)(p.p / (2.0 * M_PI)) : (R)p.p;
+    v.pd = p.p;
     v.a = (R)(1.0 - 0.5 * p.gamma * p.dt);
     v.c = (R)(1.0 / (1.0 + 0.5 * p.gamma * p.dt));
     v.hdt = (R)(0.5 * p.dt);
@@ -430,7 +444,8 @@ static void lattice_omega(xyl_lattice* h, double* omega) {
 }
 
 template <typename R>
-static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, DevBuf<int32_t>& parent, DevBuf<uint32_t>& usz,
+static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, DevBuf<int32_t>& parent,
+                        DevBuf<uint32_t>& usz,
                         DevBuf<uint32_t>& hist, DevBuf<uint32_t>& stats, hipStream_t s, int32_t* labels,
                         uint64_t* sizes, uint64_t* counts, uint64_t cap, uint64_t* n_sizes, uint64_t* n_domains,
                         uint64_t* max_size) {
@@ -441,7 +456,7 @@ static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, DevBuf<int3
     stats.reserve(2);
     check_hip(hipMemsetAsync(hist.p, 0, sizeof(uint32_t) * (N + 1), s), "hipMemsetAsync");
     check_hip(hipMemsetAsync(stats.p, 0, sizeof(uint32_t) * 2, s), "hipMemsetAsync");
-    launch_domains<R>(th, Lx, Ly, sx, sy, parent.p, usz.p, hist.p, stats.p, s);
+    launch_domains<R>(th, Lx, Ly, sx, sy, model, parent.p, usz.p, hist.p, stats.p, s);
     std::vector<uint32_t> hh(N + 1);
     uint32_t st[2];
     check_hip(hipMemcpyAsync(hh.data(), hist.p, sizeof(uint32_t) * (N + 1), hipMemcpyDeviceToHost, s), "D2H");
@@ -585,9 +600,25 @@ int xyl_set_stream(xyl_lattice* h, void* stream) {
 int xyl_set_params(xyl_lattice* h, double Jx, double Jy, double hf, double gamma, double dt) {
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");
-        Params p{Jx, Jy, hf, gamma, dt};
+        Params p = h->p;
+        p.Jx = Jx;
+        p.Jy = Jy;
+        p.h = hf;
+        p.gamma = gamma;
+        p.dt = dt;
         validate_params(p);
         h->p = p;
+        h->touch();
+    });
+}
+
+int xyl_set_model(xyl_lattice* h, int32_t model, double pfield) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        validate_model(model, pfield);
+        if (model != h->p.model) h->initialized = false;   // the angle ranges differ
+        h->p.model = model;
+        h->p.p = pfield;
         h->touch();
     });
 }
@@ -628,9 +659,17 @@ int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");
         require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
+        // SI: the field is evaluated on the raw angle, so the state must already
+        // lie in the half circle [-pi_p/2, pi_p/2) of the state precision
+        const bool si = h->p.model == kModelSI;
+        const double wp = h->dtype == XYL_F64 ? Prec<double>::kHalfPi : (double)Prec<float>::kHalfPi;
         for (size_t i = 0; i < h->N; ++i) {
             require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI, XYL_EINVAL,
                     "theta entries must be finite with |theta| <= 3 pi");
+            if (si) {
+                const double t = h->dtype == XYL_F64 ? theta[i] : (double)(float)theta[i];
+                require(t >= -wp && t < wp, XYL_EINVAL, "theta entries must lie in [-pi/2, pi/2) for the SI model");
+            }
             require(std::isfinite(omega[i]), XYL_EINVAL, "omega entries must be finite");
         }
         DeviceGuard g(h->device);
@@ -656,12 +695,15 @@ int xyl_init_ordered(xyl_lattice* h, int32_t sign) {
     }
     std::vector<double> th(h->N), om(h->N, 0.0);
     const double pi_p = h->dtype == XYL_F64 ? Prec<double>::kPi : (double)Prec<float>::kPi;
+    // SI: the field -h cos(p th) with h < 0 is lowest at th = +-pi/p
+    const double th0 = (h->p.h < 0.0 && h->p.p > 2.0) ? M_PI / h->p.p : 0.0;
     const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
     for (int y = 0; y < h->Ly; ++y)
         for (int x = 0; x < h->Lx; ++x) {
             int e = ((x * sx + y * sy) & 1) ? -1 : 1;
             if (sign < 0) e = -e;
-            th[(size_t)y * h->Lx + x] = e > 0 ? 0.0 : -pi_p;
+            if (h->p.model == kModelSI) th[(size_t)y * h->Lx + x] = e > 0 ? th0 : -th0;
+            else th[(size_t)y * h->Lx + x] = e > 0 ? 0.0 : -pi_p;
         }
     return xyl_set_state(h, th.data(), om.data(), 0);
 }
@@ -765,11 +807,11 @@ int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C) {
         double* outd = h->dscratch.p + (size_t)nlines * (rmax + 1);
         const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
         if (h->dtype == XYL_F64)
-            launch_correlation<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, axis, rmax,
-                                       part, outd, h->stream);
+            launch_correlation<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model,
+                                       axis, rmax, part, outd, h->stream);
         else
-            launch_correlation<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, axis, rmax,
-                                      part, outd, h->stream);
+            launch_correlation<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model,
+                                      axis, rmax, part, outd, h->stream);
         check_hip(hipMemcpyAsync(C, outd, sizeof(double) * (rmax + 1), hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     });
@@ -782,10 +824,12 @@ int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* coun
         DeviceGuard g(h->device);
         const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
         if (h->dtype == XYL_F64)
-            run_domains<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->parent, h->usz,
+            run_domains<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model,
+                                h->parent, h->usz,
                                 h->hist, h->stats, h->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
         else
-            run_domains<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->parent, h->usz,
+            run_domains<float>(static_cast<const float*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model,
+                               h->parent, h->usz,
                                h->hist, h->stats, h->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
     });
 }
@@ -1067,7 +1111,7 @@ struct xyl_ensemble {
         v.th[1] = t1;
         v.u = static_cast<R*>(u) + off[r];
         v.cur = 0;
-        Params p{d.Jx, d.Jy, d.h, d.gamma, d.dt};
+        Params p{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p};
         Schedule s{};
         s.n = d.nknots;
         for (int q = 0; q < d.nknots; ++q) {
@@ -1091,6 +1135,7 @@ struct xyl_ensemble {
         return static_cast<char*>(th[(int)(k[r] & 1)]) + es * off[r];
     }
     int nrp(int r) const { return desc[r].Ly * ((desc[r].Lx + kWaveSites - 1) / kWaveSites); }
+    int model() const { return desc[0].model; }
 };
 
 template <typename R>
@@ -1271,20 +1316,21 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                       "H2D");
             check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
             launch_ensemble_lds(reinterpret_cast<const Lat<float>*>(e->lds_reps.p), e->lds_jobs.p,
-                                (int)lds_set.size(), e->lds_threads, e->lds_max_sites, e->j, e->side);
+                                (int)lds_set.size(), e->lds_threads, e->lds_max_sites, e->model(), e->j, e->side);
         }
         // large replicas
         if (!active_g.empty()) {
             if (active_g != e->task_active) ens_upload_table<R>(e, e->j, active_g);
             const Lat<R>* reps = reinterpret_cast<const Lat<R>*>(e->reps.p);
             launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, meas_g.empty() ? kStore : (kStore | kMeasure),
-                                    e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
+                                    e->model(), e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
             for (int r : meas_g)
                 jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                                (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
             flush_finalize(e, jobs);
             for (uint64_t c = 1; c < chunk; ++c)
-                launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->launch.rows, e->launch.wpb, nullptr,
+                launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->model(), e->launch.rows, e->launch.wpb,
+                                        nullptr,
                                         e->j + c, e->stream);
         }
         for (int r : only_meas_g) {
@@ -1365,7 +1411,7 @@ static Launch ensemble_autotune_impl(xyl_ensemble* e) {
             check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             for (int i = 0; i < steps; ++i)
                 launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), dtasks.p, (int)tk.size(), kStore,
-                                        rows, w, kc.p, (uint64_t)i, cap);
+                                        e->model(), rows, w, kc.p, (uint64_t)i, cap);
             check_hip(hipStreamEndCapture(cap, &g), "hipStreamEndCapture");
             hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -1429,7 +1475,9 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
         for (int r = 0; r < n; ++r) {
             const xyl_replica_desc& d = desc[r];
             validate_shape(d.Lx, d.Ly);
-            validate_params(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt});
+            validate_params(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p});
+            validate_model(d.model, d.p);
+            require(d.model == desc[0].model, XYL_EINVAL, "all replicas of an ensemble must use the same model");
             (void)make_schedule(d.knot_step, d.knot_T, d.nknots);
             e->off.push_back(e->total);
             // keep every replica's base 256-byte aligned
@@ -1555,9 +1603,16 @@ int xyl_ensemble_set_state(xyl_ensemble* e, int32_t r, const double* theta, cons
         require(e != nullptr && r >= 0 && r < e->n, XYL_EINVAL, "bad handle or replica");
         require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
         const size_t N = (size_t)e->desc[r].Lx * e->desc[r].Ly;
-        for (size_t i = 0; i < N; ++i)
+        const bool si = e->model() == kModelSI;
+        const double wp = e->dtype == XYL_F64 ? Prec<double>::kHalfPi : (double)Prec<float>::kHalfPi;
+        for (size_t i = 0; i < N; ++i) {
             require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI && std::isfinite(omega[i]), XYL_EINVAL,
                     "state entries must be finite with |theta| <= 3 pi");
+            if (si) {
+                const double t = e->dtype == XYL_F64 ? theta[i] : (double)(float)theta[i];
+                require(t >= -wp && t < wp, XYL_EINVAL, "theta entries must lie in [-pi/2, pi/2) for the SI model");
+            }
+        }
         DeviceGuard g(e->device);
         e->k[r] = step;
         e->fresh_k[r] = step;
@@ -1583,10 +1638,12 @@ int xyl_ensemble_domains(xyl_ensemble* e, int32_t r, int32_t* labels, uint64_t* 
         const xyl_replica_desc& d = e->desc[r];
         const int sx = d.Jx > 0.0, sy = d.Jy > 0.0;
         if (e->dtype == XYL_F64)
-            run_domains<double>(static_cast<const double*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, e->parent, e->usz,
+            run_domains<double>(static_cast<const double*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, d.model, e->parent,
+                                e->usz,
                                 e->hist, e->stats, e->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
         else
-            run_domains<float>(static_cast<const float*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, e->parent, e->usz,
+            run_domains<float>(static_cast<const float*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, d.model, e->parent,
+                               e->usz,
                                e->hist, e->stats, e->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
     });
 }
@@ -1778,6 +1835,8 @@ int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, ui
         require(nsteps >= 1, XYL_EINVAL, "nsteps must be >= 1");
         require(window >= 1 && window <= nsteps, XYL_EINVAL, "window must be in [1, nsteps]");
         require(ckpt_every >= 1, XYL_EINVAL, "ckpt_every must be >= 1");
+        require(h->p.model == kModelXY, XYL_EUNSUPPORTED,
+                "the adjoint needs a smooth force: the SI model's field jumps at the wrap point");
         DeviceGuard g(h->device);
         if (h->dtype == XYL_F64) adjoint_forward_impl<double>(h, nsteps, ckpt_every, window, loss);
         else adjoint_forward_impl<float>(h, nsteps, ckpt_every, window, loss);
@@ -1790,6 +1849,7 @@ int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* 
         AdjState* a = static_cast<AdjState*>(h->adj);
         require(a != nullptr, XYL_ESTATE, "no adjoint forward run to differentiate");
         require(h->k == a->k0 + a->N, XYL_ESTATE, "lattice was stepped or reset after xyl_adjoint_forward");
+        require(h->p.model == kModelXY, XYL_EUNSUPPORTED, "the adjoint supports the XY model only");
         DeviceGuard g(h->device);
         if (h->dtype == XYL_F64) adjoint_backward_impl<double>(h, grad, dtheta0, domega0);
         else adjoint_backward_impl<float>(h, grad, dtheta0, domega0);

@@ -29,7 +29,7 @@ struct RowSet {
     R u[4];
 };
 
-template <typename R, int MODE>
+template <typename R, int MODE, int M>
 __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
     const int Lx = v.Lx, Ly = v.Ly;
     const uint64_t k = v.k_base + j;
@@ -63,7 +63,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     };
     auto trig = [&](RowSet<R>& S) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Prec<R>::sincos(S.th[q], S.s[q], S.c[q]);
+        for (int q = 0; q < 4; ++q) rotor<R, M>(S.th[q], S.s[q], S.c[q]);
     };
 
     // One row y with the window P = y-1, C = y, N = y+1 and F = y+2.  At entry
@@ -85,14 +85,14 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         // its right one, from the extra angle loaded with the row; a wave with
         // a single active lane needs both)
         R se, ce;
-        Prec<R>::sincos(edgeL ? C.eL : C.eR, se, ce);
+        rotor<R, M>(edgeL ? C.eL : C.eR, se, ce);
         R sL = from_lane_below(C.s[3]), cL = from_lane_below(C.c[3]);
         R sR = from_lane_above(C.s[0]), cR = from_lane_above(C.c[0]);
         sL = edgeL ? se : sL;
         cL = edgeL ? ce : cL;
         sR = edgeR ? se : sR;
         cR = edgeR ? ce : cR;
-        if (nact == 1) Prec<R>::sincos(C.eR, sR, cR);
+        if (nact == 1) rotor<R, M>(C.eR, sR, cR);
 
         R n[4];
         noise4<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, n);
@@ -102,8 +102,9 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            const R f = site_force<R>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q]);
-            site_update<R>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
+            const R f =
+                site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q]);
+            site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
         }
         if ((MODE & kStore) && act) {
             store4(tho + row + x, tho4);
@@ -124,11 +125,13 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                     const double sxp = (double)(q == 3 ? sR : C.s[q + 1]);
                     const double cxp = (double)(q == 3 ? cR : C.c[q + 1]);
                     const double syp = (double)N.s[q], cyp = (double)N.c[q];
-                    acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) - v.hd * (c * c - s * s);
+                    acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) -
+                              v.hd * onsite_cos<R, M>(v, C.th[q], s, c);
                     acc[1] += 0.5 * (double)w[q] * (double)w[q];
                     const int xs = x + q;
                     const double e = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
-                    const double ec = e * c, es = e * s;
+                    // order-parameter component first: cos th (XY), sin 2th (SI)
+                    const double ec = e * (M == kModelSI ? s : c), es = e * (M == kModelSI ? c : s);
                     acc[2] += ec;
                     acc[3] += es;
                     double pxs, pxc;
@@ -193,17 +196,17 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     }
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int M>
 __global__ __launch_bounds__(512) void k_step(Lat<R> v, const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
     const int wpb = blockDim.x / kWave;
     const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int t = b * wpb + (int)(threadIdx.x / kWave);
     if (t >= ntasks) return;
     const uint64_t j = j0 + (kdev ? *kdev : 0);
-    run_strip<R, MODE>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
+    run_strip<R, MODE, M>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int M>
 __global__ __launch_bounds__(512) void k_ensemble_step(const Lat<R>* __restrict__ reps, const Task* __restrict__ tasks,
                                                        const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
     const int wpb = blockDim.x / kWave;
@@ -212,20 +215,22 @@ __global__ __launch_bounds__(512) void k_ensemble_step(const Lat<R>* __restrict_
     if (t >= ntasks) return;
     const Task task = tasks[t];
     const uint64_t j = j0 + (kdev ? *kdev : 0);
-    run_strip<R, MODE>(reps[task.rep], task.xw, task.strip, rows, j, threadIdx.x & (kWave - 1));
+    run_strip<R, MODE, M>(reps[task.rep], task.xw, task.strip, rows, j, threadIdx.x & (kWave - 1));
 }
 
-template <typename R>
+template <typename R, int M>
 static void dispatch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j, hipStream_t s) {
     const int nstrips = (v.Ly + l.rows - 1) / l.rows;
     const int ntasks = nstrips * v.nxw;
     const int nblocks = (ntasks + l.wpb - 1) / l.wpb;
     const dim3 grid(nblocks), block(l.wpb * kWave);
     switch (mode) {
-        case kStore: k_step<R, kStore><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
-        case kStore | kMeasure: k_step<R, kStore | kMeasure><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
-        case kMeasure: k_step<R, kMeasure><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
-        case kOmega: k_step<R, kOmega><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kStore: k_step<R, kStore, M><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kStore | kMeasure:
+            k_step<R, kStore | kMeasure, M><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks);
+            break;
+        case kMeasure: k_step<R, kMeasure, M><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
+        case kOmega: k_step<R, kOmega, M><<<grid, block, 0, s>>>(v, kdev, j, l.rows, ntasks); break;
         default: throw Error(-5, "unsupported step mode");
     }
     check_hip(hipGetLastError(), "step kernel launch");
@@ -233,24 +238,34 @@ static void dispatch_step(const Lat<R>& v, int mode, const Launch& l, const uint
 
 template <typename R>
 void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j, hipStream_t s) {
-    dispatch_step<R>(v, mode, l, kdev, j, s);
+    if (v.model == kModelSI) dispatch_step<R, kModelSI>(v, mode, l, kdev, j, s);
+    else dispatch_step<R, kModelXY>(v, mode, l, kdev, j, s);
 }
 
-template <typename R>
-void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int rows, int wpb,
-                          const uint64_t* kdev, uint64_t j, hipStream_t s) {
+template <typename R, int M>
+static void dispatch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int rows, int wpb,
+                                   const uint64_t* kdev, uint64_t j, hipStream_t s) {
     const int nblocks = (ntasks + wpb - 1) / wpb;
     const dim3 grid(nblocks), block(wpb * kWave);
     switch (mode) {
-        case kStore: k_ensemble_step<R, kStore><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
+        case kStore: k_ensemble_step<R, kStore, M><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
         case kStore | kMeasure:
-            k_ensemble_step<R, kStore | kMeasure><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks);
+            k_ensemble_step<R, kStore | kMeasure, M><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks);
             break;
-        case kMeasure: k_ensemble_step<R, kMeasure><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
-        case kOmega: k_ensemble_step<R, kOmega><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
+        case kMeasure:
+            k_ensemble_step<R, kMeasure, M><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks);
+            break;
+        case kOmega: k_ensemble_step<R, kOmega, M><<<grid, block, 0, s>>>(reps, tasks, kdev, j, rows, ntasks); break;
         default: throw Error(-5, "unsupported step mode");
     }
     check_hip(hipGetLastError(), "ensemble step kernel launch");
+}
+
+template <typename R>
+void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int model, int rows, int wpb,
+                          const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    if (model == kModelSI) dispatch_ensemble_step<R, kModelSI>(reps, tasks, ntasks, mode, rows, wpb, kdev, j, s);
+    else dispatch_ensemble_step<R, kModelXY>(reps, tasks, ntasks, mode, rows, wpb, kdev, j, s);
 }
 
 // -------------------------------------------- whole replica in LDS (FP32)
@@ -269,6 +284,7 @@ struct LdsJob {
     double* obs;        // 6 doubles
 };
 
+template <int M>
 __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restrict__ reps,
                                                        const LdsJob* __restrict__ jobs, uint64_t j0) {
     extern __shared__ float lds[];
@@ -303,15 +319,15 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             if (g < ng) {
                 float s4[4], c4[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Prec<float>::sincos(th[q][e], s4[e], c4[e]);
+                for (int e = 0; e < 4; ++e) rotor<float, M>(th[q][e], s4[e], c4[e]);
                 store4(S + 4 * g, s4);
                 store4(C + 4 * g, c4);
             }
         }
     };
     // neighbours of group g from the tables; returns the force of its 4 sites
-    auto forces = [&](int g, float f[4], float s4[4], float c4[4], float& sR, float& cR, float sd[4],
-                      float cd[4]) {
+    auto forces = [&](int g, const float t4[4], float f[4], float s4[4], float c4[4], float& sR, float& cR,
+                      float sd[4], float cd[4]) {
         const int i0 = 4 * g;
         const int y = i0 / Lx, x = i0 - y * Lx;
         const int ym = y == 0 ? Ly - 1 : y - 1, yp = y + 1 == Ly ? 0 : y + 1;
@@ -331,7 +347,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
         for (int e = 0; e < 4; ++e) {
             const float sxm = e == 0 ? sL : s4[e - 1], cxm = e == 0 ? cL : c4[e - 1];
             const float sxp = e == 3 ? sR : s4[e + 1], cxp = e == 3 ? cR : c4[e + 1];
-            f[e] = site_force<float>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e]);
+            f[e] = site_force<float, M>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e], t4[e]);
         }
     };
 
@@ -349,7 +365,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                forces(g, f, s4, c4, sR, cR, sd, cd);
+                forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
                 noise4<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, n);
                 const int i0 = 4 * g;
                 const int y = i0 / Lx, x = i0 - y * Lx;
@@ -358,16 +374,16 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w, un, tn;
-                    site_update<float>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, un, tn);
+                    site_update<float, M>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, un, tn);
                     const double sv = (double)s4[e], cv = (double)c4[e];
                     const double sxp = (double)(e == 3 ? sR : s4[e + 1]);
                     const double cxp = (double)(e == 3 ? cR : c4[e + 1]);
                     acc[0] += v.Jxd * (cv * cxp + sv * sxp) + v.Jyd * (cv * (double)cd[e] + sv * (double)sd[e]) -
-                              v.hd * (cv * cv - sv * sv);
+                              v.hd * onsite_cos<float, M>(v, th[q][e], sv, cv);
                     acc[1] += 0.5 * (double)w * (double)w;
                     const int xs = x + e;
                     const double ep = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
-                    const double ec = ep * cv, es = ep * sv;
+                    const double ec = ep * (M == kModelSI ? sv : cv), es = ep * (M == kModelSI ? cv : sv);
                     acc[2] += ec;
                     acc[3] += es;
                     double pxs, pxc;
@@ -420,12 +436,12 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                forces(g, f, s4, c4, sR, cR, sd, cd);
+                forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
                 noise4<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, n);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w;
-                    site_update<float>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, u[q][e], th[q][e]);
+                    site_update<float, M>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, u[q][e], th[q][e]);
                 }
             }
         }
@@ -450,14 +466,21 @@ int lds_threads(int N) {
     return t < kWave ? kWave : t;
 }
 
-void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites,
-                         uint64_t j0, hipStream_t s) {
-    const size_t lds = 2 * sizeof(float) * (size_t)max_sites;
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble_lds),
+template <int M>
+static void dispatch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, size_t lds,
+                                  uint64_t j0, hipStream_t s) {
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble_lds<M>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute");
-    k_ensemble_lds<<<njobs, threads, lds, s>>>(reps, reinterpret_cast<const LdsJob*>(jobs), j0);
+    k_ensemble_lds<M><<<njobs, threads, lds, s>>>(reps, reinterpret_cast<const LdsJob*>(jobs), j0);
     check_hip(hipGetLastError(), "LDS ensemble kernel launch");
+}
+
+void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites, int model,
+                         uint64_t j0, hipStream_t s) {
+    const size_t lds = 2 * sizeof(float) * (size_t)max_sites;
+    if (model == kModelSI) dispatch_ensemble_lds<kModelSI>(reps, jobs, njobs, threads, lds, j0, s);
+    else dispatch_ensemble_lds<kModelXY>(reps, jobs, njobs, threads, lds, j0, s);
 }
 
 // ------------------------------------------------------------------ init
@@ -473,7 +496,9 @@ __global__ void k_init_random(Lat<R> v) {
         const size_t i = q * 4 + p;
         if (i < N) {
             const double uni = ((double)(r.v[p] >> 9) + 0.5) * 0x1p-23;
-            th[i] = (R)(Prec<double>::kPi * (2.0 * uni - 1.0));
+            // W (2U - 1), W = pi or pi/2 (half-circle rotors of the Si mapping)
+            const double W = v.model == kModelSI ? Prec<double>::kPi / 2.0 : Prec<double>::kPi;
+            th[i] = (R)(W * (2.0 * uni - 1.0));
             v.u[i] = R(0);
         }
     }
@@ -633,9 +658,9 @@ void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s) {
 
 template void launch_step<float>(const Lat<float>&, int, const Launch&, const uint64_t*, uint64_t, hipStream_t);
 template void launch_step<double>(const Lat<double>&, int, const Launch&, const uint64_t*, uint64_t, hipStream_t);
-template void launch_ensemble_step<float>(const Lat<float>*, const Task*, int, int, int, int, const uint64_t*,
+template void launch_ensemble_step<float>(const Lat<float>*, const Task*, int, int, int, int, int, const uint64_t*,
                                           uint64_t, hipStream_t);
-template void launch_ensemble_step<double>(const Lat<double>*, const Task*, int, int, int, int, const uint64_t*,
+template void launch_ensemble_step<double>(const Lat<double>*, const Task*, int, int, int, int, int, const uint64_t*,
                                            uint64_t, hipStream_t);
 template void launch_init_random<float>(const Lat<float>&, hipStream_t);
 template void launch_init_random<double>(const Lat<double>&, hipStream_t);

@@ -18,6 +18,16 @@ them, the two-fold field h and damping gamma, dt = 0.01):
     from 1.5 to 0 over tau_Q steps, then holds at 0 for 1000 steps.
   * ``adjoint_512`` 512 x 512, FP32, T = 0.6, seed 7, 5000 steps, loss window
     1000, checkpoints every 100 steps.
+Si(001) model variant (the paper's own mapping, Sec. III.C and IV): q = 2,
+p = 2.5, angles in [-pi/2, pi/2), I J_par = 10, I J_perp = 0.1, I h = 1, eta = 1
+(Sec. IV), i.e. Jx = -10, Jy = -0.1, h = -1 in this project's sign convention;
+the Binder crossing of the paper puts T_c at 0.1969 J_par:
+  * ``si_lattice``   one lattice at a given temperature.
+  * ``si_fss_ensemble`` L in {32, 48, 64, 80, 96, 112, 128, 144} x temperatures
+    around T_c x 2 seeds, ordered starts (Fig. 4 starts ordered).
+  * ``si_quench``    symmetric linear quench T_c (1 + e) -> T_c (1 - e) at rate
+    1/tau_Q in reduced temperature (Sec. II.B, Eq. Linear-Quench), stopped at the
+    end of the ramp (Sec. V).
 The paper runs on synthetic lattices only (no dataset), so nothing here stands
 in for external data.
 """
@@ -44,13 +54,16 @@ class LatticeSpec:
     seed: int = 0
     replica: int = 0
     nsteps: int = 0
+    model: str = "xy"
+    p: float = 2.0
 
     def params(self):
-        return dict(Jx=self.Jx, Jy=self.Jy, h=self.h, gamma=self.gamma, dt=self.dt)
+        return dict(Jx=self.Jx, Jy=self.Jy, h=self.h, gamma=self.gamma, dt=self.dt, model=self.model, p=self.p)
 
     def oracle_kwargs(self):
         return dict(Lx=self.Lx, Ly=self.Ly, Jx=self.Jx, Jy=self.Jy, h=self.h, gamma=self.gamma,
-                    dt=self.dt, schedule=list(self.schedule), seed=self.seed, replica=self.replica)
+                    dt=self.dt, schedule=list(self.schedule), seed=self.seed, replica=self.replica,
+                    model=self.model, p=self.p)
 
 
 def small_fp64() -> LatticeSpec:
@@ -97,6 +110,52 @@ def kz_quench(L: int = 2048, taus=(1_000, 10_000, 100_000), gammas=(0.1, 1.0), h
 
 def adjoint_512(L: int = 512) -> LatticeSpec:
     return LatticeSpec(L, L, schedule=((0, 0.6),), seed=7, replica=0, nsteps=5000)
+
+
+SI = dict(Jx=-10.0, Jy=-0.1, h=-1.0, gamma=1.0, dt=0.01, model="si", p=2.5)
+SI_TC = 0.1969 * 10.0
+
+
+def si_lattice(Lx: int, Ly: int, T: float = SI_TC, seed: int = 0, replica: int = 0, nsteps: int = 0,
+               **overrides) -> LatticeSpec:
+    args = dict(SI)
+    args.update(overrides)
+    return LatticeSpec(Lx, Ly, schedule=((0, T),), seed=seed, replica=replica, nsteps=nsteps, **args)
+
+
+def si_fss_ensemble(sizes: Sequence[int] = (32, 48, 64, 80, 96, 112, 128, 144), ntemps: int = 8,
+                    seeds=(0, 1), nsteps: int = 100_000) -> List[LatticeSpec]:
+    temps = [SI_TC * (0.94 + 0.12 * t / (ntemps - 1)) for t in range(ntemps)]
+    out = []
+    for iL, L in enumerate(sizes):
+        for iT, T in enumerate(temps):
+            for iS, sd in enumerate(seeds):
+                r = (iL * ntemps + iT) * len(seeds) + iS
+                out.append(si_lattice(L, L, T, seed=sd, replica=r, nsteps=nsteps))
+    return out
+
+
+def si_quench(L: int = 1024, taus=(100.0, 1000.0), eps: float = 0.25, seeds=range(2)) -> List[LatticeSpec]:
+    """tau_Q in time units; the ramp from eps to -eps lasts 2 eps tau_Q time units."""
+    out = []
+    r = 0
+    for tq in taus:
+        n = int(round(2 * eps * tq / SI["dt"]))
+        for sd in seeds:
+            out.append(LatticeSpec(L, L, schedule=((0, SI_TC * (1 + eps)), (n, SI_TC * (1 - eps))), seed=sd,
+                                   replica=r, nsteps=n, **SI))
+            r += 1
+    return out
+
+
+def half_circle_state(Lx: int, Ly: int, seed: int, omega_scale: float = 1.0):
+    """Arbitrary (theta, omega) of the SI model: theta uniform in [-pi/2, pi/2)."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-np.pi / 2, np.pi / 2, size=(Ly, Lx))
+    # keep the FP32 rounding inside the half circle too
+    th = np.where(th.astype(np.float32) >= np.float32(np.pi / 2), -np.pi / 2, th)
+    om = omega_scale * rng.standard_normal((Ly, Lx))
+    return th, om
 
 
 def random_state(Lx: int, Ly: int, seed: int, omega_scale: float = 1.0, dtype=np.float64):

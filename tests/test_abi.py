@@ -35,7 +35,30 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.xyl_abi_version() == 1
+    import re
+    with open(os.path.join(ROOT, "include", "xyl.h")) as f:
+        want = int(re.search(r"#define XYL_ABI_VERSION (\d+)", f.read()).group(1))
+    assert lib.xyl_abi_version() == want
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of xyl_replica_desc and xyl_obs have the C layout
+    (sizes and field offsets printed by a program compiled against the header)."""
+    import subprocess
+    import paper_2409_06412_amd as xyl
+    fields = [f for f, _ in xyl.ReplicaDesc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "xyl.h"\nint main(void) {\n'
+                   '  printf("%zu %zu\\n", sizeof(xyl_replica_desc), sizeof(xyl_obs));\n'
+                   + "".join('  printf("%%zu\\n", offsetof(xyl_replica_desc, %s));\n' % f for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(xyl.ReplicaDesc)
+    assert int(out[1]) == 6 * 8
+    for f, off in zip(fields, out[2:]):
+        assert getattr(xyl.ReplicaDesc, f).offset == int(off), f
 
 
 def test_invalid_arguments_are_rejected_without_a_device(lib):
