@@ -18,6 +18,8 @@ Also reported on the same line:
     finite-size-scaling ensemble (L = 32..512);
   * adjoint / forward time on the 512 x 512 differentiation workload;
   * frozen-domain labelling time on one 2048 x 2048 quench replica;
+  * the step kernel of the paper's Si(001) model variant on 4096 x 4096 and
+    its 128-replica finite-size-scaling ensemble;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
@@ -188,6 +190,47 @@ def bench_control_8192(torch, xyl, workloads, nlaunch=200):
             "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
 
 
+def bench_si_4096(torch, xyl, workloads, nlaunch=500, launch=None):
+    """Step kernel of the Si(001) model variant (q = 2, p = 2.5, half-circle
+    angles) on 4096^2 at T_c: same bytes per site as the XY model, one more
+    transcendental per site.  launch = (rows, waves) fixes the shape instead of
+    autotuning."""
+    spec = workloads.si_lattice(4096, 4096)
+    lat = xyl.Lattice(4096, 4096, dtype="f32", schedule=spec.schedule, seed=spec.seed,
+                      stream=torch.cuda.current_stream().cuda_stream, **spec.params())
+    lat.init_random()
+    if launch:
+        lat.set_launch(*launch)
+        launch = lat.launch()
+    else:
+        launch = lat.autotune()
+    lat.step(200)
+    us = 1e3 * time_step_kernel(torch, lat, nlaunch)
+    lat.close()
+    gbs = BYTES_PER_SITE_F32 * 4096 * 4096 / (us * 1e-6) / 1e9
+    return {"L": 4096, "model": "si", "p": spec.p, "T": spec.schedule[0][1], "launch": list(launch),
+            "avg_kernel_us": us, "site_updates_per_s": 4096 * 4096 / (us * 1e-6),
+            "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+
+
+def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
+    """The Si-model finite-size-scaling ensemble (128 replicas, L = 32..144),
+    batched, sampled every 100 steps."""
+    specs = workloads.si_fss_ensemble(nsteps=10 ** 9)
+    ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
+    launch = ens.autotune()
+    ens.step(3)
+    ens.sync()
+    t0 = time.perf_counter()
+    ens.step(nsteps, every=every)
+    ens.sync()
+    t1 = time.perf_counter()
+    ens.close()
+    sites = sum(s.Lx * s.Ly for s in specs)
+    return {"replicas": len(specs), "sites": sites, "steps": nsteps, "sample_every": every, "launch": list(launch),
+            "site_updates_per_s": sites * nsteps / (t1 - t0)}
+
+
 def bench_domains(torch, xyl):
     lat = xyl.Lattice(2048, 2048, dtype="f32", schedule=[(0, 1.5), (1000, 0.0)], seed=0,
                       stream=torch.cuda.current_stream().cuda_stream)
@@ -217,7 +260,7 @@ def cpu_baseline(L, nsteps):
 
 
 # ----------------------------------------------------------- profile summaries
-STEP_KERNEL = "xyl::k_step<float, 1>"
+STEP_KERNEL = "xyl::k_step<float, 1, 0>"   # plain store step of the XY model
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -313,10 +356,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--only", type=str, default="",
-                    help="comma list of extras to run alone (ensemble, quench, adjoint, domains, control); "
+                    help="comma list of extras to run alone (copy, ensemble, quench, adjoint, domains, control, "
+                         "si, si_fss); "
                          "prints their JSON and skips the headline measurement")
     ap.add_argument("--launch", type=str, default="",
-                    help="rows,waves: fixed launch shape of the step kernel instead of autotuning")
+                    help="rows,waves: fixed launch shape of the step kernel (headline, and the si extra) "
+                         "instead of autotuning")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"))
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "OUT_MD", "FETCH_CMD", "WRITE_CMD"))
@@ -338,13 +383,16 @@ def main():
     from paper_2409_06412_amd import workloads
 
     assert torch.cuda.is_available(), "no GPU visible"
+    fixed = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     if args.only:
         runs = {"copy": lambda: bench_copy(torch),
                 "ensemble": lambda: bench_ensemble(torch, xyl, workloads, 200),
                 "quench": lambda: bench_quench(torch, xyl, workloads, 100),
                 "adjoint": lambda: bench_adjoint(torch, xyl, workloads),
                 "domains": lambda: bench_domains(torch, xyl),
-                "control": lambda: bench_control_8192(torch, xyl, workloads)}
+                "control": lambda: bench_control_8192(torch, xyl, workloads),
+                "si": lambda: bench_si_4096(torch, xyl, workloads, launch=fixed),
+                "si_fss": lambda: bench_si_fss(torch, xyl, workloads)}
         print(json.dumps({k: runs[k]() for k in args.only.split(",")}), flush=True)
         return
     L = args.L
@@ -358,9 +406,8 @@ def main():
     calib = lat.theta_tensor().clone()
     torch.cuda.synchronize()
     del calib
-    if args.launch:
-        r, w = (int(v) for v in args.launch.split(","))
-        lat.set_launch(r, w)
+    if fixed:
+        lat.set_launch(*fixed)
         launch = lat.launch()
     else:
         launch = lat.autotune()
@@ -403,6 +450,10 @@ def main():
         log("adjoint:", extras["adjoint_512"])
         extras["domains_2048"] = bench_domains(torch, xyl)
         log("domains:", extras["domains_2048"])
+        extras["si_4096"] = bench_si_4096(torch, xyl, workloads)
+        log("si model 4096^2:", extras["si_4096"])
+        extras["si_fss"] = bench_si_fss(torch, xyl, workloads)
+        log("si model FSS ensemble:", extras["si_fss"])
 
     cpu = None if args.no_cpu else cpu_baseline(L, args.cpu_steps)
     if cpu:

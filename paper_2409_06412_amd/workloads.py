@@ -23,8 +23,10 @@ p = 2.5, angles in [-pi/2, pi/2), I J_par = 10, I J_perp = 0.1, I h = 1, eta = 1
 (Sec. IV), i.e. Jx = -10, Jy = -0.1, h = -1 in this project's sign convention;
 the Binder crossing of the paper puts T_c at 0.1969 J_par:
   * ``si_lattice``   one lattice at a given temperature.
-  * ``si_fss_ensemble`` L in {32, 48, 64, 80, 96, 112, 128, 144} x temperatures
-    around T_c x 2 seeds, ordered starts (Fig. 4 starts ordered).
+  * ``si_fss_ensemble`` L in {32, 48, 64, 80, 96, 112, 128, 144} x 8
+    temperatures in [0.94, 1.06] T_c x 2 seeds (the paper starts its Binder runs
+    ordered, Fig. 4; an ensemble starts from the init stream, and ordered
+    states can be set per replica).
   * ``si_quench``    symmetric linear quench T_c (1 + e) -> T_c (1 - e) at rate
     1/tau_Q in reduced temperature (Sec. II.B, Eq. Linear-Quench), stopped at the
     end of the ramp (Sec. V).
