@@ -165,6 +165,16 @@ int xyl_measure(xyl_lattice* h, xyl_obs* out);
  * C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along the axis,
  * r = 0..rmax, 0 <= rmax <= L_axis/2.  C has rmax+1 entries.  Synchronises. */
 int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C);
+/* Directional structure factor along axis (0 = x, 1 = y) at the current step
+ * (App. C, Eqs. FT-Corr-delta and S-as-lattice-FT):
+ * S(k) = sum_r C(r) exp(-2 pi i k r / L) = (1/N) sum over the lines along the
+ * axis of sum_kappa |sum_r s^kappa_r exp(-2 pi i k r / L)|^2 with the staggered
+ * rotor components s = eps (cos q th, sin q th), for k = 0..kmax,
+ * 0 <= kmax <= L_axis/2 (S(L - k) = S(k)).  S has kmax+1 entries.  FP64,
+ * summed over lines in a fixed order.  L_axis <= 4096 (XYL_EUNSUPPORTED
+ * otherwise); power-of-two L_axis uses an FFT per line, other lengths a
+ * direct sum.  Uses 16 bytes of device scratch per site.  Synchronises. */
+int xyl_structure_factor(xyl_lattice* h, int32_t axis, int32_t kmax, double* S);
 /* Frozen domains of the current angles (Abstract; Figs. 1 and 6): spin
  * s_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1) (XY; eps_i * (th_i >= 0 ? +1 : -1)
  * for SI), clusters of equal spin under
@@ -207,6 +217,14 @@ int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double*
  * Sokal, c = 6) and standard error of the mean of f[discard..n-1] (App. B,
  * Eqs. Autocorrelation-Time and Time-Series-Var).  Pure host computation. */
 int xyl_mean_error(const double* f, uint64_t n, uint64_t discard, double* mean, double* se, double* tau);
+/* Correlation length as the parameter of a least-squares fit of the
+ * Lorentzian S(k) = A 2 xi / (1 + 4 pi^2 xi^2 (k/L)^2) (App. C, Eq.
+ * Lorentzian-Peak, with the wave number read as k / L) to S[k_first..k_last],
+ * 0 <= k_first < k_last <= L/2; k_first = 1 drops S(0), as the paper does below
+ * T_c.  S(k) must be positive over the range.  Returns xi and the amplitude A
+ * (nullable); XYL_ENUMERIC if S is not peaked at k = 0 over the range or the
+ * fit does not converge.  Pure host computation. */
+int xyl_lorentzian_xi(const double* S, int32_t L, int32_t k_first, int32_t k_last, double* xi, double* amplitude);
 
 /* --------------------------------------------------------------- ensemble */
 /* One replica of a batched ensemble: its own lattice size, parameters,
@@ -256,6 +274,8 @@ int xyl_ensemble_set_state(xyl_ensemble* e, int32_t r, const double* theta, cons
                            uint64_t step);
 int xyl_ensemble_domains(xyl_ensemble* e, int32_t r, int32_t* labels, uint64_t* sizes, uint64_t* counts,
                          uint64_t cap, uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size);
+/* xyl_structure_factor of replica r. */
+int xyl_ensemble_structure_factor(xyl_ensemble* e, int32_t r, int32_t axis, int32_t kmax, double* S);
 int xyl_ensemble_sync(xyl_ensemble* e);
 
 /* ---------------------------------------------------------------- adjoint */

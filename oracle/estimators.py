@@ -13,6 +13,12 @@ Written from their definitions, in numpy, for a reader to check by eye:
   * Second-moment correlation length from the structure factor at k = 0 and
     at the smallest nonzero wave number (the Lorentzian of App. C, Eq.
     Lorentzian-Peak, evaluated at those two points).
+  * Directional structure factor S(k) = sum_r C(r) exp(-2 pi i k r / N), the
+    Fourier transform of the correlation function (App. C, Eq. FT-Corr-delta),
+    written as that sum; and the correlation length as the parameter of a
+    least-squares fit of the Lorentzian A 2 xi / (1 + 4 pi^2 xi^2 (k/N)^2)
+    around k = 0 (App. C, Eq. Lorentzian-Peak, with k read as k / N), by
+    scipy's curve_fit.
 """
 from __future__ import annotations
 
@@ -67,3 +73,38 @@ def xi_second_moment(F0_mean: float, Fk_mean: float, L: int) -> float:
     if r <= 0:
         return 0.0
     return float(np.sqrt(r) / (2.0 * np.sin(np.pi / L)))
+
+
+def structure_factor(C) -> np.ndarray:
+    """S(k) for k = 0..N-1 from C(r), r = 0..N-1 (the full periodic range)."""
+    C = np.asarray(C, dtype=np.float64)
+    N = len(C)
+    r = np.arange(N)
+    S = np.empty(N)
+    for k in range(N):
+        ph = 2.0 * np.pi * k * r / N
+        re = np.sum(C * np.cos(ph))
+        im = -np.sum(C * np.sin(ph))
+        assert abs(im) <= 1e-9 * max(1.0, abs(re)), "C(r) is not symmetric"
+        S[k] = re
+    return S
+
+
+def lorentzian(k, xi, amplitude, N):
+    return amplitude * 2.0 * xi / (1.0 + 4.0 * np.pi ** 2 * xi ** 2 * (np.asarray(k, dtype=np.float64) / N) ** 2)
+
+
+def lorentzian_xi(S, N: int, k_first: int, k_last: int):
+    """Least-squares fit of S(k), k_first <= k <= k_last, to the Lorentzian;
+    returns (xi, amplitude).  Start values from the straight line 1/S against
+    (k/N)^2."""
+    from scipy.optimize import curve_fit
+    k = np.arange(k_first, k_last + 1)
+    y = np.asarray(S, dtype=np.float64)[k_first:k_last + 1]
+    u = (k / N) ** 2
+    b, a = np.polyfit(u, 1.0 / y, 1)
+    xi0 = np.sqrt(max(b / a, 1e-12)) / (2 * np.pi)
+    A0 = 1.0 / (2.0 * a * xi0)
+    (xi, A), _ = curve_fit(lambda kk, xi, A: lorentzian(kk, xi, A, N), k, y, p0=(xi0, A0), maxfev=10000)
+    return float(abs(xi)), float(A)
+

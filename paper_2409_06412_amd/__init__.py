@@ -75,6 +75,9 @@ _SIGS = {
     "xyl_set_stream": (_i32, [_vp, _vp]),
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
+    "xyl_structure_factor": (_i32, [_vp, _i32, _i32, P(_d)]),
+    "xyl_ensemble_structure_factor": (_i32, [_vp, _i32, _i32, _i32, P(_d)]),
+    "xyl_lorentzian_xi": (_i32, [P(_d), _i32, _i32, _i32, P(_d), P(_d)]),
     "xyl_set_schedule": (_i32, [_vp, P(_u64), P(_d), _i32]),
     "xyl_set_seed": (_i32, [_vp, _u64, _u32]),
     "xyl_init_random": (_i32, [_vp]),
@@ -311,6 +314,12 @@ class Lattice:
         _check(load().xyl_correlation(self._h, int(axis), int(rmax), _pd(C)))
         return C
 
+    def structure_factor(self, axis: int, kmax: int) -> np.ndarray:
+        """S(k), k = 0..kmax, along axis 0 (x) or 1 (y)."""
+        S = np.empty(int(kmax) + 1)
+        _check(load().xyl_structure_factor(self._h, int(axis), int(kmax), _pd(S)))
+        return S
+
     def domains(self, want_labels: bool = True):
         """Returns (labels or None, sizes, counts, n_domains, max_size)."""
         return _domains(lambda *a: load().xyl_domains(self._h, *a), self.N, (self.Ly, self.Lx), want_labels)
@@ -471,6 +480,11 @@ class Ensemble:
         return _domains(lambda *a: load().xyl_ensemble_domains(self._h, int(r), *a), s.Lx * s.Ly,
                         (s.Ly, s.Lx), want_labels)
 
+    def structure_factor(self, r: int, axis: int, kmax: int) -> np.ndarray:
+        S = np.empty(int(kmax) + 1)
+        _check(load().xyl_ensemble_structure_factor(self._h, int(r), int(axis), int(kmax), _pd(S)))
+        return S
+
     def sync(self):
         _check(load().xyl_ensemble_sync(self._h))
 
@@ -488,6 +502,16 @@ def binder(m, discard: int = 0):
     U, se = _d(), _d()
     _check(load().xyl_binder(_pd(m), m.size, int(discard), ctypes.byref(U), ctypes.byref(se)))
     return U.value, se.value
+
+
+def lorentzian_xi(S, L: int, k_first: int, k_last: int):
+    """(xi, amplitude) of the Lorentzian fitted to S[k_first..k_last]."""
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    if S.size <= k_last:
+        raise ValueError("S needs k_last + 1 entries")
+    xi, A = _d(), _d()
+    _check(load().xyl_lorentzian_xi(_pd(S), int(L), int(k_first), int(k_last), ctypes.byref(xi), ctypes.byref(A)))
+    return xi.value, A.value
 
 
 def mean_error(f, discard: int = 0):

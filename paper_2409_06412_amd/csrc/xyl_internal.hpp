@@ -98,6 +98,10 @@ void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uin
 template <typename R>
 void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,
                         double* out, hipStream_t s);
+// S_delta(k), k = 0..kmax: zbuf holds 16 * Lx * Ly bytes, part nlines * (kmax + 1) doubles
+template <typename R>
+void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax, void* zbuf,
+                             double* part, double* out, hipStream_t s);
 template <typename R>
 void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
                     uint32_t* hist, uint32_t* stats, hipStream_t s);

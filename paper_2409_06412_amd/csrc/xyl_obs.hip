@@ -1,5 +1,7 @@
 // Measurements outside the step: the staggered rotor correlation function and
 // the frozen-domain labelling.
+#include <algorithm>
+
 #include "xyl_device.hpp"
 
 namespace xyl {
@@ -59,6 +61,144 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
     check_hip(hipGetLastError(), "correlation kernel launch");
     k_corr_sum<<<(rmax + 256) / 256, 256, 0, s>>>(part, nlines, rmax, (double)Lx * (double)Ly, out);
     check_hip(hipGetLastError(), "correlation sum launch");
+}
+
+// ------------------------------------------------- structure factor
+// S_delta(k) = (1/N) sum over lines along delta of sum_kappa |s~^kappa_k|^2,
+// s~^kappa_k = sum_r s^kappa_r exp(-2 pi i k r / L) (App. C, Eq.
+// S-as-lattice-FT: the transform of C_delta(r), Eq. FT-Corr-delta).  Each
+// line's two real rotor components are packed as one complex sequence
+// z = eps (cos q th + i sin q th), whose transform Z gives
+// sum_kappa |s~^kappa_k|^2 = (|Z_k|^2 + |Z_{L-k}|^2) / 2.
+// Pass 1 writes z line-major (rows as they are; columns through a 32 x 32
+// LDS transpose), pass 2 transforms one line per workgroup in LDS (radix-2
+// decimation in time for power-of-two L, a direct sum otherwise), pass 3
+// sums the lines in order (k_corr_sum).
+template <typename R>
+__global__ __launch_bounds__(256) void k_rotor_rows(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
+                                                    double q, double2* __restrict__ z) {
+    const size_t N = (size_t)Lx * Ly;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / (size_t)Lx), x = (int)(i - (size_t)y * Lx);
+        const double e = (((x * sx) + (y * sy)) & 1) ? -1.0 : 1.0;
+        double sn, cs;
+        sincos(q * (double)th[i], &sn, &cs);
+        z[i] = make_double2(e * cs, e * sn);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_rotor_cols(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
+                                                    double q, double2* __restrict__ z) {
+    __shared__ double2 tile[32][33];
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + tx, y = y0 + ty + 8 * j;
+        if (x < Lx && y < Ly) {
+            const double e = (((x * sx) + (y * sy)) & 1) ? -1.0 : 1.0;
+            double sn, cs;
+            sincos(q * (double)th[(size_t)y * Lx + x], &sn, &cs);
+            tile[ty + 8 * j][tx] = make_double2(e * cs, e * sn);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + ty + 8 * j, y = y0 + tx;
+        if (x < Lx && y < Ly) z[(size_t)x * Ly + y] = tile[tx][ty + 8 * j];
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ int bit_reverse(int i, int bits) { return (int)(__brev((unsigned)i) >> (32 - bits)); }
+
+__global__ __launch_bounds__(256) void k_sf_lines(const double2* __restrict__ z, int L, int log2L, int kmax,
+                                                  double* __restrict__ part) {
+    extern __shared__ double2 sm[];
+    double2* buf = sm;
+    double2* tw = sm + L;   // tw[m] = exp(-2 pi i m / L)
+    const double2* zl = z + (size_t)blockIdx.x * L;
+    const int ntw = log2L >= 0 ? L / 2 : L;
+    for (int m = threadIdx.x; m < ntw; m += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)L, &sn, &cs);
+        tw[m] = make_double2(cs, -sn);
+    }
+    double* out = part + (size_t)blockIdx.x * (kmax + 1);
+    if (log2L >= 0) {
+        for (int i = threadIdx.x; i < L; i += blockDim.x) buf[log2L > 0 ? bit_reverse(i, log2L) : 0] = zl[i];
+        __syncthreads();
+        for (int half = 1; half < L; half <<= 1) {
+            const int step = L / (2 * half);
+            for (int b = threadIdx.x; b < L / 2; b += blockDim.x) {
+                const int j = b & (half - 1);
+                const int i0 = ((b - j) << 1) + j, i1 = i0 + half;
+                const double2 a = buf[i0];
+                const double2 t = cmul(tw[j * step], buf[i1]);
+                buf[i0] = make_double2(a.x + t.x, a.y + t.y);
+                buf[i1] = make_double2(a.x - t.x, a.y - t.y);
+            }
+            __syncthreads();
+        }
+        for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
+            const double2 a = buf[k], b = buf[(L - k) & (L - 1)];
+            out[k] = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+        }
+    } else {
+        for (int i = threadIdx.x; i < L; i += blockDim.x) buf[i] = zl[i];
+        __syncthreads();
+        for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
+            // A = Z_k = sum z_x w^(k x), B = Z_{L-k} = sum z_x conj(w)^(k x)
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            int m = 0;
+            for (int x = 0; x < L; ++x) {
+                const double2 w = tw[m], v = buf[x];
+                ar += v.x * w.x - v.y * w.y;
+                ai += v.x * w.y + v.y * w.x;
+                br += v.x * w.x + v.y * w.y;
+                bi += v.y * w.x - v.x * w.y;
+                m += k;
+                if (m >= L) m -= L;
+            }
+            out[k] = 0.5 * (ar * ar + ai * ai + br * br + bi * bi);
+        }
+    }
+}
+
+template <typename R>
+void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax, void* zbuf,
+                             double* part, double* out, hipStream_t s) {
+    const double q = model == kModelSI ? 2.0 : 1.0;
+    double2* z = static_cast<double2*>(zbuf);
+    const int L = axis == 0 ? Lx : Ly;
+    const int nlines = axis == 0 ? Ly : Lx;
+    if (axis == 0) {
+        const size_t N = (size_t)Lx * Ly;
+        const unsigned nb = (unsigned)std::min<size_t>((N + 255) / 256, 65536);
+        k_rotor_rows<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
+    } else {
+        const dim3 grid((Lx + 31) / 32, (Ly + 31) / 32);
+        k_rotor_cols<R><<<grid, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
+    }
+    check_hip(hipGetLastError(), "rotor kernel launch");
+    int log2L = -1;
+    if ((L & (L - 1)) == 0) {
+        log2L = 0;
+        while ((1 << log2L) < L) ++log2L;
+    }
+    const size_t lds = sizeof(double2) * (size_t)(L + (log2L >= 0 ? L / 2 : L));
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_lines),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+              "hipFuncSetAttribute");
+    k_sf_lines<<<nlines, 256, lds, s>>>(z, L, log2L, kmax, part);
+    check_hip(hipGetLastError(), "structure factor kernel launch");
+    k_corr_sum<<<(kmax + 256) / 256, 256, 0, s>>>(part, nlines, kmax, (double)Lx * (double)Ly, out);
+    check_hip(hipGetLastError(), "structure factor sum launch");
 }
 
 // -------------------------------------------------------------- domains
@@ -179,6 +319,10 @@ template void launch_correlation<float>(const float*, int, int, int, int, int, i
                                         hipStream_t);
 template void launch_correlation<double>(const double*, int, int, int, int, int, int, int, double*, double*,
                                          hipStream_t);
+template void launch_structure_factor<float>(const float*, int, int, int, int, int, int, int, void*, double*,
+                                             double*, hipStream_t);
+template void launch_structure_factor<double>(const double*, int, int, int, int, int, int, int, void*, double*,
+                                              double*, hipStream_t);
 template void launch_domains<float>(const float*, int, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,
                                     hipStream_t);
 template void launch_domains<double>(const double*, int, int, int, int, int, int32_t*, uint32_t*, uint32_t*, uint32_t*,

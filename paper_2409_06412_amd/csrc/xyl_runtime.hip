@@ -817,6 +817,138 @@ int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C) {
     });
 }
 
+}  // extern "C"
+
+// S_delta(k) of one lattice's current angles into host S[0..kmax].
+template <typename R>
+static void structure_factor_into(const void* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax,
+                                  DevBuf<double>& scratch, hipStream_t s, double* S) {
+    const int L = axis == 0 ? Lx : Ly;
+    const int nlines = axis == 0 ? Ly : Lx;
+    const size_t N = (size_t)Lx * Ly;
+    scratch.reserve(2 * N + (size_t)nlines * (kmax + 1) + (size_t)(kmax + 1));
+    double* z = scratch.p;
+    double* part = scratch.p + 2 * N;
+    double* outd = part + (size_t)nlines * (kmax + 1);
+    (void)L;
+    launch_structure_factor<R>(static_cast<const R*>(th), Lx, Ly, sx, sy, model, axis, kmax, z, part, outd, s);
+    check_hip(hipMemcpyAsync(S, outd, sizeof(double) * (kmax + 1), hipMemcpyDeviceToHost, s), "D2H");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    require_finite(S, (size_t)kmax + 1, "structure factor");
+}
+
+static void validate_sf(int Lx, int Ly, int axis, int kmax, const double* S) {
+    require(axis == 0 || axis == 1, XYL_EINVAL, "axis must be 0 or 1");
+    const int L = axis == 0 ? Lx : Ly;
+    require(kmax >= 0 && kmax <= L / 2, XYL_EINVAL, "kmax must be in [0, L/2]");
+    require(L <= 4096, XYL_EUNSUPPORTED, "the structure factor needs the axis length <= 4096");
+    require(S != nullptr, XYL_EINVAL, "S is NULL");
+}
+
+// Least-squares fit of S(k) = A 2 xi / (1 + 4 pi^2 xi^2 (k/L)^2) over
+// k_first..k_last: start from the straight line 1/S = a + b (k/L)^2, then
+// Levenberg-Marquardt on (xi, A).
+static void lorentzian_fit(const double* S, int L, int k0, int k1, double* xi_out, double* amp_out) {
+    const double c = 4.0 * M_PI * M_PI;
+    const int n = k1 - k0 + 1;
+    double su = 0, sv = 0, suu = 0, suv = 0;
+    for (int k = k0; k <= k1; ++k) {
+        const double u = ((double)k / L) * ((double)k / L), v = 1.0 / S[k];
+        su += u;
+        sv += v;
+        suu += u * u;
+        suv += u * v;
+    }
+    const double det = n * suu - su * su;
+    require(det > 0.0, XYL_EINVAL, "fit range needs two distinct k");
+    const double b = (n * suv - su * sv) / det, a = (sv - b * su) / n;
+    require(a > 0.0 && b > 0.0, XYL_ENUMERIC, "S(k) is not peaked at k = 0 over the fit range");
+    double xi = std::sqrt(b / (a * c)), A = 1.0 / (2.0 * a * xi);
+    auto sse = [&](double x, double amp) {
+        double e = 0.0;
+        for (int k = k0; k <= k1; ++k) {
+            const double u = ((double)k / L) * ((double)k / L);
+            const double r = S[k] - amp * 2.0 * x / (1.0 + c * x * x * u);
+            e += r * r;
+        }
+        return e;
+    };
+    double E = sse(xi, A), lam = 1e-3;
+    for (int it = 0; it < 200; ++it) {
+        double jj[3] = {0, 0, 0}, jr[2] = {0, 0};
+        for (int k = k0; k <= k1; ++k) {
+            const double u = ((double)k / L) * ((double)k / L);
+            const double D = 1.0 + c * xi * xi * u;
+            const double f = A * 2.0 * xi / D;
+            const double dA = 2.0 * xi / D;
+            const double dx = 2.0 * A * (1.0 - c * xi * xi * u) / (D * D);
+            const double r = S[k] - f;
+            jj[0] += dx * dx;
+            jj[1] += dx * dA;
+            jj[2] += dA * dA;
+            jr[0] += dx * r;
+            jr[1] += dA * r;
+        }
+        bool accepted = false;
+        for (int tries = 0; tries < 30 && !accepted; ++tries) {
+            const double m00 = jj[0] * (1.0 + lam), m11 = jj[2] * (1.0 + lam), m01 = jj[1];
+            const double d = m00 * m11 - m01 * m01;
+            if (!(d > 0.0)) {
+                lam *= 10.0;
+                continue;
+            }
+            const double dxi = (m11 * jr[0] - m01 * jr[1]) / d, dA = (m00 * jr[1] - m01 * jr[0]) / d;
+            const double E1 = sse(xi + dxi, A + dA);
+            if (E1 <= E) {
+                const bool small = std::fabs(dxi) <= 1e-13 * std::fabs(xi) && std::fabs(dA) <= 1e-13 * std::fabs(A);
+                xi += dxi;
+                A += dA;
+                E = E1;
+                lam = std::max(lam * 0.1, 1e-15);
+                accepted = true;
+                if (small) it = 200;
+            } else {
+                lam *= 10.0;
+            }
+        }
+        if (!accepted) break;
+    }
+    require(std::isfinite(xi) && std::isfinite(A), XYL_ENUMERIC, "Lorentzian fit did not converge");
+    *xi_out = std::fabs(xi);
+    *amp_out = A;
+}
+
+extern "C" {
+
+int xyl_structure_factor(xyl_lattice* h, int32_t axis, int32_t kmax, double* S) {
+    return guarded([&] {
+        require_init(h);
+        validate_sf(h->Lx, h->Ly, axis, kmax, S);
+        DeviceGuard g(h->device);
+        const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
+        if (h->dtype == XYL_F64)
+            structure_factor_into<double>(h->cur_theta(), h->Lx, h->Ly, sx, sy, h->p.model, axis, kmax, h->dscratch,
+                                          h->stream, S);
+        else
+            structure_factor_into<float>(h->cur_theta(), h->Lx, h->Ly, sx, sy, h->p.model, axis, kmax, h->dscratch,
+                                         h->stream, S);
+    });
+}
+
+int xyl_lorentzian_xi(const double* S, int32_t L, int32_t k_first, int32_t k_last, double* xi, double* amplitude) {
+    return guarded([&] {
+        require(S != nullptr && xi != nullptr, XYL_EINVAL, "S/xi are NULL");
+        require(L >= 2, XYL_EINVAL, "L must be >= 2");
+        require(k_first >= 0 && k_last > k_first && k_last <= L / 2, XYL_EINVAL,
+                "fit range must satisfy 0 <= k_first < k_last <= L/2");
+        for (int k = k_first; k <= k_last; ++k)
+            require(std::isfinite(S[k]) && S[k] > 0.0, XYL_EINVAL, "S(k) must be finite and > 0 over the fit range");
+        double amp = 0.0;
+        lorentzian_fit(S, L, k_first, k_last, xi, &amp);
+        if (amplitude) *amplitude = amp;
+    });
+}
+
 int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap, uint64_t* n_sizes,
                 uint64_t* n_domains, uint64_t* max_size) {
     return guarded([&] {
@@ -1645,6 +1777,23 @@ int xyl_ensemble_domains(xyl_ensemble* e, int32_t r, int32_t* labels, uint64_t* 
             run_domains<float>(static_cast<const float*>(e->cur_theta(r)), d.Lx, d.Ly, sx, sy, d.model, e->parent,
                                e->usz,
                                e->hist, e->stats, e->stream, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+    });
+}
+
+int xyl_ensemble_structure_factor(xyl_ensemble* e, int32_t r, int32_t axis, int32_t kmax, double* S) {
+    return guarded([&] {
+        require(e != nullptr && r >= 0 && r < e->n, XYL_EINVAL, "bad handle or replica");
+        const xyl_replica_desc& d = e->desc[r];
+        validate_sf(d.Lx, d.Ly, axis, kmax, S);
+        DeviceGuard g(e->device);
+        check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
+        const int sx = d.Jx > 0.0, sy = d.Jy > 0.0;
+        if (e->dtype == XYL_F64)
+            structure_factor_into<double>(e->cur_theta(r), d.Lx, d.Ly, sx, sy, d.model, axis, kmax, e->dscratch,
+                                          e->stream, S);
+        else
+            structure_factor_into<float>(e->cur_theta(r), d.Lx, d.Ly, sx, sy, d.model, axis, kmax, e->dscratch,
+                                         e->stream, S);
     });
 }
 

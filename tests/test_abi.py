@@ -92,6 +92,28 @@ def test_binder_and_errors_match_oracle_estimators():
     assert e == pytest.approx(eo, rel=1e-12)
 
 
+def test_lorentzian_fit_matches_oracle_estimator():
+    """The library's Levenberg-Marquardt fit and scipy's curve_fit (oracle)
+    agree on noisy peaks; exact Lorentzians are recovered; bad input fails."""
+    import paper_2409_06412_amd as xyl
+    rng = np.random.default_rng(8)
+    N = 1024
+    k = np.arange(N // 2 + 1)
+    for xi, A in ((4.0, 1.3), (25.0, 0.4), (80.0, 2.0)):
+        exact = estimators.lorentzian(k, xi, A, N)
+        got, amp = xyl.lorentzian_xi(exact, N, 0, 30)
+        assert got == pytest.approx(xi, rel=1e-9) and amp == pytest.approx(A, rel=1e-9)
+        noisy = exact * (1 + 0.03 * rng.standard_normal(k.size))
+        for k0 in (0, 1):
+            g, a = xyl.lorentzian_xi(noisy, N, k0, 40)
+            go, ao = estimators.lorentzian_xi(noisy, N, k0, 40)
+            assert g == pytest.approx(go, rel=1e-6) and a == pytest.approx(ao, rel=1e-6)
+    with pytest.raises(xyl.XylError):
+        xyl.lorentzian_xi(np.linspace(1, 2, 20), 64, 0, 10)            # rising: not a peak
+    with pytest.raises(xyl.XylError):
+        xyl.lorentzian_xi(np.ones(20), 64, 5, 5)                       # one point
+
+
 def test_oracle_library_is_independent_of_product():
     """The oracle neither links nor imports the HIP library."""
     for f in ("xyo.c", "xyo.h", "__init__.py", "estimators.py"):

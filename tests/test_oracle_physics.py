@@ -401,3 +401,41 @@ def test_pathwise_gradient_conditioning_horizon():
         assert fd(1000, rel) == pytest.approx(g[0], rel=1e-3)
     long = [fd(5000, rel) for rel in (1e-3, 1e-4, 1e-5, 1e-6)]
     assert max(long) - min(long) > 10 * max(abs(v) for v in long[:1])
+
+
+# ------------------------------------------------- structure factor (App. C)
+def test_structure_factor_definition_matches_lattice_fft():
+    """Eq. FT-Corr-delta (transform of C) equals Eq. S-as-lattice-FT (summed
+    squared lattice transforms of the rotor components), for both axes, both
+    models."""
+    for model, Lx, Ly, q in (("xy", 12, 8, 1.0), ("si", 10, 6, 2.0)):
+        o = oracle.Oracle(Lx, Ly, model=model, p=2.5 if model == "si" else 2.0)
+        rng = np.random.default_rng(41)
+        W = np.pi if model == "xy" else np.pi / 2
+        th = rng.uniform(-W, W, size=(Ly, Lx))
+        eps = o.stagger()
+        X = [np.fft.fft2(eps * np.cos(q * th)), np.fft.fft2(eps * np.sin(q * th))]
+        N = Lx * Ly
+        for axis, L in ((0, Lx), (1, Ly)):
+            S = estimators.structure_factor(o.correlation(th, axis, L - 1))
+            other = Ly if axis == 0 else Lx
+            want = sum(np.sum(np.abs(Xk) ** 2, axis=0 if axis == 0 else 1) for Xk in X) / (N * other)
+            np.testing.assert_allclose(S, want, rtol=1e-11, atol=1e-12)
+            assert np.sum(S) == pytest.approx(L, rel=1e-12)          # sum rule: L C(0) = L
+
+
+def test_lorentzian_fit_recovers_xi():
+    N = 512
+    k = np.arange(N)
+    for xi in (3.0, 12.5, 40.0):
+        S = estimators.lorentzian(np.minimum(k, N - k), xi, 0.7, N)
+        got, A = estimators.lorentzian_xi(S, N, 0, 20)
+        assert got == pytest.approx(xi, rel=1e-7)
+        assert A == pytest.approx(0.7, rel=1e-7)
+    # exponential correlations C(r) = exp(-|r|/xi) (periodic images): the
+    # Lorentzian is their transform's small-k form, good to O(1/xi)
+    for xi in (10.0, 30.0):
+        r = np.arange(N)
+        S = estimators.structure_factor(np.exp(-np.minimum(r, N - r) / xi))
+        got, _ = estimators.lorentzian_xi(S, N, 0, int(N / (2 * np.pi * xi)) + 2)
+        assert got == pytest.approx(xi, rel=0.05)
