@@ -18,6 +18,8 @@ Also reported on the same line:
     finite-size-scaling ensemble (L = 32..512);
   * adjoint / forward time on the 512 x 512 differentiation workload;
   * frozen-domain labelling time on one 2048 x 2048 quench replica;
+  * the directional structure factor (both axes) and Lorentzian correlation
+    lengths of a 4096 x 4096 lattice;
   * the step kernel of the paper's Si(001) model variant on 4096 x 4096 and
     its 128-replica finite-size-scaling ensemble;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
@@ -231,6 +233,31 @@ def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
             "site_updates_per_s": sites * nsteps / (t1 - t0)}
 
 
+def bench_structure_factor(torch, xyl, workloads, reps=5):
+    """S_delta(k) for k = 0..L/2 along both axes of a 4096^2 lattice (the
+    paper's correlation-length observable, App. C), and the Lorentzian xi of
+    each axis, on a lattice quenched for 1000 steps."""
+    spec = workloads.large_fp32(0, 4096)
+    lat = xyl.Lattice(4096, 4096, dtype="f32", schedule=spec.schedule, seed=spec.seed,
+                      stream=torch.cuda.current_stream().cuda_stream, **spec.params())
+    lat.init_random()
+    lat.step(1000)
+    out = {"L": 4096, "kmax": 2048}
+    for axis, name in ((0, "x"), (1, "y")):
+        lat.structure_factor(axis, 2048)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            S = lat.structure_factor(axis, 2048)
+        out["ms_" + name] = 1e3 * (time.perf_counter() - t0) / reps
+        try:
+            out["xi_" + name] = xyl.lorentzian_xi(S, 4096, 1, 64)[0]
+        except xyl.XylError as e:      # no Lorentzian peak along this axis (e.g. unaligned rows)
+            out["xi_" + name] = None
+            out["fit_" + name] = str(e)
+    lat.close()
+    return out
+
+
 def bench_domains(torch, xyl):
     lat = xyl.Lattice(2048, 2048, dtype="f32", schedule=[(0, 1.5), (1000, 0.0)], seed=0,
                       stream=torch.cuda.current_stream().cuda_stream)
@@ -357,7 +384,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--only", type=str, default="",
                     help="comma list of extras to run alone (copy, ensemble, quench, adjoint, domains, control, "
-                         "si, si_fss); "
+                         "si, si_fss, structure); "
                          "prints their JSON and skips the headline measurement")
     ap.add_argument("--launch", type=str, default="",
                     help="rows,waves: fixed launch shape of the step kernel (headline, and the si extra) "
@@ -392,6 +419,7 @@ def main():
                 "domains": lambda: bench_domains(torch, xyl),
                 "control": lambda: bench_control_8192(torch, xyl, workloads),
                 "si": lambda: bench_si_4096(torch, xyl, workloads, launch=fixed),
+                "structure": lambda: bench_structure_factor(torch, xyl, workloads),
                 "si_fss": lambda: bench_si_fss(torch, xyl, workloads)}
         print(json.dumps({k: runs[k]() for k in args.only.split(",")}), flush=True)
         return
@@ -450,6 +478,8 @@ def main():
         log("adjoint:", extras["adjoint_512"])
         extras["domains_2048"] = bench_domains(torch, xyl)
         log("domains:", extras["domains_2048"])
+        extras["structure_factor_4096"] = bench_structure_factor(torch, xyl, workloads)
+        log("structure factor:", extras["structure_factor_4096"])
         extras["si_4096"] = bench_si_4096(torch, xyl, workloads)
         log("si model 4096^2:", extras["si_4096"])
         extras["si_fss"] = bench_si_fss(torch, xyl, workloads)

@@ -217,6 +217,24 @@ int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double*
  * Sokal, c = 6) and standard error of the mean of f[discard..n-1] (App. B,
  * Eqs. Autocorrelation-Time and Time-Series-Var).  Pure host computation. */
 int xyl_mean_error(const double* f, uint64_t n, uint64_t discard, double* mean, double* se, double* tau);
+/* Time-resolved Binder cumulant (Sec. IV.B; App. B restricts the time
+ * integral of Eq. ensemble-average-calculation to bins of width d sigma):
+ * m holds nrep independent replicas' order-parameter series, replica-major
+ * (m[r*nt + j], equally spaced samples).  For each bin b of `bin`
+ * consecutive samples (nt/bin bins; a ragged tail is dropped),
+ * U[b] = <m^4> / <m^2>^2 with both averages over all replicas and the bin's
+ * samples; U_se[b] (nullable) is the jackknife error over replicas (NaN for
+ * one replica).  Pure host computation. */
+int xyl_binder_relaxation(const double* m, uint64_t nrep, uint64_t nt, uint64_t bin, double* U, double* U_se);
+/* Dynamic exponent by curve collapse (Sec. IV.B): for z on the raster
+ * z_lo, z_lo + z_step, ... <= z_hi, the mean squared deviation between
+ * U1(t) of size L1 and U2(b^-z t) of size L2, b = L1/L2, with U2 linearly
+ * interpolated in t (t2 strictly increasing) over the points of curve 1 that
+ * fall inside curve 2's time range (at least 3); returns the minimising z and
+ * its mean squared deviation (cost, nullable).  The paper rasterises z in
+ * steps of 0.01.  Pure host computation. */
+int xyl_z_collapse(const double* t1, const double* U1, uint64_t n1, double L1, const double* t2, const double* U2,
+                   uint64_t n2, double L2, double z_lo, double z_hi, double z_step, double* z_best, double* cost);
 /* Correlation length as the parameter of a least-squares fit of the
  * Lorentzian S(k) = A 2 xi / (1 + 4 pi^2 xi^2 (k/L)^2) (App. C, Eq.
  * Lorentzian-Peak, with the wave number read as k / L) to S[k_first..k_last],

@@ -78,6 +78,8 @@ _SIGS = {
     "xyl_structure_factor": (_i32, [_vp, _i32, _i32, P(_d)]),
     "xyl_ensemble_structure_factor": (_i32, [_vp, _i32, _i32, _i32, P(_d)]),
     "xyl_lorentzian_xi": (_i32, [P(_d), _i32, _i32, _i32, P(_d), P(_d)]),
+    "xyl_binder_relaxation": (_i32, [P(_d), _u64, _u64, _u64, P(_d), P(_d)]),
+    "xyl_z_collapse": (_i32, [P(_d), P(_d), _u64, _d, P(_d), P(_d), _u64, _d, _d, _d, _d, P(_d), P(_d)]),
     "xyl_set_schedule": (_i32, [_vp, P(_u64), P(_d), _i32]),
     "xyl_set_seed": (_i32, [_vp, _u64, _u32]),
     "xyl_init_random": (_i32, [_vp]),
@@ -502,6 +504,30 @@ def binder(m, discard: int = 0):
     U, se = _d(), _d()
     _check(load().xyl_binder(_pd(m), m.size, int(discard), ctypes.byref(U), ctypes.byref(se)))
     return U.value, se.value
+
+
+def binder_relaxation(m, bin: int = 1):
+    """U(t) per bin of `bin` samples from an (nrep, nt) array of order-parameter
+    series; returns (U, U_se)."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    if m.ndim != 2:
+        raise ValueError("m must be (nrep, nt)")
+    nrep, nt = m.shape
+    nb = nt // int(bin) if bin >= 1 else 0
+    U, se = np.empty(max(nb, 1)), np.empty(max(nb, 1))
+    _check(load().xyl_binder_relaxation(_pd(m), nrep, nt, int(bin), _pd(U), _pd(se)))
+    return U[:nb], se[:nb]
+
+
+def z_collapse(t1, U1, L1, t2, U2, L2, z_lo=1.0, z_hi=3.5, z_step=0.01):
+    """(z, cost) collapsing U(t, L1) onto U(b^-z t, L2), b = L1 / L2."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (t1, U1, t2, U2)]
+    if a[0].size != a[1].size or a[2].size != a[3].size:
+        raise ValueError("t and U arrays differ in length")
+    z, c = _d(), _d()
+    _check(load().xyl_z_collapse(_pd(a[0]), _pd(a[1]), a[0].size, float(L1), _pd(a[2]), _pd(a[3]), a[2].size,
+                                 float(L2), float(z_lo), float(z_hi), float(z_step), ctypes.byref(z), ctypes.byref(c)))
+    return z.value, c.value
 
 
 def lorentzian_xi(S, L: int, k_first: int, k_last: int):

@@ -1174,6 +1174,93 @@ int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double*
     });
 }
 
+int xyl_binder_relaxation(const double* m, uint64_t nrep, uint64_t nt, uint64_t bin, double* U, double* U_se) {
+    return guarded([&] {
+        require(m != nullptr && U != nullptr, XYL_EINVAL, "NULL argument");
+        require(nrep >= 1 && bin >= 1 && nt >= bin, XYL_EINVAL, "need nrep >= 1 and nt >= bin >= 1");
+        const uint64_t nb = nt / bin;
+        std::vector<double> s2(nrep), s4(nrep);
+        for (uint64_t b = 0; b < nb; ++b) {
+            // per-replica sums over the bin, then the pooled ratio of averages
+            double t2 = 0.0, t4 = 0.0;
+            for (uint64_t r = 0; r < nrep; ++r) {
+                double a2 = 0.0, a4 = 0.0;
+                for (uint64_t j = b * bin; j < (b + 1) * bin; ++j) {
+                    const double q = m[r * nt + j] * m[r * nt + j];
+                    a2 += q;
+                    a4 += q * q;
+                }
+                s2[r] = a2;
+                s4[r] = a4;
+                t2 += a2;
+                t4 += a4;
+            }
+            const double cnt = (double)nrep * (double)bin;
+            require(t2 > 0.0, XYL_ENUMERIC, "<m^2> is zero in a bin");
+            U[b] = (t4 / cnt) / ((t2 / cnt) * (t2 / cnt));
+            if (U_se) {
+                if (nrep < 2) {
+                    U_se[b] = NAN;
+                    continue;
+                }
+                // jackknife over replicas (independent realisations)
+                const double c1 = (double)(nrep - 1) * (double)bin;
+                double mean = 0.0;
+                std::vector<double> uj(nrep);
+                for (uint64_t r = 0; r < nrep; ++r) {
+                    const double a2 = (t2 - s2[r]) / c1, a4 = (t4 - s4[r]) / c1;
+                    uj[r] = a2 > 0.0 ? a4 / (a2 * a2) : NAN;
+                    mean += uj[r];
+                }
+                mean /= (double)nrep;
+                double var = 0.0;
+                for (uint64_t r = 0; r < nrep; ++r) var += (uj[r] - mean) * (uj[r] - mean);
+                U_se[b] = std::sqrt(var * (double)(nrep - 1) / (double)nrep);
+            }
+        }
+    });
+}
+
+int xyl_z_collapse(const double* t1, const double* U1, uint64_t n1, double L1, const double* t2, const double* U2,
+                   uint64_t n2, double L2, double z_lo, double z_hi, double z_step, double* z_best, double* cost) {
+    return guarded([&] {
+        require(t1 && U1 && t2 && U2 && z_best, XYL_EINVAL, "NULL argument");
+        require(n1 >= 2 && n2 >= 2, XYL_EINVAL, "curves need >= 2 points");
+        require(L1 > 0.0 && L2 > 0.0 && L1 != L2, XYL_EINVAL, "sizes must be positive and different");
+        require(z_step > 0.0 && z_hi >= z_lo && std::isfinite(z_lo) && std::isfinite(z_hi), XYL_EINVAL,
+                "bad z raster");
+        for (uint64_t i = 1; i < n2; ++i) require(t2[i] > t2[i - 1], XYL_EINVAL, "t2 must increase");
+        const double b = L1 / L2;
+        const uint64_t nz = (uint64_t)std::floor((z_hi - z_lo) / z_step + 1e-9) + 1;
+        double best = INFINITY, zb = NAN;
+        for (uint64_t j = 0; j < nz; ++j) {
+            const double z = z_lo + (double)j * z_step;
+            const double scale = std::pow(b, -z);
+            double e = 0.0;
+            uint64_t cnt = 0;
+            for (uint64_t i = 0; i < n1; ++i) {
+                // U(t, L1) against U(b^-z t, L2), the latter interpolated linearly
+                const double t = scale * t1[i];
+                if (!(t >= t2[0] && t <= t2[n2 - 1])) continue;
+                uint64_t hi = (uint64_t)(std::upper_bound(t2, t2 + n2, t) - t2);
+                hi = std::min<uint64_t>(std::max<uint64_t>(hi, 1), n2 - 1);
+                const uint64_t lo = hi - 1;
+                const double w = (t - t2[lo]) / (t2[hi] - t2[lo]);
+                const double u = U2[lo] + w * (U2[hi] - U2[lo]);
+                e += (U1[i] - u) * (U1[i] - u);
+                ++cnt;
+            }
+            if (cnt >= 3 && e / (double)cnt < best) {
+                best = e / (double)cnt;
+                zb = z;
+            }
+        }
+        require(std::isfinite(best), XYL_EINVAL, "no z in the raster overlaps the curves in >= 3 points");
+        *z_best = zb;
+        if (cost) *cost = best;
+    });
+}
+
 int xyl_mean_error(const double* f, uint64_t n, uint64_t discard, double* mean, double* se, double* tau) {
     return guarded([&] {
         require(f != nullptr, XYL_EINVAL, "NULL argument");

@@ -114,6 +114,28 @@ def test_lorentzian_fit_matches_oracle_estimator():
         xyl.lorentzian_xi(np.ones(20), 64, 5, 5)                       # one point
 
 
+def test_binder_relaxation_and_z_collapse_match_oracle_estimators():
+    import paper_2409_06412_amd as xyl
+    rng = np.random.default_rng(12)
+    m = rng.standard_normal((37, 103)) * np.linspace(1.0, 0.2, 103) + 0.3 * np.linspace(0, 1, 103)
+    U, se = xyl.binder_relaxation(m, 5)
+    np.testing.assert_allclose(U, estimators.binder_relaxation(m, 5), rtol=1e-13)
+    assert U.size == 20 and np.all(np.isfinite(se)) and np.all(se > 0)
+    f = lambda t: 1.1 + 1.9 * np.exp(-t / 30.0)
+    t = np.linspace(0.0, 300.0, 151)
+    t2 = np.linspace(0.0, 300.0, 97)
+    for z0, L1, L2 in ((2.16, 144, 112), (1.9, 64, 96)):
+        U1 = f((L1 / L2) ** (-z0) * t) + 1e-3 * rng.standard_normal(t.size)
+        z, c = xyl.z_collapse(t, U1, L1, t2, f(t2), L2, 1.5, 3.0, 0.01)
+        zo, co = estimators.z_collapse(t, U1, L1, t2, f(t2), L2, 1.5, 3.0, 0.01)
+        assert z == pytest.approx(zo, abs=1e-12) and c == pytest.approx(co, rel=1e-9)
+        assert abs(z - z0) < 0.05
+    with pytest.raises(xyl.XylError):
+        xyl.z_collapse(t, f(t), 64, t, f(t), 64)                    # equal sizes
+    with pytest.raises(xyl.XylError):
+        xyl.binder_relaxation(np.zeros((3, 4)), 2)                   # <m^2> = 0
+
+
 def test_oracle_library_is_independent_of_product():
     """The oracle neither links nor imports the HIP library."""
     for f in ("xyo.c", "xyo.h", "__init__.py", "estimators.py"):

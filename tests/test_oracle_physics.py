@@ -439,3 +439,31 @@ def test_lorentzian_fit_recovers_xi():
         S = estimators.structure_factor(np.exp(-np.minimum(r, N - r) / xi))
         got, _ = estimators.lorentzian_xi(S, N, 0, int(N / (2 * np.pi * xi)) + 2)
         assert got == pytest.approx(xi, rel=0.05)
+
+
+# ------------------------------------- time-resolved Binder cumulant, z
+def test_binder_relaxation_pins():
+    # hand-computed: two replicas, four samples, bins of two
+    m = np.array([[1.0, 2.0, 0.5, 0.5], [1.0, 0.0, 1.5, 0.5]])
+    U = estimators.binder_relaxation(m, 2)
+    x = np.array([1.0, 2.0, 1.0, 0.0])
+    assert U[0] == pytest.approx(np.mean(x ** 4) / np.mean(x ** 2) ** 2, rel=1e-15)
+    assert U[0] == pytest.approx((1 + 16 + 1) / 4 / ((1 + 4 + 1) / 4) ** 2, rel=1e-15)
+    # constant magnitude: U = 1; Gaussian magnetisation: U = 3
+    assert np.all(estimators.binder_relaxation(np.full((5, 6), -0.3), 3) == pytest.approx(1.0, abs=1e-15))
+    g = np.random.default_rng(2).standard_normal((4000, 20))
+    Ug = estimators.binder_relaxation(g, 10)
+    assert np.all(np.abs(Ug - 3.0) < 0.15)
+
+
+def test_z_collapse_recovers_planted_exponent():
+    """U(t, L1) = f(b^-z t) with f the relaxation of U(t, L2): the raster
+    minimum lies at the planted z (to its step), for either size order."""
+    f = lambda t: 1.2 + 1.8 * np.exp(-t / 40.0) + 0.1 * np.exp(-t / 7.0)
+    t = np.linspace(0.0, 400.0, 200)
+    for z0, L1, L2 in ((2.13, 144.0, 112.0), (2.17, 80.0, 112.0)):
+        b = L1 / L2
+        U1 = f(b ** (-z0) * t)
+        z, cost = estimators.z_collapse(t, U1, L1, t, f(t), L2, 1.5, 3.0, 0.01)
+        assert z == pytest.approx(z0, abs=0.006)
+        assert cost < 1e-5
