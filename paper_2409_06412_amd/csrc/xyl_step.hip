@@ -200,7 +200,9 @@ template <typename R, int MODE, int M>
 __global__ __launch_bounds__(512) void k_step(Lat<R> v, const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
     const int wpb = blockDim.x / kWave;
     const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int t = b * wpb + (int)(threadIdx.x / kWave);
+    // the wave's index is uniform: read it into a scalar register, so that the
+    // strip, row and address arithmetic derived from it stays scalar
+    const int t = b * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (t >= ntasks) return;
     const uint64_t j = j0 + (kdev ? *kdev : 0);
     run_strip<R, MODE, M>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(512) void k_ensemble_step(const Lat<R>* __restrict_
                                                        const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
     const int wpb = blockDim.x / kWave;
     const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int t = b * wpb + (int)(threadIdx.x / kWave);
+    const int t = b * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (t >= ntasks) return;
     const Task task = tasks[t];
     const uint64_t j = j0 + (kdev ? *kdev : 0);
