@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<R> A, const uint64_t* k
                                                  int ntasks) {
     const int wpb = blockDim.x / kWave;
     const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int t = b * wpb + (int)(threadIdx.x / kWave);
+    const int t = b * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave-uniform
     if (t >= ntasks) return;
     const uint64_t k = koff + (kdev ? *kdev : 0);
     adj_strip<R>(A, t, t % A.v.nxw, t / A.v.nxw, rows, k, threadIdx.x & (kWave - 1));

@@ -208,9 +208,13 @@ template <typename R, int M>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
     if constexpr (sizeof(R) == 4) {
-        // FP32: the kick g = hdt F + hs n is formed once and used by both halves
+        // FP32: the kick g = hdt F + hs n is formed once and used by both halves.
+        // The fresh-step choice is folded into two step-uniform coefficients:
+        // c (u + g) on ordinary steps (fma(1, g, u) = u + g exactly), u itself
+        // on the fresh step.
         const R g = Prec<R>::fma(v.hdt, f, hs * n);
-        const R ww = fresh ? u : v.c * (u + g);
+        const R cf = fresh ? R(1) : v.c, gf = fresh ? R(0) : R(1);
+        const R ww = cf * Prec<R>::fma(gf, g, u);
         w = ww;
         unew = Prec<R>::fma(v.a, ww, g);
     } else {
