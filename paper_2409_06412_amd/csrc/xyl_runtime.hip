@@ -283,16 +283,41 @@ struct xyl_lattice {
 // xyl_adjoint_backward: checkpoints every K steps, the loss samples and the
 // device buffers of the reverse sweep.
 struct AdjState {
+    bool valid = false;          // a forward run completed and may be differentiated
     uint64_t k0 = 0, N = 0, K = 0, W = 0;
     double loss = 0.0;
     std::vector<double> m;       // m_s at steps k0+N-W+1 .. k0+N
     DevBuf<char> ckpt, seg, lam;
     DevBuf<double> cm, gacc, obs, win;
-    DevBuf<uint64_t> kseg;
-    hipGraphExec_t seg_graph = nullptr;   // recompute + reverse of one full segment
-    int seg_graph_li = -1;                // adjoint buffer parity it was captured for
+    DevBuf<uint64_t> kseg;                 // step counters: [0] reverse (main stream), [1] recompute (side)
+    // Backward sweep: segment buffers b = 0, 1 (K + 1 states each); the
+    // recomputation of the next segment runs on a second stream into one
+    // buffer while the reverse steps of the current one read the other.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr}, ev_start = nullptr;
+    hipGraphExec_t rec_graph[2] = {nullptr, nullptr};        // K recompute steps into buffer b
+    hipGraphExec_t rev_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [b][adjoint parity]
+    // what the captured graphs bake in; they are rebuilt when it changes
+    std::vector<uint64_t> graph_key;
+    void drop_graphs() {
+        for (auto& g : rec_graph) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+        for (auto& r : rev_graph)
+            for (auto& g : r) {
+                if (g) (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
     ~AdjState() {
-        if (seg_graph) (void)hipGraphExecDestroy(seg_graph);
+        drop_graphs();
+        for (int b = 0; b < 2; ++b) {
+            if (ev_rec[b]) (void)hipEventDestroy(ev_rec[b]);
+            if (ev_rev[b]) (void)hipEventDestroy(ev_rev[b]);
+        }
+        if (ev_start) (void)hipEventDestroy(ev_start);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -1897,8 +1922,11 @@ int xyl_ensemble_sync(xyl_ensemble* e) {
 // ===================================================================== adjoint
 template <typename R>
 static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_t W, double* loss) {
-    adjoint_release(h);
-    std::unique_ptr<AdjState> a(new AdjState());
+    // the state (buffers, streams, captured backward graphs) is kept from one
+    // forward run to the next, so repeated gradient evaluations reuse it
+    if (!h->adj) h->adj = new AdjState();
+    AdjState* a = static_cast<AdjState*>(h->adj);
+    a->valid = false;
     const size_t bytes = sizeof(R) * h->N;
     a->k0 = h->k;
     a->N = N;
@@ -1952,7 +1980,7 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
     }
     a->loss = L / (double)W;
     if (loss) *loss = a->loss;
-    h->adj = a.release();
+    a->valid = true;
 }
 
 template <typename R>
@@ -1977,68 +2005,127 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, double* dth0, do
     R* lu[2] = {reinterpret_cast<R*>(a->lam.p + 2 * bytes), reinterpret_cast<R*>(a->lam.p + 3 * bytes)};
     launch_adjoint_seed<R>(v, static_cast<const R*>(h->cur_theta()), lt[0], lu[0], cmh[N], h->stream);
     int li = 0;
-    a->seg.reserve((K + 1) * 2 * bytes);
-    auto slot_th = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes); };
-    auto slot_u = [&](uint64_t j) { return reinterpret_cast<R*>(a->seg.p + j * 2 * bytes + bytes); };
-    a->kseg.reserve(1);
-    auto recompute_node = [&](uint64_t j, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
+    const size_t seg_bytes = (K + 1) * 2 * bytes;
+    a->seg.reserve(2 * seg_bytes);
+    auto slot_th = [&](int b, uint64_t j) { return reinterpret_cast<R*>(a->seg.p + b * seg_bytes + j * 2 * bytes); };
+    auto slot_u = [&](int b, uint64_t j) {
+        return reinterpret_cast<R*>(a->seg.p + b * seg_bytes + j * 2 * bytes + bytes);
+    };
+    a->kseg.reserve(2);
+    if (!a->side) {
+        check_hip(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking), "hipStreamCreate");
+        for (int b = 0; b < 2; ++b) {
+            check_hip(hipEventCreateWithFlags(&a->ev_rec[b], hipEventDisableTiming), "hipEventCreate");
+            check_hip(hipEventCreateWithFlags(&a->ev_rev[b], hipEventDisableTiming), "hipEventCreate");
+        }
+        check_hip(hipEventCreateWithFlags(&a->ev_start, hipEventDisableTiming), "hipEventCreate");
+    }
+    auto recompute_node = [&](int b, uint64_t j, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
         Lat<R> w = v;
         w.pingpong = 0;
-        w.th[0] = slot_th(j);
-        w.th[1] = slot_th(j + 1);
-        w.u = slot_u(j);
-        w.u_out = slot_u(j + 1);
+        w.th[0] = slot_th(b, j);
+        w.th[1] = slot_th(b, j + 1);
+        w.u = slot_u(b, j);
+        w.u_out = slot_u(b, j + 1);
         launch_step<R>(w, kStore, h->launch, kdev, kj, st);
     };
-    auto reverse_node = [&](uint64_t j, int parity, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
-        launch_adjoint_step<R>(v, slot_th(j), slot_u(j), lt[parity], lu[parity], lt[parity ^ 1], lu[parity ^ 1],
-                               a->cm.p, k0, a->gacc.p, kdev, kj, l, st);
+    auto reverse_node = [&](int b, uint64_t j, int parity, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
+        launch_adjoint_step<R>(v, slot_th(b, j), slot_u(b, j), lt[parity], lu[parity], lt[parity ^ 1],
+                               lu[parity ^ 1], a->cm.p, k0, a->gacc.p, kdev, kj, l, st);
     };
-    // Full segments of even length replay one captured graph (K recompute
-    // steps into the slots, then K reverse steps) whose step indices come
-    // from a device counter set to the segment's first step.
+    // Full segments of even length replay captured graphs whose step indices
+    // come from device counters set to the segment's first step: one graph
+    // per buffer for the K recompute steps, one per (buffer, adjoint parity)
+    // for the K reverse steps.
     const bool use_graph = h->graph_steps > 1 && K % 2 == 0 && K <= 4096;
-    for (uint64_t s = S; s-- > 0;) {
+    // key: every kernel argument the graphs capture (the lattice view by value,
+    // the buffers, the step base and the launch shapes)
+    std::vector<uint64_t> key = {K, (uint64_t)(uintptr_t)a->seg.p, (uint64_t)(uintptr_t)a->lam.p,
+                                 (uint64_t)(uintptr_t)a->cm.p, (uint64_t)(uintptr_t)a->gacc.p,
+                                 (uint64_t)(uintptr_t)a->kseg.p, (uint64_t)l.rows, (uint64_t)l.wpb,
+                                 (uint64_t)h->launch.rows, (uint64_t)h->launch.wpb, (uint64_t)ntasks, k0};
+    {
+        Lat<R> vz{};
+        std::memcpy(&vz, &v, sizeof(vz));
+        const size_t nw = (sizeof(vz) + 7) / 8;
+        std::vector<uint64_t> words(nw, 0);
+        std::memcpy(words.data(), &vz, sizeof(vz));
+        key.insert(key.end(), words.begin(), words.end());
+    }
+    if (key != a->graph_key) {
+        a->drop_graphs();
+        a->graph_key = key;
+    }
+    auto capture = [&](auto&& body) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            body();
+        } catch (...) {
+            (void)hipStreamEndCapture(h->cap_stream, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            throw;
+        }
+        check_hip(hipStreamEndCapture(h->cap_stream, &gr), "hipStreamEndCapture");
+        hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        check_hip(e, "hipGraphInstantiate");
+        return ex;
+    };
+    // segment s occupies buffer (S - 1 - s) & 1
+    auto recompute_segment = [&](uint64_t s) {
+        const int b = (int)((S - 1 - s) & 1);
         const uint64_t ks = k0 + s * K;
         const uint64_t len = std::min<uint64_t>(K, k0 + N - ks);
         const char* ck = a->ckpt.p + s * 2 * bytes;
-        check_hip(hipMemcpyAsync(slot_th(0), ck, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
-        check_hip(hipMemcpyAsync(slot_u(0), ck + bytes, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+        check_hip(hipMemcpyAsync(slot_th(b, 0), ck, bytes, hipMemcpyDeviceToDevice, a->side), "D2D");
+        check_hip(hipMemcpyAsync(slot_u(b, 0), ck + bytes, bytes, hipMemcpyDeviceToDevice, a->side), "D2D");
         if (use_graph && len == K) {
-            if (!a->seg_graph || a->seg_graph_li != li) {
-                if (a->seg_graph) (void)hipGraphExecDestroy(a->seg_graph);
-                a->seg_graph = nullptr;
-                hipGraph_t gr = nullptr;
-                check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal),
-                          "hipStreamBeginCapture");
-                try {
-                    for (uint64_t j = 0; j < K; ++j) recompute_node(j, a->kseg.p, j, h->cap_stream);
+            if (!a->rec_graph[b])
+                a->rec_graph[b] = capture([&] {
+                    for (uint64_t j = 0; j < K; ++j) recompute_node(b, j, a->kseg.p + 1, j, h->cap_stream);
+                });
+            launch_set_counter(a->kseg.p + 1, ks, a->side);
+            check_hip(hipGraphLaunch(a->rec_graph[b], a->side), "hipGraphLaunch");
+        } else {
+            for (uint64_t j = 0; j < len; ++j) recompute_node(b, j, nullptr, ks + j, a->side);
+        }
+        check_hip(hipEventRecord(a->ev_rec[b], a->side), "hipEventRecord");
+    };
+    // the side stream starts after everything issued so far (checkpoints, seed)
+    check_hip(hipEventRecord(a->ev_start, h->stream), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(a->side, a->ev_start, 0), "hipStreamWaitEvent");
+    recompute_segment(S - 1);
+    for (uint64_t s = S; s-- > 0;) {
+        const int b = (int)((S - 1 - s) & 1);
+        if (s > 0) {
+            // the next segment's buffer is free once the reverse that used it ended
+            if (S - 1 - s >= 1) check_hip(hipStreamWaitEvent(a->side, a->ev_rev[b ^ 1], 0), "hipStreamWaitEvent");
+            recompute_segment(s - 1);
+        }
+        check_hip(hipStreamWaitEvent(h->stream, a->ev_rec[b], 0), "hipStreamWaitEvent");
+        const uint64_t ks = k0 + s * K;
+        const uint64_t len = std::min<uint64_t>(K, k0 + N - ks);
+        if (use_graph && len == K) {
+            if (!a->rev_graph[b][li])
+                a->rev_graph[b][li] = capture([&] {
                     int p = li;
                     for (uint64_t j = K; j-- > 0;) {
-                        reverse_node(j, p, a->kseg.p, j, h->cap_stream);
+                        reverse_node(b, j, p, a->kseg.p, j, h->cap_stream);
                         p ^= 1;
                     }
-                } catch (...) {
-                    (void)hipStreamEndCapture(h->cap_stream, &gr);
-                    if (gr) (void)hipGraphDestroy(gr);
-                    throw;
-                }
-                check_hip(hipStreamEndCapture(h->cap_stream, &gr), "hipStreamEndCapture");
-                hipError_t e = hipGraphInstantiate(&a->seg_graph, gr, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(gr);
-                check_hip(e, "hipGraphInstantiate");
-                a->seg_graph_li = li;
-            }
+                });
             launch_set_counter(a->kseg.p, ks, h->stream);
-            check_hip(hipGraphLaunch(a->seg_graph, h->stream), "hipGraphLaunch");
+            check_hip(hipGraphLaunch(a->rev_graph[b][li], h->stream), "hipGraphLaunch");
             // K even: the adjoint state ends in the buffer it started from
         } else {
-            for (uint64_t j = 0; j < len; ++j) recompute_node(j, nullptr, ks + j, h->stream);
             for (uint64_t j = len; j-- > 0;) {
-                reverse_node(j, li, nullptr, ks + j, h->stream);
+                reverse_node(b, j, li, nullptr, ks + j, h->stream);
                 li ^= 1;
             }
         }
+        check_hip(hipEventRecord(a->ev_rev[b], h->stream), "hipEventRecord");
     }
     std::vector<double> g((size_t)ntasks * 4);
     check_hip(hipMemcpyAsync(g.data(), a->gacc.p, sizeof(double) * ntasks * 4, hipMemcpyDeviceToHost, h->stream),
@@ -2083,7 +2170,7 @@ int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* 
     return guarded([&] {
         require_init(h);
         AdjState* a = static_cast<AdjState*>(h->adj);
-        require(a != nullptr, XYL_ESTATE, "no adjoint forward run to differentiate");
+        require(a != nullptr && a->valid, XYL_ESTATE, "no adjoint forward run to differentiate");
         require(h->k == a->k0 + a->N, XYL_ESTATE, "lattice was stepped or reset after xyl_adjoint_forward");
         require(h->p.model == kModelXY, XYL_EUNSUPPORTED, "the adjoint supports the XY model only");
         DeviceGuard g(h->device);

@@ -120,3 +120,34 @@ def test_autograd_function(xyl):
     np.testing.assert_allclose(params.grad.numpy(), go, rtol=1e-8, atol=1e-12)
     np.testing.assert_allclose(th.grad.cpu().numpy(), dtho, rtol=1e-7, atol=1e-11 * np.abs(dtho).max())
     lat.close()
+
+
+def test_repeated_gradients_reuse_state_correctly(xyl):
+    """One lattice evaluates several gradients in a row. The backward graphs are
+    captured once and reused. Every evaluation equals the same evaluation on a
+    fresh lattice, bit for bit: from a new initial state, after a parameter
+    change (which must rebuild the graphs), and from a different step origin."""
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=0.8, dt=0.01, schedule=[(0, 0.9)], seed=4, replica=3)
+
+    def evaluate(lat, seed, lead, params):
+        lat.set_seed(seed, 3)
+        lat.set_params(*params)
+        lat.init_random()
+        lat.step(lead)
+        L = lat.adjoint_forward(200, 20, 40)
+        g, dth, dom = lat.adjoint_backward()
+        return L, g, dth, dom
+
+    base = (1.0, -0.1, 0.5, 0.8, 0.01)
+    cases = [(4, 0, base), (9, 0, base), (9, 0, (1.1, -0.1, 0.45, 0.8, 0.01)), (9, 6, base), (4, 0, base)]
+    shared = xyl.Lattice(96, 40, dtype="f32", **spec)
+    for seed, lead, params in cases:
+        got = evaluate(shared, seed, lead, params)
+        fresh = xyl.Lattice(96, 40, dtype="f32", **spec)
+        want = evaluate(fresh, seed, lead, params)
+        fresh.close()
+        assert got[0] == want[0]
+        np.testing.assert_array_equal(got[1], want[1])
+        np.testing.assert_array_equal(got[2], want[2])
+        np.testing.assert_array_equal(got[3], want[3])
+    shared.close()
