@@ -43,12 +43,36 @@ __global__ __launch_bounds__(256) void k_corr_lines(const R* __restrict__ th, in
     }
 }
 
+// Sum of the per-line rows part[l][0..rmax] over the lines, in two passes of
+// fixed order: chunks of kLineChunk lines are summed in parallel (thread r of
+// chunk c writes its sum into column r of the chunk's first row, which only it
+// touches), then the chunk sums are added in chunk order.
+constexpr int kLineChunk = 64;
+
+__global__ void k_line_sum_chunks(double* __restrict__ part, int nlines, int rmax) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > rmax) return;
+    const int l0 = blockIdx.y * kLineChunk;
+    const int l1 = min(l0 + kLineChunk, nlines);
+    double acc = 0.0;
+    for (int l = l0; l < l1; ++l) acc += part[(size_t)l * (rmax + 1) + r];
+    part[(size_t)l0 * (rmax + 1) + r] = acc;
+}
+
 __global__ void k_corr_sum(const double* __restrict__ part, int nlines, int rmax, double N, double* __restrict__ out) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > rmax) return;
     double acc = 0.0;
-    for (int l = 0; l < nlines; ++l) acc += part[(size_t)l * (rmax + 1) + r];
+    for (int l = 0; l < nlines; l += kLineChunk) acc += part[(size_t)l * (rmax + 1) + r];
     out[r] = acc / N;
+}
+
+static void launch_line_sum(double* part, int nlines, int rmax, double N, double* out, hipStream_t s) {
+    const dim3 g1((rmax + 256) / 256, (nlines + kLineChunk - 1) / kLineChunk);
+    k_line_sum_chunks<<<g1, 256, 0, s>>>(part, nlines, rmax);
+    check_hip(hipGetLastError(), "line sum launch");
+    k_corr_sum<<<(rmax + 256) / 256, 256, 0, s>>>(part, nlines, rmax, N, out);
+    check_hip(hipGetLastError(), "line sum launch");
 }
 
 template <typename R>
@@ -59,8 +83,7 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
     const size_t lds = 2 * sizeof(double) * (size_t)L;
     k_corr_lines<R><<<nlines, 256, lds, s>>>(th, Lx, Ly, sx, sy, model == kModelSI ? 2.0 : 1.0, axis, rmax, part);
     check_hip(hipGetLastError(), "correlation kernel launch");
-    k_corr_sum<<<(rmax + 256) / 256, 256, 0, s>>>(part, nlines, rmax, (double)Lx * (double)Ly, out);
-    check_hip(hipGetLastError(), "correlation sum launch");
+    launch_line_sum(part, nlines, rmax, (double)Lx * (double)Ly, out, s);
 }
 
 // ------------------------------------------------- structure factor
@@ -73,7 +96,7 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
 // Pass 1 writes z line-major (rows as they are; columns through a 32 x 32
 // LDS transpose), pass 2 transforms one line per workgroup in LDS (radix-2
 // decimation in time for power-of-two L, a direct sum otherwise), pass 3
-// sums the lines in order (k_corr_sum).
+// sums the lines in a fixed order (launch_line_sum).
 template <typename R>
 __global__ __launch_bounds__(256) void k_rotor_rows(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
                                                     double q, double2* __restrict__ z) {
@@ -197,8 +220,7 @@ void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int mo
               "hipFuncSetAttribute");
     k_sf_lines<<<nlines, 256, lds, s>>>(z, L, log2L, kmax, part);
     check_hip(hipGetLastError(), "structure factor kernel launch");
-    k_corr_sum<<<(kmax + 256) / 256, 256, 0, s>>>(part, nlines, kmax, (double)Lx * (double)Ly, out);
-    check_hip(hipGetLastError(), "structure factor sum launch");
+    launch_line_sum(part, nlines, kmax, (double)Lx * (double)Ly, out, s);
 }
 
 // -------------------------------------------------------------- domains
