@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define XYL_ABI_VERSION 2
+#define XYL_ABI_VERSION 3
 
 enum {
     XYL_OK = 0,
@@ -130,6 +130,16 @@ int xyl_set_model(xyl_lattice* h, int32_t model, double p);
  * reduced temperature written as T).  1 <= n <= XYL_MAX_KNOTS, knot steps
  * strictly increasing, T_j >= 0 and finite. */
 int xyl_set_schedule(xyl_lattice* h, const uint64_t* knot_step, const double* knot_T, int32_t n);
+/* The same with a shape per segment (the nonlinear quench protocols
+ * eps(t) ~ t^g of Sec. V): between knots j and j+1, with f the fraction of
+ * the segment elapsed, T = T_j + (T_{j+1} - T_j) w where w = f for
+ * knot_gamma[j] in {0, 1}, w = f^g for g > 1 (accelerating away from knot j)
+ * and w = 1 - (1 - f)^|g| for g < 0 (decelerating into knot j+1).  Powers are
+ * products of f in FP64, |g| <= 16.  A protocol through T_c with
+ * eps = -sign(t) |t / tau|^g uses a segment of shape -g into the T_c knot and
+ * one of shape g out of it. */
+int xyl_set_schedule_shaped(xyl_lattice* h, const uint64_t* knot_step, const double* knot_T,
+                            const int32_t* knot_gamma, int32_t n);
 int xyl_set_seed(xyl_lattice* h, uint64_t seed, uint32_t replica);
 /* th_i = W (2 U(w_{i&3}) - 1) from the Philox block of counter
  * (i>>2, replica, 2^32-1, 2^32-1) (the reserved step 2^64 - 1), with W = pi
@@ -160,6 +170,19 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
                       uint64_t* nout);
 /* Observables at the current step.  Synchronises. */
 int xyl_measure(xyl_lattice* h, xyl_obs* out);
+/* Adaptive sampling (App. B: samples ds >~ 100 dt apart, ds ~ tau_C / 10,
+ * adapted during the run).  Advances nsteps steps from the current step k0,
+ * recording observables (and their steps) at k0 and then ds steps apart, ds
+ * starting at ds0; the last sample is at k0 + nsteps.  Whenever `block`
+ * samples (>= 4; the first block includes the one at k0) have been taken, the
+ * integrated autocorrelation time tau of observable `which` (0..5, an xyl_obs
+ * field index; automatic window, c = 6) over them, in samples, sets the
+ * spacing of the following samples:
+ * ds = clamp(floor(ds tau / 10 + 1/2), ds_min, ds_max), 1 <= ds_min <= ds0 <=
+ * ds_max.  out and steps have room for cap >= nsteps / ds_min + 2 entries;
+ * *nout receives the count.  Synchronises once per block. */
+int xyl_step_adaptive(xyl_lattice* h, uint64_t nsteps, uint64_t ds0, uint64_t ds_min, uint64_t ds_max,
+                      int32_t which, uint64_t block, xyl_obs* out, uint64_t* steps, uint64_t cap, uint64_t* nout);
 /* Staggered rotor correlation along axis (0 = x, 1 = y) at the current step
  * (App. C, two-point function of the rotors, lattice average):
  * C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along the axis,
@@ -258,6 +281,7 @@ typedef struct {
     uint64_t nsteps;
     int32_t model;    /* XYL_MODEL_*; every replica of an ensemble has the same */
     double p;         /* field order, as for xyl_set_model */
+    int32_t knot_gamma[XYL_MAX_KNOTS];   /* segment shapes as for xyl_set_schedule_shaped (0 = linear) */
 } xyl_replica_desc;
 
 /* Creates n >= 1 replicas on one device in one state allocation, indexed by a

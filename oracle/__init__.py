@@ -46,6 +46,7 @@ class Model(ctypes.Structure):
         ("knot_T", ctypes.c_double * MAX_KNOTS),
         ("model", ctypes.c_int32),
         ("p", ctypes.c_double),
+        ("knot_gamma", ctypes.c_int32 * MAX_KNOTS),
     ]
 
 
@@ -114,9 +115,10 @@ class Oracle:
         if not 1 <= len(sched) <= MAX_KNOTS:
             raise ValueError("schedule needs 1..16 knots")
         m.nknots = len(sched)
-        for j, (k, T) in enumerate(sched):
-            m.knot_step[j] = int(k)
-            m.knot_T[j] = float(T)
+        for j, kt in enumerate(sched):
+            m.knot_step[j] = int(kt[0])
+            m.knot_T[j] = float(kt[1])
+            m.knot_gamma[j] = int(kt[2]) if len(kt) > 2 else 1
         self.m = m
         self.N = m.Lx * m.Ly
         self._p = ctypes.byref(m)
@@ -220,7 +222,7 @@ class Oracle:
     def with_params(self, **kw) -> "Oracle":
         m = self.m
         args = dict(Lx=m.Lx, Ly=m.Ly, Jx=m.Jx, Jy=m.Jy, h=m.h, gamma=m.gamma, dt=m.dt,
-                    schedule=[(m.knot_step[j], m.knot_T[j]) for j in range(m.nknots)],
+                    schedule=[(m.knot_step[j], m.knot_T[j], m.knot_gamma[j]) for j in range(m.nknots)],
                     seed=m.seed, replica=m.replica, model=self.model, p=m.p)
         args.update(kw)
         return Oracle(**args)

@@ -19,6 +19,10 @@ Written from their definitions, in numpy, for a reader to check by eye:
     least-squares fit of the Lorentzian A 2 xi / (1 + 4 pi^2 xi^2 (k/N)^2)
     around k = 0 (App. C, Eq. Lorentzian-Peak, with k read as k / N), by
     scipy's curve_fit.
+  * Adaptive sampling (App. B: ds ~ tau_C / 10, adapted during the run): the
+    plan of sample steps that the rule ds' = clamp(floor(ds tau / 10 + 1/2))
+    produces from the samples' values, tau of each block of samples in
+    samples.
   * Time-resolved Binder cumulant U(t) (Sec. IV.B; App. B: the ensemble
     average over replicas restricted to a time bin) and the dynamic exponent
     z from the collapse U(t, L1) = U(b^-z t, L2), b = L1 / L2, by a raster of
@@ -141,4 +145,22 @@ def z_collapse(t1, U1, L1, t2, U2, L2, z_lo=1.0, z_hi=3.5, z_step=0.01):
         if cost < best[0]:
             best = (cost, z)
     return best[1], best[0]
+
+
+def adaptive_steps(values, k0: int, nsteps: int, ds0: int, ds_min: int, ds_max: int, block: int):
+    """Sample steps of the adaptive rule, replayed from the sequence of the
+    chosen observable's sample values (one per sample, in order)."""
+    steps = [k0]
+    ds = ds0
+    blk = [values[0]]
+    i = 0
+    while steps[-1] < k0 + nsteps:
+        if len(blk) == block:
+            tau = tau_int(np.array(blk))
+            ds = int(min(max(np.floor(ds * tau / 10.0 + 0.5), ds_min), ds_max))
+            blk = []
+        steps.append(steps[-1] + min(ds, k0 + nsteps - steps[-1]))
+        i += 1
+        blk.append(values[i])
+    return steps
 

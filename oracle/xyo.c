@@ -100,7 +100,17 @@ double xyo_temperature(const xyo_model* m, uint64_t k) {
         while (!(k >= m->knot_step[j] && k < m->knot_step[j + 1])) ++j;
         double ka = (double)m->knot_step[j], kb = (double)m->knot_step[j + 1];
         double frac = ((double)k - ka) / (kb - ka);
-        T = m->knot_T[j] + (m->knot_T[j + 1] - m->knot_T[j]) * frac;
+        int g = m->knot_gamma[j];
+        double w = frac;
+        if (g > 1) {
+            for (int i = 1; i < g; ++i) w = w * frac;
+        } else if (g < 0) {
+            double r = 1.0 - frac;
+            w = r;
+            for (int i = 1; i < -g; ++i) w = w * r;
+            w = 1.0 - w;
+        }
+        T = m->knot_T[j] + (m->knot_T[j + 1] - m->knot_T[j]) * w;
     }
     if (T < 0.0) T = 0.0;
     return T;

@@ -44,6 +44,8 @@ typedef struct {
     double knot_T[XYO_MAX_KNOTS];        /* >= 0 */
     int32_t model;                       /* XYO_MODEL_XY or XYO_MODEL_SI */
     double p;                            /* field order of XYO_MODEL_SI (> 0) */
+    int32_t knot_gamma[XYO_MAX_KNOTS];   /* shape of the segment from knot j: 0 or 1 linear,
+                                            g > 1: w = f^g, g < 0: w = 1 - (1 - f)^|g| */
 } xyo_model;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): one block. */
@@ -54,7 +56,10 @@ double xyo_uniform(uint32_t r);
  * with counter (i>>2, replica, k_lo, k_hi) and key (seed_lo, seed_hi)). */
 double xyo_normal(const xyo_model* m, uint64_t k, int64_t i);
 void xyo_normals(const xyo_model* m, uint64_t k, double* n);
-/* Temperature T_k: piecewise linear in the step index, held outside the knots. */
+/* Temperature T_k between knots a, b: T_a + (T_b - T_a) w with f = (k - k_a) /
+ * (k_b - k_a) and w = f (linear, Sec. II.B Eq. Linear-Quench), w = f^g or
+ * w = 1 - (1 - f)^|g| (the nonlinear protocols eps ~ t^g of Sec. V), powers
+ * by repeated multiplication; held outside the knots. */
 double xyo_temperature(const xyo_model* m, uint64_t k);
 
 /* Initial states.  Random: th_i = W (2U - 1) from the reserved init stream

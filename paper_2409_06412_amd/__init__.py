@@ -49,6 +49,7 @@ class ReplicaDesc(ctypes.Structure):
         ("nsteps", ctypes.c_uint64),
         ("model", ctypes.c_int32),
         ("p", ctypes.c_double),
+        ("knot_gamma", ctypes.c_int32 * MAX_KNOTS),
     ]
 
 
@@ -75,6 +76,8 @@ _SIGS = {
     "xyl_set_stream": (_i32, [_vp, _vp]),
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
+    "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
+    "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
     "xyl_structure_factor": (_i32, [_vp, _i32, _i32, P(_d)]),
     "xyl_ensemble_structure_factor": (_i32, [_vp, _i32, _i32, _i32, P(_d)]),
     "xyl_lorentzian_xi": (_i32, [P(_d), _i32, _i32, _i32, P(_d), P(_d)]),
@@ -149,10 +152,13 @@ def _f64(a, shape) -> np.ndarray:
 
 
 def _sched_arrays(schedule):
+    """Knots (k, T) or (k, T, g): g is the shape of the segment that starts
+    at the knot (1 linear, g > 1 power law, g < 0 mirrored power law)."""
     sched = list(schedule)
-    ks = (_u64 * len(sched))(*[int(k) for k, _ in sched])
-    Ts = (_d * len(sched))(*[float(T) for _, T in sched])
-    return ks, Ts, len(sched)
+    ks = (_u64 * len(sched))(*[int(kt[0]) for kt in sched])
+    Ts = (_d * len(sched))(*[float(kt[1]) for kt in sched])
+    gs = (_i32 * len(sched))(*[int(kt[2]) if len(kt) > 2 else 1 for kt in sched])
+    return ks, Ts, gs, len(sched)
 
 
 def _dtype_code(dtype) -> int:
@@ -227,9 +233,9 @@ class Lattice:
         self.model, self.p = code, float(p)
 
     def set_schedule(self, schedule):
-        ks, Ts, n = _sched_arrays(schedule)
-        _check(load().xyl_set_schedule(self._h, ks, Ts, n))
-        self._schedule = [(int(k), float(T)) for k, T in schedule]
+        ks, Ts, gs, n = _sched_arrays(schedule)
+        _check(load().xyl_set_schedule_shaped(self._h, ks, Ts, gs, n))
+        self._schedule = [(int(kt[0]), float(kt[1]), int(kt[2]) if len(kt) > 2 else 1) for kt in schedule]
 
     def set_seed(self, seed, replica=0):
         _check(load().xyl_set_seed(self._h, int(seed), int(replica)))
@@ -306,6 +312,17 @@ class Lattice:
         _check(load().xyl_step_measured(self._h, int(nsteps), int(every), _pd(out), ns, ctypes.byref(nout)))
         return out[: nout.value]
 
+    def step_adaptive(self, nsteps: int, ds0: int, ds_min: int, ds_max: int, which: int = 2, block: int = 32):
+        """Samples whose spacing follows tau_C / 10 of observable `which`;
+        returns (steps, samples)."""
+        cap = int(nsteps) // int(ds_min) + 2
+        out = np.empty((cap, 6))
+        steps = np.empty(cap, dtype=np.uint64)
+        n = _u64()
+        _check(load().xyl_step_adaptive(self._h, int(nsteps), int(ds0), int(ds_min), int(ds_max), int(which),
+                                        int(block), _pd(out), steps.ctypes.data_as(P(_u64)), cap, ctypes.byref(n)))
+        return steps[: n.value].astype(np.int64), out[: n.value]
+
     def measure(self) -> np.ndarray:
         out = np.empty(6)
         _check(load().xyl_measure(self._h, _pd(out)))
@@ -354,7 +371,7 @@ class Lattice:
         if bytes(d.pop("checksum")) != _checksum(d):
             raise XylError(-1, "checkpoint %s is corrupt (checksum mismatch)" % path)
         p = d["params"]
-        sched = [(int(k), float(T)) for k, T in d["schedule"]]
+        sched = [(int(row[0]), float(row[1])) + ((int(row[2]),) if len(row) > 2 else ()) for row in d["schedule"]]
         seed, rep = (int(v) for v in d["key"])
         lat = cls(int(d["Lx"]), int(d["Ly"]), dtype=int(d["dtype"]), device=device, Jx=p[0], Jy=p[1], h=p[2],
                   gamma=p[3], dt=p[4], schedule=sched, seed=seed, replica=rep, stream=stream,
@@ -415,9 +432,10 @@ class Ensemble:
             d.seed, d.replica = s.seed, s.replica
             sched = list(s.schedule)
             d.nknots = len(sched)
-            for j, (k, T) in enumerate(sched):
-                d.knot_step[j] = int(k)
-                d.knot_T[j] = float(T)
+            for j, kt in enumerate(sched):
+                d.knot_step[j] = int(kt[0])
+                d.knot_T[j] = float(kt[1])
+                d.knot_gamma[j] = int(kt[2]) if len(kt) > 2 else 1
             d.nsteps = int(s.nsteps)
             d.model = _model_code(getattr(s, "model", "xy"))
             d.p = float(getattr(s, "p", 2.0))

@@ -45,8 +45,11 @@ __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 }
 
 // --------------------------------------------------------------- schedule
-// T(k), piecewise linear in the step index, held outside the knots; FP64 with
-// the operation order fixed so that every caller gets the same bits.
+// T(k) between knots a, b: T_a + (T_b - T_a) w, f = (k - k_a) / (k_b - k_a),
+// w = f (linear quench, Sec. II.B), f^g or 1 - (1 - f)^|g| (the power-law
+// protocols of Sec. V; powers by repeated multiplication); held outside the
+// knots.  FP64 with the operation order fixed so that every caller gets the
+// same bits.
 __host__ __device__ __forceinline__ double schedule_T(const Schedule& s, uint64_t k) {
     double T;
     if (k <= s.step[0]) {
@@ -58,7 +61,17 @@ __host__ __device__ __forceinline__ double schedule_T(const Schedule& s, uint64_
         while (!(k >= s.step[j] && k < s.step[j + 1])) ++j;
         const double ka = (double)s.step[j], kb = (double)s.step[j + 1];
         const double frac = ((double)k - ka) / (kb - ka);
-        T = s.T[j] + (s.T[j + 1] - s.T[j]) * frac;
+        const int g = s.g[j];
+        double w = frac;
+        if (g > 1) {
+            for (int i = 1; i < g; ++i) w = w * frac;
+        } else if (g < 0) {
+            const double r = 1.0 - frac;
+            w = r;
+            for (int i = 1; i < -g; ++i) w = w * r;
+            w = 1.0 - w;
+        }
+        T = s.T[j] + (s.T[j + 1] - s.T[j]) * w;
     }
     return T < 0.0 ? 0.0 : T;
 }

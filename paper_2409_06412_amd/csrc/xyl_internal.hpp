@@ -15,10 +15,13 @@ constexpr int kMaxKnots = 16;
 constexpr int kNPart = 12;                 // measurement partial sums per (row, wave chunk)
 constexpr uint64_t kInitStep = ~(uint64_t)0;  // reserved step counter of the init stream
 
+// Piecewise schedule: segment j runs from knot j to knot j+1 with the shape
+// g[j] (0 or 1: linear; g > 1: f^g; g < 0: 1 - (1 - f)^|g|).
 struct Schedule {
     int32_t n;
     uint64_t step[kMaxKnots];
     double T[kMaxKnots];
+    int32_t g[kMaxKnots];
 };
 
 // Everything a step kernel needs to know about one lattice (or one replica of

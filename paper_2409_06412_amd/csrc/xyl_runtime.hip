@@ -111,7 +111,7 @@ static void validate_params(const Params& p) {
     require(p.gamma >= 0.0, XYL_EINVAL, "gamma must be >= 0");
 }
 
-static Schedule make_schedule(const uint64_t* ks, const double* Ts, int32_t n) {
+static Schedule make_schedule(const uint64_t* ks, const double* Ts, int32_t n, const int32_t* gs = nullptr) {
     require(n >= 1 && n <= kMaxKnots, XYL_EINVAL, "schedule needs 1..16 knots");
     require(ks != nullptr && Ts != nullptr, XYL_EINVAL, "schedule arrays are NULL");
     Schedule s{};
@@ -121,6 +121,9 @@ static Schedule make_schedule(const uint64_t* ks, const double* Ts, int32_t n) {
         if (j > 0) require(ks[j] > ks[j - 1], XYL_EINVAL, "schedule steps must be strictly increasing");
         s.step[j] = ks[j];
         s.T[j] = Ts[j];
+        const int g = gs ? gs[j] : 1;
+        require(g >= -16 && g <= 16, XYL_EINVAL, "schedule shape exponents must lie in [-16, 16]");
+        s.g[j] = g == 0 ? 1 : g;
     }
     return s;
 }
@@ -656,6 +659,15 @@ int xyl_set_schedule(xyl_lattice* h, const uint64_t* ks, const double* Ts, int32
     });
 }
 
+int xyl_set_schedule_shaped(xyl_lattice* h, const uint64_t* ks, const double* Ts, const int32_t* gs, int32_t n) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(gs != nullptr, XYL_EINVAL, "shape array is NULL");
+        h->sched = make_schedule(ks, Ts, n, gs);
+        h->touch();
+    });
+}
+
 int xyl_set_seed(xyl_lattice* h, uint64_t seed, uint32_t replica) {
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");
@@ -800,6 +812,71 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         if (nout) *nout = ns;
         require_finite(reinterpret_cast<const double*>(out), 6 * ns, "observables");
+    });
+}
+
+int xyl_step_adaptive(xyl_lattice* h, uint64_t nsteps, uint64_t ds0, uint64_t ds_min, uint64_t ds_max, int32_t which,
+                      uint64_t block, xyl_obs* out, uint64_t* steps, uint64_t cap, uint64_t* nout) {
+    return guarded([&] {
+        require_init(h);
+        require(out != nullptr && steps != nullptr, XYL_EINVAL, "out/steps are NULL");
+        require(ds_min >= 1 && ds_min <= ds0 && ds0 <= ds_max, XYL_EINVAL, "need 1 <= ds_min <= ds0 <= ds_max");
+        require(which >= 0 && which < 6, XYL_EINVAL, "which must index an observable (0..5)");
+        require(block >= 4, XYL_EINVAL, "block must be >= 4 samples");
+        require(cap >= nsteps / ds_min + 2, XYL_EINVAL, "cap must be >= nsteps / ds_min + 2");
+        DeviceGuard g(h->device);
+        h->obs.reserve(6 * block);
+        const uint64_t kend = h->k + nsteps;
+        uint64_t ds = ds0, n = 0;
+        std::vector<double> vals;
+        vals.reserve(block);
+        // samples are measured into a device block and copied out when it is
+        // full (the spacing decision needs them) or at the end
+        uint64_t in_dev = 0;
+        auto flush = [&]() {
+            if (!in_dev) return;
+            check_hip(hipMemcpyAsync(out + (n - in_dev), h->obs.p, sizeof(double) * 6 * in_dev,
+                                     hipMemcpyDeviceToHost, h->stream),
+                      "D2H");
+            check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+            in_dev = 0;
+        };
+        auto sample = [&](bool advance) {
+            if (in_dev == block) flush();
+            steps[n] = h->k;
+            if (h->dtype == XYL_F64) lattice_measure_into<double>(h, advance, h->obs.p + 6 * in_dev);
+            else lattice_measure_into<float>(h, advance, h->obs.p + 6 * in_dev);
+            ++in_dev;
+            ++n;
+        };
+        uint64_t blk = 0;   // samples in the current block (equal spacing)
+        while (true) {
+            const bool last = h->k == kend;
+            sample(!last);   // measures at k and, unless last, advances one step
+            ++blk;
+            if (last) break;
+            if (blk == block) {
+                // the block's series of the chosen observable decides the
+                // spacing from here on: ds' = ds tau / 10 with tau in samples
+                // (App. B: ds ~ tau_C / 10)
+                flush();
+                vals.assign(block, 0.0);
+                const xyl_obs* o = out + (n - block);
+                for (uint64_t i = 0; i < block; ++i) vals[i] = reinterpret_cast<const double*>(o + i)[which];
+                const double tau = tau_int(vals.data(), block);
+                const double want = std::floor((double)ds * tau / 10.0 + 0.5);
+                ds = (uint64_t)std::min<double>(std::max<double>(want, (double)ds_min), (double)ds_max);
+                blk = 0;
+            }
+            const uint64_t adv = std::min<uint64_t>(ds, kend - (h->k - 1));
+            if (adv > 1) {
+                if (h->dtype == XYL_F64) lattice_steps<double>(h, adv - 1);
+                else lattice_steps<float>(h, adv - 1);
+            }
+        }
+        flush();
+        if (nout) *nout = n;
+        require_finite(reinterpret_cast<const double*>(out), 6 * n, "observables");
     });
 }
 
@@ -1361,6 +1438,7 @@ struct xyl_ensemble {
         for (int q = 0; q < d.nknots; ++q) {
             s.step[q] = d.knot_step[q];
             s.T[q] = d.knot_T[q];
+            s.g[q] = d.knot_gamma[q] == 0 ? 1 : d.knot_gamma[q];
         }
         fill_lat(v, d.Lx, d.Ly, p, s, d.seed, d.replica);
         v.k_base = k[r] - jbase;   // k = k_base + j for the launches numbered from jbase
@@ -1722,7 +1800,7 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
             validate_params(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p});
             validate_model(d.model, d.p);
             require(d.model == desc[0].model, XYL_EINVAL, "all replicas of an ensemble must use the same model");
-            (void)make_schedule(d.knot_step, d.knot_T, d.nknots);
+            (void)make_schedule(d.knot_step, d.knot_T, d.nknots, d.knot_gamma);
             e->off.push_back(e->total);
             // keep every replica's base 256-byte aligned
             const size_t N = (size_t)d.Lx * d.Ly;

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import estimators
 from paper_2409_06412_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -347,4 +348,40 @@ def test_thermal_averages_fp32_vs_oracle(xyl):
         mo, eo, _ = estimators.mean_and_error(f(so[:, col]), 0.2)
         say("col", col, "gpu", mg, "+-", eg, "oracle", mo, "+-", eo)
         assert abs(mg - mo) <= 3 * math.hypot(eg, eo) + 1e-6
+    lat.close()
+
+
+# ------------------------------------------------------- adaptive sampling
+def test_adaptive_sampling_matches_oracle(xyl):
+    """The GPU driver's sample steps equal the oracle's replay of the rule on
+    the GPU's own sample values, and its samples equal the oracle's at those
+    steps (FP64)."""
+    nsteps, ds0, dmin, dmax, block, which = 3000, 20, 5, 300, 16, 0
+    lat, o = make_pair(xyl, 64, 48, "f64", schedule=[(0, 0.7)], seed=13, replica=4)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    steps, samples = lat.step_adaptive(nsteps, ds0, dmin, dmax, which, block)
+    want = estimators.adaptive_steps(samples[:, which], 0, nsteps, ds0, dmin, dmax, block)
+    assert list(steps) == want
+    d = np.diff(steps)
+    say("adaptive spacings", sorted(set(d.tolist()))[:12], "samples", len(steps))
+    assert len(set(d.tolist())) > 1                 # the spacing did adapt
+    _, _, so = o.run(th0, om0, 0, nsteps, every=1)
+    np.testing.assert_allclose(samples, so[steps], rtol=1e-10, atol=1e-12)
+    k = lat.step_index
+    assert k == nsteps
+    lat.close()
+
+
+def test_shaped_schedule_matches_oracle(xyl):
+    """A nonlinear protocol through T_c (eps ~ -sign(t) |t/tau|^2, Sec. V):
+    the GPU's trajectory follows the oracle's, whose temperatures are pinned
+    against the closed form on the CPU."""
+    sched = [(0, 1.2, -2), (300, 0.7, 3), (600, 0.2)]
+    lat, o = make_pair(xyl, 64, 64, "f64", schedule=sched, seed=5)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    s = lat.step_measured(700, 50)
+    _, _, so = o.run(th0, om0, 0, 700, every=50)
+    np.testing.assert_allclose(s, so, rtol=1e-10, atol=1e-12)
     lat.close()

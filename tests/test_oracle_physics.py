@@ -467,3 +467,62 @@ def test_z_collapse_recovers_planted_exponent():
         z, cost = estimators.z_collapse(t, U1, L1, t, f(t), L2, 1.5, 3.0, 0.01)
         assert z == pytest.approx(z0, abs=0.006)
         assert cost < 1e-5
+
+
+# ------------------------------------------------ quench schedules (Sec. II.B, V)
+def test_schedule_shapes():
+    """Piecewise schedules: linear segments (Eq. Linear-Quench), power-law
+    segments w = f^g (eps ~ t^g, Sec. V) and their mirror 1 - (1 - f)^g,
+    checked against the closed forms; held outside the knots."""
+    sched = [(100, 2.0, 3), (200, 1.0, -2), (300, 1.0), (400, 0.5, 1)]
+    o = oracle.Oracle(4, 4, schedule=sched)
+    for k in range(0, 500, 7):
+        if k <= 100:
+            want = 2.0
+        elif k < 200:
+            f = (k - 100) / 100
+            want = 2.0 - 1.0 * f ** 3
+        elif k < 300:
+            f = (k - 200) / 100
+            want = 1.0 + 0.0 * (1 - (1 - f) ** 2)
+        elif k < 400:
+            want = 1.0 - 0.5 * (k - 300) / 100
+        else:
+            want = 0.5
+        assert o.temperature(k) == pytest.approx(want, rel=1e-14, abs=1e-15), k
+    # a symmetric protocol through T_c: decelerating into the critical point,
+    # accelerating out of it, eps(t) = -sign(t) |t / tau|^2 about the crossing
+    Tc, tau = 1.0, 1000
+    o = oracle.Oracle(4, 4, schedule=[(0, 1.25, -2), (tau, Tc, 2), (2 * tau, 0.75)])
+    for t in (-900, -400, -37, 0, 52, 300, 999):
+        eps = -np.sign(t) * (abs(t) / tau) ** 2 * 0.25
+        assert o.temperature(tau + t) == pytest.approx(Tc * (1 + eps), rel=1e-13), t
+
+
+def test_adaptive_sampling_rule():
+    """The rule ds' = clamp(floor(ds tau / 10 + 1/2)) on series of known
+    autocorrelation: white noise (tau = 1/2) drives ds to ds_min, a slow AR(1)
+    series (tau = 0.5 (1 + phi) / (1 - phi) = 19.5 samples) to ds_max within a
+    few blocks, and every spacing stays inside the clamp; the plan ends at
+    k0 + nsteps."""
+    rng = np.random.default_rng(3)
+    white = rng.standard_normal(10000)
+    st = estimators.adaptive_steps(white, 7, 20000, 40, 10, 400, 64)
+    d = np.diff(st)
+    assert st[0] == 7 and st[-1] == 20007
+    assert np.all(d[:-1] >= 10) and np.all(d <= 400)
+    assert np.all(d[64:-1] == 10)
+    phi = 0.95                                   # tau = 19.5 samples: ds roughly doubles per block
+    x = np.empty(12000)
+    x[0] = 0.0
+    for t in range(1, x.size):
+        x[t] = phi * x[t - 1] + rng.standard_normal()
+    st = estimators.adaptive_steps(x, 0, 1000000, 20, 10, 400, 1024)
+    d = np.diff(st)
+    assert d[0] == 20 and np.max(d) == 400 and np.all(d[:-1] >= 10)
+    # every decision follows the rule on its block
+    blocks = [x[i * 1024:(i + 1) * 1024] for i in range(3)]
+    ds = 20
+    for b in blocks:
+        ds = int(min(max(np.floor(ds * estimators.tau_int(b) / 10 + 0.5), 10), 400))
+    assert d[3 * 1024 - 1] == ds
