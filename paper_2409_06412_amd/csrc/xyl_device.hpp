@@ -112,10 +112,12 @@ struct Prec<float> {
         return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, r, 9u)) - 0x1.fffffep-1f;
     }
     // One Box-Muller pair: radius sqrt(-2 ln u1) (ln via the native log2),
-    // angle 2 pi u2 (native sine/cosine in revolutions, no multiplication).
-    __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, float& nc, float& ns) {
+    // angle 2 pi u2 (native sine/cosine in revolutions, no multiplication);
+    // both draws scaled by `scale` through the radius.
+    __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, float& nc, float& ns,
+                                                      float scale = 1.0f) {
         const float u1 = uniform(r1), u2 = uniform(r2);
-        const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989062f * __builtin_amdgcn_logf(u1));
+        const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989062f * __builtin_amdgcn_logf(u1)) * scale;
         nc = rad * __builtin_amdgcn_cosf(u2);
         ns = rad * __builtin_amdgcn_sinf(u2);
     }
@@ -142,18 +144,16 @@ struct Prec<double> {
 };
 
 // Wrap to [-W, W) with W = pi_p (XY) or pi_p / 2 (SI, whose rotors are half
-// circles): exact by Sterbenz's lemma while |dt * u| < W.  Two selects
-// instead of branches; same result as "if t >= W: t -= 2W, else if t < -W:
-// t += 2W" for every input (after the first select t < W holds, and a value
-// that the first select moved is >= -W).
+// circles): exact by Sterbenz's lemma while |dt * u| < W.  Same result as
+// "if t >= W: t -= 2W, else if t < -W: t += 2W" for every input.
+// The shift is selected first and subtracted once: t - 2W, t + 2W (both exact)
+// or t - (+0) = t, which keeps the sign of a zero.
 template <typename R, int M>
 __device__ __forceinline__ R wrap_angle(R t) {
     constexpr R W = M == kModelSI ? Prec<R>::kHalfPi : Prec<R>::kPi;
     constexpr R W2 = M == kModelSI ? Prec<R>::kPi : Prec<R>::kTwoPi;
-    const R lo = t - W2;
-    t = t >= W ? lo : t;
-    const R hi = t + W2;
-    return t < -W ? hi : t;
+    const R shift = t >= W ? W2 : (t < -W ? -W2 : R(0));
+    return t - shift;
 }
 
 // Rotor of a site, (sin q t, cos q t): q = 1 (XY) or 2 (SI).
@@ -169,6 +169,21 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
     const U32x4 r = philox4x32_10(q, replica, (uint32_t)k, (uint32_t)(k >> 32), s0, s1);
     Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1]);
     Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3]);
+}
+
+// The draws as site_update takes them: FP32 multiplies in the half-kick noise
+// amplitude hs through the Box-Muller radius (one multiplication per pair);
+// FP64 returns the plain draws and site_update applies hs in the oracle's order.
+template <typename R>
+__device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64_t k, uint32_t s0, uint32_t s1, R hs,
+                                            R n[4]) {
+    if constexpr (sizeof(R) == 4) {
+        const U32x4 r = philox4x32_10(q, replica, (uint32_t)k, (uint32_t)(k >> 32), s0, s1);
+        Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1], hs);
+        Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3], hs);
+    } else {
+        noise4<R>(q, replica, k, s0, s1, n);
+    }
 }
 
 // ------------------------------------------------------ per-site BBK math
@@ -221,11 +236,12 @@ template <typename R, int M>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
     if constexpr (sizeof(R) == 4) {
-        // FP32: the kick g = hdt F + hs n is formed once and used by both halves.
-        // The fresh-step choice is folded into two step-uniform coefficients:
-        // c (u + g) on ordinary steps (fma(1, g, u) = u + g exactly), u itself
-        // on the fresh step.
-        const R g = Prec<R>::fma(v.hdt, f, hs * n);
+        // FP32: n arrives as hs n (noise4_kick); the kick g = hdt F + hs n is
+        // formed once and used by both halves.  The fresh-step choice is folded
+        // into two step-uniform coefficients: c (u + g) on ordinary steps
+        // (fma(1, g, u) = u + g exactly), u itself on the fresh step.
+        (void)hs;
+        const R g = Prec<R>::fma(v.hdt, f, n);
         const R cf = fresh ? R(1) : v.c, gf = fresh ? R(0) : R(1);
         const R ww = cf * Prec<R>::fma(gf, g, u);
         w = ww;
@@ -250,20 +266,26 @@ __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n
 // ---------------------------------------------------- lane exchange (DPP)
 // wave_shr:1 moves a value to the next lane up, wave_shl:1 to the next lane
 // down; lanes at the ends receive `old`.
-__device__ __forceinline__ float from_lane_below(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+__device__ __forceinline__ float from_lane_below(float v, float old = 0.0f) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float from_lane_above(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+__device__ __forceinline__ float from_lane_above(float v, float old = 0.0f) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
-__device__ __forceinline__ double from_lane_below(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x138, 0xF, 0xF, false);
+__device__ __forceinline__ double from_lane_below(double v, double old = 0.0) {
+    const int lo =
+        __builtin_amdgcn_update_dpp((int)__double2loint(old), (int)__double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp((int)__double2hiint(old), (int)__double2hiint(v), 0x138, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double from_lane_above(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xF, 0xF, false);
+__device__ __forceinline__ double from_lane_above(double v, double old = 0.0) {
+    const int lo =
+        __builtin_amdgcn_update_dpp((int)__double2loint(old), (int)__double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp((int)__double2hiint(old), (int)__double2hiint(v), 0x130, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 

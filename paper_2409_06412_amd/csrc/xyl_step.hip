@@ -84,18 +84,25 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         // (the wave's first lane takes its left neighbour, the last active lane
         // its right one, from the extra angle loaded with the row; a wave with
         // a single active lane needs both)
+        // (lane 0 is the first lane of every wave: the shift leaves it its own
+        // value; in a full wave the same holds for lane 63 and the right edge)
         R se, ce;
         rotor<R, M>(edgeL ? C.eL : C.eR, se, ce);
-        R sL = from_lane_below(C.s[3]), cL = from_lane_below(C.c[3]);
-        R sR = from_lane_above(C.s[0]), cR = from_lane_above(C.c[0]);
-        sL = edgeL ? se : sL;
-        cL = edgeL ? ce : cL;
-        sR = edgeR ? se : sR;
-        cR = edgeR ? ce : cR;
-        if (nact == 1) rotor<R, M>(C.eR, sR, cR);
+        const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
+        R sR, cR;
+        if (nact == kWave) {
+            sR = from_lane_above(C.s[0], se);
+            cR = from_lane_above(C.c[0], ce);
+        } else {
+            sR = from_lane_above(C.s[0]);
+            cR = from_lane_above(C.c[0]);
+            sR = edgeR ? se : sR;
+            cR = edgeR ? ce : cR;
+            if (nact == 1) rotor<R, M>(C.eR, sR, cR);
+        }
 
         R n[4];
-        noise4<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hs, n);
 
         R tho4[4], uo4[4], w[4];
 #pragma unroll
@@ -368,7 +375,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
                 forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
-                noise4<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, n);
+                noise4_kick<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, hs, n);
                 const int i0 = 4 * g;
                 const int y = i0 / Lx, x = i0 - y * Lx;
                 double rps, rpc;
@@ -439,7 +446,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
                 forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
-                noise4<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, n);
+                noise4_kick<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, hs, n);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w;
