@@ -278,17 +278,41 @@ def bench_domains(torch, xyl):
 
 
 def cpu_baseline(L, nsteps):
+    """The FP64 oracle on the host: the headline's lattice for a bounded number
+    of steps on all the threads OpenMP uses, plus (informational) one thread on
+    a smaller sample and the 64^2 FP64 acceptance run in full."""
     import oracle
     from paper_2409_06412_amd import workloads
+    cores = oracle.max_threads()
     spec = workloads.large_fp32(0, L)
     o = oracle.Oracle(**spec.oracle_kwargs())
     th, om = o.init_random()
     t0 = time.perf_counter()
     o.run(th, om, 0, nsteps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": L * L * nsteps / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 oracle, %dx%d lattice, %d BBK steps (%.1f s)" % (L, L, nsteps, dt)}
+    out = {"value": L * L * nsteps / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+           "sample": "FP64 oracle, %dx%d lattice, %d BBK steps (%.1f s)" % (L, L, nsteps, dt)}
+    # one thread, 1024^2 x 20 steps
+    oracle.set_threads(1)
+    try:
+        o1 = oracle.Oracle(**workloads.large_fp32(0, 1024).oracle_kwargs())
+        th1, om1 = o1.init_random()
+        t0 = time.perf_counter()
+        o1.run(th1, om1, 0, 20)
+        out["single_thread"] = {"value": 1024 * 1024 * 20 / (time.perf_counter() - t0),
+                                "sample": "1024x1024, 20 steps"}
+    finally:
+        oracle.set_threads(cores)
+    # the small FP64 configuration in full: 64^2, 10,000 steps, observables every 100
+    s0 = workloads.small_fp64()
+    o0 = oracle.Oracle(**s0.oracle_kwargs())
+    th0, om0 = o0.init_random()
+    t0 = time.perf_counter()
+    o0.run(th0, om0, 0, s0.nsteps, every=100)
+    t = time.perf_counter() - t0
+    out["small_fp64_full"] = {"seconds": t, "value": 64 * 64 * s0.nsteps / t,
+                              "sample": "64x64, 10,000 steps, observables every 100"}
+    return out
 
 
 # ----------------------------------------------------------- profile summaries

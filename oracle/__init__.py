@@ -91,6 +91,20 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's loops use (its OpenMP runtime's
+    omp_set_num_threads)."""
+    lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(int(n))
+
+
+def max_threads() -> int:
+    lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    return int(gomp.omp_get_max_threads())
+
+
 def _pd(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

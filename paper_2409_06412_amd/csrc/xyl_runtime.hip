@@ -925,14 +925,12 @@ int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C) {
 template <typename R>
 static void structure_factor_into(const void* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax,
                                   DevBuf<double>& scratch, hipStream_t s, double* S) {
-    const int L = axis == 0 ? Lx : Ly;
     const int nlines = axis == 0 ? Ly : Lx;
     const size_t N = (size_t)Lx * Ly;
     scratch.reserve(2 * N + (size_t)nlines * (kmax + 1) + (size_t)(kmax + 1));
     double* z = scratch.p;
     double* part = scratch.p + 2 * N;
     double* outd = part + (size_t)nlines * (kmax + 1);
-    (void)L;
     launch_structure_factor<R>(static_cast<const R*>(th), Lx, Ly, sx, sy, model, axis, kmax, z, part, outd, s);
     check_hip(hipMemcpyAsync(S, outd, sizeof(double) * (kmax + 1), hipMemcpyDeviceToHost, s), "D2H");
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
