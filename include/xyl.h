@@ -226,6 +226,13 @@ int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
 /* Raw Philox4x32-10 blocks computed on the device: for j < n, counter
  * ctr[4j..4j+3] and key (seed_lo, seed_hi) -> out[4j..4j+3]. */
 int xyl_philox_blocks(int32_t device, uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n);
+/* Measured streaming ceiling of the step's memory traffic shape on `device`:
+ * best bandwidth (GB/s, 16 bytes per element) of a plain kernel that reads two
+ * float arrays of n elements and writes two, ping-ponging between two pairs
+ * like a lattice's state, over a few grid sizes and `reps` (>= 2) launches
+ * each.  Allocates 16 n bytes while it runs.  A reference for the step
+ * kernel's bandwidth besides the 8 TB/s peak. */
+int xyl_stream_ceiling(int32_t device, uint64_t n, int32_t reps, double* gbs);
 /* The Gaussian draws n_i^k of every site at step k as the step kernel of this
  * lattice computes them (in its precision), converted to float64. */
 int xyl_noise(xyl_lattice* h, uint64_t k, double* out);

@@ -76,6 +76,7 @@ _SIGS = {
     "xyl_set_stream": (_i32, [_vp, _vp]),
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
+    "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
     "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
     "xyl_structure_factor": (_i32, [_vp, _i32, _i32, P(_d)]),
@@ -507,6 +508,13 @@ class Ensemble:
 
     def sync(self):
         _check(load().xyl_ensemble_sync(self._h))
+
+
+def stream_ceiling(n: int, reps: int = 100, device: int = 0) -> float:
+    """GB/s of a plain read-two/write-two float stream over n elements per array."""
+    g = _d()
+    _check(load().xyl_stream_ceiling(int(device), int(n), int(reps), ctypes.byref(g)))
+    return g.value
 
 
 def philox_blocks(counters: np.ndarray, seed: int, device: int = 0) -> np.ndarray:

@@ -97,6 +97,7 @@ void launch_finalize_many(const double* part, int nrowparts, uint64_t stride, do
                           hipStream_t s);
 void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
 void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
+void launch_stream_probe(const void* a, const void* b, void* c, void* d, size_t n4, int grid, hipStream_t s);
 void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
 template <typename R>
 void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,

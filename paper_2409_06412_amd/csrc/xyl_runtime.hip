@@ -1209,6 +1209,43 @@ int xyl_philox_blocks(int32_t device, uint64_t seed, const uint32_t* ctr, uint32
     });
 }
 
+int xyl_stream_ceiling(int32_t device, uint64_t n, int32_t reps, double* gbs) {
+    return guarded([&] {
+        require(gbs != nullptr, XYL_EINVAL, "gbs is NULL");
+        require(n >= 4 && n % 4 == 0, XYL_EINVAL, "n must be a positive multiple of 4");
+        require(reps >= 2, XYL_EINVAL, "reps must be >= 2");
+        select_device(device);
+        DevBuf<float> buf;
+        buf.reserve(4 * n);
+        check_hip(hipMemset(buf.p, 0, sizeof(float) * 4 * n), "hipMemset");
+        float* A = buf.p;
+        float* B = buf.p + n;
+        float* C = buf.p + 2 * n;
+        float* D = buf.p + 3 * n;
+        hipEvent_t e0, e1;
+        check_hip(hipEventCreate(&e0), "hipEventCreate");
+        check_hip(hipEventCreate(&e1), "hipEventCreate");
+        double best = 0.0;
+        for (int grid : {1024, 2048, 4096, 8192, 16384, 65536}) {
+            for (int w = 0; w < 4; ++w) launch_stream_probe(A, B, C, D, n / 4, grid, nullptr);
+            check_hip(hipEventRecord(e0, nullptr), "hipEventRecord");
+            for (int r = 0; r < reps; ++r) {
+                // ping-pong between the two pairs, like a lattice's state
+                if (r & 1) launch_stream_probe(C, D, A, B, n / 4, grid, nullptr);
+                else launch_stream_probe(A, B, C, D, n / 4, grid, nullptr);
+            }
+            check_hip(hipEventRecord(e1, nullptr), "hipEventRecord");
+            check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            best = std::max(best, 16.0 * (double)n * reps / ((double)ms * 1e-3) / 1e9);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *gbs = best;
+    });
+}
+
 int xyl_noise(xyl_lattice* h, uint64_t k, double* out) {
     return guarded([&] {
         require(h != nullptr && out != nullptr, XYL_EINVAL, "NULL argument");

@@ -540,6 +540,25 @@ void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s) {
     check_hip(hipGetLastError(), "noise kernel launch");
 }
 
+// Streaming ceiling for the step's traffic shape: per element read two float
+// arrays and write two (16 B), float4 accesses, grid-stride.
+__global__ __launch_bounds__(256) void k_stream_probe(const float4* __restrict__ a, const float4* __restrict__ b,
+                                                      float4* __restrict__ c, float4* __restrict__ d, size_t n4) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+        float4 x = a[i], y = b[i];
+        x.x += 1.f;
+        y.x += 1.f;
+        c[i] = x;
+        d[i] = y;
+    }
+}
+
+void launch_stream_probe(const void* a, const void* b, void* c, void* d, size_t n4, int grid, hipStream_t s) {
+    k_stream_probe<<<grid, 256, 0, s>>>(static_cast<const float4*>(a), static_cast<const float4*>(b),
+                                        static_cast<float4*>(c), static_cast<float4*>(d), n4);
+    check_hip(hipGetLastError(), "stream probe launch");
+}
+
 __global__ void k_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
