@@ -221,6 +221,16 @@ int xyl_get_launch(xyl_lattice* h, int32_t* rows_per_strip, int32_t* waves_per_b
 int xyl_autotune(xyl_lattice* h);
 /* Steps per captured HIP graph used by xyl_step (0 or 1 disables graphs). */
 int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
+/* Steps per pass over the state for plain FP32 stepping (1 or 2; default 2).
+ * With 2, runs of 4m steps without measurements advance two steps per pass
+ * (one workgroup per strip of rows across the whole width, the second step
+ * one row behind the first) where Lx is a multiple of 256 up to 4096 and
+ * Ly >= 4; other shapes, FP64 and measurement steps use single steps.
+ * Results are bitwise identical either way; two steps per pass read and write
+ * the state once per two steps.  The library allocates a second velocity
+ * buffer (4 Lx Ly bytes) on first use; the state returns to the lattice's own
+ * buffers at the end of every call. */
+int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass);
 
 /* -------------------------------------------------------------- test hooks */
 /* Raw Philox4x32-10 blocks computed on the device: for j < n, counter

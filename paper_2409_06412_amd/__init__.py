@@ -76,6 +76,7 @@ _SIGS = {
     "xyl_set_stream": (_i32, [_vp, _vp]),
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
+    "xyl_set_fusion": (_i32, [_vp, _i32]),
     "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
     "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
@@ -244,6 +245,11 @@ class Lattice:
 
     def set_stream(self, stream):
         _check(load().xyl_set_stream(self._h, _vp(int(stream) if stream is not None else 0)))
+
+    def set_fusion(self, steps_per_pass: int):
+        """1: one step per pass over the state; 2: two (FP32, width a multiple of
+        256 up to 4096); results are identical."""
+        _check(load().xyl_set_fusion(self._h, int(steps_per_pass)))
 
     def set_launch(self, rows_per_strip=0, waves_per_block=0):
         _check(load().xyl_set_launch(self._h, int(rows_per_strip), int(waves_per_block)))

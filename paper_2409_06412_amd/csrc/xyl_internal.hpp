@@ -87,6 +87,11 @@ void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kde
 template <typename R>
 void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int model, int rows, int wpb,
                           const uint64_t* kdev, uint64_t j, hipStream_t s);
+// Two steps per pass (FP32; Lx a multiple of 256 up to 4096, Ly >= 4): angles
+// and velocities at step k are read from th_in / u_in and those at k+2
+// written to th_out / u_out (distinct buffers); k = v.k_base + j (+ *kdev).
+void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
+                  const uint64_t* kdev, uint64_t j, hipStream_t s);
 template <typename R>
 void launch_init_random(const Lat<R>& v, hipStream_t s);
 template <typename R>

@@ -245,6 +245,8 @@ struct xyl_lattice {
     std::vector<GraphEntry> graphs;
     uint64_t version = 0;
     bool counter_valid = false;
+    int fusion = 2;                // steps per pass of plain FP32 stepping where the shape allows (1 or 2)
+    DevBuf<char> u2;               // second velocity buffer of the two-step passes
     // device scratch
     DevBuf<uint64_t> kdev;
     DevBuf<double> part;
@@ -363,11 +365,107 @@ static hipGraphExec_t capture_steps(xyl_lattice* h, const Lat<R>& v, int mode, i
     return ex;
 }
 
+// Two steps per pass (FP32 plain stepping, width a multiple of 256 up to 4096).
+static bool step2_eligible(const xyl_lattice* h) {
+    return h->dtype == XYL_F32 && h->fusion == 2 && h->Lx % kWaveSites == 0 && h->Lx <= 16 * kWaveSites &&
+           h->Ly >= 4;
+}
+
+// Rows per strip of the two-step kernel: one strip per CU where possible.
+static int step2_rows(const xyl_lattice* h) {
+    return std::max(2, std::min(16, h->Ly / 256));
+}
+
+// Launches for 4m steps from the current step: pairs of two-step passes,
+// (A, u) -> (B, u2) -> (A, u), A the buffer holding the angles at step k, so
+// that the state ends where it started.  With kdev the step index comes from
+// the device counter (graph capture), else from j.
+static void step2_launches(xyl_lattice* h, const Lat<float>& v, uint64_t nsteps, const uint64_t* kdev, uint64_t j,
+                           int parity, hipStream_t s) {
+    float* A = static_cast<float*>(h->th[parity]);
+    float* Bb = static_cast<float*>(h->th[parity ^ 1]);
+    float* u = static_cast<float*>(h->u);
+    float* u2 = reinterpret_cast<float*>(h->u2.p);
+    const int rows = step2_rows(h);
+    for (uint64_t i = 0; i < nsteps; i += 4) {
+        launch_step2(v, A, u, Bb, u2, rows, kdev, j + i, s);
+        launch_step2(v, Bb, u2, A, u, rows, kdev, j + i + 2, s);
+    }
+}
+
+// Captures S (a multiple of 4) steps as two-step passes, then the counter bump.
+static hipGraphExec_t capture_steps2(xyl_lattice* h, const Lat<float>& v, int S, int parity) {
+    hipGraph_t g = nullptr;
+    check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        step2_launches(h, v, (uint64_t)S, h->kdev.p, 0, parity, h->cap_stream);
+        launch_bump(h->kdev.p, (uint64_t)S, h->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(e, "hipGraphInstantiate");
+    return ex;
+}
+
 // Advances n steps in the given mode.  With part_stride > 0 every step writes
 // its measurement partials to part + (k - part_k0) * part_stride.
 template <typename R>
 static void lattice_steps_mode(xyl_lattice* h, uint64_t n, int mode, double* part, uint64_t part_k0,
                                uint64_t part_stride) {
+    if constexpr (sizeof(R) == 4) {
+        if (mode == kStore && part_stride == 0 && step2_eligible(h) && n >= 4) {
+            h->u2.reserve(sizeof(float) * h->N);
+            Lat<float> v2 = h->view<float>();
+            v2.k_base = 0;
+            const uint64_t n4 = n - n % 4;
+            uint64_t done = 0;
+            const int S = h->graph_steps - h->graph_steps % 4;
+            while (done < n4) {
+                const int parity = (int)((h->k + (uint64_t)h->cur) & 1);
+                if (S >= 4 && n4 - done >= (uint64_t)S) {
+                    const int key = kStore | (2 << 8) | (parity << 10);
+                    xyl_lattice::GraphEntry* ge = nullptr;
+                    for (auto& g : h->graphs)
+                        if (g.mode == key && g.S == S) ge = &g;
+                    if (ge && ge->version != h->version) {
+                        (void)hipGraphExecDestroy(ge->exec);
+                        ge->exec = nullptr;
+                    }
+                    if (!ge) {
+                        if (h->graphs.size() >= 8) destroy_graph(h);
+                        h->graphs.push_back(xyl_lattice::GraphEntry());
+                        ge = &h->graphs.back();
+                        ge->mode = key;
+                        ge->S = S;
+                    }
+                    if (!ge->exec) {
+                        ge->exec = capture_steps2(h, v2, S, parity);
+                        ge->version = h->version;
+                    }
+                    if (!h->counter_valid) {
+                        launch_set_counter(h->kdev.p, h->k, h->stream);
+                        h->counter_valid = true;
+                    }
+                    check_hip(hipGraphLaunch(ge->exec, h->stream), "hipGraphLaunch");
+                    h->k += (uint64_t)S;
+                    done += (uint64_t)S;
+                } else {
+                    const uint64_t m = std::min<uint64_t>(n4 - done, 4);
+                    step2_launches(h, v2, m, nullptr, h->k, parity, h->stream);
+                    h->k += m;
+                    done += m;
+                    h->counter_valid = false;
+                }
+            }
+            n -= n4;
+        }
+    }
     Lat<R> v = h->view<R>();
     if (part_stride) {
         v.part = part;
@@ -1183,6 +1281,14 @@ int xyl_autotune(xyl_lattice* h) {
         h->touch();
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[{h->Lx, h->Ly, h->dtype}] = l;
+    });
+}
+
+int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(steps_per_pass == 1 || steps_per_pass == 2, XYL_EINVAL, "steps_per_pass must be 1 or 2");
+        h->fusion = steps_per_pass;
     });
 }
 

@@ -277,6 +277,179 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
     else dispatch_ensemble_step<R, kModelXY>(reps, tasks, ntasks, mode, rows, wpb, kdev, j, s);
 }
 
+// ------------------------------------------------ two steps per pass (FP32)
+// Temporal blocking: one workgroup owns a strip of rows across the whole
+// lattice width (Lx / 256 waves, Lx <= 4096) and advances it two steps per
+// pass.  Stage A (step k) runs one row ahead of stage B (step k+1): after
+// stage A has produced row y, stage B advances row y-1 from stage-A rows
+// y-2..y held in registers.  Stage A also covers one halo row on each side of
+// the strip (recomputed by the neighbouring strip as well; the arithmetic is
+// the same, so the values are too).  Stage B's x-neighbours across wave
+// boundaries come through LDS (each wave publishes the rotors of its first and
+// last site of every stage-A row; one barrier per row; three slots, so that a
+// wave that runs ahead never overwrites a slot another wave still reads).
+// Outputs go to the other angle buffer and a second velocity buffer, so no
+// strip overwrites rows its neighbours still read.  Per-site arithmetic is the
+// shared rotor / site_force / site_update / noise4_kick, so the states equal
+// those of two single steps bit for bit.  Bytes per two site-updates: read
+// angle and velocity (plus the halo rows), write both.
+struct Step2Buffers {
+    const float* th_in;
+    const float* u_in;
+    float* th_out;
+    float* u_out;
+};
+
+template <typename R>
+struct ARow {          // step-k row: angles, outer x-neighbours, rotors, velocities
+    R th[4];
+    R eL, eR;
+    R s[4], c[4];
+    R u[4];
+};
+template <typename R>
+struct BRow {          // step-(k+1) row from stage A
+    R t[4], u[4];
+    R s[4], c[4];
+};
+
+template <int M>
+__global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, const uint64_t* kdev, uint64_t j0,
+                                                int rows) {
+    using R = float;
+    __shared__ R edge[3][16][4];   // [slot][wave][s_first, c_first, s_last, c_last]
+    const int Lx = v.Lx, Ly = v.Ly;
+    const int nw = Lx >> 8;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int y0 = strip * rows;
+    const int y1 = min(y0 + rows, Ly);
+    const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
+    const int x = (wv << 8) + kLaneSites * lane;
+    const int xm = x == 0 ? Lx - 1 : x - 1;
+    const int xp = x + 4 == Lx ? 0 : x + 4;
+    const bool edgeL = lane == 0, edgeR = lane == kWave - 1;
+    const int wl = wv == 0 ? nw - 1 : wv - 1, wr = wv + 1 == nw ? 0 : wv + 1;
+    const R hsA = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
+    const R hsB = (R)half_sigma(v.sched, v.gamma, v.dtd, k + 1);
+    const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
+    const uint32_t qrow = (uint32_t)(Lx >> 2);
+    auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
+
+    auto load_row = [&](ARow<R>& S, int y) {
+        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
+        load4(B.th_in + row + x, S.th);
+        load4(B.u_in + row + x, S.u);
+        if (edgeL) S.eL = B.th_in[row + xm];
+        if (edgeR) S.eR = B.th_in[row + xp];
+    };
+    auto trig = [&](ARow<R>& S) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rotor<R, M>(S.th[q], S.s[q], S.c[q]);
+    };
+    // stage A on row y (wrapped): P, C, N = rows y-1, y, y+1 at step k
+    auto stage_a = [&](const ARow<R>& P, const ARow<R>& C, const ARow<R>& N, int y, BRow<R>& out) {
+        R se, ce;
+        rotor<R, M>(edgeL ? C.eL : C.eR, se, ce);
+        const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
+        const R sR = from_lane_above(C.s[0], se), cR = from_lane_above(C.c[0], ce);
+        R n[4];
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
+            const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
+            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q]);
+            R w;
+            site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
+            rotor<R, M>(out.t[q], out.s[q], out.c[q]);
+        }
+    };
+    // stage B on row y (wrapped): P, C, N = rows y-1, y, y+1 at step k+1;
+    // the neighbours across the wave's edges come from LDS slot `sl`
+    auto stage_b = [&](const BRow<R>& P, const BRow<R>& C, const BRow<R>& N, int y, int sl) {
+        const R seL = edge[sl][wl][2], ceL = edge[sl][wl][3];
+        const R seR = edge[sl][wr][0], ceR = edge[sl][wr][1];
+        const R sL = from_lane_below(C.s[3], seL), cL = from_lane_below(C.c[3], ceL);
+        const R sR = from_lane_above(C.s[0], seR), cR = from_lane_above(C.c[0], ceR);
+        R n[4];
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n);
+        R tho[4], uo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
+            const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
+            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.t[q]);
+            R w;
+            site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
+        }
+        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
+        store4(B.th_out + row + x, tho);
+        store4(B.u_out + row + x, uo);
+    };
+
+    // iteration it (0 .. rows+1) runs stage A on row ya = y0 - 1 + it and, from
+    // it = 2 on, stage B on row ya - 1; A slots hold rows ya-1, ya, ya+1 (the
+    // row ya+2 is loaded into the first one as soon as stage A has used it)
+    ARow<R> A0, A1, A2;
+    BRow<R> B0, B1, B2;
+    load_row(A0, wrap_y(y0 - 2));
+    load_row(A1, wrap_y(y0 - 1));
+    load_row(A2, wrap_y(y0));
+    trig(A0);
+    trig(A1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B0.t[q] = B0.u[q] = B0.s[q] = B0.c[q] = B1.t[q] = B1.u[q] = B1.s[q] = B1.c[q] = R(0);
+    const int nit = (y1 - y0) + 2;
+    // one iteration with the window (P, C, N) and the stage-A output ring
+    // (Bo = row ya-2, Bp = row ya-1, Bn = row ya, written here)
+    auto iterate = [&](ARow<R>& P, ARow<R>& C, ARow<R>& N, BRow<R>& Bo, BRow<R>& Bp, BRow<R>& Bn, int it) {
+        const int ya = y0 - 1 + it;
+        trig(N);
+        stage_a(P, C, N, wrap_y(ya), Bn);
+        if (it + 1 < nit) load_row(P, wrap_y(ya + 2));   // P (row ya-1) is free now
+        const int sl = it % 3;
+        if (edgeL) {
+            edge[sl][wv][0] = Bn.s[0];
+            edge[sl][wv][1] = Bn.c[0];
+        }
+        if (edgeR) {
+            edge[sl][wv][2] = Bn.s[3];
+            edge[sl][wv][3] = Bn.c[3];
+        }
+        __syncthreads();
+        if (it >= 2) stage_b(Bo, Bp, Bn, wrap_y(ya - 1), (it + 2) % 3);
+    };
+    int it = 0;
+    for (; it + 3 <= nit; it += 3) {
+        iterate(A0, A1, A2, B0, B1, B2, it);
+        iterate(A1, A2, A0, B1, B2, B0, it + 1);
+        iterate(A2, A0, A1, B2, B0, B1, it + 2);
+    }
+    if (it < nit) {
+        iterate(A0, A1, A2, B0, B1, B2, it);
+        if (it + 1 < nit) iterate(A1, A2, A0, B1, B2, B0, it + 1);
+    }
+}
+
+template <int M>
+static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows, const uint64_t* kdev, uint64_t j,
+                           hipStream_t s) {
+    const int nstrips = (v.Ly + rows - 1) / rows;
+    k_step2<M><<<nstrips, (v.Lx >> 8) * kWave, 0, s>>>(v, b, kdev, j, rows);
+    check_hip(hipGetLastError(), "two-step kernel launch");
+}
+
+void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
+                  const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    if (v.Lx % kWaveSites != 0 || v.Lx > 16 * kWaveSites || v.Ly < 4 || rows < 1)
+        throw Error(-5, "two-step kernel needs Lx a multiple of 256 up to 4096 and Ly >= 4");
+    const Step2Buffers b{th_in, u_in, th_out, u_out};
+    if (v.model == kModelSI) dispatch_step2<kModelSI>(v, b, rows, kdev, j, s);
+    else dispatch_step2<kModelXY>(v, b, rows, kdev, j, s);
+}
+
 // -------------------------------------------- whole replica in LDS (FP32)
 // Small replicas of an ensemble: one workgroup holds the sine/cosine tables
 // of a whole lattice in LDS (8 B per site, 128 KB at 128 x 128) and its

@@ -1,0 +1,92 @@
+"""Two steps per pass (temporal blocking) against single steps, through the
+C-ABI: the states must be bitwise identical, for both models, widths from one
+to sixteen waves, ragged strips, step counts that are not multiples of four,
+a fresh start inside the fused run, graphs and direct launches; and the fused
+trajectory against the FP64 oracle to the FP32 bar."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_06412_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None):
+    lat = xyl.Lattice(spec.Lx, spec.Ly, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
+                      **spec.params())
+    lat.set_fusion(fusion)
+    lat.set_graph_steps(graph_steps)
+    if state is None:
+        lat.init_random()
+    else:
+        lat.set_state(*state)
+    for n in nsteps_list:
+        lat.step(n)
+    out = lat.get_state()
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("Lx,Ly,model,graphs,steps", [
+    (256, 37, "xy", 32, [41]),             # one wave per row, ragged strips, remainder steps
+    (512, 64, "xy", 0, [8, 3, 12]),        # direct launches, mixed counts
+    (1024, 20, "si", 32, [64, 7]),         # Si model
+    (4096, 48, "xy", 32, [100]),           # sixteen waves per row (full workgroup)
+    (768, 9, "xy", 8, [40]),               # three waves, 9 rows (strips of 2 rows)
+])
+def test_two_steps_per_pass_equal_single_steps(xyl, Lx, Ly, model, graphs, steps):
+    say("fusion", Lx, Ly, model, graphs, steps)
+    if model == "si":
+        spec = workloads.si_lattice(Lx, Ly, seed=3, replica=2)
+    else:
+        spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.9), (60, 0.2)), seed=3, replica=2)
+    a = run(xyl, spec, 1, steps, graphs)
+    b = run(xyl, spec, 2, steps, graphs)
+    assert a[2] == b[2] == sum(steps)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_fused_run_from_a_fresh_state_matches_oracle(xyl):
+    """set_state makes the first step fresh; the fused path takes it inside a
+    pass.  Against the FP64 oracle from the same FP32-representable start."""
+    Lx, Ly = 512, 40
+    spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.5),), seed=6, replica=1)
+    th, om = workloads.random_state(Lx, Ly, seed=8, omega_scale=0.5)
+    th = th.astype(np.float32).astype(np.float64)
+    om = om.astype(np.float32).astype(np.float64)
+    a = run(xyl, spec, 2, [100], 32, state=(th, om))
+    b = run(xyl, spec, 1, [100], 32, state=(th, om))
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    tr, wr = o.run(th, om, 0, 100)
+    d = np.abs(np.remainder(a[0] - tr + np.pi, 2 * np.pi) - np.pi).max()
+    say("fused vs oracle max|dtheta|", d)
+    assert d <= 1e-4
+
+
+def test_fusion_keeps_measurement_and_state_buffers(xyl):
+    """Sampled runs (measurement steps are single steps) and the lattice's own
+    buffers: after fused stepping the velocity lives in the lattice's buffer."""
+    spec = workloads.LatticeSpec(1024, 64, schedule=((0, 0.6),), seed=2)
+    res = []
+    for fusion in (1, 2):
+        lat = xyl.Lattice(1024, 64, dtype="f32", schedule=spec.schedule, seed=2, **spec.params())
+        lat.set_fusion(fusion)
+        lat.init_random()
+        s = lat.step_measured(250, 50)
+        th_buf, u_buf, fresh = lat.state_buffers()
+        assert u_buf == lat._bufs[2].data_ptr()          # the lattice's own velocity buffer
+        res.append((s, lat.get_state()))
+        lat.close()
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1][0], res[1][1][0])
+    np.testing.assert_array_equal(res[0][1][1], res[1][1][1])
