@@ -246,6 +246,7 @@ struct xyl_lattice {
     uint64_t version = 0;
     bool counter_valid = false;
     int fusion = 2;                // steps per pass of plain FP32 stepping where the shape allows (1 or 2)
+    int cus = 256;                 // compute units of the device
     DevBuf<char> u2;               // second velocity buffer of the two-step passes
     // device scratch
     DevBuf<uint64_t> kdev;
@@ -371,9 +372,19 @@ static bool step2_eligible(const xyl_lattice* h) {
            h->Ly >= 4;
 }
 
-// Rows per strip of the two-step kernel: one strip per CU where possible.
+// Rows per strip of the two-step kernel.  A workgroup spans the row (Lx / 256
+// waves of up to 128 VGPRs, 32 Lx bytes of LDS), so a CU holds
+// per_cu = min(16 / waves, 160 KiB / LDS) of them.  The strip count aims at
+// CUs x max(1, per_cu / 2): every CU busy, two or more workgroups per CU where
+// they fit, and strips as tall as that allows (each strip recomputes two halo
+// rows of the first step), 2 to 16 rows.  Measured best over 512^2 .. 4096^2,
+// 4096 x 1024, 1024 x 4096 and 256 x 8192 (strip counts off a multiple of the
+// CU count leave a partial last round of workgroups).
 static int step2_rows(const xyl_lattice* h) {
-    return std::max(2, std::min(16, h->Ly / 256));
+    const int waves = h->Lx / kWaveSites;
+    const int per_cu = std::max(1, std::min(16 / waves, (160 * 1024) / (32 * h->Lx)));
+    const int strips = h->cus * std::max(1, per_cu / 2);
+    return std::max(2, std::min(16, h->Ly / strips));
 }
 
 // Launches for 4m steps from the current step: pairs of two-step passes,
@@ -655,6 +666,7 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
         std::unique_ptr<xyl_lattice> h(new xyl_lattice());
         h->dtype = dtype;
         h->device = device;
+        check_hip(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
         h->Lx = Lx;
         h->Ly = Ly;
         h->N = (size_t)Lx * Ly;

@@ -16,6 +16,7 @@
 // come from the adjacent lanes through DPP; the two wave-edge lanes load their
 // outer neighbour.  Bytes per site-update: read th and u, write th' and u'.
 #include "xyl_device.hpp"
+#include <type_traits>
 
 namespace xyl {
 
@@ -281,18 +282,23 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
 // Temporal blocking: one workgroup owns a strip of rows across the whole
 // lattice width (Lx / 256 waves, Lx <= 4096) and advances it two steps per
 // pass.  Stage A (step k) runs one row ahead of stage B (step k+1): after
-// stage A has produced row y, stage B advances row y-1 from stage-A rows
-// y-2..y held in registers.  Stage A also covers one halo row on each side of
-// the strip (recomputed by the neighbouring strip as well; the arithmetic is
-// the same, so the values are too).  Stage B's x-neighbours across wave
-// boundaries come through LDS (each wave publishes the rotors of its first and
-// last site of every stage-A row; one barrier per row; three slots, so that a
-// wave that runs ahead never overwrites a slot another wave still reads).
-// Outputs go to the other angle buffer and a second velocity buffer, so no
-// strip overwrites rows its neighbours still read.  Per-site arithmetic is the
-// shared rotor / site_force / site_update / noise4_kick, so the states equal
-// those of two single steps bit for bit.  Bytes per two site-updates: read
-// angle and velocity (plus the halo rows), write both.
+// stage A has produced row y, stage B advances row y-1.  Stage A also covers
+// one halo row on each side of the strip (recomputed by the neighbouring strip
+// as well; same arithmetic, same values).  Stage A writes the rotors of its
+// rows to an LDS ring of four rows (8 bytes per site per row), from which
+// stage B takes all its neighbours; its angles and velocities stay in
+// registers.  One barrier per row separates the stage-A writes from the
+// stage-B reads; with four slots a wave that runs one row ahead writes a slot
+// nobody still reads.  Register budget (1024 threads, 128 VGPRs, no spills, so
+// no reload wait drains the prefetch): step-k angles and rotors of three rows,
+// velocities and the outer-edge angle of two, stage-A outputs of two.  A row's
+// angles are loaded one iteration before its rotors are needed, its velocities
+// one iteration before its update.  Outputs go to the other angle buffer and a
+// second velocity buffer, so no strip overwrites rows its neighbours still
+// read.  Per-site arithmetic is the shared rotor / site_force / site_update /
+// noise4_kick, so the states equal those of two single steps bit for bit.
+// Bytes per two site-updates: read angle and velocity (plus the halo rows),
+// write both.
 struct Step2Buffers {
     const float* th_in;
     const float* u_in;
@@ -301,25 +307,27 @@ struct Step2Buffers {
 };
 
 template <typename R>
-struct ARow {          // step-k row: angles, outer x-neighbours, rotors, velocities
-    R th[4];
-    R eL, eR;
-    R s[4], c[4];
-    R u[4];
+struct TRow {          // step-k row: angles and rotors
+    R th[4], s[4], c[4];
 };
 template <typename R>
-struct BRow {          // step-(k+1) row from stage A
-    R t[4], u[4];
-    R s[4], c[4];
+struct URow {          // step-k row: velocities and the angle across the lane's outer edge
+    R u[4];
+    R e;
 };
+template <typename R>
+struct BRow {          // step-(k+1) angles and velocities of one stage-A row
+    R t[4], u[4];
+};
+
+constexpr int kStep2Slots = 4;
 
 template <int M>
 __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, const uint64_t* kdev, uint64_t j0,
                                                 int rows) {
     using R = float;
-    __shared__ R edge[3][16][4];   // [slot][wave][s_first, c_first, s_last, c_last]
+    extern __shared__ float rot[];   // [slot][s | c][Lx]
     const int Lx = v.Lx, Ly = v.Ly;
-    const int nw = Lx >> 8;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
@@ -327,60 +335,76 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
     const int y1 = min(y0 + rows, Ly);
     const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
     const int x = (wv << 8) + kLaneSites * lane;
-    const int xm = x == 0 ? Lx - 1 : x - 1;
-    const int xp = x + 4 == Lx ? 0 : x + 4;
     const bool edgeL = lane == 0, edgeR = lane == kWave - 1;
-    const int wl = wv == 0 ? nw - 1 : wv - 1, wr = wv + 1 == nw ? 0 : wv + 1;
+    // lane 0: the site left of the wave; lane 63: the site right of it; the
+    // other lanes read a site of their own wave (unused, conflict-free)
+    const int xe = edgeL ? (x == 0 ? Lx - 1 : x - 1) : (edgeR ? (x + 4 == Lx ? 0 : x + 4) : (wv << 8) + lane);
     const R hsA = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
     const R hsB = (R)half_sigma(v.sched, v.gamma, v.dtd, k + 1);
     const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
     auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
+    auto slot = [&](int it) { return rot + (size_t)(it & (kStep2Slots - 1)) * 2 * Lx; };
 
-    auto load_row = [&](ARow<R>& S, int y) {
+    auto load_th = [&](TRow<R>& T, int y) { load4(B.th_in + (uint32_t)y * (uint32_t)Lx + x, T.th); };
+    auto load_u = [&](URow<R>& U, int y) {
         const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-        load4(B.th_in + row + x, S.th);
-        load4(B.u_in + row + x, S.u);
-        if (edgeL) S.eL = B.th_in[row + xm];
-        if (edgeR) S.eR = B.th_in[row + xp];
+        load4(B.u_in + row + x, U.u);
+        U.e = B.th_in[row + xe];
     };
-    auto trig = [&](ARow<R>& S) {
+    auto trig = [&](TRow<R>& T) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rotor<R, M>(S.th[q], S.s[q], S.c[q]);
+        for (int q = 0; q < 4; ++q) rotor<R, M>(T.th[q], T.s[q], T.c[q]);
     };
-    // stage A on row y (wrapped): P, C, N = rows y-1, y, y+1 at step k
-    auto stage_a = [&](const ARow<R>& P, const ARow<R>& C, const ARow<R>& N, int y, BRow<R>& out) {
+    // stage A on row y of iteration it: P, C, N = rows y-1, y, y+1 at step k;
+    // rotors to LDS, angles and velocities to `out`
+    auto stage_a = [&](const TRow<R>& P, const TRow<R>& C, const TRow<R>& N, const URow<R>& U, int y, int it,
+                       BRow<R>& out) {
         R se, ce;
-        rotor<R, M>(edgeL ? C.eL : C.eR, se, ce);
+        rotor<R, M>(U.e, se, ce);
         const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
         const R sR = from_lane_above(C.s[0], se), cR = from_lane_above(C.c[0], ce);
         R n[4];
         noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
+        R s1[4], c1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
             const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q]);
             R w;
-            site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
-            rotor<R, M>(out.t[q], out.s[q], out.c[q]);
+            site_update<R, M>(v, f, U.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
+            rotor<R, M>(out.t[q], s1[q], c1[q]);
         }
+        float* rs = slot(it);
+        store4(rs + x, s1);
+        store4(rs + Lx + x, c1);
     };
-    // stage B on row y (wrapped): P, C, N = rows y-1, y, y+1 at step k+1;
-    // the neighbours across the wave's edges come from LDS slot `sl`
-    auto stage_b = [&](const BRow<R>& P, const BRow<R>& C, const BRow<R>& N, int y, int sl) {
-        const R seL = edge[sl][wl][2], ceL = edge[sl][wl][3];
-        const R seR = edge[sl][wr][0], ceR = edge[sl][wr][1];
-        const R sL = from_lane_below(C.s[3], seL), cL = from_lane_below(C.c[3], ceL);
-        const R sR = from_lane_above(C.s[0], seR), cR = from_lane_above(C.c[0], ceR);
+    // stage B on row y (stage-A values C in registers; the rotors of rows
+    // y-1, y, y+1 in the LDS slots of iterations it-2, it-1, it)
+    auto stage_b = [&](const BRow<R>& C, int y, int it) {
+        const float* rp = slot(it - 2);
+        const float* rc = slot(it - 1);
+        const float* rn = slot(it);
+        R sc[4], cc[4];
+        load4(rc + x, sc);
+        load4(rc + Lx + x, cc);
+        const R se = rc[xe], ce = rc[Lx + xe];
+        const R sL = from_lane_below(sc[3], se), cL = from_lane_below(cc[3], ce);
+        const R sR = from_lane_above(sc[0], se), cR = from_lane_above(cc[0], ce);
+        R sp[4], cp[4], sn[4], cn[4];
+        load4(rp + x, sp);
+        load4(rp + Lx + x, cp);
+        load4(rn + x, sn);
+        load4(rn + Lx + x, cn);
         R n[4];
         noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n);
         R tho[4], uo[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
-            const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.t[q]);
+            const R sxm = q == 0 ? sL : sc[q - 1], cxm = q == 0 ? cL : cc[q - 1];
+            const R sxp = q == 3 ? sR : sc[q + 1], cxp = q == 3 ? cR : cc[q + 1];
+            const R f = site_force<R, M>(v, sc[q], cc[q], sxm, cxm, sxp, cxp, sp[q], cp[q], sn[q], cn[q], C.t[q]);
             R w;
             site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
@@ -389,55 +413,67 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
         store4(B.u_out + row + x, uo);
     };
 
-    // iteration it (0 .. rows+1) runs stage A on row ya = y0 - 1 + it and, from
-    // it = 2 on, stage B on row ya - 1; A slots hold rows ya-1, ya, ya+1 (the
-    // row ya+2 is loaded into the first one as soon as stage A has used it)
-    ARow<R> A0, A1, A2;
-    BRow<R> B0, B1, B2;
-    load_row(A0, wrap_y(y0 - 2));
-    load_row(A1, wrap_y(y0 - 1));
-    load_row(A2, wrap_y(y0));
-    trig(A0);
-    trig(A1);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) B0.t[q] = B0.u[q] = B0.s[q] = B0.c[q] = B1.t[q] = B1.u[q] = B1.s[q] = B1.c[q] = R(0);
+    // Iteration it (0 .. nit-1) runs stage A on row ya = y0 - 1 + it and, from
+    // it = 2 on, stage B on row ya - 1.  On entry P holds the rotors of row
+    // ya-1, C the angles and rotors of row ya, N the angles of row ya+1, UC the
+    // velocities of row ya; the iteration loads the angles of row ya+2 into P
+    // and the velocities of row ya+1 into UN.
     const int nit = (y1 - y0) + 2;
-    // one iteration with the window (P, C, N) and the stage-A output ring
-    // (Bo = row ya-2, Bp = row ya-1, Bn = row ya, written here)
-    auto iterate = [&](ARow<R>& P, ARow<R>& C, ARow<R>& N, BRow<R>& Bo, BRow<R>& Bp, BRow<R>& Bn, int it) {
+    TRow<R> T0, T1, T2;
+    URow<R> U0, U1;
+    BRow<R> B0, B1;
+    load_th(T0, wrap_y(y0 - 2));
+    load_th(T1, wrap_y(y0 - 1));
+    load_th(T2, wrap_y(y0));
+    load_u(U0, wrap_y(y0 - 1));
+    trig(T0);
+    trig(T1);
+    // Every iteration loads (the last one a row nobody uses, in bounds), and
+    // stage B runs in every iteration of the loop: the first two iterations
+    // are peeled and end with a full wait, so that the compiler's counter
+    // waits inside the loop need not cover a path without stores (which would
+    // make the next row's wait also wait for the stores just issued).
+    auto iterate = [&](auto with_b, TRow<R>& P, TRow<R>& C, TRow<R>& N, URow<R>& UC, URow<R>& UN, BRow<R>& Bn,
+                       BRow<R>& Bp, int it) {
         const int ya = y0 - 1 + it;
         trig(N);
-        stage_a(P, C, N, wrap_y(ya), Bn);
-        if (it + 1 < nit) load_row(P, wrap_y(ya + 2));   // P (row ya-1) is free now
-        const int sl = it % 3;
-        if (edgeL) {
-            edge[sl][wv][0] = Bn.s[0];
-            edge[sl][wv][1] = Bn.c[0];
-        }
-        if (edgeR) {
-            edge[sl][wv][2] = Bn.s[3];
-            edge[sl][wv][3] = Bn.c[3];
-        }
+        load_th(P, wrap_y(ya + 2));
+        load_u(UN, wrap_y(ya + 1));
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of stage A
+        stage_a(P, C, N, UC, wrap_y(ya), it, Bn);
         __syncthreads();
-        if (it >= 2) stage_b(Bo, Bp, Bn, wrap_y(ya - 1), (it + 2) % 3);
+        if constexpr (decltype(with_b)::value) stage_b(Bp, wrap_y(ya - 1), it);
     };
-    int it = 0;
-    for (; it + 3 <= nit; it += 3) {
-        iterate(A0, A1, A2, B0, B1, B2, it);
-        iterate(A1, A2, A0, B1, B2, B0, it + 1);
-        iterate(A2, A0, A1, B2, B0, B1, it + 2);
+    const std::false_type first{};
+    const std::true_type full{};
+    iterate(first, T0, T1, T2, U0, U1, B0, B1, 0);
+    iterate(first, T1, T2, T0, U1, U0, B1, B0, 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    int it = 2;
+    for (; it + 6 <= nit; it += 6) {
+        iterate(full, T2, T0, T1, U0, U1, B0, B1, it);
+        iterate(full, T0, T1, T2, U1, U0, B1, B0, it + 1);
+        iterate(full, T1, T2, T0, U0, U1, B0, B1, it + 2);
+        iterate(full, T2, T0, T1, U1, U0, B1, B0, it + 3);
+        iterate(full, T0, T1, T2, U0, U1, B0, B1, it + 4);
+        iterate(full, T1, T2, T0, U1, U0, B1, B0, it + 5);
     }
-    if (it < nit) {
-        iterate(A0, A1, A2, B0, B1, B2, it);
-        if (it + 1 < nit) iterate(A1, A2, A0, B1, B2, B0, it + 1);
-    }
+    if (it < nit) iterate(full, T2, T0, T1, U0, U1, B0, B1, it);
+    if (it + 1 < nit) iterate(full, T0, T1, T2, U1, U0, B1, B0, it + 1);
+    if (it + 2 < nit) iterate(full, T1, T2, T0, U0, U1, B0, B1, it + 2);
+    if (it + 3 < nit) iterate(full, T2, T0, T1, U1, U0, B1, B0, it + 3);
+    if (it + 4 < nit) iterate(full, T0, T1, T2, U0, U1, B0, B1, it + 4);
 }
 
 template <int M>
 static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows, const uint64_t* kdev, uint64_t j,
                            hipStream_t s) {
     const int nstrips = (v.Ly + rows - 1) / rows;
-    k_step2<M><<<nstrips, (v.Lx >> 8) * kWave, 0, s>>>(v, b, kdev, j, rows);
+    const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)v.Lx;
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_step2<M>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+              "hipFuncSetAttribute");
+    k_step2<M><<<nstrips, (v.Lx >> 8) * kWave, lds, s>>>(v, b, kdev, j, rows);
     check_hip(hipGetLastError(), "two-step kernel launch");
 }
 
