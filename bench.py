@@ -9,9 +9,16 @@ correlation length) fused into every 500th step.  One "step" is one BBK
 step of the whole lattice.  The state is resident in HBM before timing.
 
 Also reported on the same line:
-  * roofline of the dominant kernel (the plain FP32 step): algorithmic bytes
-    (16 B per site: read angle and velocity, write both) / average kernel
-    duration from HIP events around back-to-back launches, against 8 TB/s;
+  * roofline of the dominant kernel, the two-steps-per-pass FP32 kernel
+    (k_step2: one launch advances every site two steps, reading angle and
+    velocity once and writing both once, 16 B per site per launch): its
+    average launch duration from HIP events on the lattice's stream around
+    back-to-back launches; the VALU instructions per launch from rocprofv3
+    counters (bound "alu": against the VALU issue rate of 256 CUs x 4 SIMDs
+    at 2.4 GHz, one wave64 instruction per SIMD every 4 cycles) and the
+    algorithmic HBM rate (16 B per site / duration, against 8 TB/s and the
+    measured streaming ceiling of the same access shape); the single-step
+    kernel measured the same way beside it;
   * HBM traffic per launch from rocprofv3 counters when the committed
     counter summary matches the current kernel source, else null;
   * batched-ensemble vs one-launch-per-replica throughput on the 288-replica
@@ -41,8 +48,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs, each SIMD 16 lanes wide, so one
+# wave64 VALU issue slot (4 cycles) per SIMD at a time, at 2.4 GHz
+# (= 157.3 TFLOP/s FP32 / 2 flops per FMA / 2 for packed FP32 / 64 lanes), in
+# G slots/s.  A full-rate instruction takes one slot, an FP32 transcendental
+# two (measured: SQ_ACTIVE_INST_VALU = SQ_INSTS_VALU + SQ_INSTS_VALU_TRANS_F32).
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 BYTES_PER_SITE_F32 = 16
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2_f32_4096_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "step2_f32_4096_valu.json")
 
 
 def log(*a):
@@ -57,30 +71,58 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(L):
+def load_profile(path, L, key):
+    """A figure from a committed counter summary, if it was taken of the
+    current kernel source at this lattice size, else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_hash") != kernel_source_hash() or t.get("L") != L:
         return None
-    return t.get("bytes_per_launch")
+    return t.get(key)
 
 
-def time_step_kernel(torch, lat, nlaunch):
-    """Average duration of the plain step kernel: HIP events on the lattice's
-    stream around nlaunch back-to-back launches (no graph, no measurement)."""
+def time_steps(torch, lat, nsteps):
+    """Average time per step of plain stepping, no graph, no measurement: HIP
+    events on the lattice's stream (torch's current stream) around nsteps
+    steps (a multiple of 4, so that with two steps per pass every launch is a
+    two-step pass).  In ms."""
+    assert nsteps % 4 == 0
     lat.set_graph_steps(0)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    lat.step(5)
+    lat.step(8)
     e0.record(s)
-    lat.step(nlaunch)
+    lat.step(nsteps)
     e1.record(s)
     e1.synchronize()
     lat.set_graph_steps(32)
-    return e0.elapsed_time(e1) / nlaunch
+    return e0.elapsed_time(e1) / nsteps
+
+
+def step_kernels(torch, lat, L, nsteps):
+    """Launch durations of the two stepping kernels on this lattice: the
+    two-step pass where it applies (16 B per site per launch for two
+    site-updates) and the single step (16 B per site per launch for one)."""
+    sp, rows = lat.fusion()
+    out = {}
+    if rows:
+        ms = time_steps(torch, lat, nsteps)
+        us = 2e3 * ms
+        gbs = BYTES_PER_SITE_F32 * L * L / (us * 1e-6) / 1e9
+        out["two_step"] = {"kernel": "k_step2", "rows_per_strip": rows, "avg_kernel_us": us,
+                           "us_per_step": 1e3 * ms, "site_updates_per_s": L * L / (ms * 1e-3),
+                           "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+    lat.set_fusion(1)
+    ms = time_steps(torch, lat, nsteps)
+    lat.set_fusion(sp)
+    gbs = BYTES_PER_SITE_F32 * L * L / (ms * 1e-3) / 1e9
+    out["single_step"] = {"kernel": "k_step", "launch": list(lat.launch()), "avg_kernel_us": 1e3 * ms,
+                          "site_updates_per_s": L * L / (ms * 1e-3), "algorithmic_GBs": gbs,
+                          "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
@@ -183,14 +225,16 @@ def bench_copy(torch, nbytes=1 << 30, reps=20):
 
 
 def bench_control_8192(torch, xyl, workloads, nlaunch=200):
-    """Same kernel on an 8192^2 lattice (805 MB of state, larger than the
-    256 MB Infinity Cache): the HBM-resident rate."""
+    """The single-step kernel on an 8192^2 lattice (805 MB of state, larger
+    than the 256 MB Infinity Cache; wider than the two-step pass takes): the
+    HBM-resident rate."""
     spec = workloads.large_fp32(0, 8192)
     lat = xyl.Lattice(8192, 8192, dtype="f32", schedule=spec.schedule, seed=spec.seed,
                       stream=torch.cuda.current_stream().cuda_stream, **spec.params())
     lat.init_random()
     launch = lat.autotune()
-    us = 1e3 * time_step_kernel(torch, lat, nlaunch)
+    assert lat.fusion()[1] == 0
+    us = 1e3 * time_steps(torch, lat, nlaunch)
     lat.close()
     gbs = BYTES_PER_SITE_F32 * 8192 * 8192 / (us * 1e-6) / 1e9
     ceiling = xyl.stream_ceiling(8192 * 8192, 30)
@@ -200,10 +244,10 @@ def bench_control_8192(torch, xyl, workloads, nlaunch=200):
 
 
 def bench_si_4096(torch, xyl, workloads, nlaunch=500, launch=None):
-    """Step kernel of the Si(001) model variant (q = 2, p = 2.5, half-circle
-    angles) on 4096^2 at T_c: same bytes per site as the XY model, one more
-    transcendental per site.  launch = (rows, waves) fixes the shape instead of
-    autotuning."""
+    """Stepping kernels of the Si(001) model variant (q = 2, p = 2.5,
+    half-circle angles) on 4096^2 at T_c: same bytes per site as the XY model,
+    one more transcendental per site.  launch = (rows, waves) fixes the shape
+    of the single-step kernel instead of autotuning."""
     spec = workloads.si_lattice(4096, 4096)
     lat = xyl.Lattice(4096, 4096, dtype="f32", schedule=spec.schedule, seed=spec.seed,
                       stream=torch.cuda.current_stream().cuda_stream, **spec.params())
@@ -214,12 +258,9 @@ def bench_si_4096(torch, xyl, workloads, nlaunch=500, launch=None):
     else:
         launch = lat.autotune()
     lat.step(200)
-    us = 1e3 * time_step_kernel(torch, lat, nlaunch)
+    out = step_kernels(torch, lat, 4096, nlaunch)
     lat.close()
-    gbs = BYTES_PER_SITE_F32 * 4096 * 4096 / (us * 1e-6) / 1e9
-    return {"L": 4096, "model": "si", "p": spec.p, "T": spec.schedule[0][1], "launch": list(launch),
-            "avg_kernel_us": us, "site_updates_per_s": 4096 * 4096 / (us * 1e-6),
-            "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+    return {"L": 4096, "model": "si", "p": spec.p, "T": spec.schedule[0][1], **out}
 
 
 def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
@@ -318,7 +359,8 @@ def cpu_baseline(L, nsteps):
 
 
 # ----------------------------------------------------------- profile summaries
-STEP_KERNEL = "xyl::k_step<float, 1, 0>"   # plain store step of the XY model
+STEP_KERNEL = "xyl::k_step<float, 1, 0>"   # single plain store step of the XY model
+STEP2_KERNEL = "xyl::k_step2<0>"           # two steps per pass of the XY model
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -347,9 +389,9 @@ def summarize_trace(d, out_md, command):
     print("\n".join(lines))
 
 
-def _counter_means(d, counter, L):
-    """Mean counter value (KiB) of the step kernel at its most frequent grid and
-    of plain device copies of one lattice array (L*L*4 bytes)."""
+def _counter_means(d, counter, L, kernel):
+    """Mean counter value of the kernel at its most frequent grid and the
+    largest value for plain device copies (the copy of one L*L*4-byte array)."""
     import csv
     from collections import defaultdict
     files = _csvs(d, "counter_collection.csv")
@@ -362,7 +404,7 @@ def _counter_means(d, counter, L):
             continue
         v = float(r["Counter_Value"])
         name = r["Kernel_Name"]
-        if STEP_KERNEL in name:
+        if kernel in name:
             step[(r["Grid_Size"], r["Workgroup_Size"])].append(v)
         elif COPY_KERNEL in name and int(r["Grid_Size"]) > 4096:
             copy.append(v)
@@ -370,35 +412,77 @@ def _counter_means(d, counter, L):
     return sum(step[key]) / len(step[key]), max(copy) if copy else None, key
 
 
-def summarize_traffic(fetch_dir, write_dir, out_json, out_md, L, commands):
-    """HBM traffic of one step launch from FETCH_SIZE and WRITE_SIZE, each scaled
-    by what it reads for a plain copy of one 4*L*L-byte array."""
+def summarize_traffic(fetch_dir, write_dir, out_json, out_md, L, commands, kernel):
+    """HBM traffic of one launch of the kernel from FETCH_SIZE and WRITE_SIZE,
+    each scaled by what it reads for a plain copy of one 4*L*L-byte array."""
     nbytes = 4 * L * L
-    f_step, f_copy, key = _counter_means(fetch_dir, "FETCH_SIZE", L)
-    w_step, w_copy, _ = _counter_means(write_dir, "WRITE_SIZE", L)
+    f_step, f_copy, key = _counter_means(fetch_dir, "FETCH_SIZE", L, kernel)
+    w_step, w_copy, _ = _counter_means(write_dir, "WRITE_SIZE", L, kernel)
     f_scale = nbytes / (f_copy * 1024.0)
     w_scale = nbytes / (w_copy * 1024.0)
     fetch_b = f_step * 1024.0 * f_scale
     write_b = w_step * 1024.0 * w_scale
     alg = BYTES_PER_SITE_F32 * L * L
-    res = {"kernel": STEP_KERNEL, "L": L, "kernel_hash": kernel_source_hash(), "grid_workgroup": list(key),
+    res = {"kernel": kernel, "L": L, "kernel_hash": kernel_source_hash(), "grid_workgroup": list(key),
            "fetch_kib_per_launch": f_step, "write_kib_per_launch": w_step,
            "copy_fetch_kib": f_copy, "copy_write_kib": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
            "fetch_bytes": fetch_b, "write_bytes": write_b, "bytes_per_launch": fetch_b + write_b,
            "algorithmic_bytes": alg, "traffic_over_algorithmic": (fetch_b + write_b) / alg,
            "commands": commands}
     json.dump(res, open(out_json, "w"), indent=1)
-    md = ["# HBM traffic of the FP32 step kernel, %dx%d lattice" % (L, L), "",
+    md = ["# HBM traffic of %s, %dx%d lattice" % (kernel, L, L), "",
           "Commands (from the repository root):", ""] + ["    " + c for c in commands] + [
           "", "| quantity | value |", "|---|---|",
-          "| step FETCH_SIZE per launch (KiB) | %.0f |" % f_step,
-          "| step WRITE_SIZE per launch (KiB) | %.0f |" % w_step,
+          "| kernel FETCH_SIZE per launch (KiB) | %.0f |" % f_step,
+          "| kernel WRITE_SIZE per launch (KiB) | %.0f |" % w_step,
           "| copy of %d B: FETCH_SIZE / WRITE_SIZE (KiB) | %.0f / %.0f |" % (nbytes, f_copy, w_copy),
           "| scale factors fetch / write | %.4f / %.4f |" % (f_scale, w_scale),
           "| scaled fetch + write per launch (MB) | %.1f + %.1f = %.1f |" % (fetch_b / 1e6, write_b / 1e6,
                                                                             (fetch_b + write_b) / 1e6),
           "| algorithmic bytes per launch (MB) | %.1f |" % (alg / 1e6),
           "| traffic / algorithmic | %.3f |" % ((fetch_b + write_b) / alg), ""]
+    open(out_md, "w").write("\n".join(md))
+    print("\n".join(md))
+
+
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F32", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", "VALUBusy")
+
+
+def summarize_valu(d, out_json, out_md, L, command, kernel):
+    """VALU instructions per launch of the kernel (summed over the device) and
+    the VALU busy fraction, from one rocprofv3 --pmc run."""
+    import csv
+    from collections import defaultdict
+    files = _csvs(d, "counter_collection.csv")
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(files[0])):
+        if kernel in r["Kernel_Name"] and r.get("Counter_Name") in VALU_COUNTERS:
+            vals[(r["Grid_Size"], r["Workgroup_Size"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    key = max(vals, key=lambda k: len(vals[k]["SQ_INSTS_VALU"]))
+    mean = {c: sum(v) / len(v) for c, v in vals[key].items()}
+    res = {"kernel": kernel, "L": L, "kernel_hash": kernel_source_hash(), "grid_workgroup": list(key),
+           "dispatches": len(vals[key]["SQ_INSTS_VALU"]),
+           "valu_instructions_per_launch": mean["SQ_INSTS_VALU"],
+           "transcendental_f32_per_launch": mean.get("SQ_INSTS_VALU_TRANS_F32"),
+           "active_inst_valu_quad_cycles": mean.get("SQ_ACTIVE_INST_VALU"),
+           "grbm_gui_active": mean.get("GRBM_GUI_ACTIVE"),
+           "valu_busy_percent": mean.get("VALUBusy"),
+           "valu_instructions_per_site_update": mean["SQ_INSTS_VALU"] * 64 / (L * L * (2 if "step2" in kernel else 1)),
+           "command": command}
+    json.dump(res, open(out_json, "w"), indent=1)
+    md = ["# VALU work of %s, %dx%d lattice" % (kernel, L, L), "",
+          "Command (from the repository root):", "", "    " + command, "",
+          "| quantity | value |", "|---|---|",
+          "| dispatches averaged | %d |" % res["dispatches"],
+          "| SQ_INSTS_VALU per launch (wave instructions) | %.4g |" % res["valu_instructions_per_launch"],
+          "| of which FP32 transcendental (SQ_INSTS_VALU_TRANS_F32) | %.4g |" % (res["transcendental_f32_per_launch"] or 0),
+          "| lane-instructions per site-update (x 64 / site-updates per launch) | %.1f |"
+          % res["valu_instructions_per_site_update"],
+          "| SQ_ACTIVE_INST_VALU per launch (quad-cycles) | %.4g |" % (res["active_inst_valu_quad_cycles"] or 0),
+          "| GRBM_GUI_ACTIVE per launch | %.4g |" % (res["grbm_gui_active"] or 0),
+          "| VALUBusy (%%) | %.1f |" % (res["valu_busy_percent"] or 0), ""]
     open(out_md, "w").write("\n".join(md))
     print("\n".join(md))
 
@@ -413,6 +497,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--kernel-steps", type=int, default=1000,
+                    help="steps (a multiple of 4) over which each stepping kernel is timed alone")
     ap.add_argument("--only", type=str, default="",
                     help="comma list of extras to run alone (copy, ensemble, quench, adjoint, domains, control, "
                          "si, si_fss, structure); "
@@ -423,13 +509,20 @@ def main():
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"))
     ap.add_argument("--summarize-traffic", nargs=6,
                     metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON", "OUT_MD", "FETCH_CMD", "WRITE_CMD"))
+    ap.add_argument("--summarize-valu", nargs=4, metavar=("DIR", "OUT_JSON", "OUT_MD", "COMMAND"))
+    ap.add_argument("--kernel", type=str, default=STEP2_KERNEL,
+                    help="kernel name the counter summaries select (default: the two-step pass)")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:
         a = args.summarize_traffic
-        summarize_traffic(a[0], a[1], a[2], a[3], args.L, [a[4], a[5]])
+        summarize_traffic(a[0], a[1], a[2], a[3], args.L, [a[4], a[5]], args.kernel)
+        return
+    if args.summarize_valu:
+        a = args.summarize_valu
+        summarize_valu(a[0], a[1], a[2], args.L, a[3], args.kernel)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -470,7 +563,9 @@ def main():
         launch = lat.launch()
     else:
         launch = lat.autotune()
-    log("launch shape (rows per strip, waves per workgroup):", launch)
+    fusion = lat.fusion()
+    log("single-step launch shape (rows per strip, waves per workgroup):", launch,
+        "; steps per pass, rows per strip of the two-step pass:", fusion)
     lat.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -482,22 +577,41 @@ def main():
     value = L * L * args.steps / wall
     log("timed %d steps in %.4f s: %.4g site-updates/s (%d samples)" % (args.steps, wall, value, len(samples)))
 
-    kern_ms = time_step_kernel(torch, lat, 500)
-    achieved = BYTES_PER_SITE_F32 * L * L / (kern_ms * 1e-3) / 1e9
-    traffic = load_traffic(L)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_step<float, store>", "avg_kernel_us": kern_ms * 1e3,
-                "algorithmic_bytes_per_launch": BYTES_PER_SITE_F32 * L * L}
-    log("step kernel %.2f us -> %.1f GB/s algorithmic (%.1f%% of 8 TB/s)" % (kern_ms * 1e3, achieved,
-                                                                              100 * achieved / HBM_PEAK_GBS))
+    # the stepping kernels timed alone (HIP events on the lattice's stream)
+    kern = step_kernels(torch, lat, L, args.kernel_steps)
     lat.close()
-    # the practical ceiling of this traffic shape: a plain stream reading two
-    # and writing two arrays of L*L floats, ping-ponging like the state
+    # the practical ceiling of the state's access shape: a plain stream reading
+    # two and writing two arrays of L*L floats, ping-ponging like the state
     ceiling = xyl.stream_ceiling(L * L, 100)
-    roofline["stream_ceiling_GBs"] = ceiling
-    roofline["frac_of_stream_ceiling"] = achieved / ceiling
-    log("stream ceiling %.1f GB/s -> step kernel at %.1f%% of it" % (ceiling, 100 * achieved / ceiling))
+    for k in kern.values():
+        k["frac_of_stream_ceiling"] = k["algorithmic_GBs"] / ceiling
+    two = kern.get("two_step")
+    dom = two or kern["single_step"]
+    us = dom["avg_kernel_us"]
+    hbm = {"algorithmic_bytes_per_launch": BYTES_PER_SITE_F32 * L * L, "achieved_GBs": dom["algorithmic_GBs"],
+           "peak_GBs": HBM_PEAK_GBS, "frac": dom["algorithmic_GBs"] / HBM_PEAK_GBS,
+           "stream_ceiling_GBs": ceiling, "frac_of_stream_ceiling": dom["algorithmic_GBs"] / ceiling}
+    traffic = load_profile(TRAFFIC_FILE, L, "bytes_per_launch") if two else None
+    slots = load_profile(VALU_FILE, L, "active_inst_valu_quad_cycles") if two else None
+    if slots:
+        # VALU issue slots (one wave64 instruction = 4 cycles of a SIMD; the
+        # transcendentals take two) per launch over the launch duration
+        achieved = slots / (us * 1e-6) / 1e9
+        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GINST, "unit": "G VALU issue slots/s",
+                    "frac": achieved / VALU_PEAK_GINST, "traffic": traffic,
+                    "kernel": "k_step2<XY> (two steps per pass)", "avg_kernel_us": us,
+                    "valu_issue_slots_per_launch": slots,
+                    "valu_instructions_per_launch": load_profile(VALU_FILE, L, "valu_instructions_per_launch"),
+                    "hbm": hbm}
+    else:
+        # no counter summary of the current kernel source: the HBM figure alone
+        roofline = {"bound": "hbm", "achieved": dom["algorithmic_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": dom["algorithmic_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                    "kernel": dom["kernel"], "avg_kernel_us": us, "hbm": hbm,
+                    "valu_profile": "absent or taken of another kernel source"}
+    roofline["single_step_kernel"] = kern["single_step"]
+    log("stepping kernels:", json.dumps(kern))
+    log("roofline:", json.dumps(roofline))
 
     extras = {}
     if not args.no_extras:
@@ -532,7 +646,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "single %dx%d periodic lattice, fp32 state, fp64 observables every %d steps"
                                % (L, L, args.every),
-                   "L": L, "T": spec.schedule[0][1], "seed": spec.seed, "launch": list(launch)},
+                   "L": L, "T": spec.schedule[0][1], "seed": spec.seed, "launch": list(launch),
+                   "steps_per_pass": fusion[0], "rows_per_strip": fusion[1]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -541,7 +656,7 @@ def main():
     if "ensemble_fss" in extras:
         line["batched_over_per_replica"] = extras["ensemble_fss"]["speedup"]
     if "copy_1GiB" in extras:
-        roofline["frac_of_torch_copy"] = achieved / extras["copy_1GiB"]["GBs_read_plus_write"]
+        hbm["frac_of_torch_copy"] = hbm["achieved_GBs"] / extras["copy_1GiB"]["GBs_read_plus_write"]
     line["extras"] = extras
     print(json.dumps(line), flush=True)
 

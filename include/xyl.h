@@ -231,6 +231,12 @@ int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
  * buffer (4 Lx Ly bytes) on first use; the state returns to the lattice's own
  * buffers at the end of every call. */
 int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass);
+/* The stepping mode in effect: *steps_per_pass = the value set by
+ * xyl_set_fusion; *rows = rows per strip of the two-step pass for this
+ * lattice on its device (chosen from the CU count and the workgroups a CU
+ * holds), 0 where two steps per pass do not apply (shape, FP64, or
+ * steps_per_pass 1).  Either pointer may be NULL. */
+int xyl_get_fusion(const xyl_lattice* h, int32_t* steps_per_pass, int32_t* rows);
 
 /* -------------------------------------------------------------- test hooks */
 /* Raw Philox4x32-10 blocks computed on the device: for j < n, counter

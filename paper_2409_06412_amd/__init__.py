@@ -77,6 +77,7 @@ _SIGS = {
     "xyl_set_params": (_i32, [_vp, _d, _d, _d, _d, _d]),
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
     "xyl_set_fusion": (_i32, [_vp, _i32]),
+    "xyl_get_fusion": (_i32, [_vp, P(_i32), P(_i32)]),
     "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
     "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
@@ -250,6 +251,13 @@ class Lattice:
         """1: one step per pass over the state; 2: two (FP32, width a multiple of
         256 up to 4096); results are identical."""
         _check(load().xyl_set_fusion(self._h, int(steps_per_pass)))
+
+    def fusion(self):
+        """(steps per pass, rows per strip of the two-step pass or 0 where it
+        does not apply)."""
+        sp, rows = _i32(), _i32()
+        _check(load().xyl_get_fusion(self._h, ctypes.byref(sp), ctypes.byref(rows)))
+        return sp.value, rows.value
 
     def set_launch(self, rows_per_strip=0, waves_per_block=0):
         _check(load().xyl_set_launch(self._h, int(rows_per_strip), int(waves_per_block)))

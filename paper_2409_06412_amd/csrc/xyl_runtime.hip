@@ -1304,6 +1304,14 @@ int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass) {
     });
 }
 
+int xyl_get_fusion(const xyl_lattice* h, int32_t* steps_per_pass, int32_t* rows) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        if (steps_per_pass) *steps_per_pass = h->fusion;
+        if (rows) *rows = step2_eligible(h) ? step2_rows(h) : 0;
+    });
+}
+
 int xyl_set_graph_steps(xyl_lattice* h, int32_t steps) {
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");

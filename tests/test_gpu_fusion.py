@@ -90,3 +90,26 @@ def test_fusion_keeps_measurement_and_state_buffers(xyl):
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][1][0], res[1][1][0])
     np.testing.assert_array_equal(res[0][1][1], res[1][1][1])
+
+
+def test_fusion_query_reports_the_mode_in_effect(xyl):
+    """xyl_get_fusion: rows per strip where the two-step pass applies (taller
+    strips on wider lattices, 2..16 rows), 0 where it does not (FP64, a width
+    that is no multiple of 256 or above 4096, steps_per_pass 1)."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cases = [((4096, 4096, "f32"), True), ((2048, 2048, "f32"), True), ((1024, 1024, "f32"), True),
+             ((256, 64, "f32"), True), ((4096, 4096, "f64"), False), ((8192, 64, "f32"), False),
+             ((300, 64, "f32"), False)]
+    for (Lx, Ly, dt), fused in cases:
+        lat = xyl.Lattice(Lx, Ly, dtype=dt, schedule=((0, 0.5),), seed=1)
+        sp, rows = lat.fusion()
+        say(Lx, Ly, dt, "->", sp, rows)
+        assert sp == 2
+        if fused:
+            assert 2 <= rows <= 16 and rows <= max(2, Ly // cus)
+        else:
+            assert rows == 0
+        lat.set_fusion(1)
+        assert lat.fusion() == (1, 0)
+        lat.close()
