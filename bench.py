@@ -590,7 +590,12 @@ def main():
     us = dom["avg_kernel_us"]
     hbm = {"algorithmic_bytes_per_launch": BYTES_PER_SITE_F32 * L * L, "achieved_GBs": dom["algorithmic_GBs"],
            "peak_GBs": HBM_PEAK_GBS, "frac": dom["algorithmic_GBs"] / HBM_PEAK_GBS,
-           "stream_ceiling_GBs": ceiling, "frac_of_stream_ceiling": dom["algorithmic_GBs"] / ceiling}
+           "stream_ceiling_GBs": ceiling, "frac_of_stream_ceiling": dom["algorithmic_GBs"] / ceiling,
+           # the rate a one-step-per-pass kernel could reach at 8 TB/s (16 B per
+           # site-update), and this kernel's site-update rate over it
+           "single_step_roofline_site_updates_per_s": HBM_PEAK_GBS * 1e9 / BYTES_PER_SITE_F32,
+           "site_updates_over_single_step_roofline":
+               dom["site_updates_per_s"] / (HBM_PEAK_GBS * 1e9 / BYTES_PER_SITE_F32)}
     traffic = load_profile(TRAFFIC_FILE, L, "bytes_per_launch") if two else None
     slots = load_profile(VALU_FILE, L, "active_inst_valu_quad_cycles") if two else None
     if slots:

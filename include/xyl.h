@@ -328,6 +328,14 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
  * grid).  Mode 1: one launch per replica per step (the reference loop the
  * batched mode is measured against).  Default 0. */
 int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
+/* Steps per pass for the batched mode (1 or 2; default 2).  With 2, when
+ * every replica on the tile path is FP32 with Lx a multiple of 256 up to 4096,
+ * Ly >= 4 and at least 2^20 sites, runs of 4m steps between samples advance
+ * each replica two steps per pass in launches of its own (as
+ * xyl_set_fusion for a lattice); otherwise every step is one batched tile
+ * launch.  Results are bitwise identical either way.  The library allocates a
+ * second velocity buffer of the ensemble's size on first use. */
+int xyl_ensemble_set_fusion(xyl_ensemble* e, int32_t steps_per_pass);
 /* Launch shape (rows per strip, waves per workgroup) of the tile launches:
  * xyl_ensemble_autotune times candidates on scratch copies of the replicas'
  * state (the ensemble itself is not advanced) and keeps the fastest.

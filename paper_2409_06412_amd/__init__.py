@@ -78,6 +78,7 @@ _SIGS = {
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
     "xyl_set_fusion": (_i32, [_vp, _i32]),
     "xyl_get_fusion": (_i32, [_vp, P(_i32), P(_i32)]),
+    "xyl_ensemble_set_fusion": (_i32, [_vp, _i32]),
     "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
     "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
@@ -474,6 +475,12 @@ class Ensemble:
 
     def set_mode(self, mode: int):
         _check(load().xyl_ensemble_set_mode(self._h, int(mode)))
+
+    def set_fusion(self, steps_per_pass: int):
+        """2 (default): large FP32 replicas (width a multiple of 256 up to 4096,
+        at least 2^20 sites, all of them) take two steps per pass between
+        samples; 1: every step is one batched launch.  Results are identical."""
+        _check(load().xyl_ensemble_set_fusion(self._h, int(steps_per_pass)))
 
     def autotune(self):
         _check(load().xyl_ensemble_autotune(self._h))

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/xyl.h"
@@ -367,9 +368,9 @@ static hipGraphExec_t capture_steps(xyl_lattice* h, const Lat<R>& v, int mode, i
 }
 
 // Two steps per pass (FP32 plain stepping, width a multiple of 256 up to 4096).
+static bool step2_shape(int Lx, int Ly) { return Lx % kWaveSites == 0 && Lx <= 16 * kWaveSites && Ly >= 4; }
 static bool step2_eligible(const xyl_lattice* h) {
-    return h->dtype == XYL_F32 && h->fusion == 2 && h->Lx % kWaveSites == 0 && h->Lx <= 16 * kWaveSites &&
-           h->Ly >= 4;
+    return h->dtype == XYL_F32 && h->fusion == 2 && step2_shape(h->Lx, h->Ly);
 }
 
 // Rows per strip of the two-step kernel.  A workgroup spans the row (Lx / 256
@@ -380,12 +381,13 @@ static bool step2_eligible(const xyl_lattice* h) {
 // rows of the first step), 2 to 16 rows.  Measured best over 512^2 .. 4096^2,
 // 4096 x 1024, 1024 x 4096 and 256 x 8192 (strip counts off a multiple of the
 // CU count leave a partial last round of workgroups).
-static int step2_rows(const xyl_lattice* h) {
-    const int waves = h->Lx / kWaveSites;
-    const int per_cu = std::max(1, std::min(16 / waves, (160 * 1024) / (32 * h->Lx)));
-    const int strips = h->cus * std::max(1, per_cu / 2);
-    return std::max(2, std::min(16, h->Ly / strips));
+static int step2_rows(int Lx, int Ly, int cus) {
+    const int waves = Lx / kWaveSites;
+    const int per_cu = std::max(1, std::min(16 / waves, (160 * 1024) / (32 * Lx)));
+    const int strips = cus * std::max(1, per_cu / 2);
+    return std::max(2, std::min(16, Ly / strips));
 }
+static int step2_rows(const xyl_lattice* h) { return step2_rows(h->Lx, h->Ly, h->cus); }
 
 // Launches for 4m steps from the current step: pairs of two-step passes,
 // (A, u) -> (B, u2) -> (A, u), A the buffer holding the angles at step k, so
@@ -1582,6 +1584,10 @@ struct xyl_ensemble {
     DevBuf<char> lds_reps;
     DevBuf<LdsJobHost> lds_jobs;
     std::vector<LdsJobHost> lds_jobs_host;
+    // two steps per pass for large FP32 replicas (one launch per replica per pass)
+    int fusion = 2;
+    int cus = 256;
+    DevBuf<char> u2;                // second velocity buffer, allocated on first use
 
     template <typename R>
     Lat<R> view(int r, uint64_t jbase) {
@@ -1735,10 +1741,44 @@ static void ens_step_per_replica(xyl_ensemble* e, uint64_t nsteps, EnsSamples& s
     }
 }
 
+// Large FP32 replicas take two steps per pass in launches of their own when
+// every replica on the tile path qualifies: width a multiple of 256 up to
+// 4096, and at least 2^20 sites, so that one replica's launch fills the GPU
+// (smaller replicas stay in the batched tile launches).
+constexpr size_t kEnsStep2MinSites = size_t(1) << 20;
+
+static bool ens_step2_ok(const xyl_ensemble* e, const std::vector<int>& reps) {
+    if (e->dtype != XYL_F32 || e->fusion != 2) return false;
+    for (int r : reps) {
+        const xyl_replica_desc& d = e->desc[r];
+        if (!step2_shape(d.Lx, d.Ly) || (size_t)d.Lx * (size_t)d.Ly < kEnsStep2MinSites) return false;
+    }
+    return true;
+}
+
+// n4 (a multiple of 4) steps of replica r from launch index j0 on, as pairs of
+// two-step passes (A, u) -> (B, u2) -> (A, u) with A the buffer of the angles
+// at the replica's current step, so that its state ends where it started.
+static void ens_steps2(xyl_ensemble* e, int r, uint64_t j0, uint64_t n4) {
+    e->u2.reserve(sizeof(float) * e->total);
+    const Lat<float> v = e->view<float>(r, e->j);
+    const uint64_t k = e->k[r] + (j0 - e->j);
+    float* A = static_cast<float*>(e->th[k & 1]) + e->off[r];
+    float* B = static_cast<float*>(e->th[(k + 1) & 1]) + e->off[r];
+    float* u = static_cast<float*>(e->u) + e->off[r];
+    float* u2 = reinterpret_cast<float*>(e->u2.p) + e->off[r];
+    const int rows = step2_rows(e->desc[r].Lx, e->desc[r].Ly, e->cus);
+    for (uint64_t i = 0; i < n4; i += 4) {
+        launch_step2(v, A, u, B, u2, rows, nullptr, j0 + i, e->stream);
+        launch_step2(v, B, u2, A, u, rows, nullptr, j0 + i + 2, e->stream);
+    }
+}
+
 // Batched loop: the steps every active replica takes before the next sample
 // or end of any of them form a chunk; large replicas advance through one
-// tile-table launch per step, small FP32 replicas through one whole-in-LDS
-// launch per chunk on a second stream.
+// tile-table launch per step (after the chunk's first step, runs of 4m steps
+// as two-step passes per replica where ens_step2_ok), small FP32 replicas
+// through one whole-in-LDS launch per chunk on a second stream.
 template <typename R>
 static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) {
     std::vector<FinalizeJobHost> jobs;
@@ -1811,7 +1851,15 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                 jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                                (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
             flush_finalize(e, jobs);
-            for (uint64_t c = 1; c < chunk; ++c)
+            uint64_t c = 1;
+            if constexpr (std::is_same<R, float>::value) {
+                const uint64_t n4 = (chunk - 1) / 4 * 4;
+                if (n4 && ens_step2_ok(e, active_g)) {
+                    for (int r : active_g) ens_steps2(e, r, e->j + 1, n4);
+                    c += n4;
+                }
+            }
+            for (; c < chunk; ++c)
                 launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->model(), e->launch.rows, e->launch.wpb,
                                         nullptr,
                                         e->j + c, e->stream);
@@ -1953,6 +2001,7 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
         std::unique_ptr<xyl_ensemble> e(new xyl_ensemble());
         e->dtype = dtype;
         e->device = device;
+        check_hip(hipDeviceGetAttribute(&e->cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
         e->n = n;
         e->desc.assign(desc, desc + n);
         for (int r = 0; r < n; ++r) {
@@ -2019,6 +2068,14 @@ int xyl_ensemble_set_stream(xyl_ensemble* e, void* stream) {
     return guarded([&] {
         require(e != nullptr, XYL_EINVAL, "NULL handle");
         e->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int xyl_ensemble_set_fusion(xyl_ensemble* e, int32_t steps_per_pass) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        require(steps_per_pass == 1 || steps_per_pass == 2, XYL_EINVAL, "steps_per_pass must be 1 or 2");
+        e->fusion = steps_per_pass;
     });
 }
 

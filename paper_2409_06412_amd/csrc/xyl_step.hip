@@ -356,7 +356,8 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
 #pragma unroll
         for (int q = 0; q < 4; ++q) rotor<R, M>(T.th[q], T.s[q], T.c[q]);
     };
-    // stage A on row y of iteration it: P, C, N = rows y-1, y, y+1 at step k;
+    // stage A on row y of iteration it: C = row y at step k, P and N its two
+    // y-neighbours (the row before and the row after in the strip's direction);
     // rotors to LDS, angles and velocities to `out`
     auto stage_a = [&](const TRow<R>& P, const TRow<R>& C, const TRow<R>& N, const URow<R>& U, int y, int it,
                        BRow<R>& out) {
@@ -380,8 +381,9 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
         store4(rs + x, s1);
         store4(rs + Lx + x, c1);
     };
-    // stage B on row y (stage-A values C in registers; the rotors of rows
-    // y-1, y, y+1 in the LDS slots of iterations it-2, it-1, it)
+    // stage B on row y (stage-A values C in registers; the rotors of row y
+    // and of its two y-neighbours in the LDS slots of iterations it-1, it-2
+    // and it)
     auto stage_b = [&](const BRow<R>& C, int y, int it) {
         const float* rp = slot(it - 2);
         const float* rc = slot(it - 1);
@@ -413,36 +415,44 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
         store4(B.u_out + row + x, uo);
     };
 
-    // Iteration it (0 .. nit-1) runs stage A on row ya = y0 - 1 + it and, from
-    // it = 2 on, stage B on row ya - 1.  On entry P holds the rotors of row
-    // ya-1, C the angles and rotors of row ya, N the angles of row ya+1, UC the
-    // velocities of row ya; the iteration loads the angles of row ya+2 into P
-    // and the velocities of row ya+1 into UN.
+    // Even strips run top-down, odd strips bottom-up (the force is symmetric in
+    // the two y-neighbours, sums of the two, so the values do not depend on
+    // the direction): the halo rows a strip shares with its neighbour are then
+    // read by both at the same end of their passes, while the rows are in L2
+    // (neighbouring strips run on one XCD).  With d = +1 or -1 and
+    // r(i) = ys + d i (wrapped), iteration it (0 .. nit-1) runs stage A on row
+    // r(it) and, from it = 2 on, stage B on row r(it-1).  On entry P holds the
+    // rotors of row r(it-1), C the angles and rotors of r(it), N the angles of
+    // r(it+1), UC the velocities of r(it); the iteration loads the angles of
+    // r(it+2) into P and the velocities of r(it+1) into UN (the last iteration
+    // reloads rows the one before loaded, so that every iteration loads and
+    // nothing outside the strip's rows is fetched).
     const int nit = (y1 - y0) + 2;
+    const int d = (strip & 1) ? -1 : 1;
+    const int ys = d > 0 ? y0 - 1 : y1;
+    auto rowof = [&](int i) { return wrap_y(ys + d * i); };
     TRow<R> T0, T1, T2;
     URow<R> U0, U1;
     BRow<R> B0, B1;
-    load_th(T0, wrap_y(y0 - 2));
-    load_th(T1, wrap_y(y0 - 1));
-    load_th(T2, wrap_y(y0));
-    load_u(U0, wrap_y(y0 - 1));
+    load_th(T0, rowof(-1));
+    load_th(T1, rowof(0));
+    load_th(T2, rowof(1));
+    load_u(U0, rowof(0));
     trig(T0);
     trig(T1);
-    // Every iteration loads (the last one a row nobody uses, in bounds), and
-    // stage B runs in every iteration of the loop: the first two iterations
+    // Stage B runs in every iteration of the loop: the first two iterations
     // are peeled and end with a full wait, so that the compiler's counter
     // waits inside the loop need not cover a path without stores (which would
     // make the next row's wait also wait for the stores just issued).
     auto iterate = [&](auto with_b, TRow<R>& P, TRow<R>& C, TRow<R>& N, URow<R>& UC, URow<R>& UN, BRow<R>& Bn,
                        BRow<R>& Bp, int it) {
-        const int ya = y0 - 1 + it;
         trig(N);
-        load_th(P, wrap_y(ya + 2));
-        load_u(UN, wrap_y(ya + 1));
+        load_th(P, rowof(min(it + 2, nit)));
+        load_u(UN, rowof(min(it + 1, nit - 1)));
         __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of stage A
-        stage_a(P, C, N, UC, wrap_y(ya), it, Bn);
+        stage_a(P, C, N, UC, rowof(it), it, Bn);
         __syncthreads();
-        if constexpr (decltype(with_b)::value) stage_b(Bp, wrap_y(ya - 1), it);
+        if constexpr (decltype(with_b)::value) stage_b(Bp, rowof(it - 1), it);
     };
     const std::false_type first{};
     const std::true_type full{};

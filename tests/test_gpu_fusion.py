@@ -113,3 +113,44 @@ def test_fusion_query_reports_the_mode_in_effect(xyl):
         lat.set_fusion(1)
         assert lat.fusion() == (1, 0)
         lat.close()
+
+
+def _ensemble_run(xyl, specs, fusion, nsteps, every, states=None):
+    ens = xyl.Ensemble(specs, dtype="f32")
+    ens.set_fusion(fusion)
+    if states:
+        for r, (th, om) in states.items():
+            ens.set_state(r, th, om)
+    samples = ens.step(nsteps, every=every)
+    out = [ens.get_state(r) for r in range(len(specs))]
+    ens.close()
+    return samples, out
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_ensemble_two_steps_per_pass_equal_batched_single_steps(xyl, mixed):
+    """Large FP32 replicas (width a multiple of 256, >= 2^20 sites) of different
+    parameters, schedules, models' settings and step budgets take two steps per
+    pass between samples; with a small replica on the tile path as well
+    (mixed) every step stays batched.  Both give the same samples and states
+    as one batched launch per step, bit for bit."""
+    specs = [
+        workloads.LatticeSpec(1024, 1024, schedule=((0, 0.6), (40, 0.2)), seed=3, replica=0, nsteps=10 ** 6),
+        workloads.LatticeSpec(2048, 512, Jx=0.8, h=0.3, schedule=((0, 0.4),), seed=3, replica=1, nsteps=57),
+        workloads.LatticeSpec(256, 4096, schedule=((0, 0.9), (30, 0.5, 2), (90, 0.1)), seed=4, replica=2,
+                              nsteps=10 ** 6),
+    ]
+    if mixed:
+        specs.append(workloads.LatticeSpec(512, 384, schedule=((0, 0.5),), seed=5, replica=3, nsteps=10 ** 6))
+    rng = np.random.default_rng(11)
+    states = {2: (rng.uniform(-np.pi, np.pi, (4096, 256)).astype(np.float32).astype(np.float64),
+                  rng.normal(0, 0.5, (4096, 256)).astype(np.float32).astype(np.float64))}
+    say("ensemble", [(s.Lx, s.Ly) for s in specs], "mixed", mixed)
+    a = _ensemble_run(xyl, specs, 2, 83, 20, states)
+    b = _ensemble_run(xyl, specs, 1, 83, 20, states)
+    for r in range(len(specs)):
+        np.testing.assert_array_equal(a[0][r], b[0][r])
+        np.testing.assert_array_equal(a[1][r][0], b[1][r][0])
+        np.testing.assert_array_equal(a[1][r][1], b[1][r][1])
+        assert a[1][r][2] == b[1][r][2]
+    assert a[1][1][2] == 57 and a[1][0][2] == 83
