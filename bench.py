@@ -656,6 +656,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    # the metric's "% HBM roofline": site-updates/s x 16 B per site-update over
+    # 8 TB/s (above 100 when two steps share one pass over the state)
+    line["pct_hbm_roofline"] = 100.0 * value * BYTES_PER_SITE_F32 / (HBM_PEAK_GBS * 1e9)
     if "adjoint_512" in extras and "adjoint_over_forward" in extras["adjoint_512"]:
         line["adjoint_over_forward"] = extras["adjoint_512"]["adjoint_over_forward"]
     if "ensemble_fss" in extras:

@@ -214,8 +214,13 @@ int xyl_sync(xyl_lattice* h);
 /* ------------------------------------------------------ tuning and graphs */
 /* Launch shape of the step kernels: rows per strip (>= 1) and waves per
  * workgroup (1, 2, 4 or 8); 0 keeps the current value.  Results do not
- * depend on it.  xyl_autotune times candidates on this lattice and keeps the
- * fastest; the choice is cached per (shape, precision) for the process. */
+ * depend on it.  xyl_autotune times candidates on this lattice (as captured
+ * graphs on scratch copies of the state, which it leaves untouched) and keeps
+ * the fastest; for FP32 lattices that two steps per pass apply to, it also
+ * times that pass at several strip heights and sets the steps per pass
+ * (xyl_set_fusion) to whichever of 1 and 2 is faster per step.  The choices
+ * are cached per (shape, precision) for the process and applied to lattices
+ * created later. */
 int xyl_set_launch(xyl_lattice* h, int32_t rows_per_strip, int32_t waves_per_block);
 int xyl_get_launch(xyl_lattice* h, int32_t* rows_per_strip, int32_t* waves_per_block);
 int xyl_autotune(xyl_lattice* h);
@@ -232,10 +237,11 @@ int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
  * buffers at the end of every call. */
 int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass);
 /* The stepping mode in effect: *steps_per_pass = the value set by
- * xyl_set_fusion; *rows = rows per strip of the two-step pass for this
- * lattice on its device (chosen from the CU count and the workgroups a CU
- * holds), 0 where two steps per pass do not apply (shape, FP64, or
- * steps_per_pass 1).  Either pointer may be NULL. */
+ * xyl_set_fusion or chosen by xyl_autotune; *rows = rows per strip of the
+ * two-step pass for this lattice on its device (xyl_autotune's choice, else a
+ * rule from the CU count and the workgroups a CU holds), 0 where two steps
+ * per pass do not apply (shape, FP64, or steps_per_pass 1).  Either pointer
+ * may be NULL. */
 int xyl_get_fusion(const xyl_lattice* h, int32_t* steps_per_pass, int32_t* rows);
 
 /* -------------------------------------------------------------- test hooks */

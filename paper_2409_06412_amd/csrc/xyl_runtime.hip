@@ -172,6 +172,8 @@ static size_t elem_size(int dtype) { return dtype == XYL_F64 ? sizeof(double) : 
 // -------------------------------------------------------- launch tuning
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Launch> g_tuned;
+// steps per pass and rows per strip of the two-step pass, chosen by xyl_autotune
+static std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tuned2;
 
 // Launch shape before any autotuning: enough waves to occupy every SIMD of
 // the 256 CUs (strips of up to 16 rows while there are >= 4096 wave-rows,
@@ -248,6 +250,7 @@ struct xyl_lattice {
     bool counter_valid = false;
     int fusion = 2;                // steps per pass of plain FP32 stepping where the shape allows (1 or 2)
     int cus = 256;                 // compute units of the device
+    int step2_rows_tuned = 0;      // rows per strip of the two-step pass from xyl_autotune (0: the size rule)
     DevBuf<char> u2;               // second velocity buffer of the two-step passes
     // device scratch
     DevBuf<uint64_t> kdev;
@@ -387,7 +390,9 @@ static int step2_rows(int Lx, int Ly, int cus) {
     const int strips = cus * std::max(1, per_cu / 2);
     return std::max(2, std::min(16, Ly / strips));
 }
-static int step2_rows(const xyl_lattice* h) { return step2_rows(h->Lx, h->Ly, h->cus); }
+static int step2_rows(const xyl_lattice* h) {
+    return h->step2_rows_tuned ? h->step2_rows_tuned : step2_rows(h->Lx, h->Ly, h->cus);
+}
 
 // Launches for 4m steps from the current step: pairs of two-step passes,
 // (A, u) -> (B, u2) -> (A, u), A the buffer holding the angles at step k, so
@@ -695,6 +700,11 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find({Lx, Ly, dtype});
             if (it != g_tuned.end()) h->launch = it->second;
+            auto it2 = g_tuned2.find({Lx, Ly, dtype});
+            if (it2 != g_tuned2.end()) {
+                h->fusion = it2->second.first;
+                h->step2_rows_tuned = it2->second.second;
+            }
         }
         *out = h.release();
     });
@@ -1208,14 +1218,18 @@ int xyl_get_launch(xyl_lattice* h, int32_t* rows, int32_t* wpb) {
 
 }  // extern "C"
 
+// Times the single-step launch shapes and, for FP32 lattices of a shape the
+// two-step pass takes, the two-step pass at several strip heights; returns
+// the best single-step shape and sets *fusion (1 or 2, whichever is faster
+// per step) and *rows2 (rows per strip of the best two-step pass, 0 if none).
 template <typename R>
-static Launch autotune_impl(xyl_lattice* h) {
+static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
     // time candidates on scratch copies so the lattice state is untouched;
     // each candidate runs as a captured graph of back-to-back steps, so the
     // host's launch overhead does not mask kernel time on small lattices
     const size_t bytes = sizeof(R) * h->N;
     DevBuf<char> tmp;
-    tmp.reserve(3 * bytes);
+    tmp.reserve(4 * bytes);
     DevBuf<uint64_t> kc;
     kc.reserve(1);
     Lat<R> v = h->view<R>();
@@ -1279,6 +1293,62 @@ static Launch autotune_impl(xyl_lattice* h) {
             best = scores[i].second;
         }
     }
+    // two steps per pass: the same timing over a multiple of 4 steps, per step
+    *fusion = 1;
+    *rows2 = 0;
+    if constexpr (std::is_same<R, float>::value) {
+        if (step2_shape(h->Lx, h->Ly)) {
+            const int reps4 = (reps + 3) / 4 * 4;
+            float* A = v.th[0];
+            float* B = v.th[1];
+            float* u = v.u;
+            float* u2 = reinterpret_cast<float*>(tmp.p + 3 * bytes);
+            check_hip(hipMemcpyAsync(u2, v.u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
+            auto time_step2 = [&](int rows, int repeats) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ex = nullptr;
+                check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal),
+                          "hipStreamBeginCapture");
+                for (int i = 0; i < reps4; i += 4) {
+                    launch_step2(v, A, u, B, u2, rows, kc.p, (uint64_t)i, h->cap_stream);
+                    launch_step2(v, B, u2, A, u, rows, kc.p, (uint64_t)i + 2, h->cap_stream);
+                }
+                check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+                hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                check_hip(err, "hipGraphInstantiate");
+                check_hip(hipGraphLaunch(ex, h->stream), "hipGraphLaunch");   // warm-up
+                float best_t = 1e30f;
+                for (int rep = 0; rep < repeats; ++rep) {
+                    check_hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+                    check_hip(hipGraphLaunch(ex, h->stream), "hipGraphLaunch");
+                    check_hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+                    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0.f;
+                    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    best_t = std::min(best_t, ms);
+                }
+                (void)hipGraphExecDestroy(ex);
+                return best_t / (float)reps4;
+            };
+            std::vector<int> rows_c2 = {2, 4, 8, 16, step2_rows(h->Lx, h->Ly, h->cus)};
+            std::sort(rows_c2.begin(), rows_c2.end());
+            rows_c2.erase(std::unique(rows_c2.begin(), rows_c2.end()), rows_c2.end());
+            std::vector<std::pair<float, int>> s2;
+            for (int r : rows_c2)
+                if (r <= h->Ly) s2.push_back({time_step2(r, 1), r});
+            std::sort(s2.begin(), s2.end());
+            float best2 = 1e30f;
+            for (size_t i = 0; i < std::min<size_t>(2, s2.size()); ++i) {
+                const float t = time_step2(s2[i].second, 3);
+                if (t < best2) {
+                    best2 = t;
+                    *rows2 = s2[i].second;
+                }
+            }
+            if (best2 < best_ms / (float)reps) *fusion = 2;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;
@@ -1290,11 +1360,18 @@ int xyl_autotune(xyl_lattice* h) {
     return guarded([&] {
         require_init(h);
         DeviceGuard g(h->device);
-        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h) : autotune_impl<float>(h);
+        int fusion = 1, rows2 = 0;
+        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h, &fusion, &rows2)
+                                       : autotune_impl<float>(h, &fusion, &rows2);
         h->launch = l;
+        if (h->dtype == XYL_F32) {
+            h->fusion = fusion;
+            h->step2_rows_tuned = rows2;
+        }
         h->touch();
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[{h->Lx, h->Ly, h->dtype}] = l;
+        if (h->dtype == XYL_F32) g_tuned2[{h->Lx, h->Ly, h->dtype}] = {fusion, rows2};
     });
 }
 
