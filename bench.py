@@ -64,10 +64,17 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernels' code: the sources with comments and
+    whitespace removed, so that only a change to the code itself marks the
+    committed counter summaries as taken of another kernel."""
+    import re
     h = hashlib.sha256()
     for f in ("xyl_step.hip", "xyl_device.hpp", "xyl_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2409_06412_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2409_06412_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

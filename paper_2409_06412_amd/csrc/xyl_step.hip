@@ -15,6 +15,10 @@
 // per strip and its sine/cosine evaluated once.  x-neighbours inside the wave
 // come from the adjacent lanes through DPP; the two wave-edge lanes load their
 // outer neighbour.  Bytes per site-update: read th and u, write th' and u'.
+//
+// FP32 plain stepping also has a two-steps-per-pass kernel (k_step2, below):
+// a workgroup spans the row and runs the second step one row behind the
+// first, so the state is read and written once per two site-updates.
 #include "xyl_device.hpp"
 #include <type_traits>
 

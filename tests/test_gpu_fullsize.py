@@ -1,0 +1,86 @@
+"""The benchmark's lattice at full size, in the configuration bench.py times:
+4096^2 FP32, launch shape and steps per pass from xyl_autotune (two steps per
+pass, 16-row strips on MI355X), FP64 observables fused into sampled steps.
+Every site is compared with the FP64 oracle run on the whole lattice from the
+same FP32-representable start (the oracle takes about 1 s per 10 steps of
+4096^2 on 16 host threads).
+
+XY model: max |dtheta| <= 1e-4 over 100 steps at every site, observables of the
+samples within FP32 rounding of the oracle's.
+
+Si model: its field term sin(p th) with p = 2.5 is not periodic under the
+half-circle wrap, so the force jumps where a site crosses +-pi/2.  A site that
+one side puts just above the boundary and the other just below takes a
+different kick, and its neighbourhood follows.  That is the model's own
+sensitivity, not the kernel's: two FP64 oracle runs of 2048^2 whose starts
+differ by 6e-8 relative (FP32 rounding) differ by up to 4.5e-3 within 20
+steps, at 3 of 4.2 M sites beyond 1e-4 and 10 beyond 1e-6.  The bar there is
+per site for all but a 1e-5 fraction (<= 1e-4), and the samples' observables
+as for XY.
+
+The structure-factor modes F(q) of the samples are squares of sums over all
+N sites: their bar grows with sqrt(F N) times the FP32 rotor's per-term error
+(below), which at 4096^2 exceeds 1e-4 relative when the couplings make eps = +1
+everywhere (Si) and the rotor's rounding does not cancel between columns."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_06412_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def wrapped_diff(a, b, period=2 * np.pi):
+    h = period / 2
+    return np.abs(np.remainder(np.asarray(a) - np.asarray(b) + h, period) - h)
+
+
+@pytest.mark.parametrize("model,nsteps,every", [("xy", 100, 50), ("si", 20, 10)])
+def test_full_size_bench_configuration_matches_oracle(xyl, model, nsteps, every):
+    L = 4096
+    spec = workloads.large_fp32(0, L) if model == "xy" else workloads.si_lattice(L, L, seed=1)
+    lat = xyl.Lattice(L, L, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
+                      **spec.params())
+    lat.init_random()
+    launch = lat.autotune()
+    sp, rows = lat.fusion()
+    say(model, "launch", launch, "steps per pass", sp, "rows", rows)
+    th0, om0, k0 = lat.get_state()
+    assert k0 == 0
+    s = lat.step_measured(nsteps, every)
+    th, om, k = lat.get_state()
+    assert k == nsteps
+    lat.close()
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    tr, wr, so = o.run(th0, om0, 0, nsteps, every=every)
+    period = 2 * np.pi if model == "xy" else np.pi
+    dth = wrapped_diff(th, tr, period).max()
+    dom = np.abs(om - wr).max()
+    d = wrapped_diff(th, tr, period)
+    n_out = int(np.count_nonzero(d > 1e-4))
+    say(model, "4096^2", nsteps, "steps: max|dtheta|", dth, "max|domega|", dom, "sites beyond 1e-4", n_out,
+        "beyond 1e-6", int(np.count_nonzero(d > 1e-6)))
+    if model == "xy":
+        assert dth <= 1e-4
+        assert dom <= 1e-3
+    else:
+        assert n_out <= 1e-5 * L * L
+        assert np.quantile(d, 1 - 1e-5) <= 1e-4
+    assert s.shape == so.shape == (nsteps // every + 1, 6)
+    # energies and the order parameter are site means: within FP32 rounding
+    np.testing.assert_allclose(s[:, :3], so[:, :3], rtol=1e-4, atol=2e-6)
+    # F(q) = |sum_i eps_i z_i|^2 / N over N unit rotors: a per-term rotor error
+    # delta (FP32 sine/cosine, two ulps of 1) moves the sum by up to N delta,
+    # hence F by up to 2 sqrt(F N) delta; with eps = +1 everywhere (the Si
+    # couplings) the terms' rounding does add up coherently
+    bound = 1e-4 * np.abs(so[:, 3:]) + 2.0 * np.sqrt(np.abs(so[:, 3:]) * L * L) * 2.0 ** -22
+    excess = np.abs(s[:, 3:] - so[:, 3:]) / bound
+    say(model, "structure-factor modes: worst |dF| / bound", excess.max())
+    assert np.all(excess <= 1.0)

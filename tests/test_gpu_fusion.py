@@ -40,6 +40,9 @@ def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None):
     (1024, 20, "si", 32, [64, 7]),         # Si model
     (4096, 48, "xy", 32, [100]),           # sixteen waves per row (full workgroup)
     (768, 9, "xy", 8, [40]),               # three waves, 9 rows (strips of 2 rows)
+    (4096, 4, "xy", 0, [24]),              # the smallest height: two strips whose halos wrap onto each other
+    (256, 5, "si", 32, [20]),              # one wave, an odd height (a one-row last strip)
+    (2048, 2048, "si", 32, [36]),          # the size rule's 8-row strips, Si model
 ])
 def test_two_steps_per_pass_equal_single_steps(xyl, Lx, Ly, model, graphs, steps):
     say("fusion", Lx, Ly, model, graphs, steps)
