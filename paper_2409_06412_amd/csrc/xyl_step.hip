@@ -20,6 +20,8 @@
 // a workgroup spans the row and runs the second step one row behind the
 // first, so the state is read and written once per two site-updates.
 #include "xyl_device.hpp"
+#include <mutex>
+#include <set>
 #include <type_traits>
 
 namespace xyl {
@@ -482,11 +484,24 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
 template <int M>
 static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows, const uint64_t* kdev, uint64_t j,
                            hipStream_t s) {
+    // the LDS ring of the widest rows (4096 sites: 128 KiB) is allowed once per
+    // device and kernel instance, not on every launch
+    static std::mutex mu;
+    static std::set<int> allowed;
+    {
+        int dev = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice");
+        std::lock_guard<std::mutex> lk(mu);
+        if (!allowed.count(dev)) {
+            const int max_lds = (int)(sizeof(float) * 2 * kStep2Slots * 16 * kWaveSites);
+            check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_step2<M>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, max_lds),
+                      "hipFuncSetAttribute");
+            allowed.insert(dev);
+        }
+    }
     const int nstrips = (v.Ly + rows - 1) / rows;
     const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)v.Lx;
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_step2<M>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-              "hipFuncSetAttribute");
     k_step2<M><<<nstrips, (v.Lx >> 8) * kWave, lds, s>>>(v, b, kdev, j, rows);
     check_hip(hipGetLastError(), "two-step kernel launch");
 }
