@@ -249,8 +249,9 @@ class Lattice:
         _check(load().xyl_set_stream(self._h, _vp(int(stream) if stream is not None else 0)))
 
     def set_fusion(self, steps_per_pass: int):
-        """1: one step per pass over the state; 2: two (FP32, width a multiple of
-        256 up to 4096); results are identical."""
+        """1: one step per pass over the state; 2: two (FP32, width up to 4096
+        filling at least 3/4 of its last wave of 256 sites); results are
+        identical."""
         _check(load().xyl_set_fusion(self._h, int(steps_per_pass)))
 
     def fusion(self):
@@ -477,9 +478,10 @@ class Ensemble:
         _check(load().xyl_ensemble_set_mode(self._h, int(mode)))
 
     def set_fusion(self, steps_per_pass: int):
-        """2 (default): large FP32 replicas (width a multiple of 256 up to 4096,
-        at least 2^20 sites, all of them) take two steps per pass between
-        samples; 1: every step is one batched launch.  Results are identical."""
+        """2 (default): FP32 replicas on the tile path whose width the two-step
+        pass takes advance two steps per pass between samples, batched by
+        waves per row; 1: every step is one batched launch.  Results are
+        identical."""
         _check(load().xyl_ensemble_set_fusion(self._h, int(steps_per_pass)))
 
     def autotune(self):

@@ -80,6 +80,20 @@ struct Task {
     int32_t rep, xw, strip, pad;
 };
 
+// One workgroup of a batched two-step pass: rows [y0, y1) of replica rep,
+// swept top-down (dir = +1) or bottom-up (-1).
+struct Task2 {
+    int32_t rep, y0, y1, dir;
+};
+
+// Widths the two-step pass takes: up to 4096 sites (16 waves of 256), the
+// last wave at least three quarters full (lanes past the row's end idle).
+inline bool step2_width_ok(int Lx) {
+    if (Lx < 4 || Lx % 4 != 0 || Lx > 16 * kWaveSites) return false;
+    const int waves = (Lx + kWaveSites - 1) / kWaveSites;
+    return 4 * Lx >= 3 * waves * kWaveSites;
+}
+
 // ------------------------------------------------------------- launchers
 template <typename R>
 void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kdev, uint64_t j,
@@ -92,6 +106,14 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
 // written to th_out / u_out (distinct buffers); k = v.k_base + j (+ *kdev).
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
                   const uint64_t* kdev, uint64_t j, hipStream_t s);
+// Two steps per pass of many FP32 replicas (reps: the table of their views,
+// k = k_base + j (+ *kdev)): one workgroup per task, every task's replica
+// spanning `waves` waves (partial: some width not a multiple of 256), max_lx
+// the widest.  phase 0 reads th[k & 1] and u and writes the other angle
+// buffer and the velocities' place in u2_base; phase 1 the reverse.
+void launch_ensemble_step2(const Lat<float>* reps, const Task2* tasks, int ntasks, int waves, bool partial,
+                           int max_lx, int model, int phase, const float* u_base, float* u2_base,
+                           const uint64_t* kdev, uint64_t j, hipStream_t s);
 template <typename R>
 void launch_init_random(const Lat<R>& v, hipStream_t s);
 template <typename R>

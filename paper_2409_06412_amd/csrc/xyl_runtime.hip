@@ -75,6 +75,24 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    // owns its allocation: movable, not copyable
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
     void reserve(size_t count) {
         if (count <= n && p) return;
         if (p) (void)hipFree(p);
@@ -371,7 +389,7 @@ static hipGraphExec_t capture_steps(xyl_lattice* h, const Lat<R>& v, int mode, i
 }
 
 // Two steps per pass (FP32 plain stepping, width a multiple of 256 up to 4096).
-static bool step2_shape(int Lx, int Ly) { return Lx % kWaveSites == 0 && Lx <= 16 * kWaveSites && Ly >= 4; }
+static bool step2_shape(int Lx, int Ly) { return step2_width_ok(Lx) && Ly >= 4; }
 static bool step2_eligible(const xyl_lattice* h) {
     return h->dtype == XYL_F32 && h->fusion == 2 && step2_shape(h->Lx, h->Ly);
 }
@@ -385,7 +403,7 @@ static bool step2_eligible(const xyl_lattice* h) {
 // 4096 x 1024, 1024 x 4096 and 256 x 8192 (strip counts off a multiple of the
 // CU count leave a partial last round of workgroups).
 static int step2_rows(int Lx, int Ly, int cus) {
-    const int waves = Lx / kWaveSites;
+    const int waves = (Lx + kWaveSites - 1) / kWaveSites;
     const int per_cu = std::max(1, std::min(16 / waves, (160 * 1024) / (32 * Lx)));
     const int strips = cus * std::max(1, per_cu / 2);
     return std::max(2, std::min(16, Ly / strips));
@@ -1661,9 +1679,23 @@ struct xyl_ensemble {
     DevBuf<char> lds_reps;
     DevBuf<LdsJobHost> lds_jobs;
     std::vector<LdsJobHost> lds_jobs_host;
-    // two steps per pass for large FP32 replicas (one launch per replica per pass)
+    // two steps per pass for FP32 replicas on the tile path: one batched launch
+    // per class of replicas spanning the same number of waves, per pass; the
+    // other tile-path replicas keep one tile launch per step (tasks_rest)
+    struct Step2Class {
+        int waves = 0;
+        bool partial = false;
+        int max_lx = 0;
+        int rows = 0;
+        DevBuf<Task2> tasks;
+        int ntasks = 0;
+    };
     int fusion = 2;
     int cus = 256;
+    int tables_fusion = 0;          // fusion setting the task tables were built for
+    std::vector<Step2Class> s2cls;
+    DevBuf<Task> tasks_rest;
+    int ntasks_rest = 0;
     DevBuf<char> u2;                // second velocity buffer, allocated on first use
 
     template <typename R>
@@ -1722,9 +1754,59 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
     if (!tk.empty())
         check_hip(hipMemcpyAsync(e->tasks.p, tk.data(), sizeof(Task) * tk.size(), hipMemcpyHostToDevice, e->stream),
                   "H2D");
+    // two-step classes (FP32): replicas whose width the two-step pass takes,
+    // grouped by waves per row; the rest of the tile-path replicas
+    std::vector<std::vector<Task2>> t2(17);
+    std::vector<Task> rest;
+    e->s2cls.clear();
+    if (e->dtype == XYL_F32 && e->fusion == 2) {
+        std::vector<std::vector<int>> byw(17);
+        for (int r : active) {
+            const xyl_replica_desc& d = e->desc[r];
+            if (step2_shape(d.Lx, d.Ly)) byw[(d.Lx + kWaveSites - 1) / kWaveSites].push_back(r);
+            else
+                for (const Task& t : tk)
+                    if (t.rep == r) rest.push_back(t);
+        }
+        for (int w = 1; w <= 16; ++w) {
+            if (byw[w].empty()) continue;
+            xyl_ensemble::Step2Class cl;
+            cl.waves = w;
+            // strips as tall as keep at least two waves per SIMD busy (2 to 16 rows)
+            cl.rows = 2;
+            for (int rows = 16; rows >= 2; rows /= 2) {
+                long strips = 0;
+                for (int r : byw[w]) strips += (e->desc[r].Ly + rows - 1) / rows;
+                if (strips * w >= 8L * e->cus) {
+                    cl.rows = rows;
+                    break;
+                }
+            }
+            for (int r : byw[w]) {
+                const xyl_replica_desc& d = e->desc[r];
+                cl.partial = cl.partial || d.Lx % kWaveSites != 0;
+                cl.max_lx = std::max(cl.max_lx, d.Lx);
+                for (int s = 0; s * cl.rows < d.Ly; ++s)
+                    t2[w].push_back(Task2{r, s * cl.rows, std::min(d.Ly, (s + 1) * cl.rows), (s & 1) ? -1 : 1});
+            }
+            cl.ntasks = (int)t2[w].size();
+            cl.tasks.reserve(t2[w].size());
+            check_hip(hipMemcpyAsync(cl.tasks.p, t2[w].data(), sizeof(Task2) * t2[w].size(), hipMemcpyHostToDevice,
+                                     e->stream),
+                      "H2D");
+            e->s2cls.push_back(std::move(cl));
+        }
+        e->ntasks_rest = (int)rest.size();
+        e->tasks_rest.reserve(std::max<size_t>(rest.size(), 1));
+        if (!rest.empty())
+            check_hip(hipMemcpyAsync(e->tasks_rest.p, rest.data(), sizeof(Task) * rest.size(), hipMemcpyHostToDevice,
+                                     e->stream),
+                      "H2D");
+    }
     // the host vectors must outlive the copies
     check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     e->task_active = active;
+    e->tables_fusion = e->fusion;
 }
 
 // Sample bookkeeping of one xyl_ensemble_step call: observables gathered in
@@ -1818,44 +1900,12 @@ static void ens_step_per_replica(xyl_ensemble* e, uint64_t nsteps, EnsSamples& s
     }
 }
 
-// Large FP32 replicas take two steps per pass in launches of their own when
-// every replica on the tile path qualifies: width a multiple of 256 up to
-// 4096, and at least 2^20 sites, so that one replica's launch fills the GPU
-// (smaller replicas stay in the batched tile launches).
-constexpr size_t kEnsStep2MinSites = size_t(1) << 20;
-
-static bool ens_step2_ok(const xyl_ensemble* e, const std::vector<int>& reps) {
-    if (e->dtype != XYL_F32 || e->fusion != 2) return false;
-    for (int r : reps) {
-        const xyl_replica_desc& d = e->desc[r];
-        if (!step2_shape(d.Lx, d.Ly) || (size_t)d.Lx * (size_t)d.Ly < kEnsStep2MinSites) return false;
-    }
-    return true;
-}
-
-// n4 (a multiple of 4) steps of replica r from launch index j0 on, as pairs of
-// two-step passes (A, u) -> (B, u2) -> (A, u) with A the buffer of the angles
-// at the replica's current step, so that its state ends where it started.
-static void ens_steps2(xyl_ensemble* e, int r, uint64_t j0, uint64_t n4) {
-    e->u2.reserve(sizeof(float) * e->total);
-    const Lat<float> v = e->view<float>(r, e->j);
-    const uint64_t k = e->k[r] + (j0 - e->j);
-    float* A = static_cast<float*>(e->th[k & 1]) + e->off[r];
-    float* B = static_cast<float*>(e->th[(k + 1) & 1]) + e->off[r];
-    float* u = static_cast<float*>(e->u) + e->off[r];
-    float* u2 = reinterpret_cast<float*>(e->u2.p) + e->off[r];
-    const int rows = step2_rows(e->desc[r].Lx, e->desc[r].Ly, e->cus);
-    for (uint64_t i = 0; i < n4; i += 4) {
-        launch_step2(v, A, u, B, u2, rows, nullptr, j0 + i, e->stream);
-        launch_step2(v, B, u2, A, u, rows, nullptr, j0 + i + 2, e->stream);
-    }
-}
-
 // Batched loop: the steps every active replica takes before the next sample
 // or end of any of them form a chunk; large replicas advance through one
 // tile-table launch per step (after the chunk's first step, runs of 4m steps
-// as two-step passes per replica where ens_step2_ok), small FP32 replicas
-// through one whole-in-LDS launch per chunk on a second stream.
+// as batched two-step passes for the FP32 replicas whose width that pass
+// takes), small FP32 replicas through one whole-in-LDS launch per chunk on a
+// second stream.
 template <typename R>
 static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) {
     std::vector<FinalizeJobHost> jobs;
@@ -1920,7 +1970,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
         }
         // large replicas
         if (!active_g.empty()) {
-            if (active_g != e->task_active) ens_upload_table<R>(e, e->j, active_g);
+            if (active_g != e->task_active || e->tables_fusion != e->fusion) ens_upload_table<R>(e, e->j, active_g);
             const Lat<R>* reps = reinterpret_cast<const Lat<R>*>(e->reps.p);
             launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, meas_g.empty() ? kStore : (kStore | kMeasure),
                                     e->model(), e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
@@ -1931,8 +1981,20 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
             uint64_t c = 1;
             if constexpr (std::is_same<R, float>::value) {
                 const uint64_t n4 = (chunk - 1) / 4 * 4;
-                if (n4 && ens_step2_ok(e, active_g)) {
-                    for (int r : active_g) ens_steps2(e, r, e->j + 1, n4);
+                if (n4 && !e->s2cls.empty()) {
+                    e->u2.reserve(sizeof(float) * e->total);
+                    const float* ub = static_cast<const float*>(e->u);
+                    float* u2b = reinterpret_cast<float*>(e->u2.p);
+                    for (uint64_t i = 0; i < n4; i += 4)
+                        for (int ph = 0; ph < 2; ++ph)
+                            for (const auto& cl : e->s2cls)
+                                launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
+                                                      e->model(), ph, ub, u2b, nullptr, e->j + 1 + i + 2 * ph,
+                                                      e->stream);
+                    if (e->ntasks_rest)
+                        for (uint64_t i = 0; i < n4; ++i)
+                            launch_ensemble_step<R>(reps, e->tasks_rest.p, e->ntasks_rest, kStore, e->model(),
+                                                    e->launch.rows, e->launch.wpb, nullptr, e->j + 1 + i, e->stream);
                     c += n4;
                 }
             }

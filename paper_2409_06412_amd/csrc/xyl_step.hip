@@ -328,23 +328,34 @@ struct BRow {          // step-(k+1) angles and velocities of one stage-A row
 
 constexpr int kStep2Slots = 4;
 
-template <int M>
-__global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, const uint64_t* kdev, uint64_t j0,
-                                                int rows) {
+// One strip of a two-step pass: rows [y0, y1) of the lattice v, swept in
+// direction d (+1 top-down, -1 bottom-up), from step k.  rot is the LDS ring
+// (4 slots x 2 x Lx floats).  With PARTIAL the row's width need not be a
+// multiple of 256: lanes past its end work on its last quad (every access in
+// bounds) and store nothing, and the last active lane takes its right
+// neighbour across the row's end like a wave's last lane.
+template <int M, bool PARTIAL>
+__device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buffers& B, int y0, int y1, int d,
+                                            uint64_t k, float* rot) {
     using R = float;
-    extern __shared__ float rot[];   // [slot][s | c][Lx]
     const int Lx = v.Lx, Ly = v.Ly;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
-    const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int y0 = strip * rows;
-    const int y1 = min(y0 + rows, Ly);
-    const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
-    const int x = (wv << 8) + kLaneSites * lane;
-    const bool edgeL = lane == 0, edgeR = lane == kWave - 1;
-    // lane 0: the site left of the wave; lane 63: the site right of it; the
-    // other lanes read a site of their own wave (unused, conflict-free)
-    const int xe = edgeL ? (x == 0 ? Lx - 1 : x - 1) : (edgeR ? (x + 4 == Lx ? 0 : x + 4) : (wv << 8) + lane);
+    const int xl = (wv << 8) + kLaneSites * lane;
+    const bool valid = !PARTIAL || xl < Lx;
+    const int x = valid ? xl : Lx - kLaneSites;
+    const bool edgeL = lane == 0;
+    const bool edgeR = lane == kWave - 1 || (PARTIAL && xl + kLaneSites == Lx);
+    // lane 0: the site left of the wave; the right edge: the site right of it;
+    // the other lanes read a site of their own wave (unused, conflict-free)
+    const int xe = edgeL ? (x == 0 ? Lx - 1 : x - 1)
+                         : (edgeR ? (x + 4 == Lx ? 0 : x + 4) : min((wv << 8) + lane, Lx - 1));
+    // right neighbour of the lane's last site: from the lane above, or the
+    // edge value (DPP hands it to lane 63; a partial row's last lane selects it)
+    auto right_of = [&](float v_above, float edge) {
+        const float r = from_lane_above(v_above, edge);
+        return PARTIAL ? (edgeR ? edge : r) : r;
+    };
     const R hsA = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
     const R hsB = (R)half_sigma(v.sched, v.gamma, v.dtd, k + 1);
     const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
         R se, ce;
         rotor<R, M>(U.e, se, ce);
         const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
-        const R sR = from_lane_above(C.s[0], se), cR = from_lane_above(C.c[0], ce);
+        const R sR = right_of(C.s[0], se), cR = right_of(C.c[0], ce);
         R n[4];
         noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
         R s1[4], c1[4];
@@ -383,9 +394,11 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
             site_update<R, M>(v, f, U.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
             rotor<R, M>(out.t[q], s1[q], c1[q]);
         }
-        float* rs = slot(it);
-        store4(rs + x, s1);
-        store4(rs + Lx + x, c1);
+        if (valid) {
+            float* rs = slot(it);
+            store4(rs + x, s1);
+            store4(rs + Lx + x, c1);
+        }
     };
     // stage B on row y (stage-A values C in registers; the rotors of row y
     // and of its two y-neighbours in the LDS slots of iterations it-1, it-2
@@ -399,7 +412,7 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
         load4(rc + Lx + x, cc);
         const R se = rc[xe], ce = rc[Lx + xe];
         const R sL = from_lane_below(sc[3], se), cL = from_lane_below(cc[3], ce);
-        const R sR = from_lane_above(sc[0], se), cR = from_lane_above(cc[0], ce);
+        const R sR = right_of(sc[0], se), cR = right_of(cc[0], ce);
         R sp[4], cp[4], sn[4], cn[4];
         load4(rp + x, sp);
         load4(rp + Lx + x, cp);
@@ -416,9 +429,11 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
             R w;
             site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
-        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-        store4(B.th_out + row + x, tho);
-        store4(B.u_out + row + x, uo);
+        if (valid) {
+            const uint32_t row = (uint32_t)y * (uint32_t)Lx;
+            store4(B.th_out + row + x, tho);
+            store4(B.u_out + row + x, uo);
+        }
     };
 
     // Even strips run top-down, odd strips bottom-up (the force is symmetric in
@@ -434,7 +449,6 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
     // reloads rows the one before loaded, so that every iteration loads and
     // nothing outside the strip's rows is fetched).
     const int nit = (y1 - y0) + 2;
-    const int d = (strip & 1) ? -1 : 1;
     const int ys = d > 0 ? y0 - 1 : y1;
     auto rowof = [&](int i) { return wrap_y(ys + d * i); };
     TRow<R> T0, T1, T2;
@@ -481,38 +495,112 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
     if (it + 4 < nit) iterate(full, T0, T1, T2, U0, U1, B0, B1, it + 4);
 }
 
-template <int M>
+// The two-step pass of one lattice: strip b = rows [b rows, (b+1) rows), even
+// strips top-down, odd strips bottom-up.
+template <int M, bool PARTIAL>
+__global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, const uint64_t* kdev, uint64_t j0,
+                                                int rows) {
+    extern __shared__ float rot[];   // [slot][s | c][Lx]
+    const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int y0 = strip * rows;
+    const int y1 = min(y0 + rows, v.Ly);
+    const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
+    step2_strip<M, PARTIAL>(v, B, y0, y1, (strip & 1) ? -1 : 1, k, rot);
+}
+
+// The two-step pass of many replicas in one launch: one workgroup per task
+// (replica, strip); every replica of the launch spans the same number of waves.
+// The first pass of a pair (phase 0) reads the angles at step k from
+// th[k & 1] and the velocities from u, and writes the other angle buffer and
+// u2; the second (phase 1) goes back, so that a pair of passes leaves the
+// state where the replica's step parity expects it.  u2 is the replica's
+// velocities' place in a second array: u2_base + (v.u - u_base).
+template <int M, bool PARTIAL>
+__global__ __launch_bounds__(1024) void k_ensemble_step2(const Lat<float>* __restrict__ reps,
+                                                         const Task2* __restrict__ tasks, int phase,
+                                                         const float* u_base, float* u2_base, const uint64_t* kdev,
+                                                         uint64_t j0) {
+    extern __shared__ float rot[];
+    const Task2 t = tasks[xcd_contiguous_block(blockIdx.x, gridDim.x)];
+    const Lat<float>& v = reps[t.rep];
+    const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
+    float* u = v.u;
+    float* u2 = u2_base + (u - u_base);
+    float* tA = v.th[(int)((k + (uint64_t)v.cur + (uint64_t)phase) & 1)];
+    float* tB = v.th[(int)((k + (uint64_t)v.cur + (uint64_t)phase + 1) & 1)];
+    const Step2Buffers B{tA, phase ? u2 : u, tB, phase ? u : u2};
+    step2_strip<M, PARTIAL>(v, B, t.y0, t.y1, t.dir, k, rot);
+}
+
+// the LDS ring of the widest rows (4096 sites: 128 KiB) is allowed once per
+// device and kernel instance, not on every launch
+template <typename F>
+static void allow_step2_lds(F* kernel) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const void*>> allowed;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(mu);
+    if (allowed.count({dev, reinterpret_cast<const void*>(kernel)})) return;
+    const int max_lds = (int)(sizeof(float) * 2 * kStep2Slots * 16 * kWaveSites);
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  max_lds),
+              "hipFuncSetAttribute");
+    allowed.insert({dev, reinterpret_cast<const void*>(kernel)});
+}
+
+template <int M, bool PARTIAL>
 static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows, const uint64_t* kdev, uint64_t j,
                            hipStream_t s) {
-    // the LDS ring of the widest rows (4096 sites: 128 KiB) is allowed once per
-    // device and kernel instance, not on every launch
-    static std::mutex mu;
-    static std::set<int> allowed;
-    {
-        int dev = 0;
-        check_hip(hipGetDevice(&dev), "hipGetDevice");
-        std::lock_guard<std::mutex> lk(mu);
-        if (!allowed.count(dev)) {
-            const int max_lds = (int)(sizeof(float) * 2 * kStep2Slots * 16 * kWaveSites);
-            check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_step2<M>),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, max_lds),
-                      "hipFuncSetAttribute");
-            allowed.insert(dev);
-        }
-    }
+    allow_step2_lds(k_step2<M, PARTIAL>);
     const int nstrips = (v.Ly + rows - 1) / rows;
     const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)v.Lx;
-    k_step2<M><<<nstrips, (v.Lx >> 8) * kWave, lds, s>>>(v, b, kdev, j, rows);
+    const int waves = (v.Lx + kWaveSites - 1) / kWaveSites;
+    k_step2<M, PARTIAL><<<nstrips, waves * kWave, lds, s>>>(v, b, kdev, j, rows);
     check_hip(hipGetLastError(), "two-step kernel launch");
 }
 
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
                   const uint64_t* kdev, uint64_t j, hipStream_t s) {
-    if (v.Lx % kWaveSites != 0 || v.Lx > 16 * kWaveSites || v.Ly < 4 || rows < 1)
-        throw Error(-5, "two-step kernel needs Lx a multiple of 256 up to 4096 and Ly >= 4");
+    if (!step2_width_ok(v.Lx) || v.Ly < 4 || rows < 1)
+        throw Error(-5, "two-step kernel needs a width that fills its last wave to 3/4, up to 4096, and Ly >= 4");
     const Step2Buffers b{th_in, u_in, th_out, u_out};
-    if (v.model == kModelSI) dispatch_step2<kModelSI>(v, b, rows, kdev, j, s);
-    else dispatch_step2<kModelXY>(v, b, rows, kdev, j, s);
+    const bool partial = v.Lx % kWaveSites != 0;
+    if (v.model == kModelSI) {
+        if (partial) dispatch_step2<kModelSI, true>(v, b, rows, kdev, j, s);
+        else dispatch_step2<kModelSI, false>(v, b, rows, kdev, j, s);
+    } else {
+        if (partial) dispatch_step2<kModelXY, true>(v, b, rows, kdev, j, s);
+        else dispatch_step2<kModelXY, false>(v, b, rows, kdev, j, s);
+    }
+}
+
+template <int M, bool PARTIAL>
+static void dispatch_ensemble_step2(const Lat<float>* reps, const Task2* tasks, int ntasks, int waves, int max_lx,
+                                    int phase, const float* u_base, float* u2_base, const uint64_t* kdev, uint64_t j,
+                                    hipStream_t s) {
+    allow_step2_lds(k_ensemble_step2<M, PARTIAL>);
+    const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)max_lx;
+    k_ensemble_step2<M, PARTIAL><<<ntasks, waves * kWave, lds, s>>>(reps, tasks, phase, u_base, u2_base, kdev, j);
+    check_hip(hipGetLastError(), "ensemble two-step kernel launch");
+}
+
+void launch_ensemble_step2(const Lat<float>* reps, const Task2* tasks, int ntasks, int waves, bool partial,
+                           int max_lx, int model, int phase, const float* u_base, float* u2_base,
+                           const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    if (ntasks < 1 || waves < 1 || waves > 16 || max_lx > 16 * kWaveSites)
+        throw Error(-5, "ensemble two-step launch: bad task count or width");
+    if (model == kModelSI) {
+        if (partial) dispatch_ensemble_step2<kModelSI, true>(reps, tasks, ntasks, waves, max_lx, phase, u_base, u2_base,
+                                                             kdev, j, s);
+        else dispatch_ensemble_step2<kModelSI, false>(reps, tasks, ntasks, waves, max_lx, phase, u_base, u2_base,
+                                                      kdev, j, s);
+    } else {
+        if (partial) dispatch_ensemble_step2<kModelXY, true>(reps, tasks, ntasks, waves, max_lx, phase, u_base, u2_base,
+                                                             kdev, j, s);
+        else dispatch_ensemble_step2<kModelXY, false>(reps, tasks, ntasks, waves, max_lx, phase, u_base, u2_base,
+                                                      kdev, j, s);
+    }
 }
 
 // -------------------------------------------- whole replica in LDS (FP32)

@@ -43,6 +43,11 @@ def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None):
     (4096, 4, "xy", 0, [24]),              # the smallest height: two strips whose halos wrap onto each other
     (256, 5, "si", 32, [20]),              # one wave, an odd height (a one-row last strip)
     (2048, 2048, "si", 32, [36]),          # the size rule's 8-row strips, Si model
+    (192, 20, "xy", 32, [44]),             # a partial wave: 48 of 64 lanes
+    (384, 33, "si", 0, [24]),              # a full and a half wave, Si model
+    (448, 64, "xy", 32, [40]),             # 2 waves, the last 48 lanes
+    (640, 17, "xy", 8, [16, 8]),           # 3 waves, the last half full
+    (4000, 10, "xy", 32, [20]),            # 16 waves, the last 40 lanes
 ])
 def test_two_steps_per_pass_equal_single_steps(xyl, Lx, Ly, model, graphs, steps):
     say("fusion", Lx, Ly, model, graphs, steps)
@@ -98,12 +103,12 @@ def test_fusion_keeps_measurement_and_state_buffers(xyl):
 def test_fusion_query_reports_the_mode_in_effect(xyl):
     """xyl_get_fusion: rows per strip where the two-step pass applies (taller
     strips on wider lattices, 2..16 rows), 0 where it does not (FP64, a width
-    that is no multiple of 256 or above 4096, steps_per_pass 1)."""
+    above 4096 or filling less than 3/4 of its last wave, steps_per_pass 1)."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [((4096, 4096, "f32"), True), ((2048, 2048, "f32"), True), ((1024, 1024, "f32"), True),
              ((256, 64, "f32"), True), ((4096, 4096, "f64"), False), ((8192, 64, "f32"), False),
-             ((300, 64, "f32"), False)]
+             ((300, 64, "f32"), False), ((192, 64, "f32"), True), ((320, 64, "f32"), False)]
     for (Lx, Ly, dt), fused in cases:
         lat = xyl.Lattice(Lx, Ly, dtype=dt, schedule=((0, 0.5),), seed=1)
         lat.set_fusion(2)      # a shape tuned earlier in the process may have chosen 1
@@ -133,11 +138,11 @@ def _ensemble_run(xyl, specs, fusion, nsteps, every, states=None):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_ensemble_two_steps_per_pass_equal_batched_single_steps(xyl, mixed):
-    """Large FP32 replicas (width a multiple of 256, >= 2^20 sites) of different
-    parameters, schedules, models' settings and step budgets take two steps per
-    pass between samples; with a small replica on the tile path as well
-    (mixed) every step stays batched.  Both give the same samples and states
-    as one batched launch per step, bit for bit."""
+    """FP32 replicas on the tile path whose width the two-step pass takes, of
+    different shapes, parameters, schedules and step budgets, take batched
+    two-step passes between samples (one launch per class of waves per row);
+    the others keep one tile launch per step, small ones stay whole-in-LDS.
+    The same samples and states as one batched launch per step, bit for bit."""
     specs = [
         workloads.LatticeSpec(1024, 1024, schedule=((0, 0.6), (40, 0.2)), seed=3, replica=0, nsteps=10 ** 6),
         workloads.LatticeSpec(2048, 512, Jx=0.8, h=0.3, schedule=((0, 0.4),), seed=3, replica=1, nsteps=57),
@@ -145,7 +150,14 @@ def test_ensemble_two_steps_per_pass_equal_batched_single_steps(xyl, mixed):
                               nsteps=10 ** 6),
     ]
     if mixed:
-        specs.append(workloads.LatticeSpec(512, 384, schedule=((0, 0.5),), seed=5, replica=3, nsteps=10 ** 6))
+        # both two-step classes (one and two waves, partial ones included), a
+        # width the two-step pass does not take (tile launches alone) and a
+        # whole-in-LDS replica
+        specs += [workloads.LatticeSpec(512, 384, schedule=((0, 0.5),), seed=5, replica=3, nsteps=10 ** 6),
+                  workloads.LatticeSpec(192, 192, schedule=((0, 0.8),), seed=5, replica=4, nsteps=10 ** 6),
+                  workloads.LatticeSpec(384, 96, h=0.25, schedule=((0, 0.3),), seed=5, replica=5, nsteps=70),
+                  workloads.LatticeSpec(320, 40, schedule=((0, 0.6),), seed=5, replica=6, nsteps=10 ** 6),
+                  workloads.LatticeSpec(64, 64, schedule=((0, 0.6),), seed=5, replica=7, nsteps=10 ** 6)]
     rng = np.random.default_rng(11)
     states = {2: (rng.uniform(-np.pi, np.pi, (4096, 256)).astype(np.float32).astype(np.float64),
                   rng.normal(0, 0.5, (4096, 256)).astype(np.float32).astype(np.float64))}
