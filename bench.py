@@ -367,7 +367,7 @@ def cpu_baseline(L, nsteps):
 
 # ----------------------------------------------------------- profile summaries
 STEP_KERNEL = "xyl::k_step<float, 1, 0>"   # single plain store step of the XY model
-STEP2_KERNEL = "xyl::k_step2<0>"           # two steps per pass of the XY model
+STEP2_KERNEL = "xyl::k_step2<0, false>"    # two steps per pass of the XY model (full waves)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -510,6 +510,9 @@ def main():
                     help="comma list of extras to run alone (copy, ensemble, quench, adjoint, domains, control, "
                          "si, si_fss, structure); "
                          "prints their JSON and skips the headline measurement")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch rules instead of autotuning (for profiler runs, whose "
+                         "serialised dispatches distort the autotuner's timings)")
     ap.add_argument("--launch", type=str, default="",
                     help="rows,waves: fixed launch shape of the step kernel (headline, and the si extra) "
                          "instead of autotuning")
@@ -567,6 +570,8 @@ def main():
     del calib
     if fixed:
         lat.set_launch(*fixed)
+        launch = lat.launch()
+    elif args.no_autotune:
         launch = lat.launch()
     else:
         launch = lat.autotune()
