@@ -1697,6 +1697,22 @@ struct xyl_ensemble {
     DevBuf<Task> tasks_rest;
     int ntasks_rest = 0;
     DevBuf<char> u2;                // second velocity buffer, allocated on first use
+    // the classes hold different replicas: all but the first run on streams of
+    // their own (default priority), forked from and joined to the ensemble's
+    std::vector<hipStream_t> cls_streams;
+    std::vector<hipEvent_t> cls_events;   // [0] fork, [1 + i] join of class i + 1
+    void class_streams(size_t ncls) {
+        while (cls_streams.size() + 1 < ncls) {
+            hipStream_t st = nullptr;
+            check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+            cls_streams.push_back(st);
+        }
+        while (cls_events.size() < ncls) {
+            hipEvent_t ev = nullptr;
+            check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+            cls_events.push_back(ev);
+        }
+    }
 
     template <typename R>
     Lat<R> view(int r, uint64_t jbase) {
@@ -1985,12 +2001,26 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                     e->u2.reserve(sizeof(float) * e->total);
                     const float* ub = static_cast<const float*>(e->u);
                     float* u2b = reinterpret_cast<float*>(e->u2.p);
-                    for (uint64_t i = 0; i < n4; i += 4)
-                        for (int ph = 0; ph < 2; ++ph)
-                            for (const auto& cl : e->s2cls)
+                    const size_t ncls = e->s2cls.size();
+                    e->class_streams(ncls);
+                    if (ncls > 1) {
+                        check_hip(hipEventRecord(e->cls_events[0], e->stream), "hipEventRecord");
+                        for (size_t c2 = 1; c2 < ncls; ++c2)
+                            check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
+                                      "hipStreamWaitEvent");
+                    }
+                    for (size_t c2 = 0; c2 < ncls; ++c2) {
+                        const auto& cl = e->s2cls[c2];
+                        hipStream_t st = c2 == 0 ? e->stream : e->cls_streams[c2 - 1];
+                        for (uint64_t i = 0; i < n4; i += 4)
+                            for (int ph = 0; ph < 2; ++ph)
                                 launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
-                                                      e->model(), ph, ub, u2b, nullptr, e->j + 1 + i + 2 * ph,
-                                                      e->stream);
+                                                      e->model(), ph, ub, u2b, nullptr, e->j + 1 + i + 2 * ph, st);
+                    }
+                    for (size_t c2 = 1; c2 < ncls; ++c2) {
+                        check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
+                        check_hip(hipStreamWaitEvent(e->stream, e->cls_events[c2], 0), "hipStreamWaitEvent");
+                    }
                     if (e->ntasks_rest)
                         for (uint64_t i = 0; i < n4; ++i)
                             launch_ensemble_step<R>(reps, e->tasks_rest.p, e->ntasks_rest, kStore, e->model(),
@@ -2196,9 +2226,12 @@ int xyl_ensemble_destroy(xyl_ensemble* e) {
         for (int b = 0; b < 2; ++b)
             if (e->th[b]) (void)hipFree(e->th[b]);
         if (e->u) (void)hipFree(e->u);
+        for (hipStream_t st : e->cls_streams) (void)hipStreamSynchronize(st);
         if (e->side) (void)hipStreamDestroy(e->side);
         if (e->ev_main) (void)hipEventDestroy(e->ev_main);
         if (e->ev_side) (void)hipEventDestroy(e->ev_side);
+        for (hipStream_t st : e->cls_streams) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : e->cls_events) (void)hipEventDestroy(ev);
         delete e;
     });
 }
