@@ -229,9 +229,10 @@ int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
 /* Steps per pass over the state for plain FP32 stepping (1 or 2; default 2).
  * With 2, runs of 4m steps without measurements advance two steps per pass
  * (one workgroup per strip of rows across the whole width, the second step
- * one row behind the first) where Lx is at most 4096 and fills at least
- * three quarters of its last wave of 256 sites, and Ly >= 4; other shapes,
- * FP64 and measurement steps use single steps.
+ * one row behind the first) where Lx is at most 4096, uses at least three
+ * quarters of the lanes of its waves (256 sites per wave) and at least two
+ * lanes of the last, and Ly >= 4; other shapes, FP64 and measurement steps
+ * use single steps.
  * Results are bitwise identical either way; two steps per pass read and write
  * the state once per two steps.  The library allocates a second velocity
  * buffer (4 Lx Ly bytes) on first use; the state returns to the lattice's own
@@ -337,8 +338,8 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
 int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
 /* Steps per pass for the batched mode (1 or 2; default 2).  With 2 (FP32),
  * runs of 4m steps between samples advance the replicas on the tile path
- * whose width the two-step pass takes (up to 4096, the last wave of 256 sites
- * at least three quarters full, Ly >= 4) two steps per pass, in one launch
+ * whose width the two-step pass takes (as for xyl_set_fusion) two steps per
+ * pass, in one launch
  * per pass for each class of replicas of the same number of waves per row;
  * the other tile-path replicas keep one batched tile launch per step.
  * Results are bitwise identical either way.  The library allocates a second

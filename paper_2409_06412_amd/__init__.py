@@ -250,8 +250,8 @@ class Lattice:
 
     def set_fusion(self, steps_per_pass: int):
         """1: one step per pass over the state; 2: two (FP32, width up to 4096
-        filling at least 3/4 of its last wave of 256 sites); results are
-        identical."""
+        using at least 3/4 of the lanes of its waves of 256 sites and two of
+        the last); results are identical."""
         _check(load().xyl_set_fusion(self._h, int(steps_per_pass)))
 
     def fusion(self):

@@ -86,12 +86,15 @@ struct Task2 {
     int32_t rep, y0, y1, dir;
 };
 
-// Widths the two-step pass takes: up to 4096 sites (16 waves of 256), the
-// last wave at least three quarters full (lanes past the row's end idle).
+// Widths the two-step pass takes: up to 4096 sites (16 waves of 256), at
+// least three quarters of the waves' lanes in use (lanes past the row's end
+// idle), and at least two lanes in the last wave, whose first and last lanes
+// take the row's two outer neighbours.
 inline bool step2_width_ok(int Lx) {
-    if (Lx < 4 || Lx % 4 != 0 || Lx > 16 * kWaveSites) return false;
+    if (Lx % 4 != 0 || Lx > 16 * kWaveSites) return false;
     const int waves = (Lx + kWaveSites - 1) / kWaveSites;
-    return 4 * Lx >= 3 * waves * kWaveSites;
+    const int last = Lx - (waves - 1) * kWaveSites;   // sites in the last wave
+    return last >= 2 * kLaneSites && 4 * Lx >= 3 * waves * kWaveSites;
 }
 
 // ------------------------------------------------------------- launchers

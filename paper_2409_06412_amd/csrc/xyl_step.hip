@@ -333,7 +333,9 @@ constexpr int kStep2Slots = 4;
 // (4 slots x 2 x Lx floats).  With PARTIAL the row's width need not be a
 // multiple of 256: lanes past its end work on its last quad (every access in
 // bounds) and store nothing, and the last active lane takes its right
-// neighbour across the row's end like a wave's last lane.
+// neighbour across the row's end like a wave's last lane.  The last wave has
+// at least two active lanes (step2_width_ok), so no lane is both the left and
+// the right edge.
 template <int M, bool PARTIAL>
 __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buffers& B, int y0, int y1, int d,
                                             uint64_t k, float* rot) {
