@@ -90,6 +90,32 @@ struct Task2 {
 // least three quarters of the waves' lanes in use (lanes past the row's end
 // idle), and at least two lanes in the last wave, whose first and last lanes
 // take the row's two outer neighbours.
+// A width wider than one workgroup's 16 waves is split into the fewest column
+// tiles ntx of w columns (the last takes the rest), each workgroup covering
+// its tile and one quad on each side (w + 8 <= 4096 sites).  No tile may leave
+// a single lane in its last wave.  Returns false if Lx needs no tiles or none
+// fit.  Tiles of up to kStep2SmallTileWaves waves run in a kernel instance
+// bounded to that many (so the compiler may use more registers per lane).
+constexpr int kStep2SmallTileWaves = 11;
+struct Step2Tiles {
+    int ntx = 0, w = 0;
+};
+inline bool step2_tiles(int Lx, Step2Tiles* t) {
+    constexpr int kMax = 16 * kWaveSites;
+    if (Lx <= kMax || Lx % 4 != 0) return false;
+    auto lanes_ok = [](int W) { return W % kWaveSites == 0 || W % kWaveSites >= 2 * kLaneSites; };
+    for (int ntx = (Lx + kMax - 9) / (kMax - 8); ntx <= 64; ++ntx) {
+        const int w = ((Lx + ntx - 1) / ntx + 3) / 4 * 4;
+        const int wl = Lx - (ntx - 1) * w;
+        if (w + 8 <= kMax && wl >= 4 && lanes_ok(w + 8) && lanes_ok(wl + 8)) {
+            t->ntx = ntx;
+            t->w = w;
+            return true;
+        }
+    }
+    return false;
+}
+
 inline bool step2_width_ok(int Lx) {
     if (Lx % 4 != 0 || Lx > 16 * kWaveSites) return false;
     const int waves = (Lx + kWaveSites - 1) / kWaveSites;
@@ -107,6 +133,7 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
 // Two steps per pass (FP32; Lx a multiple of 256 up to 4096, Ly >= 4): angles
 // and velocities at step k are read from th_in / u_in and those at k+2
 // written to th_out / u_out (distinct buffers); k = v.k_base + j (+ *kdev).
+// Widths above 4096 run as column tiles (step2_tiles); rows per strip as given.
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
                   const uint64_t* kdev, uint64_t j, hipStream_t s);
 // Two steps per pass of many FP32 replicas (reps: the table of their views,

@@ -390,8 +390,13 @@ static hipGraphExec_t capture_steps(xyl_lattice* h, const Lat<R>& v, int mode, i
 
 // Two steps per pass (FP32 plain stepping, width a multiple of 256 up to 4096).
 static bool step2_shape(int Lx, int Ly) { return step2_width_ok(Lx) && Ly >= 4; }
+// single lattices also take widths above 4096, as column tiles
+static bool step2_lattice_shape(int Lx, int Ly) {
+    Step2Tiles t;
+    return Ly >= 4 && (step2_width_ok(Lx) || step2_tiles(Lx, &t));
+}
 static bool step2_eligible(const xyl_lattice* h) {
-    return h->dtype == XYL_F32 && h->fusion == 2 && step2_shape(h->Lx, h->Ly);
+    return h->dtype == XYL_F32 && h->fusion == 2 && step2_lattice_shape(h->Lx, h->Ly);
 }
 
 // Rows per strip of the two-step kernel.  A workgroup spans the row (Lx / 256
@@ -403,6 +408,25 @@ static bool step2_eligible(const xyl_lattice* h) {
 // 4096 x 1024, 1024 x 4096 and 256 x 8192 (strip counts off a multiple of the
 // CU count leave a partial last round of workgroups).
 static int step2_rows(int Lx, int Ly, int cus) {
+    Step2Tiles t;
+    if (step2_tiles(Lx, &t)) {
+        // column tiles (one workgroup of up to 11 waves per CU at a time): the
+        // workgroup count is large, so the last round of workgroups matters.
+        // Score = rows / (rows + 1) (the halo rows' share of the work) times
+        // the fraction of the last round that is filled.
+        int best = 16;
+        double best_score = -1.0;
+        for (int rows = 16; rows >= 2; rows /= 2) {
+            const long wgs = (long)((Ly + rows - 1) / rows) * t.ntx;
+            const long rounds = (wgs + cus - 1) / cus;
+            const double score = (double)rows / (rows + 1) * (double)wgs / (double)(rounds * cus);
+            if (score > best_score + 1e-9) {
+                best_score = score;
+                best = rows;
+            }
+        }
+        return best;
+    }
     const int waves = (Lx + kWaveSites - 1) / kWaveSites;
     const int per_cu = std::max(1, std::min(16 / waves, (160 * 1024) / (32 * Lx)));
     const int strips = cus * std::max(1, per_cu / 2);
@@ -1315,7 +1339,7 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
     *fusion = 1;
     *rows2 = 0;
     if constexpr (std::is_same<R, float>::value) {
-        if (step2_shape(h->Lx, h->Ly)) {
+        if (step2_lattice_shape(h->Lx, h->Ly)) {
             const int reps4 = (reps + 3) / 4 * 4;
             float* A = v.th[0];
             float* B = v.th[1];

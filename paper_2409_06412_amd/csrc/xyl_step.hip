@@ -330,45 +330,60 @@ constexpr int kStep2Slots = 4;
 
 // One strip of a two-step pass: rows [y0, y1) of the lattice v, swept in
 // direction d (+1 top-down, -1 bottom-up), from step k.  rot is the LDS ring
-// (4 slots x 2 x Lx floats).  With PARTIAL the row's width need not be a
-// multiple of 256: lanes past its end work on its last quad (every access in
-// bounds) and store nothing, and the last active lane takes its right
-// neighbour across the row's end like a wave's last lane.  The last wave has
-// at least two active lanes (step2_width_ok), so no lane is both the left and
-// the right edge.
-template <int M, bool PARTIAL>
+// (4 slots x 2 x W floats).
+//  * Whole rows (TILE false, xs = 0, W = Lx).  With PARTIAL the width need not
+//    be a multiple of 256: lanes past the row's end work on its last quad
+//    (every access in bounds) and store nothing, and the last active lane takes
+//    its right neighbour across the row's end like a wave's last lane.  The
+//    last wave has at least two active lanes (step2_width_ok), so no lane is
+//    both the left and the right edge.
+//  * A column tile of a wider row (TILE): the workgroup covers the W sites from
+//    global column xs (wrapped; xs and W multiples of 4): the tile's own
+//    columns and one quad on each side.  Stage A runs on all of them; stage B
+//    stores all but the two outer quads, whose second step the neighbouring
+//    tiles compute.  Every stored site so sees the same inputs as in single
+//    steps.
+template <int M, bool PARTIAL, bool TILE = false>
 __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buffers& B, int y0, int y1, int d,
-                                            uint64_t k, float* rot) {
+                                            uint64_t k, float* rot, int xs = 0, int W = 0) {
     using R = float;
     const int Lx = v.Lx, Ly = v.Ly;
+    const int Wd = TILE ? W : Lx;                    // sites the workgroup covers
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
     const int xl = (wv << 8) + kLaneSites * lane;
-    const bool valid = !PARTIAL || xl < Lx;
-    const int x = valid ? xl : Lx - kLaneSites;
+    const bool valid = !(PARTIAL || TILE) || xl < Wd;
+    const int x = valid ? xl : Wd - kLaneSites;      // local column of the lane's quad
+    auto wrap_x = [&](int g) { return g < 0 ? g + Lx : (g >= Lx ? g - Lx : g); };
+    const int gx = TILE ? wrap_x(xs + x) : x;        // its global column
     const bool edgeL = lane == 0;
-    const bool edgeR = lane == kWave - 1 || (PARTIAL && xl + kLaneSites == Lx);
-    // lane 0: the site left of the wave; the right edge: the site right of it;
-    // the other lanes read a site of their own wave (unused, conflict-free)
-    const int xe = edgeL ? (x == 0 ? Lx - 1 : x - 1)
-                         : (edgeR ? (x + 4 == Lx ? 0 : x + 4) : min((wv << 8) + lane, Lx - 1));
+    const bool edgeR = lane == kWave - 1 || ((PARTIAL || TILE) && xl + kLaneSites == Wd);
+    // global column of the lane's outer neighbour (lane 0: left of the wave;
+    // the right edge: right of it; other lanes: a site of their own, unused)
+    const int xe = edgeL ? (TILE ? wrap_x(gx - 1) : (x == 0 ? Lx - 1 : x - 1))
+                         : (edgeR ? (TILE ? wrap_x(gx + 4) : (x + 4 == Lx ? 0 : x + 4))
+                                  : (TILE ? gx : min((wv << 8) + lane, Lx - 1)));
+    // the same neighbour in the LDS ring (local columns; a tile's two outer
+    // quads store no second step, so theirs is any column in range)
+    const int xel = TILE ? (edgeL ? (x == 0 ? 0 : x - 1) : (edgeR ? (x + 4 == Wd ? Wd - 1 : x + 4) : x)) : xe;
+    const bool store_b = valid && (!TILE || (x != 0 && x + kLaneSites != Wd));
     // right neighbour of the lane's last site: from the lane above, or the
     // edge value (DPP hands it to lane 63; a partial row's last lane selects it)
     auto right_of = [&](float v_above, float edge) {
         const float r = from_lane_above(v_above, edge);
-        return PARTIAL ? (edgeR ? edge : r) : r;
+        return (PARTIAL || TILE) ? (edgeR ? edge : r) : r;
     };
     const R hsA = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
     const R hsB = (R)half_sigma(v.sched, v.gamma, v.dtd, k + 1);
     const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
     auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
-    auto slot = [&](int it) { return rot + (size_t)(it & (kStep2Slots - 1)) * 2 * Lx; };
+    auto slot = [&](int it) { return rot + (size_t)(it & (kStep2Slots - 1)) * 2 * Wd; };
 
-    auto load_th = [&](TRow<R>& T, int y) { load4(B.th_in + (uint32_t)y * (uint32_t)Lx + x, T.th); };
+    auto load_th = [&](TRow<R>& T, int y) { load4(B.th_in + (uint32_t)y * (uint32_t)Lx + gx, T.th); };
     auto load_u = [&](URow<R>& U, int y) {
         const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-        load4(B.u_in + row + x, U.u);
+        load4(B.u_in + row + gx, U.u);
         U.e = B.th_in[row + xe];
     };
     auto trig = [&](TRow<R>& T) {
@@ -385,7 +400,7 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
         const R sR = right_of(C.s[0], se), cR = right_of(C.c[0], ce);
         R n[4];
-        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
         R s1[4], c1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -399,7 +414,7 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         if (valid) {
             float* rs = slot(it);
             store4(rs + x, s1);
-            store4(rs + Lx + x, c1);
+            store4(rs + Wd + x, c1);
         }
     };
     // stage B on row y (stage-A values C in registers; the rotors of row y
@@ -411,17 +426,17 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         const float* rn = slot(it);
         R sc[4], cc[4];
         load4(rc + x, sc);
-        load4(rc + Lx + x, cc);
-        const R se = rc[xe], ce = rc[Lx + xe];
+        load4(rc + Wd + x, cc);
+        const R se = rc[xel], ce = rc[Wd + xel];
         const R sL = from_lane_below(sc[3], se), cL = from_lane_below(cc[3], ce);
         const R sR = right_of(sc[0], se), cR = right_of(cc[0], ce);
         R sp[4], cp[4], sn[4], cn[4];
         load4(rp + x, sp);
-        load4(rp + Lx + x, cp);
+        load4(rp + Wd + x, cp);
         load4(rn + x, sn);
-        load4(rn + Lx + x, cn);
+        load4(rn + Wd + x, cn);
         R n[4];
-        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n);
         R tho[4], uo[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -431,10 +446,10 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
             R w;
             site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
-        if (valid) {
+        if (store_b) {
             const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-            store4(B.th_out + row + x, tho);
-            store4(B.u_out + row + x, uo);
+            store4(B.th_out + row + gx, tho);
+            store4(B.u_out + row + gx, uo);
         }
     };
 
@@ -510,6 +525,22 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
     step2_strip<M, PARTIAL>(v, B, y0, y1, (strip & 1) ? -1 : 1, k, rot);
 }
 
+// The two-step pass of a lattice wider than 4096: each strip is split into ntx
+// column tiles of w columns (the last takes the rest); workgroup b covers tile
+// b % ntx of strip b / ntx and one quad on each side.
+template <int M, int MAXW>
+__global__ __launch_bounds__(MAXW * kWave) void k_step2_tiled(Lat<float> v, Step2Buffers B, const uint64_t* kdev,
+                                                             uint64_t j0, int rows, int ntx, int w) {
+    extern __shared__ float rot[];   // [slot][s | c][w + 8]
+    const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int strip = b / ntx, tx = b - strip * ntx;
+    const int y0 = strip * rows;
+    const int y1 = min(y0 + rows, v.Ly);
+    const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
+    const int wt = tx == ntx - 1 ? v.Lx - tx * w : w;
+    step2_strip<M, true, true>(v, B, y0, y1, (strip & 1) ? -1 : 1, k, rot, tx * w - kLaneSites, wt + 2 * kLaneSites);
+}
+
 // The two-step pass of many replicas in one launch: one workgroup per task
 // (replica, strip); every replica of the launch spans the same number of waves.
 // The first pass of a pair (phase 0) reads the angles at step k from
@@ -562,11 +593,36 @@ static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows,
     check_hip(hipGetLastError(), "two-step kernel launch");
 }
 
+template <int M>
+static void dispatch_step2_tiled(const Lat<float>& v, const Step2Buffers& b, int rows, const Step2Tiles& t,
+                                 const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    const int nstrips = (v.Ly + rows - 1) / rows;
+    const int W = t.w + 2 * kLaneSites;
+    const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)W;
+    const int waves = (W + kWaveSites - 1) / kWaveSites;
+    if (waves <= kStep2SmallTileWaves) {
+        allow_step2_lds(k_step2_tiled<M, kStep2SmallTileWaves>);
+        k_step2_tiled<M, kStep2SmallTileWaves>
+            <<<nstrips * t.ntx, waves * kWave, lds, s>>>(v, b, kdev, j, rows, t.ntx, t.w);
+    } else {
+        allow_step2_lds(k_step2_tiled<M, 16>);
+        k_step2_tiled<M, 16><<<nstrips * t.ntx, waves * kWave, lds, s>>>(v, b, kdev, j, rows, t.ntx, t.w);
+    }
+    check_hip(hipGetLastError(), "tiled two-step kernel launch");
+}
+
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
                   const uint64_t* kdev, uint64_t j, hipStream_t s) {
-    if (!step2_width_ok(v.Lx) || v.Ly < 4 || rows < 1)
-        throw Error(-5, "two-step kernel needs a width that fills its last wave to 3/4, up to 4096, and Ly >= 4");
+    if (v.Ly < 4 || rows < 1) throw Error(-5, "two-step kernel needs Ly >= 4");
     const Step2Buffers b{th_in, u_in, th_out, u_out};
+    Step2Tiles t;
+    if (step2_tiles(v.Lx, &t)) {
+        if (v.model == kModelSI) dispatch_step2_tiled<kModelSI>(v, b, rows, t, kdev, j, s);
+        else dispatch_step2_tiled<kModelXY>(v, b, rows, t, kdev, j, s);
+        return;
+    }
+    if (!step2_width_ok(v.Lx))
+        throw Error(-5, "two-step kernel: width must use 3/4 of its waves' lanes and two of the last, or exceed 4096");
     const bool partial = v.Lx % kWaveSites != 0;
     if (v.model == kModelSI) {
         if (partial) dispatch_step2<kModelSI, true>(v, b, rows, kdev, j, s);

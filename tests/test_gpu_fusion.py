@@ -52,6 +52,10 @@ def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None):
     (1020, 19, "si", 0, [16]),             # 4 waves, the last 63 lanes
     (4092, 6, "xy", 32, [12]),             # 16 waves, the last 63 lanes
     (196, 33, "xy", 8, [20]),              # one wave of 49 lanes
+    (4100, 9, "xy", 32, [24]),             # wider than 16 waves: two column tiles with one-quad halos
+    (5000, 7, "si", 0, [16]),              # two tiles, Si model
+    (8192, 12, "xy", 32, [20]),            # three tiles
+    (12288, 6, "xy", 8, [12, 8]),          # four tiles
 ])
 def test_two_steps_per_pass_equal_single_steps(xyl, Lx, Ly, model, graphs, steps):
     say("fusion", Lx, Ly, model, graphs, steps)
@@ -106,15 +110,16 @@ def test_fusion_keeps_measurement_and_state_buffers(xyl):
 
 def test_fusion_query_reports_the_mode_in_effect(xyl):
     """xyl_get_fusion: rows per strip where the two-step pass applies (taller
-    strips on wider lattices, 2..16 rows), 0 where it does not (FP64, a width
-    above 4096, using less than 3/4 of its waves' lanes or a single lane of the
-    last wave, steps_per_pass 1)."""
+    strips on wider lattices, 2..16 rows), 0 where it does not (FP64, a width up
+    to 4096 using less than 3/4 of its waves' lanes or a single lane of the last
+    wave, steps_per_pass 1); widths above 4096 run as column tiles."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [((4096, 4096, "f32"), True), ((2048, 2048, "f32"), True), ((1024, 1024, "f32"), True),
-             ((256, 64, "f32"), True), ((4096, 4096, "f64"), False), ((8192, 64, "f32"), False),
+             ((256, 64, "f32"), True), ((4096, 4096, "f64"), False), ((8192, 64, "f64"), False),
              ((300, 64, "f32"), False), ((192, 64, "f32"), True), ((320, 64, "f32"), False),
-             ((772, 64, "f32"), False), ((2052, 64, "f32"), False), ((776, 64, "f32"), True)]
+             ((772, 64, "f32"), False), ((2052, 64, "f32"), False), ((776, 64, "f32"), True),
+             ((8200, 64, "f32"), True)]
     for (Lx, Ly, dt), fused in cases:
         lat = xyl.Lattice(Lx, Ly, dtype=dt, schedule=((0, 0.5),), seed=1)
         lat.set_fusion(2)      # a shape tuned earlier in the process may have chosen 1
