@@ -150,11 +150,49 @@ def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
         ens.sync()
         out[name] = time.perf_counter() - t0
         ens.close()
+    out.update(bench_solo_lattices(torch, xyl, specs, nsteps, every))
     sites = sum(s.Lx * s.Ly for s in specs)
     return {"replicas": len(specs), "sites": sites, "steps": nsteps, "sample_every": every,
             "batched_site_updates_per_s": sites * nsteps / out["batched"],
             "per_replica_site_updates_per_s": sites * nsteps / out["per_replica"],
-            "speedup": out["per_replica"] / out["batched"]}
+            "speedup": out["per_replica"] / out["batched"],
+            # the replicas as separate lattices through the single-lattice path
+            # (graph-captured steps): one after the other with their samples,
+            # and all at once on a stream each (plain stepping, no samples)
+            "solo_sequential_site_updates_per_s": sites * nsteps / out["solo_sequential"],
+            "solo_concurrent_streams_site_updates_per_s": sites * nsteps / out["solo_concurrent"],
+            "speedup_over_solo_sequential": out["solo_sequential"] / out["batched"],
+            "speedup_over_solo_concurrent_streams": out["solo_concurrent"] / out["batched"]}
+
+
+def bench_solo_lattices(torch, xyl, specs, nsteps, every):
+    """The ensemble's replicas as separate single lattices: seconds for nsteps
+    steps of every replica run one after the other, sampled every `every`
+    steps, and for nsteps plain steps of all of them issued together, each
+    lattice on a stream of its own (default priority)."""
+    streams = [torch.cuda.Stream() for _ in specs]
+    lats = []
+    try:
+        for sp, st in zip(specs, streams):
+            lat = xyl.Lattice(sp.Lx, sp.Ly, dtype="f32", schedule=sp.schedule, seed=sp.seed, replica=sp.replica,
+                              stream=st.cuda_stream, **sp.params())
+            lat.init_random()
+            lat.step(2 * every)          # captures the lattice's step graphs
+            lats.append(lat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lat in lats:
+            lat.step_measured(nsteps, every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for lat in lats:
+            lat.step(nsteps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        for lat in lats:
+            lat.close()
+    return {"solo_sequential": t1 - t0, "solo_concurrent": t2 - t1}
 
 
 def bench_quench(torch, xyl, workloads, nsteps):
