@@ -39,6 +39,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -364,6 +365,35 @@ def bench_domains(torch, xyl):
     t1 = time.perf_counter()
     lat.close()
     return {"L": 2048, "seconds": t1 - t0, "n_domains": int(nd), "max_size": int(mx)}
+
+
+def device_info(torch):
+    """What the device reports about itself: torch's properties and `amd-smi
+    static` (ASIC, memory and clock levels), beside the published peaks the
+    roofline uses.  Fields amd-smi does not give are left out."""
+    p = torch.cuda.get_device_properties(0)
+    out = {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+           "memory_bytes": p.total_memory}
+    try:
+        r = subprocess.run(["amd-smi", "static", "--asic", "--vram", "--clock", "--json"], capture_output=True,
+                           text=True, timeout=60)
+        g = json.loads(r.stdout)["gpu_data"][0]
+        asic, vram, clk = g.get("asic", {}), g.get("vram", {}), g.get("clock", {})
+        smi = {"market_name": asic.get("market_name"), "compute_units": asic.get("num_compute_units"),
+               "target": asic.get("target_graphics_version"), "vram_type": vram.get("type"),
+               "vram_bit_width": vram.get("bit_width"),
+               "vram_max_bandwidth_GBs": (vram.get("max_bandwidth") or {}).get("value")}
+        levels = (clk.get("sys") or {}).get("frequency_levels") or {}
+        mhz = [float(v.split()[0]) for v in levels.values() if v.split()[0].replace(".", "").isdigit()]
+        if mhz:
+            smi["sclk_max_MHz"] = max(mhz)
+            if smi["compute_units"]:
+                # one wave64 VALU instruction per SIMD every 4 cycles, 4 SIMDs per CU
+                smi["valu_issue_peak_G_per_s"] = smi["compute_units"] * 4 * max(mhz) * 1e-3 / 4
+        out["amd_smi"] = smi
+    except Exception as e:          # amd-smi missing or its output not as expected
+        out["amd_smi"] = {"error": repr(e)[:200]}
+    return out
 
 
 def cpu_baseline(L, nsteps):
@@ -706,6 +736,7 @@ def main():
                    "steps_per_pass": fusion[0], "rows_per_strip": fusion[1]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "device": device_info(torch),
     }
     # the metric's "% HBM roofline": site-updates/s x 16 B per site-update over
     # 8 TB/s (above 100 when two steps share one pass over the state)
