@@ -431,7 +431,27 @@ def cpu_baseline(L, nsteps):
     t = time.perf_counter() - t0
     out["small_fp64_full"] = {"seconds": t, "value": 64 * 64 * s0.nsteps / t,
                               "sample": "64x64, 10,000 steps, observables every 100"}
+    out["host"] = host_info()
     return out
+
+
+def host_info():
+    """The host the oracle ran on: CPU model, logical CPUs, and those this
+    process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 # ----------------------------------------------------------- profile summaries
