@@ -229,10 +229,12 @@ int xyl_set_graph_steps(xyl_lattice* h, int32_t steps);
 /* Steps per pass over the state for plain FP32 stepping (1 or 2; default 2).
  * With 2, runs of 4m steps without measurements advance two steps per pass
  * (one workgroup per strip of rows across the whole width, the second step
- * one row behind the first) where Lx is at most 4096, uses at least three
- * quarters of the lanes of its waves (256 sites per wave) and at least two
- * lanes of the last, and Ly >= 4; other shapes, FP64 and measurement steps
- * use single steps.
+ * one row behind the first) where Ly >= 4 and Lx is at most 4096, uses at
+ * least three quarters of the lanes of its waves (256 sites per wave) and at
+ * least two lanes of the last.  Wider rows (Lx a multiple of 4) run as the
+ * fewest column tiles that fit one workgroup with one quad of halo on each
+ * side (at most 4096 sites) under the same lane rules, where such a split
+ * exists.  Other shapes, FP64 and measurement steps use single steps.
  * Results are bitwise identical either way; two steps per pass read and write
  * the state once per two steps.  The library allocates a second velocity
  * buffer (4 Lx Ly bytes) on first use; the state returns to the lattice's own
