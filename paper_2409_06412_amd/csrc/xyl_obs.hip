@@ -319,6 +319,22 @@ __global__ void k_uf_label(int32_t* parent, size_t N) {
     parent[i] = uf_find(parent, (int32_t)i);
 }
 
+// The size distribution as (size, count) pairs: every nonzero histogram entry
+// hist[sz], sz = 1..N, appends one pair after stats[0..3] (stats[2] counts
+// them; the order is arbitrary).  Distinct sizes sum to at most N, so there
+// are at most `cap` >= sqrt(2 N) of them.
+__global__ void k_uf_sizes(const uint32_t* __restrict__ hist, uint32_t* stats, size_t N, uint32_t cap) {
+    const size_t sz = (size_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (sz > N) return;
+    const uint32_t c = hist[sz];
+    if (c == 0u) return;
+    const uint32_t j = atomicAdd(stats + 2, 1u);
+    if (j < cap) {
+        stats[kDomainPairs + 2 * (size_t)j] = (uint32_t)sz;
+        stats[kDomainPairs + 2 * (size_t)j + 1] = c;
+    }
+}
+
 template <typename R>
 void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
                     uint32_t* hist,
@@ -335,6 +351,8 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
     check_hip(hipGetLastError(), "uf finish launch");
     k_uf_label<<<nb, 256, 0, s>>>(parent, N);
     check_hip(hipGetLastError(), "uf label launch");
+    k_uf_sizes<<<nb, 256, 0, s>>>(hist, stats, N, domain_size_cap(N));
+    check_hip(hipGetLastError(), "uf sizes launch");
 }
 
 template void launch_correlation<float>(const float*, int, int, int, int, int, int, int, double*, double*,

@@ -636,30 +636,30 @@ static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, 
                         uint64_t* sizes, uint64_t* counts, uint64_t cap, uint64_t* n_sizes, uint64_t* n_domains,
                         uint64_t* max_size) {
     const size_t N = (size_t)Lx * Ly;
+    const uint32_t pcap = domain_size_cap(N);
+    const size_t nst = kDomainPairs + 2 * (size_t)pcap;
     parent.reserve(N);
     usz.reserve(N);
     hist.reserve(N + 1);
-    stats.reserve(2);
+    stats.reserve(nst);
     check_hip(hipMemsetAsync(hist.p, 0, sizeof(uint32_t) * (N + 1), s), "hipMemsetAsync");
-    check_hip(hipMemsetAsync(stats.p, 0, sizeof(uint32_t) * 2, s), "hipMemsetAsync");
+    check_hip(hipMemsetAsync(stats.p, 0, sizeof(uint32_t) * kDomainPairs, s), "hipMemsetAsync");
     launch_domains<R>(th, Lx, Ly, sx, sy, model, parent.p, usz.p, hist.p, stats.p, s);
-    std::vector<uint32_t> hh(N + 1);
-    uint32_t st[2];
-    check_hip(hipMemcpyAsync(hh.data(), hist.p, sizeof(uint32_t) * (N + 1), hipMemcpyDeviceToHost, s), "D2H");
-    check_hip(hipMemcpyAsync(st, stats.p, sizeof(st), hipMemcpyDeviceToHost, s), "D2H");
+    // the (size, count) pairs were compacted on the device: only they come back
+    std::vector<uint32_t> st(nst);
+    check_hip(hipMemcpyAsync(st.data(), stats.p, sizeof(uint32_t) * nst, hipMemcpyDeviceToHost, s), "D2H");
     if (labels) check_hip(hipMemcpyAsync(labels, parent.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s), "D2H");
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    uint64_t ns = 0;
-    for (size_t sz = 1; sz <= N; ++sz)
-        if (hh[sz]) ++ns;
+    const uint64_t ns = st[2];
+    require(ns >= 1 && ns <= pcap, XYL_EDEVICE, "domain size distribution overflowed its bound");
+    std::vector<std::pair<uint32_t, uint32_t>> pairs(ns);
+    for (uint64_t j = 0; j < ns; ++j) pairs[j] = {st[kDomainPairs + 2 * j], st[kDomainPairs + 2 * j + 1]};
+    std::sort(pairs.begin(), pairs.end());
     if (sizes || counts) require(cap >= ns, XYL_EINVAL, "size-distribution capacity too small");
-    uint64_t j = 0;
-    for (size_t sz = 1; sz <= N; ++sz)
-        if (hh[sz]) {
-            if (sizes) sizes[j] = sz;
-            if (counts) counts[j] = hh[sz];
-            ++j;
-        }
+    for (uint64_t j = 0; j < ns; ++j) {
+        if (sizes) sizes[j] = pairs[j].first;
+        if (counts) counts[j] = pairs[j].second;
+    }
     if (n_sizes) *n_sizes = ns;
     if (n_domains) *n_domains = st[0];
     if (max_size) *max_size = st[1];
