@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <cmath>
 #include <stdexcept>
 #include <string>
 
@@ -164,17 +163,6 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
 template <typename R>
 void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax, void* zbuf,
                              double* part, double* out, hipStream_t s);
-// Domains: parent (N labels), size (N), hist (N + 1) and stats, which holds
-// {number of domains, largest, number of distinct sizes, unused} and then up
-// to domain_size_cap(N) (size, count) pairs; hist and stats[0..3] must be
-// zero on entry.
-constexpr size_t kDomainPairs = 4;
-inline uint32_t domain_size_cap(size_t N) {
-    // k distinct sizes sum to at least k (k + 1) / 2 <= N
-    uint32_t k = (uint32_t)std::sqrt(2.0 * (double)N) + 2u;
-    while ((uint64_t)(k - 1) * k / 2 > N) --k;
-    return k;
-}
 template <typename R>
 void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
                     uint32_t* hist, uint32_t* stats, hipStream_t s);

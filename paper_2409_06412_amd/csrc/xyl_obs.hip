@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "xyl_device.hpp"
+#include "xyl_domains.hpp"
 
 namespace xyl {
 

@@ -16,6 +16,7 @@
 
 #include "../../include/xyl.h"
 #include "xyl_device.hpp"
+#include "xyl_domains.hpp"
 #include "xyl_internal.hpp"
 
 namespace xyl {
