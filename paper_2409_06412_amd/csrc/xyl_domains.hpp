@@ -9,9 +9,9 @@
 namespace xyl {
 
 // launch_domains takes parent (N labels), size (N), hist (N + 1) and stats,
-// which holds {number of domains, largest, number of distinct sizes, unused}
-// and then up to domain_size_cap(N) (size, count) pairs; hist and stats[0..3]
-// must be zero on entry.
+// which receives the number of distinct sizes in stats[0] and the (size,
+// count) pairs, at most domain_size_cap(N) of them, from stats[kDomainPairs]
+// on; hist and stats[0] must be zero on entry.
 constexpr size_t kDomainPairs = 4;
 inline uint32_t domain_size_cap(size_t N) {
     // k distinct sizes sum to at least k (k + 1) / 2 <= N

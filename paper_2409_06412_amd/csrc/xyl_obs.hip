@@ -293,43 +293,73 @@ __global__ void k_uf_merge(const R* __restrict__ th, int Lx, int Ly, int sx, int
     if (spin_of(th, Lx, x, yp, sx, sy, model) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)yp * Lx + x));
 }
 
-__global__ void k_uf_flatten(int32_t* parent, uint32_t* size, size_t N) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t r = uf_find(parent, (int32_t)i);
-    atomicAdd(size + r, 1u);
-}
-
-// After the flatten pass every find is settled: write the roots and histogram
-// the cluster sizes; stats = {number of clusters, largest cluster}.
-__global__ void k_uf_finish(int32_t* parent, const uint32_t* size, uint32_t* hist, uint32_t* stats, size_t N) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t r = uf_find(parent, (int32_t)i);
-    if (r == (int32_t)i) {
-        const uint32_t sz = size[i];
-        atomicAdd(hist + sz, 1u);
-        atomicAdd(stats, 1u);
-        atomicMax(stats + 1, sz);
+// Adds, for every lane with `valid`, one to base[key]: lanes of the wave with
+// equal keys are counted together and their first lane adds their number, so
+// a domain spanning the wave costs one atomic, not 64 on one address.  Every
+// lane of the wave must take part (the loop runs on wave-wide ballots).
+__device__ __forceinline__ void add_grouped(uint32_t* base, uint32_t key, bool valid) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    uint64_t active = __ballot(valid);
+    while (active) {
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const uint32_t lk = (uint32_t)__shfl((int)key, leader);
+        const uint64_t same = __ballot(valid && key == lk) & active;
+        if (lane == leader) atomicAdd(base + lk, (uint32_t)__popcll(same));
+        active &= ~same;
     }
 }
 
-__global__ void k_uf_label(int32_t* parent, size_t N) {
+// Once the merges are done: every site's root (its label) replaces its parent,
+// and each root's cluster size is counted.  Concurrent finds see either a
+// site's old parent or its root, both ancestors, so every find still ends at
+// the root.
+__global__ void k_uf_flatten(int32_t* parent, uint32_t* size, size_t N) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    parent[i] = uf_find(parent, (int32_t)i);
+    const bool valid = i < N;
+    int32_t r = 0;
+    if (valid) {
+        r = uf_find(parent, (int32_t)i);
+        __hip_atomic_store(parent + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    add_grouped(size, (uint32_t)r, valid);
+}
+
+// After the flatten pass every parent is a root: histogram the cluster sizes
+// of the roots.  Each workgroup takes a contiguous chunk of sites and counts
+// sizes below kHistLds in LDS, flushing each nonzero bin with one atomic;
+// larger sizes (few, and spread over many bins) go to the histogram directly.
+// This keeps the many small domains from queueing on a few global addresses.
+constexpr int kHistLds = 1024;
+__global__ __launch_bounds__(256) void k_uf_finish(const int32_t* __restrict__ parent,
+                                                   const uint32_t* __restrict__ size, uint32_t* hist, size_t N) {
+    __shared__ uint32_t h[kHistLds];
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    const size_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const size_t i0 = (size_t)blockIdx.x * chunk;
+    const size_t i1 = i0 + chunk < N ? i0 + chunk : N;
+    for (size_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        if (parent[i] == (int32_t)i) {
+            const uint32_t sz = size[i];
+            if (sz < (uint32_t)kHistLds) atomicAdd(&h[sz], 1u);
+            else atomicAdd(hist + sz, 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
+        if (h[b]) atomicAdd(hist + b, h[b]);
 }
 
 // The size distribution as (size, count) pairs: every nonzero histogram entry
-// hist[sz], sz = 1..N, appends one pair after stats[0..3] (stats[2] counts
-// them; the order is arbitrary).  Distinct sizes sum to at most N, so there
-// are at most `cap` >= sqrt(2 N) of them.
+// hist[sz], sz = 1..N, appends one pair from stats[kDomainPairs] on (stats[0]
+// counts them; the order is arbitrary).  Distinct sizes sum to at most N, so
+// there are at most `cap` >= sqrt(2 N) of them.
 __global__ void k_uf_sizes(const uint32_t* __restrict__ hist, uint32_t* stats, size_t N, uint32_t cap) {
     const size_t sz = (size_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
     if (sz > N) return;
     const uint32_t c = hist[sz];
     if (c == 0u) return;
-    const uint32_t j = atomicAdd(stats + 2, 1u);
+    const uint32_t j = atomicAdd(stats, 1u);
     if (j < cap) {
         stats[kDomainPairs + 2 * (size_t)j] = (uint32_t)sz;
         stats[kDomainPairs + 2 * (size_t)j + 1] = c;
@@ -348,10 +378,8 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
     check_hip(hipGetLastError(), "uf merge launch");
     k_uf_flatten<<<nb, 256, 0, s>>>(parent, size, N);
     check_hip(hipGetLastError(), "uf flatten launch");
-    k_uf_finish<<<nb, 256, 0, s>>>(parent, size, hist, stats, N);
+    k_uf_finish<<<(unsigned)std::min<size_t>(nb, 1024), 256, 0, s>>>(parent, size, hist, N);
     check_hip(hipGetLastError(), "uf finish launch");
-    k_uf_label<<<nb, 256, 0, s>>>(parent, N);
-    check_hip(hipGetLastError(), "uf label launch");
     k_uf_sizes<<<nb, 256, 0, s>>>(hist, stats, N, domain_size_cap(N));
     check_hip(hipGetLastError(), "uf sizes launch");
 }

@@ -651,19 +651,23 @@ static void run_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, 
     check_hip(hipMemcpyAsync(st.data(), stats.p, sizeof(uint32_t) * nst, hipMemcpyDeviceToHost, s), "D2H");
     if (labels) check_hip(hipMemcpyAsync(labels, parent.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s), "D2H");
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    const uint64_t ns = st[2];
+    const uint64_t ns = st[0];
     require(ns >= 1 && ns <= pcap, XYL_EDEVICE, "domain size distribution overflowed its bound");
     std::vector<std::pair<uint32_t, uint32_t>> pairs(ns);
     for (uint64_t j = 0; j < ns; ++j) pairs[j] = {st[kDomainPairs + 2 * j], st[kDomainPairs + 2 * j + 1]};
     std::sort(pairs.begin(), pairs.end());
     if (sizes || counts) require(cap >= ns, XYL_EINVAL, "size-distribution capacity too small");
+    uint64_t nd = 0, covered = 0;
     for (uint64_t j = 0; j < ns; ++j) {
         if (sizes) sizes[j] = pairs[j].first;
         if (counts) counts[j] = pairs[j].second;
+        nd += pairs[j].second;
+        covered += (uint64_t)pairs[j].first * pairs[j].second;
     }
+    require(covered == N, XYL_EDEVICE, "domain sizes do not cover the lattice");
     if (n_sizes) *n_sizes = ns;
-    if (n_domains) *n_domains = st[0];
-    if (max_size) *max_size = st[1];
+    if (n_domains) *n_domains = nd;
+    if (max_size) *max_size = pairs[ns - 1].first;
 }
 
 // ============================================================ error wrapper
