@@ -95,9 +95,10 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
 // z = eps (cos q th + i sin q th), whose transform Z gives
 // sum_kappa |s~^kappa_k|^2 = (|Z_k|^2 + |Z_{L-k}|^2) / 2.
 // Pass 1 writes z line-major (rows as they are; columns through a 32 x 32
-// LDS transpose), pass 2 transforms one line per workgroup in LDS (radix-2
-// decimation in time for power-of-two L, a direct sum otherwise), pass 3
-// sums the lines in a fixed order (launch_line_sum).
+// LDS transpose), pass 2 transforms one line per workgroup in LDS (Stockham
+// passes of radix 16 for power-of-two L, a direct sum otherwise), pass 3
+// sums the lines in a fixed order (launch_line_sum).  zbuf holds N + L
+// complex values: the lines, then the twiddle table.
 template <typename R>
 __global__ __launch_bounds__(256) void k_rotor_rows(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
                                                     double q, double2* __restrict__ z) {
@@ -138,59 +139,152 @@ __global__ __launch_bounds__(256) void k_rotor_cols(const R* __restrict__ th, in
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-__device__ __forceinline__ int bit_reverse(int i, int bits) { return (int)(__brev((unsigned)i) >> (32 - bits)); }
+// tw[m] = exp(-2 pi i m / L), m < L: the twiddle table of one transform length
+__global__ void k_sf_twiddles(double2* __restrict__ tw, int L) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < L) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)L, &sn, &cs);
+        tw[m] = make_double2(cs, -sn);
+    }
+}
 
-__global__ __launch_bounds__(256) void k_sf_lines(const double2* __restrict__ z, int L, int log2L, int kmax,
-                                                  double* __restrict__ part) {
+// LDS slot of element i: one 16-B pad after every 16 elements, so that the
+// strided stores of the early passes spread over the banks.
+__device__ __forceinline__ int sf_slot(int i) { return i + (i >> 4); }
+
+constexpr int bit_reverse_c(int q, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((q >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+constexpr int log2_c(int n) { return n <= 1 ? 0 : 1 + log2_c(n / 2); }
+
+// R-point DFT in registers, natural order in and out: radix-2 decimation in
+// frequency (its result comes out bit-reversed and is read back through the
+// bit reversal).  w_R^m = tw[m L / R].
+template <int R>
+__device__ __forceinline__ void dft_regs(double2 v[R], const double2* __restrict__ tw, int L) {
+#pragma unroll
+    for (int span = R / 2; span >= 1; span >>= 1) {
+#pragma unroll
+        for (int i0 = 0; i0 < R; i0 += 2 * span) {
+#pragma unroll
+            for (int j = 0; j < span; ++j) {
+                const double2 a = v[i0 + j], b = v[i0 + j + span];
+                v[i0 + j] = cadd(a, b);
+                // w_{2 span}^j = exp(-2 pi i j / (2 span)) = tw[j L / (2 span)]
+                v[i0 + j + span] = j == 0 ? csub(a, b) : cmul(csub(a, b), tw[j * (L / (2 * span))]);
+            }
+        }
+    }
+    double2 t[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) t[q] = v[bit_reverse_c(q, log2_c(R))];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = t[q];
+}
+
+// One Stockham pass of radix R over a line of L points held in LDS (or, for
+// the first pass, read from global memory), with Ns the product of the radices
+// of the passes before it: group j (of L / R) takes the points j + r L / R,
+// multiplies point r by w^(r (j mod Ns)) with w = exp(-2 pi i / (Ns R)), takes
+// their R-point DFT and stores output q at (j - j mod Ns) R + j mod Ns + q Ns.
+// After the last pass the line holds its transform in natural order.  Every
+// group of the pass is loaded before any is stored (L / R <= blockDim.x), so
+// the pass runs in place.
+template <int R>
+__device__ __forceinline__ void sf_pass(const double2* __restrict__ gsrc, double2* buf,
+                                        const double2* __restrict__ tw, int L, int Ns) {
+    const int G = L / R;
+    const int j = threadIdx.x;
+    const bool act = j < G;
+    double2 v[R];
+    if (act) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = gsrc ? gsrc[j + r * G] : buf[sf_slot(j + r * G)];
+        if (Ns > 1) {
+            const int ts = (j & (Ns - 1)) * (L / (Ns * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * ts]);
+        }
+        dft_regs<R>(v, tw, L);
+    }
+    __syncthreads();
+    if (act) {
+        const int k = j & (Ns - 1);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[sf_slot(base + q * Ns)] = v[q];
+    }
+    __syncthreads();
+}
+
+// Power-of-two line lengths (2 .. 4096): one line per workgroup of 256
+// threads, transformed in LDS by Stockham passes of radix 16 (then one of 8,
+// 4 or 2 for the rest of log2 L), twiddles from the table tw.
+__global__ __launch_bounds__(256) void k_sf_fft(const double2* __restrict__ z, const double2* __restrict__ tw,
+                                                int L, int kmax, double* __restrict__ part) {
+    extern __shared__ double2 sm[];
+    const double2* zl = z + (size_t)blockIdx.x * L;
+    int Ns = 1;
+    while (Ns < L) {
+        const int left = L / Ns;
+        const double2* g = Ns == 1 ? zl : nullptr;
+        if (left >= 16) {
+            sf_pass<16>(g, sm, tw, L, Ns);
+            Ns *= 16;
+        } else if (left == 8) {
+            sf_pass<8>(g, sm, tw, L, Ns);
+            Ns *= 8;
+        } else if (left == 4) {
+            sf_pass<4>(g, sm, tw, L, Ns);
+            Ns *= 4;
+        } else {
+            sf_pass<2>(g, sm, tw, L, Ns);
+            Ns *= 2;
+        }
+    }
+    double* out = part + (size_t)blockIdx.x * (kmax + 1);
+    for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
+        const double2 a = sm[sf_slot(k)], b = sm[sf_slot((L - k) & (L - 1))];
+        out[k] = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+    }
+}
+
+// Other lengths: the direct sum, one line per workgroup, with the full-circle
+// twiddle table in LDS.
+__global__ __launch_bounds__(256) void k_sf_direct(const double2* __restrict__ z, int L, int kmax,
+                                                   double* __restrict__ part) {
     extern __shared__ double2 sm[];
     double2* buf = sm;
     double2* tw = sm + L;   // tw[m] = exp(-2 pi i m / L)
     const double2* zl = z + (size_t)blockIdx.x * L;
-    const int ntw = log2L >= 0 ? L / 2 : L;
-    for (int m = threadIdx.x; m < ntw; m += blockDim.x) {
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
         double sn, cs;
         sincospi(2.0 * (double)m / (double)L, &sn, &cs);
         tw[m] = make_double2(cs, -sn);
     }
     double* out = part + (size_t)blockIdx.x * (kmax + 1);
-    if (log2L >= 0) {
-        for (int i = threadIdx.x; i < L; i += blockDim.x) buf[log2L > 0 ? bit_reverse(i, log2L) : 0] = zl[i];
-        __syncthreads();
-        for (int half = 1; half < L; half <<= 1) {
-            const int step = L / (2 * half);
-            for (int b = threadIdx.x; b < L / 2; b += blockDim.x) {
-                const int j = b & (half - 1);
-                const int i0 = ((b - j) << 1) + j, i1 = i0 + half;
-                const double2 a = buf[i0];
-                const double2 t = cmul(tw[j * step], buf[i1]);
-                buf[i0] = make_double2(a.x + t.x, a.y + t.y);
-                buf[i1] = make_double2(a.x - t.x, a.y - t.y);
-            }
-            __syncthreads();
+    for (int i = threadIdx.x; i < L; i += blockDim.x) buf[i] = zl[i];
+    __syncthreads();
+    for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
+        // A = Z_k = sum z_x w^(k x), B = Z_{L-k} = sum z_x conj(w)^(k x)
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+        int m = 0;
+        for (int x = 0; x < L; ++x) {
+            const double2 w = tw[m], v = buf[x];
+            ar += v.x * w.x - v.y * w.y;
+            ai += v.x * w.y + v.y * w.x;
+            br += v.x * w.x + v.y * w.y;
+            bi += v.y * w.x - v.x * w.y;
+            m += k;
+            if (m >= L) m -= L;
         }
-        for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
-            const double2 a = buf[k], b = buf[(L - k) & (L - 1)];
-            out[k] = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
-        }
-    } else {
-        for (int i = threadIdx.x; i < L; i += blockDim.x) buf[i] = zl[i];
-        __syncthreads();
-        for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
-            // A = Z_k = sum z_x w^(k x), B = Z_{L-k} = sum z_x conj(w)^(k x)
-            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-            int m = 0;
-            for (int x = 0; x < L; ++x) {
-                const double2 w = tw[m], v = buf[x];
-                ar += v.x * w.x - v.y * w.y;
-                ai += v.x * w.y + v.y * w.x;
-                br += v.x * w.x + v.y * w.y;
-                bi += v.y * w.x - v.x * w.y;
-                m += k;
-                if (m >= L) m -= L;
-            }
-            out[k] = 0.5 * (ar * ar + ai * ai + br * br + bi * bi);
-        }
+        out[k] = 0.5 * (ar * ar + ai * ai + br * br + bi * bi);
     }
 }
 
@@ -210,17 +304,24 @@ void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int mo
         k_rotor_cols<R><<<grid, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
     }
     check_hip(hipGetLastError(), "rotor kernel launch");
-    int log2L = -1;
     if ((L & (L - 1)) == 0) {
-        log2L = 0;
-        while ((1 << log2L) < L) ++log2L;
+        double2* tw = z + (size_t)Lx * Ly;     // zbuf holds N + L complex values
+        k_sf_twiddles<<<(L + 255) / 256, 256, 0, s>>>(tw, L);
+        check_hip(hipGetLastError(), "twiddle kernel launch");
+        const size_t lds = sizeof(double2) * (size_t)(L + L / 16);
+        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_fft),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                  "hipFuncSetAttribute");
+        k_sf_fft<<<nlines, 256, lds, s>>>(z, tw, L, kmax, part);
+        check_hip(hipGetLastError(), "structure factor kernel launch");
+    } else {
+        const size_t lds = sizeof(double2) * (size_t)(2 * L);
+        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_direct),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                  "hipFuncSetAttribute");
+        k_sf_direct<<<nlines, 256, lds, s>>>(z, L, kmax, part);
+        check_hip(hipGetLastError(), "structure factor kernel launch");
     }
-    const size_t lds = sizeof(double2) * (size_t)(L + (log2L >= 0 ? L / 2 : L));
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_lines),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-              "hipFuncSetAttribute");
-    k_sf_lines<<<nlines, 256, lds, s>>>(z, L, log2L, kmax, part);
-    check_hip(hipGetLastError(), "structure factor kernel launch");
     launch_line_sum(part, nlines, kmax, (double)Lx * (double)Ly, out, s);
 }
 

@@ -1095,10 +1095,13 @@ template <typename R>
 static void structure_factor_into(const void* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax,
                                   DevBuf<double>& scratch, hipStream_t s, double* S) {
     const int nlines = axis == 0 ? Ly : Lx;
+    const int L = axis == 0 ? Lx : Ly;
     const size_t N = (size_t)Lx * Ly;
-    scratch.reserve(2 * N + (size_t)nlines * (kmax + 1) + (size_t)(kmax + 1));
+    // the lines (N complex), the twiddle table (L complex), the per-line
+    // spectra and the sum
+    scratch.reserve(2 * (N + (size_t)L) + (size_t)nlines * (kmax + 1) + (size_t)(kmax + 1));
     double* z = scratch.p;
-    double* part = scratch.p + 2 * N;
+    double* part = scratch.p + 2 * (N + (size_t)L);
     double* outd = part + (size_t)nlines * (kmax + 1);
     launch_structure_factor<R>(static_cast<const R*>(th), Lx, Ly, sx, sy, model, axis, kmax, z, part, outd, s);
     check_hip(hipMemcpyAsync(S, outd, sizeof(double) * (kmax + 1), hipMemcpyDeviceToHost, s), "D2H");

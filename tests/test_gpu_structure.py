@@ -38,6 +38,9 @@ def full_spectrum(S_half, L):
     ("xy", "f64", 260, 16),     # direct along x, FFT along y
     ("si", "f64", 64, 48),      # q = 2 rotors; FFT along x, direct along y
     ("si", "f32", 128, 128),
+    ("xy", "f64", 8, 2048),     # one radix-8 pass along x; radix 16, 16, 8 along y
+    ("xy", "f64", 512, 4),      # radix 16, 16, 2 along x; one radix-4 pass along y
+    ("si", "f64", 256, 2),      # two radix-16 passes along x; a single radix-2 pass along y
 ])
 def test_structure_factor_matches_oracle(xyl, model, dtype, Lx, Ly):
     say("structure factor", model, dtype, Lx, Ly)
