@@ -97,8 +97,9 @@ void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, 
 // Pass 1 writes z line-major (rows as they are; columns through a 32 x 32
 // LDS transpose), pass 2 transforms one line per workgroup in LDS (Stockham
 // passes of radix 16 for power-of-two L, a direct sum otherwise), pass 3
-// sums the lines in a fixed order (launch_line_sum).  zbuf holds N + L
-// complex values: the lines, then the twiddle table.
+// sums the lines in a fixed order (launch_line_sum).  Power-of-two rows skip
+// pass 1: the transform computes their rotors as it reads them.  zbuf holds
+// N + L complex values: the lines, then the twiddle table.
 template <typename R>
 __global__ __launch_bounds__(256) void k_rotor_rows(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
                                                     double q, double2* __restrict__ z) {
@@ -189,27 +190,32 @@ __device__ __forceinline__ void dft_regs(double2 v[R], const double2* __restrict
 }
 
 // One Stockham pass of radix R over a line of L points held in LDS (or, for
-// the first pass, read from global memory), with Ns the product of the radices
-// of the passes before it: group j (of L / R) takes the points j + r L / R,
+// the first pass, produced by `first`), with Ns the product of the radices of
+// the passes before it: group j (of L / R) takes the points j + r L / R,
 // multiplies point r by w^(r (j mod Ns)) with w = exp(-2 pi i / (Ns R)), takes
 // their R-point DFT and stores output q at (j - j mod Ns) R + j mod Ns + q Ns.
 // After the last pass the line holds its transform in natural order.  Every
 // group of the pass is loaded before any is stored (L / R <= blockDim.x), so
 // the pass runs in place.
-template <int R>
-__device__ __forceinline__ void sf_pass(const double2* __restrict__ gsrc, double2* buf,
-                                        const double2* __restrict__ tw, int L, int Ns) {
+template <int R, typename Src>
+__device__ __forceinline__ void sf_pass(const Src& first, double2* buf, const double2* __restrict__ tw, int L,
+                                        int Ns) {
     const int G = L / R;
     const int j = threadIdx.x;
     const bool act = j < G;
     double2 v[R];
     if (act) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = gsrc ? gsrc[j + r * G] : buf[sf_slot(j + r * G)];
+        for (int r = 0; r < R; ++r) v[r] = Ns == 1 ? first(j + r * G) : buf[sf_slot(j + r * G)];
         if (Ns > 1) {
-            const int ts = (j & (Ns - 1)) * (L / (Ns * R));
+            // w^r for r = 1 .. R-1 from one table load: w^2 = w w, w^3 = w^2 w, ...
+            const double2 w1 = tw[(j & (Ns - 1)) * (L / (Ns * R))];
+            double2 w = w1;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * ts]);
+            for (int r = 1; r < R; ++r) {
+                v[r] = cmul(v[r], w);
+                w = cmul(w, w1);
+            }
         }
         dft_regs<R>(v, tw, L);
     }
@@ -223,36 +229,69 @@ __device__ __forceinline__ void sf_pass(const double2* __restrict__ gsrc, double
     __syncthreads();
 }
 
-// Power-of-two line lengths (2 .. 4096): one line per workgroup of 256
-// threads, transformed in LDS by Stockham passes of radix 16 (then one of 8,
-// 4 or 2 for the rest of log2 L), twiddles from the table tw.
-__global__ __launch_bounds__(256) void k_sf_fft(const double2* __restrict__ z, const double2* __restrict__ tw,
-                                                int L, int kmax, double* __restrict__ part) {
-    extern __shared__ double2 sm[];
-    const double2* zl = z + (size_t)blockIdx.x * L;
+// The transform of one line of L = 2^n points (2 .. 4096) by one workgroup of
+// 256 threads: Stockham passes of radix 16 (then one of 8, 4 or 2 for the
+// rest of n), then sum_kappa |s~^kappa_k|^2 for k <= kmax into out.
+template <typename Src>
+__device__ __forceinline__ void sf_line(const Src& src, double2* sm, const double2* __restrict__ tw, int L, int kmax,
+                                        double* __restrict__ out) {
     int Ns = 1;
     while (Ns < L) {
         const int left = L / Ns;
-        const double2* g = Ns == 1 ? zl : nullptr;
         if (left >= 16) {
-            sf_pass<16>(g, sm, tw, L, Ns);
+            sf_pass<16>(src, sm, tw, L, Ns);
             Ns *= 16;
         } else if (left == 8) {
-            sf_pass<8>(g, sm, tw, L, Ns);
+            sf_pass<8>(src, sm, tw, L, Ns);
             Ns *= 8;
         } else if (left == 4) {
-            sf_pass<4>(g, sm, tw, L, Ns);
+            sf_pass<4>(src, sm, tw, L, Ns);
             Ns *= 4;
         } else {
-            sf_pass<2>(g, sm, tw, L, Ns);
+            sf_pass<2>(src, sm, tw, L, Ns);
             Ns *= 2;
         }
     }
-    double* out = part + (size_t)blockIdx.x * (kmax + 1);
     for (int k = threadIdx.x; k <= kmax; k += blockDim.x) {
         const double2 a = sm[sf_slot(k)], b = sm[sf_slot((L - k) & (L - 1))];
         out[k] = 0.5 * (a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
     }
+}
+
+// Points of a line: complex values written by the rotor pass, or the staggered
+// rotors of one lattice row computed on the fly (the same arithmetic as
+// k_rotor_rows).
+struct ZLine {
+    const double2* z;
+    __device__ double2 operator()(int i) const { return z[i]; }
+};
+template <typename R>
+struct RotorRow {
+    const R* th;   // the row
+    int y, sx, sy;
+    double q;
+    __device__ double2 operator()(int x) const {
+        const double e = (((x * sx) + (y * sy)) & 1) ? -1.0 : 1.0;
+        double sn, cs;
+        sincos(q * (double)th[x], &sn, &cs);
+        return make_double2(e * cs, e * sn);
+    }
+};
+
+// Power-of-two lines, one per workgroup: columns from the transposed rotor
+// field z, rows straight from the angles.
+__global__ __launch_bounds__(256) void k_sf_fft(const double2* __restrict__ z, const double2* __restrict__ tw,
+                                                int L, int kmax, double* __restrict__ part) {
+    extern __shared__ double2 sm[];
+    sf_line(ZLine{z + (size_t)blockIdx.x * L}, sm, tw, L, kmax, part + (size_t)blockIdx.x * (kmax + 1));
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_sf_fft_rows(const R* __restrict__ th, int sx, int sy, double q,
+                                                     const double2* __restrict__ tw, int L, int kmax,
+                                                     double* __restrict__ part) {
+    extern __shared__ double2 sm[];
+    const int y = blockIdx.x;
+    sf_line(RotorRow<R>{th + (size_t)y * L, y, sx, sy, q}, sm, tw, L, kmax, part + (size_t)y * (kmax + 1));
 }
 
 // Other lengths: the direct sum, one line per workgroup, with the full-circle
@@ -295,26 +334,39 @@ void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int mo
     double2* z = static_cast<double2*>(zbuf);
     const int L = axis == 0 ? Lx : Ly;
     const int nlines = axis == 0 ? Ly : Lx;
-    if (axis == 0) {
-        const size_t N = (size_t)Lx * Ly;
-        const unsigned nb = (unsigned)std::min<size_t>((N + 255) / 256, 65536);
-        k_rotor_rows<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
-    } else {
-        const dim3 grid((Lx + 31) / 32, (Ly + 31) / 32);
-        k_rotor_cols<R><<<grid, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
-    }
-    check_hip(hipGetLastError(), "rotor kernel launch");
-    if ((L & (L - 1)) == 0) {
+    const bool pow2 = (L & (L - 1)) == 0;
+    if (pow2) {
+        // rows go straight from the angles into the transform; columns are
+        // transposed into z first
         double2* tw = z + (size_t)Lx * Ly;     // zbuf holds N + L complex values
         k_sf_twiddles<<<(L + 255) / 256, 256, 0, s>>>(tw, L);
         check_hip(hipGetLastError(), "twiddle kernel launch");
         const size_t lds = sizeof(double2) * (size_t)(L + L / 16);
-        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_fft),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                  "hipFuncSetAttribute");
-        k_sf_fft<<<nlines, 256, lds, s>>>(z, tw, L, kmax, part);
+        if (axis == 0) {
+            check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_fft_rows<R>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                      "hipFuncSetAttribute");
+            k_sf_fft_rows<R><<<nlines, 256, lds, s>>>(th, sx, sy, q, tw, L, kmax, part);
+        } else {
+            const dim3 grid((Lx + 31) / 32, (Ly + 31) / 32);
+            k_rotor_cols<R><<<grid, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
+            check_hip(hipGetLastError(), "rotor kernel launch");
+            check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_fft),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                      "hipFuncSetAttribute");
+            k_sf_fft<<<nlines, 256, lds, s>>>(z, tw, L, kmax, part);
+        }
         check_hip(hipGetLastError(), "structure factor kernel launch");
     } else {
+        if (axis == 0) {
+            const size_t N = (size_t)Lx * Ly;
+            const unsigned nb = (unsigned)std::min<size_t>((N + 255) / 256, 65536);
+            k_rotor_rows<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
+        } else {
+            const dim3 grid((Lx + 31) / 32, (Ly + 31) / 32);
+            k_rotor_cols<R><<<grid, 256, 0, s>>>(th, Lx, Ly, sx, sy, q, z);
+        }
+        check_hip(hipGetLastError(), "rotor kernel launch");
         const size_t lds = sizeof(double2) * (size_t)(2 * L);
         check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_sf_direct),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),

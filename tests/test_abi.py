@@ -68,6 +68,9 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert b"Lx and Ly" in lib.xyl_last_error()
     assert lib.xyl_create(ctypes.byref(h), 8, 8, 7, 0) == -1        # unknown dtype
     assert lib.xyl_create(ctypes.byref(h), 6, 8, 0, 0) == -5        # Lx not a multiple of 4
+    assert lib.xyl_create(ctypes.byref(h), 65536, 32768, 0, 0) == -5  # 2^31 sites: labels overflow int32
+    assert b"int32" in lib.xyl_last_error()
+    assert lib.xyl_create(ctypes.byref(h), 1 << 20, 1 << 14, 0, 0) == -1  # 2^34 sites
     assert lib.xyl_create(None, 8, 8, 0, 0) == -1
     assert lib.xyl_destroy(None) == 0
     assert lib.xyl_step(None, 1) == -1
