@@ -56,6 +56,8 @@ __global__ void k_line_sum_chunks(double* __restrict__ part, int nlines, int rma
     const int l0 = blockIdx.y * kLineChunk;
     const int l1 = min(l0 + kLineChunk, nlines);
     double acc = 0.0;
+    // unrolled so that the loads are in flight together; the sum keeps line order
+#pragma unroll 16
     for (int l = l0; l < l1; ++l) acc += part[(size_t)l * (rmax + 1) + r];
     part[(size_t)l0 * (rmax + 1) + r] = acc;
 }
@@ -64,6 +66,7 @@ __global__ void k_corr_sum(const double* __restrict__ part, int nlines, int rmax
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > rmax) return;
     double acc = 0.0;
+#pragma unroll 16
     for (int l = 0; l < nlines; l += kLineChunk) acc += part[(size_t)l * (rmax + 1) + r];
     out[r] = acc / N;
 }
