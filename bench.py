@@ -310,6 +310,25 @@ def bench_si_4096(torch, xyl, workloads, nlaunch=500, launch=None):
     return {"L": 4096, "model": "si", "p": spec.p, "T": spec.schedule[0][1], **out}
 
 
+def bench_fp64_4096(torch, xyl, workloads, nsteps=200):
+    """The FP64 single-step kernel on the headline's lattice: 32 B per
+    site-update (read theta, u; write theta', u' in binary64), against 8 TB/s.
+    Its per-site arithmetic (FP64 sine, cosine, logarithm and square root in
+    software) is the other bound."""
+    spec = workloads.large_fp32(0, 4096)
+    lat = xyl.Lattice(4096, 4096, dtype="f64", schedule=spec.schedule, seed=spec.seed,
+                      stream=torch.cuda.current_stream().cuda_stream, **spec.params())
+    lat.init_random()
+    launch = lat.autotune()
+    lat.step(20)
+    ms = time_steps(torch, lat, nsteps)
+    lat.close()
+    gbs = 32.0 * 4096 * 4096 / (ms * 1e-3) / 1e9
+    return {"L": 4096, "dtype": "f64", "kernel": "k_step<double>", "launch": list(launch), "us_per_step": 1e3 * ms,
+            "site_updates_per_s": 4096 * 4096 / (ms * 1e-3), "algorithmic_GBs": gbs,
+            "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+
+
 def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
     """The Si-model finite-size-scaling ensemble (128 replicas, L = 32..144),
     batched, sampled every 100 steps."""
@@ -330,8 +349,9 @@ def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
 
 def bench_structure_factor(torch, xyl, workloads, reps=5):
     """S_delta(k) for k = 0..L/2 along both axes of a 4096^2 lattice (the
-    paper's correlation-length observable, App. C), and the Lorentzian xi of
-    each axis, on a lattice quenched for 1000 steps."""
+    paper's correlation-length observable, App. C), the Lorentzian xi of each
+    axis, and the correlation function C_delta(r) for r = 0..L/2, on a lattice
+    quenched for 1000 steps."""
     spec = workloads.large_fp32(0, 4096)
     lat = xyl.Lattice(4096, 4096, dtype="f32", schedule=spec.schedule, seed=spec.seed,
                       stream=torch.cuda.current_stream().cuda_stream, **spec.params())
@@ -344,6 +364,11 @@ def bench_structure_factor(torch, xyl, workloads, reps=5):
         for _ in range(reps):
             S = lat.structure_factor(axis, 2048)
         out["ms_" + name] = 1e3 * (time.perf_counter() - t0) / reps
+        lat.correlation(axis, 2048)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lat.correlation(axis, 2048)
+        out["corr_ms_" + name] = 1e3 * (time.perf_counter() - t0) / reps
         try:
             out["xi_" + name] = xyl.lorentzian_xi(S, 4096, 1, 64)[0]
         except xyl.XylError as e:      # no Lorentzian peak along this axis (e.g. unaligned rows)
@@ -643,7 +668,8 @@ def main():
                 "control": lambda: bench_control_8192(torch, xyl, workloads),
                 "si": lambda: bench_si_4096(torch, xyl, workloads, launch=fixed),
                 "structure": lambda: bench_structure_factor(torch, xyl, workloads),
-                "si_fss": lambda: bench_si_fss(torch, xyl, workloads)}
+                "si_fss": lambda: bench_si_fss(torch, xyl, workloads),
+                "fp64": lambda: bench_fp64_4096(torch, xyl, workloads)}
         print(json.dumps({k: runs[k]() for k in args.only.split(",")}), flush=True)
         return
     L = args.L
@@ -741,6 +767,8 @@ def main():
         log("si model 4096^2:", extras["si_4096"])
         extras["si_fss"] = bench_si_fss(torch, xyl, workloads)
         log("si model FSS ensemble:", extras["si_fss"])
+        extras["fp64_4096"] = bench_fp64_4096(torch, xyl, workloads)
+        log("fp64 4096^2:", extras["fp64_4096"])
 
     cpu = None if args.no_cpu else cpu_baseline(L, args.cpu_steps)
     if cpu:

@@ -156,10 +156,11 @@ void launch_set_counter(uint64_t* kdev, uint64_t value, hipStream_t s);
 void launch_bump(uint64_t* kdev, uint64_t by, hipStream_t s);
 void launch_stream_probe(const void* a, const void* b, void* c, void* d, size_t n4, int grid, hipStream_t s);
 void launch_philox_blocks(uint64_t seed, const uint32_t* ctr, uint32_t* out, uint64_t n, hipStream_t s);
+// C_delta(r), r = 0..rmax: part holds correlation_scratch() doubles
 template <typename R>
 void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,
                         double* out, hipStream_t s);
-// S_delta(k), k = 0..kmax: zbuf holds 16 * Lx * Ly bytes, part nlines * (kmax + 1) doubles
+// S_delta(k), k = 0..kmax: zbuf holds 16 (Lx Ly + L) bytes, part nlines * (kmax + 1) doubles
 template <typename R>
 void launch_structure_factor(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int kmax, void* zbuf,
                              double* part, double* out, hipStream_t s);

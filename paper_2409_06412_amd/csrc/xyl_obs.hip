@@ -4,6 +4,7 @@
 
 #include "xyl_device.hpp"
 #include "xyl_domains.hpp"
+#include "xyl_obs.hpp"
 
 namespace xyl {
 
@@ -79,11 +80,45 @@ static void launch_line_sum(double* part, int nlines, int rmax, double N, double
     check_hip(hipGetLastError(), "line sum launch");
 }
 
+// C(r) from the structure factor of a power-of-two axis (App. C: C and S are
+// a Fourier pair along the axis): C(r) = (1/L) sum_{k<L} S(k) cos(2 pi k r / L)
+// with S(L - k) = S(k), i.e. (1/L) [S(0) + (-1)^r S(L/2) + 2 sum_{0<k<L/2}
+// S(k) cos(2 pi k r / L)].  One workgroup per r sums in a fixed order (strided
+// partial sums, then a fixed tree); cos from the twiddle table tw.
+__global__ __launch_bounds__(256) void k_corr_from_sf(const double* __restrict__ S, const double2* __restrict__ tw,
+                                                      int L, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    const int h = L / 2;
+    double acc = 0.0;
+    for (int k = 1 + (int)threadIdx.x; k < h; k += blockDim.x) acc += S[k] * tw[(k * r) & (L - 1)].x;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double last = L >= 2 ? ((r & 1) ? -S[h] : S[h]) : 0.0;
+        out[r] = (S[0] + last + 2.0 * red[0]) / (double)L;
+    }
+}
+
 template <typename R>
 void launch_correlation(const R* th, int Lx, int Ly, int sx, int sy, int model, int axis, int rmax, double* part,
                         double* out, hipStream_t s) {
     const int nlines = axis == 0 ? Ly : Lx;
     const int L = axis == 0 ? Lx : Ly;
+    if ((L & (L - 1)) == 0) {
+        const size_t N = (size_t)Lx * Ly;
+        double* z = part;
+        double* spart = part + 2 * (N + (size_t)L);
+        double* S = spart + (size_t)nlines * (L / 2 + 1);
+        launch_structure_factor<R>(th, Lx, Ly, sx, sy, model, axis, L / 2, z, spart, S, s);
+        k_corr_from_sf<<<rmax + 1, 256, 0, s>>>(S, reinterpret_cast<const double2*>(z) + N, L, out);
+        check_hip(hipGetLastError(), "correlation kernel launch");
+        return;
+    }
     const size_t lds = 2 * sizeof(double) * (size_t)L;
     k_corr_lines<R><<<nlines, 256, lds, s>>>(th, Lx, Ly, sx, sy, model == kModelSI ? 2.0 : 1.0, axis, rmax, part);
     check_hip(hipGetLastError(), "correlation kernel launch");

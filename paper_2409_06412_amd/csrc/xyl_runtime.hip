@@ -18,6 +18,7 @@
 #include "xyl_device.hpp"
 #include "xyl_domains.hpp"
 #include "xyl_internal.hpp"
+#include "xyl_obs.hpp"
 
 namespace xyl {
 
@@ -1072,10 +1073,10 @@ int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C) {
         require(L <= 4096, XYL_EUNSUPPORTED, "correlation needs the axis length <= 4096");
         require(C != nullptr, XYL_EINVAL, "C is NULL");
         DeviceGuard g(h->device);
-        const int nlines = axis == 0 ? h->Ly : h->Lx;
-        h->dscratch.reserve((size_t)nlines * (rmax + 1) + (rmax + 1));
+        const size_t nscr = correlation_scratch(h->Lx, h->Ly, axis, rmax);
+        h->dscratch.reserve(nscr + (rmax + 1));
         double* part = h->dscratch.p;
-        double* outd = h->dscratch.p + (size_t)nlines * (rmax + 1);
+        double* outd = h->dscratch.p + nscr;
         const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
         if (h->dtype == XYL_F64)
             launch_correlation<double>(static_cast<const double*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model,

@@ -222,13 +222,13 @@ def test_measure_fp32_matches_oracle_on_same_state(xyl):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_correlation_matches_oracle(xyl, dtype):
-    Lx, Ly = 48, 36
+@pytest.mark.parametrize("Lx,Ly", [(48, 36), (64, 32)])   # direct pair sums; from the structure factor
+def test_correlation_matches_oracle(xyl, dtype, Lx, Ly):
     lat, o = make_pair(xyl, Lx, Ly, dtype, schedule=[(0, 0.6)], seed=14)
     lat.init_random()
     lat.step(300)
     th, _, _ = lat.get_state()
-    for axis, rmax in ((0, 24), (1, 18), (0, 0)):
+    for axis, rmax in ((0, Lx // 2), (1, Ly // 2), (0, 0)):
         C = lat.correlation(axis, rmax)
         Cr = o.correlation(th, axis, rmax)
         tol = 1e-12 if dtype == "f64" else 1e-6
