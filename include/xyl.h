@@ -186,7 +186,11 @@ int xyl_step_adaptive(xyl_lattice* h, uint64_t nsteps, uint64_t ds0, uint64_t ds
 /* Staggered rotor correlation along axis (0 = x, 1 = y) at the current step
  * (App. C, two-point function of the rotors, lattice average):
  * C(r) = (1/N) sum_i eps_i eps_j cos(q (th_i - th_j)), j = i + r along the axis,
- * r = 0..rmax, 0 <= rmax <= L_axis/2.  C has rmax+1 entries.  Synchronises. */
+ * r = 0..rmax, 0 <= rmax <= L_axis/2.  C has rmax+1 entries.  L_axis <= 4096
+ * (XYL_EUNSUPPORTED otherwise).  Power-of-two L_axis: from the structure
+ * factor, C(r) = (1/L) sum_k S(k) cos(2 pi k r / L) (equal to the pair sums up
+ * to rounding; 16 bytes of device scratch per site); other lengths: the pair
+ * sums themselves.  Synchronises. */
 int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C);
 /* Directional structure factor along axis (0 = x, 1 = y) at the current step
  * (App. C, Eqs. FT-Corr-delta and S-as-lattice-FT):
@@ -196,7 +200,8 @@ int xyl_correlation(xyl_lattice* h, int32_t axis, int32_t rmax, double* C);
  * 0 <= kmax <= L_axis/2 (S(L - k) = S(k)).  S has kmax+1 entries.  FP64,
  * summed over lines in a fixed order.  L_axis <= 4096 (XYL_EUNSUPPORTED
  * otherwise); power-of-two L_axis uses an FFT per line, other lengths a
- * direct sum.  Uses 16 bytes of device scratch per site.  Synchronises. */
+ * direct sum.  Uses 16 bytes of device scratch per site (plus 16 per point
+ * of the axis).  Synchronises. */
 int xyl_structure_factor(xyl_lattice* h, int32_t axis, int32_t kmax, double* S);
 /* Frozen domains of the current angles (Abstract; Figs. 1 and 6): spin
  * s_i = eps_i * (|th_i| <= pi_p/2 ? +1 : -1) (XY; eps_i * (th_i >= 0 ? +1 : -1)
