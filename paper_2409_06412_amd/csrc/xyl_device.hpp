@@ -111,13 +111,15 @@ struct Prec<float> {
     __device__ static __forceinline__ float uniform(uint32_t r) {
         return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, r, 9u)) - 0x1.fffffep-1f;
     }
-    // One Box-Muller pair: radius sqrt(-2 ln u1) (ln via the native log2),
-    // angle 2 pi u2 (native sine/cosine in revolutions, no multiplication);
-    // both draws scaled by `scale` through the radius.
+    // One Box-Muller pair: radius sqrt(-2 ln u1) (ln via the native log2:
+    // kk = -2 ln 2, or -2 ln 2 scale^2 to scale both draws by `scale` inside
+    // the square root), angle 2 pi u2 (native sine/cosine in revolutions, no
+    // multiplication).
+    static constexpr float kMinus2Ln2 = -1.38629436111989062f;
     __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, float& nc, float& ns,
-                                                      float scale = 1.0f) {
+                                                      float kk = kMinus2Ln2) {
         const float u1 = uniform(r1), u2 = uniform(r2);
-        const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989062f * __builtin_amdgcn_logf(u1)) * scale;
+        const float rad = __builtin_amdgcn_sqrtf(kk * __builtin_amdgcn_logf(u1));
         nc = rad * __builtin_amdgcn_cosf(u2);
         ns = rad * __builtin_amdgcn_sinf(u2);
     }
@@ -171,16 +173,27 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
     Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3]);
 }
 
-// The draws as site_update takes them: FP32 multiplies in the half-kick noise
-// amplitude hs through the Box-Muller radius (one multiplication per pair);
-// FP64 returns the plain draws and site_update applies hs in the oracle's order.
+// The noise coefficient of step k as noise4_kick and site_update take it:
+// FP32 -2 ln 2 hs^2 (the draws' scale inside the Box-Muller square root, from
+// the FP64 amplitude hs); FP64 hs itself.
 template <typename R>
-__device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64_t k, uint32_t s0, uint32_t s1, R hs,
+__device__ __forceinline__ R noise_coeff(const Lat<R>& v, uint64_t k) {
+    const double hs = half_sigma(v.sched, v.gamma, v.dtd, k);
+    if constexpr (sizeof(R) == 4) return (R)(-1.38629436111989062 * hs * hs);
+    else return hs;
+}
+
+// The draws as site_force takes them: FP32 scales them by the half-kick noise
+// amplitude through the coefficient kk = noise_coeff (the same for every site
+// of a step); FP64 returns the plain draws and site_update applies hs in the
+// oracle's order.
+template <typename R>
+__device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64_t k, uint32_t s0, uint32_t s1, R kk,
                                             R n[4]) {
     if constexpr (sizeof(R) == 4) {
         const U32x4 r = philox4x32_10(q, replica, (uint32_t)k, (uint32_t)(k >> 32), s0, s1);
-        Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1], hs);
-        Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3], hs);
+        Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1], kk);
+        Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3], kk);
     } else {
         noise4<R>(q, replica, k, s0, s1, n);
     }
@@ -192,31 +205,39 @@ __device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64
 // site and its neighbours (x-1, x+1, y-1, y+1) and, for SI, the raw angle:
 //   XY: F = Jx [s (cx+ + cx-) - c (sx+ + sx-)] + Jy [s (cy+ + cy-) - c (sy+ + sy-)] - 4 h s c
 //   SI: F = 2Jx [s (cx+ + cx-) - c (sx+ + sx-)] + 2Jy [...] - p h sin(p th)
-// (v.Jx, v.Jy hold q Jx, q Jy).
+// (v.Jx, v.Jy hold q Jx, q Jy).  FP32 returns the whole kick g = hdt F + n
+// (n the scaled draw), with hdt folded into the couplings so that the draw
+// enters the last two fused multiply-adds; FP64 returns F in the oracle's
+// order and site_update adds the rest.
 template <typename R, int M>
 __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm, R sxp, R cxp, R sym, R cym, R syp,
-                                        R cyp, R th) {
-    if constexpr (M == kModelSI) {
-        const R sp = Prec<R>::sin_scaled(th, v.pf);
-        if constexpr (sizeof(R) == 4) {
-            const R P = Prec<R>::fma(v.Jx, cxp + cxm, v.Jy * (cyp + cym));
-            const R Q = Prec<R>::fma(v.Jx, sxp + sxm, v.Jy * (syp + sym));
-            return Prec<R>::fma(-v.ph, sp, Prec<R>::fma(s, P, -(c * Q)));
+                                        R cyp, R th, R n) {
+    if constexpr (sizeof(R) == 4) {
+        // couplings scaled by hdt on the host (kJx = hdt q Jx, ...)
+        const R P0 = Prec<R>::fma(v.kJx, cxp + cxm, v.kJy * (cyp + cym));
+        const R Q = Prec<R>::fma(v.kJx, sxp + sxm, v.kJy * (syp + sym));
+        const R cq = Prec<R>::fma(-c, Q, n);
+        if constexpr (M == kModelSI) {
+            const R sp = Prec<R>::sin_scaled(th, v.pf);
+            return Prec<R>::fma(-v.kph, sp, Prec<R>::fma(s, P0, cq));
         } else {
+            // s (kJx Cx + kJy Cy - kh4 c) - c (kJx Sx + kJy Sy) + n
+            const R P = Prec<R>::fma(-v.kh4, c, P0);
+            return Prec<R>::fma(s, P, cq);
+        }
+    } else {
+        (void)n;
+        if constexpr (M == kModelSI) {
+            const R sp = Prec<R>::sin_scaled(th, v.pf);
             const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
             const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
             return Prec<R>::fma(-v.ph, sp, Prec<R>::fma(v.Jx, fx, v.Jy * fy));
+        } else {
+            const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
+            const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
+            const R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
+            return Prec<R>::fma(-v.h4, s * c, f);
         }
-    } else if constexpr (sizeof(R) == 4) {
-        // FP32: grouped as s (Jx Cx + Jy Cy - 4h c) - c (Jx Sx + Jy Sy), 11 operations
-        const R P = Prec<R>::fma(-v.h4, c, Prec<R>::fma(v.Jx, cxp + cxm, v.Jy * (cyp + cym)));
-        const R Q = Prec<R>::fma(v.Jx, sxp + sxm, v.Jy * (syp + sym));
-        return Prec<R>::fma(s, P, -(c * Q));
-    } else {
-        const R fx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
-        const R fy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
-        const R f = Prec<R>::fma(v.Jx, fx, v.Jy * fy);
-        return Prec<R>::fma(-v.h4, s * c, f);
     }
 }
 
@@ -236,12 +257,13 @@ template <typename R, int M>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
     if constexpr (sizeof(R) == 4) {
-        // FP32: n arrives as hs n (noise4_kick); the kick g = hdt F + hs n is
-        // formed once and used by both halves.  The fresh-step choice is folded
-        // into two step-uniform coefficients: c (u + g) on ordinary steps
-        // (fma(1, g, u) = u + g exactly), u itself on the fresh step.
+        // FP32: f arrives as the kick g = hdt F + hs n (site_force), used by
+        // both halves.  The fresh-step choice is folded into two step-uniform
+        // coefficients: c (u + g) on ordinary steps (fma(1, g, u) = u + g
+        // exactly), u itself on the fresh step.
         (void)hs;
-        const R g = Prec<R>::fma(v.hdt, f, n);
+        (void)n;
+        const R g = f;
         const R cf = fresh ? R(1) : v.c, gf = fresh ? R(0) : R(1);
         const R ww = cf * Prec<R>::fma(gf, g, u);
         w = ww;

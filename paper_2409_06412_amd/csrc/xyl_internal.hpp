@@ -40,6 +40,7 @@ struct Lat {
     // force); p h and the field's angular factor (SI: p / 2pi revolutions in
     // FP32, p in FP64)
     R Jx, Jy, h4, ph, pf, a, c, hdt, dt;
+    R kJx, kJy, kh4, kph;  // FP32 kick: hdt q Jx, hdt q Jy, hdt 4h, hdt p h
     double Jxd, Jyd, hd, pd;       // FP64 copies for the energy
     double gamma, dtd;             // FP64 for the noise amplitude
     Schedule sched;

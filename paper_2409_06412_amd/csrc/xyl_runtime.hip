@@ -169,6 +169,10 @@ static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule&
     v.c = (R)(1.0 / (1.0 + 0.5 * p.gamma * p.dt));
     v.hdt = (R)(0.5 * p.dt);
     v.dt = (R)p.dt;
+    v.kJx = (R)(0.5 * p.dt * q * p.Jx);
+    v.kJy = (R)(0.5 * p.dt * q * p.Jy);
+    v.kh4 = (R)(0.5 * p.dt * 4.0 * p.h);
+    v.kph = (R)(0.5 * p.dt * p.p * p.h);
     v.Jxd = p.Jx;
     v.Jyd = p.Jy;
     v.hd = p.h;

@@ -58,7 +58,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     R* __restrict__ tho = v.pingpong ? v.th[par ^ 1] : v.th[1];
     const R* uu = v.u;
     R* uw = v.u_out ? v.u_out : v.u;
-    const R hs = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
+    const R hs = noise_coeff<R>(v, k);   // FP32: -2 ln 2 hs^2; FP64: hs
     const bool fresh = (k == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
 
@@ -117,7 +117,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
             const R f =
-                site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q]);
+                site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q], n[q]);
             site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
         }
         if ((MODE & kStore) && act) {
@@ -373,8 +373,8 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         const float r = from_lane_above(v_above, edge);
         return (PARTIAL || TILE) ? (edgeR ? edge : r) : r;
     };
-    const R hsA = (R)half_sigma(v.sched, v.gamma, v.dtd, k);
-    const R hsB = (R)half_sigma(v.sched, v.gamma, v.dtd, k + 1);
+    const R hsA = noise_coeff<R>(v, k);
+    const R hsB = noise_coeff<R>(v, k + 1);
     const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
     auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
@@ -406,7 +406,8 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q]);
+            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q],
+                                         n[q]);
             R w;
             site_update<R, M>(v, f, U.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
             rotor<R, M>(out.t[q], s1[q], c1[q]);
@@ -442,7 +443,7 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : sc[q - 1], cxm = q == 0 ? cL : cc[q - 1];
             const R sxp = q == 3 ? sR : sc[q + 1], cxp = q == 3 ? cR : cc[q + 1];
-            const R f = site_force<R, M>(v, sc[q], cc[q], sxm, cxm, sxp, cxp, sp[q], cp[q], sn[q], cn[q], C.t[q]);
+            const R f = site_force<R, M>(v, sc[q], cc[q], sxm, cxm, sxp, cxp, sp[q], cp[q], sn[q], cn[q], C.t[q], n[q]);
             R w;
             site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
@@ -718,9 +719,10 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             }
         }
     };
-    // neighbours of group g from the tables; returns the force of its 4 sites
-    auto forces = [&](int g, const float t4[4], float f[4], float s4[4], float c4[4], float& sR, float& cR,
-                      float sd[4], float cd[4]) {
+    // neighbours of group g from the tables; returns the kick of its 4 sites
+    // (site_force, with their scaled draws n)
+    auto forces = [&](int g, const float t4[4], const float n[4], float f[4], float s4[4], float c4[4], float& sR,
+                      float& cR, float sd[4], float cd[4]) {
         const int i0 = 4 * g;
         const int y = i0 / Lx, x = i0 - y * Lx;
         const int ym = y == 0 ? Ly - 1 : y - 1, yp = y + 1 == Ly ? 0 : y + 1;
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
         for (int e = 0; e < 4; ++e) {
             const float sxm = e == 0 ? sL : s4[e - 1], cxm = e == 0 ? cL : c4[e - 1];
             const float sxp = e == 3 ? sR : s4[e + 1], cxp = e == 3 ? cR : c4[e + 1];
-            f[e] = site_force<float, M>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e], t4[e]);
+            f[e] = site_force<float, M>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e], t4[e], n[e]);
         }
     };
 
@@ -748,7 +750,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
     __syncthreads();
     if (job.measure) {
         // observables of the synchronized state at k0 (same sums as the strip kernel)
-        const float hs = (float)half_sigma(v.sched, v.gamma, v.dtd, k0);
+        const float hs = noise_coeff<float>(v, k0);
         const bool fresh = (k0 == v.fresh_k);
         double acc[kNPart];
 #pragma unroll
@@ -758,8 +760,8 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
                 noise4_kick<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, hs, n);
+                forces(g, th[q], n, f, s4, c4, sR, cR, sd, cd);
                 const int i0 = 4 * g;
                 const int y = i0 / Lx, x = i0 - y * Lx;
                 double rps, rpc;
@@ -822,15 +824,15 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             tables();
             __syncthreads();
         }
-        const float hs = (float)half_sigma(v.sched, v.gamma, v.dtd, k);
+        const float hs = noise_coeff<float>(v, k);
         const bool fresh = (k == v.fresh_k);
 #pragma unroll
         for (int q = 0; q < kLdsMaxGroups; ++q) {
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                forces(g, th[q], f, s4, c4, sR, cR, sd, cd);
                 noise4_kick<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, hs, n);
+                forces(g, th[q], n, f, s4, c4, sR, cR, sd, cd);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w;
