@@ -611,8 +611,8 @@ def summarize_valu(d, out_json, out_md, L, command, kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=40000)
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--L", type=int, default=4096)
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--no-extras", action="store_true")
