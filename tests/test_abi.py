@@ -72,6 +72,11 @@ def test_invalid_arguments_are_rejected_without_a_device(lib):
     assert b"int32" in lib.xyl_last_error()
     assert lib.xyl_create(ctypes.byref(h), 1 << 20, 1 << 14, 0, 0) == -1  # 2^34 sites
     assert lib.xyl_create(None, 8, 8, 0, 0) == -1
+    e = ctypes.c_void_p()
+    desc = (xyl.ReplicaDesc * 1)()
+    assert lib.xyl_ensemble_create(ctypes.byref(e), desc, 0, 0, 0) == -1   # no replicas
+    assert b"at least one replica" in lib.xyl_last_error()
+    assert lib.xyl_ensemble_create(ctypes.byref(e), desc, 1, 7, 0) == -1   # unknown dtype
     assert lib.xyl_destroy(None) == 0
     assert lib.xyl_step(None, 1) == -1
     with pytest.raises(xyl.XylError):
