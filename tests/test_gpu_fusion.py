@@ -110,7 +110,8 @@ def test_fusion_keeps_measurement_and_state_buffers(xyl):
 
 def test_fusion_query_reports_the_mode_in_effect(xyl):
     """xyl_get_fusion: rows per strip where the two-step pass applies (taller
-    strips on wider lattices, 2..16 rows), 0 where it does not (FP64, a width up
+    strips on wider lattices, 2..16 rows, up to 32 for column tiles), 0 where
+    it does not (FP64, a width up
     to 4096 using less than 3/4 of its waves' lanes or a single lane of the last
     wave, steps_per_pass 1); widths above 4096 run as column tiles."""
     import torch
@@ -127,7 +128,7 @@ def test_fusion_query_reports_the_mode_in_effect(xyl):
         say(Lx, Ly, dt, "->", sp, rows)
         assert sp == 2
         if fused:
-            assert 1 <= rows <= 16
+            assert 1 <= rows <= 32
         else:
             assert rows == 0
         lat.set_fusion(1)
