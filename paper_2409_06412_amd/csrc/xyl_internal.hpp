@@ -131,7 +131,7 @@ void launch_step(const Lat<R>& v, int mode, const Launch& l, const uint64_t* kde
 template <typename R>
 void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int mode, int model, int rows, int wpb,
                           const uint64_t* kdev, uint64_t j, hipStream_t s);
-// Two steps per pass (FP32; Lx a multiple of 256 up to 4096, Ly >= 4): angles
+// Two steps per pass (FP32; Lx up to 4096 with step2_width_ok, Ly >= 4): angles
 // and velocities at step k are read from th_in / u_in and those at k+2
 // written to th_out / u_out (distinct buffers); k = v.k_base + j (+ *kdev).
 // Widths above 4096 run as column tiles (step2_tiles); rows per strip as given.
