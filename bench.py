@@ -212,7 +212,9 @@ def bench_quench(torch, xyl, workloads, nsteps):
     ens.close()
     return {"replicas": len(specs), "sites": sites, "steps": nsteps, "launch": list(launch),
             "site_updates_per_s": sites * nsteps / (t1 - t0),
-            "full_run_site_updates": sum(s.Lx * s.Ly * s.nsteps for s in specs)}
+            "full_run_site_updates": sum(s.Lx * s.Ly * s.nsteps for s in specs),
+            # the whole batch (each replica's ramp and hold) at this rate
+            "full_run_projected_s": sum(s.Lx * s.Ly * s.nsteps for s in specs) / (sites * nsteps / (t1 - t0))}
 
 
 def bench_adjoint(torch, xyl, workloads):
