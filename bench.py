@@ -312,6 +312,40 @@ def bench_si_4096(torch, xyl, workloads, nlaunch=500, launch=None):
     return {"L": 4096, "model": "si", "p": spec.p, "T": spec.schedule[0][1], **out}
 
 
+def bench_c1_temperatures(torch, xyl, workloads, nsteps=20000, every=500):
+    """The single-lattice configuration at all eight of its temperatures
+    (T = 0.3 .. 1.2), batched: eight 4096^2 FP32 replicas advanced together,
+    energy and staggered order parameter every 500 steps, and the Binder
+    cumulant of each temperature from its samples after the first 20%.  A
+    bounded number of steps (the configuration runs 100,000); the rate is what
+    the full run would proceed at."""
+    specs = [workloads.large_fp32(j) for j in range(8)]
+    ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        ens.autotune()
+        ens.step(4)
+        ens.sync()
+        t0 = time.perf_counter()
+        samples = ens.step(nsteps, every=every)
+        ens.sync()
+        dt = time.perf_counter() - t0
+    finally:
+        ens.close()
+    sites = sum(sp.Lx * sp.Ly for sp in specs)
+    rate = sites * nsteps / dt
+    per_T = []
+    for sp, smp in zip(specs, samples):
+        m = smp[:, 2]
+        try:
+            U, se = xyl.binder(m, discard=len(m) // 5)
+        except xyl.XylError:
+            U, se = None, None
+        per_T.append({"T": sp.schedule[0][1], "U": U, "U_se": se, "e_pot": float(smp[-1, 0]),
+                      "m_s": float(m[-1]), "samples": int(len(m))})
+    return {"replicas": len(specs), "L": 4096, "steps": nsteps, "sample_every": every, "site_updates_per_s": rate,
+            "full_run_projected_s": sites * 100_000 / rate, "per_temperature": per_T}
+
+
 def bench_fp64_4096(torch, xyl, workloads, nsteps=200):
     """The FP64 single-step kernel on the headline's lattice: 32 B per
     site-update (read theta, u; write theta', u' in binary64), against 8 TB/s.
@@ -671,7 +705,8 @@ def main():
                 "si": lambda: bench_si_4096(torch, xyl, workloads, launch=fixed),
                 "structure": lambda: bench_structure_factor(torch, xyl, workloads),
                 "si_fss": lambda: bench_si_fss(torch, xyl, workloads),
-                "fp64": lambda: bench_fp64_4096(torch, xyl, workloads)}
+                "fp64": lambda: bench_fp64_4096(torch, xyl, workloads),
+                "c1": lambda: bench_c1_temperatures(torch, xyl, workloads)}
         print(json.dumps({k: runs[k]() for k in args.only.split(",")}), flush=True)
         return
     L = args.L
@@ -771,6 +806,8 @@ def main():
         log("si model FSS ensemble:", extras["si_fss"])
         extras["fp64_4096"] = bench_fp64_4096(torch, xyl, workloads)
         log("fp64 4096^2:", extras["fp64_4096"])
+        extras["c1_temperatures"] = bench_c1_temperatures(torch, xyl, workloads)
+        log("4096^2 at eight temperatures:", extras["c1_temperatures"])
 
     cpu = None if args.no_cpu else cpu_baseline(L, args.cpu_steps)
     if cpu:
