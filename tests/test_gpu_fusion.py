@@ -89,6 +89,33 @@ def test_fused_run_from_a_fresh_state_matches_oracle(xyl):
     assert d <= 1e-4
 
 
+@pytest.mark.parametrize("Lx,Ly,model", [(8200, 6, "xy"), (4100, 9, "xy"), (448, 33, "xy")])
+def test_fused_tiles_and_partial_waves_match_oracle(xyl, Lx, Ly, model):
+    """Column tiles (8200 and 4100 wide) and a partial last wave (448) in the
+    two-step pass against the FP64 oracle over 100 steps from the same
+    FP32-representable start, to the FP32 bar at every site.  (The Si model's
+    tiles are held bitwise to single steps above; its field has a cusp at the
+    half-circle wrap, where a site FP32 puts on the other side of the cusp may
+    leave this bar, so its per-site bar is the fraction test at full size.)"""
+    if model == "si":
+        spec = workloads.si_lattice(Lx, Ly, seed=9, replica=4)
+        th, om = workloads.half_circle_state(Lx, Ly, seed=21, omega_scale=0.5)
+        period = np.pi
+    else:
+        spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.7), (50, 0.3)), seed=9, replica=4)
+        th, om = workloads.random_state(Lx, Ly, seed=21, omega_scale=0.5)
+        period = 2 * np.pi
+    th = th.astype(np.float32).astype(np.float64)
+    om = om.astype(np.float32).astype(np.float64)
+    say("fused vs oracle", Lx, Ly, model)
+    got = run(xyl, spec, 2, [100], 32, state=(th, om))
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    tr, _ = o.run(th, om, 0, 100)
+    d = np.abs(np.remainder(got[0] - tr + period / 2, period) - period / 2).max()
+    say("max|dtheta|", d)
+    assert d <= 1e-4
+
+
 def test_fusion_keeps_measurement_and_state_buffers(xyl):
     """Sampled runs (measurement steps are single steps) and the lattice's own
     buffers: after fused stepping the velocity lives in the lattice's buffer."""
