@@ -12,11 +12,12 @@ Si model: its field term sin(p th) with p = 2.5 is not periodic under the
 half-circle wrap, so the force jumps where a site crosses +-pi/2.  A site that
 one side puts just above the boundary and the other just below takes a
 different kick, and its neighbourhood follows.  That is the model's own
-sensitivity, not the kernel's: two FP64 oracle runs of 2048^2 whose starts
-differ by 6e-8 relative (FP32 rounding) differ by up to 4.5e-3 within 20
-steps, at 3 of 4.2 M sites beyond 1e-4 and 10 beyond 1e-6.  The bar there is
-per site for all but a 1e-5 fraction (<= 1e-4), and the samples' observables
-as for XY.
+sensitivity, not the kernel's: the FP64 oracle whose state is rounded to
+binary32 after every step departs from the plain FP64 oracle on this lattice
+by up to 9.4e-3 within these 20 steps, at 12 of 16.8 M sites beyond 1e-4
+(tests/test_oracle_sensitivity.py).  The bar there is therefore per site for
+all but a 1e-5 fraction (<= 1e-4), which that oracle pair also meets, and the
+samples' observables as for XY.
 
 The structure-factor modes F(q) of the samples are squares of sums over all
 N sites: their bar grows with sqrt(F N) times the FP32 rotor's per-term error

@@ -6,8 +6,9 @@ an FP64 state within 1e-10; FP32 trajectories within 1e-4 over 100 steps.  FP64
 trajectories: within 1e-12 over 100 steps; over longer runs the bar follows the
 trajectory's own sensitivity to rounding, which at the paper's couplings
 (|Jx| = 10) is about a thousand times that of the XY model: two oracle runs
-whose starts differ by 1e-16 relative (random) differ by up to 1.2e-10 within
-1000 steps (6e-12 within 250), so the bar there is ten times that.  Angles are compared
+whose starts differ by one ulp per site (random direction) differ by up to
+2e-10 within 1000 steps (4e-12 within 200), so the bars there are at least
+five times that spread (tests/test_oracle_sensitivity.py recomputes it).  Angles are compared
 modulo pi, the period of the half circle.  Besides the oracle, the GPU path is
 pinned to the canonical distribution of rings of rotors (the paper's pair
 benchmark, App. A.2, generalised to rings of four), computed by a transfer
