@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define XYL_ABI_VERSION 3
+#define XYL_ABI_VERSION 4
 
 enum {
     XYL_OK = 0,
@@ -154,6 +154,14 @@ int xyl_init_ordered(xyl_lattice* h, int32_t sign);
  * and sets the step index.  theta entries must be finite with |th| <= 3 pi
  * (XY) or, after rounding to the state precision, in [-pi_p/2, pi_p/2) (SI). */
 int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint64_t step);
+/* The same from caller-owned device buffers on the lattice's device: theta
+ * and omega hold Lx*Ly elements of precision dtype (XYL_F32 or XYL_F64, e.g.
+ * torch tensors), converted to the state precision on the device.  The
+ * entries are checked where they lie (same rules as xyl_set_state; EINVAL and
+ * the lattice unchanged if any fails); only the verdict crosses to the host.
+ * The buffers must not overlap the lattice's own state buffers and must be
+ * ready on its stream; the call returns once they have been read. */
+int xyl_set_state_device(xyl_lattice* h, const void* theta, const void* omega, int32_t dtype, uint64_t step);
 /* Copies the synchronized state (th^k, w^k) at the current step to host
  * float64 arrays (either may be NULL) and the step index (may be NULL). */
 int xyl_get_state(xyl_lattice* h, double* theta, double* omega, uint64_t* step);
@@ -369,15 +377,31 @@ int xyl_ensemble_sync(xyl_ensemble* e);
 
 /* ---------------------------------------------------------------- adjoint */
 /* Pathwise gradients with the Gaussian draws held fixed (a training-style
- * reverse mode of the discrete BBK map of App. A.1; the wrap has derivative
- * 1).  Loss L = (1/W) sum_{k=k0+N-W+1}^{k0+N} m_s(th^k)^2.
+ * reverse mode of the discrete BBK map of App. A.1, Eqs. BBK-1 and BBK-2; the
+ * wrap has derivative 1).  Loss L = (1/W) sum_{k=k0+N-W+1}^{k0+N} m_s(th^k)^2.
  * xyl_adjoint_forward runs N steps from the current state, keeping a
- * checkpoint every `ckpt_every` steps, and returns L; the lattice advances.
+ * checkpoint every `ckpt_every` steps, returns L and (run, nullable) an
+ * identifier of this run; the lattice advances.  1 <= W <= N.
+ * XYL_MODEL_XY only.
  * xyl_adjoint_backward then returns dL/d(Jx, Jy, h, gamma) in grad[4] (gamma
  * must be > 0 when T > 0) and writes dL/d th^{k0} and dL/d w^{k0} as float64
- * host arrays (nullable).  1 <= W <= N.  XYL_MODEL_XY only. */
-int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss);
-int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* domega0);
+ * host arrays (nullable).  `run` must name the lattice's latest forward run,
+ * and the lattice must not have been stepped, re-initialised or given other
+ * parameters, schedule, seed, model or launch shape since: otherwise
+ * XYL_ESTATE (a second forward on the same lattice replaces the checkpoints
+ * of the first, so the first run can no longer be differentiated).  A run
+ * may be differentiated more than once.
+ * xyl_adjoint_backward_device is the same with every output multiplied by
+ * `scale` (e.g. an upstream derivative dF/dL), grad[4] on the host and the
+ * state adjoints written into caller-owned device buffers of Lx*Ly elements
+ * of precision dtype (XYL_F32 or XYL_F64; nullable) on the lattice's stream:
+ * no per-site array passes through the host.  Returns after the stream has
+ * finished (the buffers are then ready for any stream). */
+int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss,
+                        uint64_t* run);
+int xyl_adjoint_backward(xyl_lattice* h, uint64_t run, double* grad, double* dtheta0, double* domega0);
+int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, double* grad, void* dtheta0,
+                                void* domega0, int32_t dtype);
 
 #ifdef __cplusplus
 }

@@ -119,8 +119,10 @@ _SIGS = {
     "xyl_ensemble_set_state": (_i32, [_vp, _i32, P(_d), P(_d), _u64]),
     "xyl_ensemble_domains": (_i32, [_vp, _i32, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
     "xyl_ensemble_sync": (_i32, [_vp]),
-    "xyl_adjoint_forward": (_i32, [_vp, _u64, _u64, _u64, P(_d)]),
-    "xyl_adjoint_backward": (_i32, [_vp, P(_d), P(_d), P(_d)]),
+    "xyl_adjoint_forward": (_i32, [_vp, _u64, _u64, _u64, P(_d), P(_u64)]),
+    "xyl_adjoint_backward": (_i32, [_vp, _u64, P(_d), P(_d), P(_d)]),
+    "xyl_adjoint_backward_device": (_i32, [_vp, _u64, _d, P(_d), _vp, _vp, _i32]),
+    "xyl_set_state_device": (_i32, [_vp, _vp, _vp, _i32, _u64]),
 }
 
 
@@ -191,6 +193,7 @@ class Lattice:
         self.device = int(device)
         self._h = _vp()
         self._bufs = None
+        self.adjoint_run = 0
         if torch_buffers:
             tdt = torch.float32 if self.dtype == F32 else torch.float64
             dev = torch.device("cuda", self.device)
@@ -287,6 +290,14 @@ class Lattice:
         th = _f64(theta, (self.Ly, self.Lx))
         om = _f64(omega, (self.Ly, self.Lx))
         _check(load().xyl_set_state(self._h, _pd(th), _pd(om), int(step)))
+
+    def set_state_device(self, theta, omega, step: int = 0):
+        """The state from two CUDA tensors of Lx*Ly float32 or float64 elements
+        (same dtype, on the lattice's device): checked and converted on the
+        device; nothing per site crosses to the host."""
+        th, om = _device_arrays(theta, omega, self.N, self.device)
+        _check(load().xyl_set_state_device(self._h, _vp(th.data_ptr()), _vp(om.data_ptr()),
+                                           _dtype_code_torch(th.dtype), int(step)))
 
     def get_state(self):
         th = np.empty((self.Ly, self.Lx))
@@ -398,16 +409,65 @@ class Lattice:
 
     # -- gradients ---------------------------------------------------------------------
     def adjoint_forward(self, nsteps: int, ckpt_every: int, window: int) -> float:
-        L = _d()
-        _check(load().xyl_adjoint_forward(self._h, int(nsteps), int(ckpt_every), int(window), ctypes.byref(L)))
+        """Runs the forward pass and returns the loss; the run's identifier is
+        kept as ``adjoint_run`` (what ``adjoint_backward`` differentiates)."""
+        L, run = _d(), _u64()
+        _check(load().xyl_adjoint_forward(self._h, int(nsteps), int(ckpt_every), int(window), ctypes.byref(L),
+                                          ctypes.byref(run)))
+        self.adjoint_run = run.value
         return L.value
 
-    def adjoint_backward(self):
+    def adjoint_backward(self, run: Optional[int] = None):
+        """(dL/d[Jx, Jy, h, gamma], dL/dtheta0, dL/domega0) as host arrays, of
+        the forward run `run` (default: the latest)."""
         g = np.empty(4)
         dth = np.empty((self.Ly, self.Lx))
         dom = np.empty((self.Ly, self.Lx))
-        _check(load().xyl_adjoint_backward(self._h, _pd(g), _pd(dth), _pd(dom)))
+        run = self.adjoint_run if run is None else int(run)
+        _check(load().xyl_adjoint_backward(self._h, run, _pd(g), _pd(dth), _pd(dom)))
         return g, dth, dom
+
+    def adjoint_backward_device(self, dtheta0, domega0, run: Optional[int] = None, scale: float = 1.0):
+        """dL/d[Jx, Jy, h, gamma] times `scale` (host array); writes scale *
+        dL/dtheta0 and scale * dL/domega0 into two CUDA tensors of Lx*Ly float32
+        or float64 elements (either may be None)."""
+        g = np.empty(4)
+        run = self.adjoint_run if run is None else int(run)
+        ptrs, code = [], F64
+        for t in (dtheta0, domega0):
+            if t is None:
+                ptrs.append(None)
+                continue
+            _device_arrays(t, t, self.N, self.device)
+            code = _dtype_code_torch(t.dtype)
+            ptrs.append(_vp(t.data_ptr()))
+        if dtheta0 is not None and domega0 is not None and dtheta0.dtype != domega0.dtype:
+            raise ValueError("dtheta0 and domega0 must have the same dtype")
+        _check(load().xyl_adjoint_backward_device(self._h, run, float(scale), _pd(g), ptrs[0], ptrs[1], code))
+        return g
+
+
+def _dtype_code_torch(dt) -> int:
+    import torch
+    if dt == torch.float32:
+        return F32
+    if dt == torch.float64:
+        return F64
+    raise ValueError("device arrays must be float32 or float64")
+
+
+def _device_arrays(a, b, n, device):
+    """Checks that a and b are contiguous CUDA tensors of n elements of one
+    floating dtype on `device` (no copies are made)."""
+    for t in (a, b):
+        if not getattr(t, "is_cuda", False) or t.device.index != device:
+            raise ValueError("expected CUDA tensors on device %d" % device)
+        if t.numel() != n or not t.is_contiguous():
+            raise ValueError("expected contiguous tensors of %d elements" % n)
+    if a.dtype != b.dtype:
+        raise ValueError("theta and omega must have the same dtype")
+    _dtype_code_torch(a.dtype)
+    return a, b
 
 
 def _checksum(d) -> bytes:
@@ -609,22 +669,41 @@ def _langevin_loss_class():
 
         @staticmethod
         def forward(ctx, params, theta0, omega0, lattice, nsteps, ckpt_every, window):
+            # the four parameters are host scalars; the initial state stays on
+            # the device (the library checks and converts it there)
             p = [float(v) for v in params.detach().cpu().double().tolist()]
             lattice.set_params(p[0], p[1], p[2], p[3], lattice.params["dt"])
-            lattice.set_state(theta0.detach().cpu().double().numpy(), omega0.detach().cpu().double().numpy(), 0)
+            th = theta0.detach().contiguous()
+            om = omega0.detach().contiguous()
+            if th.is_cuda:
+                # the library works on the lattice's stream: torch's pending
+                # writes of the inputs must be done first
+                torch.cuda.current_stream(th.device).synchronize()
+                lattice.set_state_device(th.view(-1), om.view(-1), 0)
+            else:
+                lattice.set_state(th.double().numpy(), om.double().numpy(), 0)
             L = lattice.adjoint_forward(int(nsteps), int(ckpt_every), int(window))
             ctx.lattice = lattice
+            ctx.run = lattice.adjoint_run
             ctx.meta = (params.dtype, params.device, theta0.dtype, theta0.device, theta0.shape)
             return torch.tensor(L, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gL):
-            g, dth, dom = ctx.lattice.adjoint_backward()
             pdt, pdev, tdt, tdev, shape = ctx.meta
-            s = float(gL)
-            gp = torch.tensor(g * s, dtype=pdt, device=pdev)
-            gth = torch.from_numpy(dth * s).to(dtype=tdt, device=tdev).reshape(shape)
-            gom = torch.from_numpy(dom * s).to(dtype=tdt, device=tdev).reshape(shape)
+            # outputs are allocated by torch and filled by the library's
+            # kernels, scaled by the upstream derivative; a later forward on
+            # the same lattice makes ctx.run stale (the library then raises)
+            if tdev.type == "cuda":
+                gth = torch.empty(shape, dtype=tdt, device=tdev)
+                gom = torch.empty(shape, dtype=tdt, device=tdev)
+                g = ctx.lattice.adjoint_backward_device(gth.view(-1), gom.view(-1), run=ctx.run, scale=float(gL))
+            else:
+                g, dth, dom = ctx.lattice.adjoint_backward(run=ctx.run)
+                g = g * float(gL)
+                gth = torch.from_numpy(dth * float(gL)).to(tdt).reshape(shape)
+                gom = torch.from_numpy(dom * float(gL)).to(tdt).reshape(shape)
+            gp = torch.tensor(g, dtype=pdt, device=pdev)
             return gp, gth, gom, None, None, None, None
 
     return LangevinLoss

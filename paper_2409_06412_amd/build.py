@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxyl.so")
-SOURCES = ["xyl_step.hip", "xyl_obs.hip", "xyl_adjoint.hip", "xyl_runtime.hip"]
+SOURCES = ["xyl_step.hip", "xyl_obs.hip", "xyl_adjoint.hip", "xyl_state.hip", "xyl_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -189,6 +189,18 @@ int lds_threads(int N);
 void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites, int model,
                          uint64_t j0, hipStream_t s);
 
+// State transfer between caller device buffers and a lattice (xyl_state.hip).
+// launch_check_state ORs kStateBad* bits into *flag (which must start at 0)
+// for offending elements of a caller's (theta, omega); launch_convert writes
+// out[i] = in[i] (or in[i] * scale in FP64) rounded to the output precision;
+// launch_fill_u32 sets n words (a kernel, so it may be captured in a graph).
+enum : uint32_t { kStateBadTheta = 1u, kStateBadOmega = 2u, kStateBadHalfCircle = 4u };
+void launch_check_state(const void* th, const void* om, int src_f64, size_t n, int half_circle, int state_f64,
+                        uint32_t* flag, hipStream_t s);
+void launch_convert(const void* in, int in_f64, void* out, int out_f64, size_t n, double scale, bool scaled,
+                    hipStream_t s);
+void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
 struct Error : std::runtime_error {
     int code;
     Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}

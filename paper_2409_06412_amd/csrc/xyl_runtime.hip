@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -286,6 +287,7 @@ struct xyl_lattice {
     DevBuf<uint32_t> usz;
     DevBuf<uint32_t> hist;
     DevBuf<uint32_t> stats;
+    DevBuf<uint32_t> flag;        // validation result of xyl_set_state_device
     // adjoint state (see xyl_adjoint.hip)
     void* adj = nullptr;
 
@@ -318,6 +320,8 @@ struct xyl_lattice {
 // device buffers of the reverse sweep.
 struct AdjState {
     bool valid = false;          // a forward run completed and may be differentiated
+    uint64_t run = 0;            // identifier of that run (process-wide, never reused)
+    uint64_t version = 0;        // the lattice's configuration version when it ended
     uint64_t k0 = 0, N = 0, K = 0, W = 0;
     double loss = 0.0;
     std::vector<double> m;       // m_s at steps k0+N-W+1 .. k0+N
@@ -354,6 +358,11 @@ struct AdjState {
         if (side) (void)hipStreamDestroy(side);
     }
 };
+
+// Identifiers of adjoint forward runs: a backward call names the run it
+// differentiates, and a later forward on the same lattice (which replaces the
+// checkpoints) makes earlier identifiers stale.
+static std::atomic<uint64_t> g_adj_runs{0};
 
 static void adjoint_release(xyl_lattice* h) {
     delete static_cast<AdjState*>(h->adj);
@@ -896,6 +905,35 @@ int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint
             to_device<float>(h->cur_theta(), theta, h->N, h->stream);
             to_device<float>(h->u, omega, h->N, h->stream);
         }
+        h->initialized = true;
+    });
+}
+
+int xyl_set_state_device(xyl_lattice* h, const void* theta, const void* omega, int32_t dtype, uint64_t step) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
+        require(dtype == XYL_F32 || dtype == XYL_F64, XYL_EINVAL, "dtype must be XYL_F32 or XYL_F64");
+        DeviceGuard g(h->device);
+        const int src64 = dtype == XYL_F64 ? 1 : 0, st64 = h->dtype == XYL_F64 ? 1 : 0;
+        // validate where the state lies; only the verdict comes back
+        h->flag.reserve(1);
+        launch_fill_u32(h->flag.p, 1, 0u, h->stream);
+        launch_check_state(theta, omega, src64, h->N, h->p.model == kModelSI ? 1 : 0, st64, h->flag.p, h->stream);
+        uint32_t bad = 0;
+        check_hip(hipMemcpyAsync(&bad, h->flag.p, sizeof(bad), hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        require(!(bad & kStateBadTheta), XYL_EINVAL, "theta entries must be finite with |theta| <= 3 pi");
+        require(!(bad & kStateBadOmega), XYL_EINVAL, "omega entries must be finite");
+        require(!(bad & kStateBadHalfCircle), XYL_EINVAL, "theta entries must lie in [-pi/2, pi/2) for the SI model");
+        h->k = step;
+        h->fresh_k = step;
+        h->counter_valid = false;
+        h->touch();
+        launch_convert(theta, src64, h->cur_theta(), st64, h->N, 1.0, false, h->stream);
+        launch_convert(omega, src64, h->u, st64, h->N, 1.0, false, h->stream);
+        // the caller may release or rewrite its buffers once this returns
+        check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         h->initialized = true;
     });
 }
@@ -2429,7 +2467,7 @@ int xyl_ensemble_sync(xyl_ensemble* e) {
 
 // ===================================================================== adjoint
 template <typename R>
-static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_t W, double* loss) {
+static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_t W, double* loss, uint64_t* run) {
     // the state (buffers, streams, captured backward graphs) is kept from one
     // forward run to the next, so repeated gradient evaluations reuse it
     if (!h->adj) h->adj = new AdjState();
@@ -2488,11 +2526,19 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
     }
     a->loss = L / (double)W;
     if (loss) *loss = a->loss;
+    a->run = ++g_adj_runs;
+    a->version = h->version;
     a->valid = true;
+    if (run) *run = a->run;
 }
 
+// Gradients of the lattice's adjoint run into grad[4] (host, times `scale`) and dL/dth^{k0},
+// dL/dw^{k0}: host float64 arrays (dth0, dom0) or, with dev_out, caller
+// device buffers of precision out_f64 (written on the lattice's stream, times
+// `scale`).
 template <typename R>
-static void adjoint_backward_impl(xyl_lattice* h, double* grad, double* dth0, double* dom0) {
+static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void* dom0, bool dev_out, int out_f64,
+                                  double scale) {
     AdjState* a = static_cast<AdjState*>(h->adj);
     const size_t bytes = sizeof(R) * h->N;
     const uint64_t N = a->N, K = a->K, W = a->W, k0 = a->k0;
@@ -2635,32 +2681,44 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, double* dth0, do
         }
         check_hip(hipEventRecord(a->ev_rev[b], h->stream), "hipEventRecord");
     }
+    constexpr int kR64 = sizeof(R) == 8 ? 1 : 0;
+    if (dev_out) {
+        // the state adjoints stay on the device: converted (and scaled) into
+        // the caller's buffers on the lattice's stream
+        if (dth0) launch_convert(lt[li], kR64, dth0, out_f64, h->N, scale, true, h->stream);
+        if (dom0) launch_convert(lu[li], kR64, dom0, out_f64, h->N, scale, true, h->stream);
+    }
     std::vector<double> g((size_t)ntasks * 4);
     check_hip(hipMemcpyAsync(g.data(), a->gacc.p, sizeof(double) * ntasks * 4, hipMemcpyDeviceToHost, h->stream),
               "D2H");
-    if (dth0) {
+    if (!dev_out && dth0) {
         std::vector<R> t(h->N);
         check_hip(hipMemcpyAsync(t.data(), lt[li], bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        for (size_t i = 0; i < h->N; ++i) dth0[i] = (double)t[i];
+        double* o = static_cast<double*>(dth0);
+        for (size_t i = 0; i < h->N; ++i) o[i] = (double)t[i];
     }
-    if (dom0) {
+    if (!dev_out && dom0) {
         std::vector<R> t(h->N);
         check_hip(hipMemcpyAsync(t.data(), lu[li], bytes, hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        for (size_t i = 0; i < h->N; ++i) dom0[i] = (double)t[i];
+        double* o = static_cast<double*>(dom0);
+        for (size_t i = 0; i < h->N; ++i) o[i] = (double)t[i];
     }
     check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     if (grad) {
         for (int p = 0; p < 4; ++p) grad[p] = 0.0;
         for (int t = 0; t < ntasks; ++t)
             for (int p = 0; p < 4; ++p) grad[p] += g[(size_t)t * 4 + p];
+        if (dev_out)
+            for (int p = 0; p < 4; ++p) grad[p] *= scale;
     }
 }
 
 extern "C" {
 
-int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss) {
+int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, uint64_t window, double* loss,
+                        uint64_t* run) {
     return guarded([&] {
         require_init(h);
         require(nsteps >= 1, XYL_EINVAL, "nsteps must be >= 1");
@@ -2669,21 +2727,43 @@ int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, ui
         require(h->p.model == kModelXY, XYL_EUNSUPPORTED,
                 "the adjoint needs a smooth force: the SI model's field jumps at the wrap point");
         DeviceGuard g(h->device);
-        if (h->dtype == XYL_F64) adjoint_forward_impl<double>(h, nsteps, ckpt_every, window, loss);
-        else adjoint_forward_impl<float>(h, nsteps, ckpt_every, window, loss);
+        if (h->dtype == XYL_F64) adjoint_forward_impl<double>(h, nsteps, ckpt_every, window, loss, run);
+        else adjoint_forward_impl<float>(h, nsteps, ckpt_every, window, loss, run);
     });
 }
 
-int xyl_adjoint_backward(xyl_lattice* h, double* grad, double* dtheta0, double* domega0) {
+// The forward run `run` may be differentiated: it is the lattice's latest,
+// and neither the state nor any parameter changed since.
+static void require_adjoint_run(xyl_lattice* h, uint64_t run) {
+    require_init(h);
+    AdjState* a = static_cast<AdjState*>(h->adj);
+    require(a != nullptr && a->valid, XYL_ESTATE, "no adjoint forward run to differentiate");
+    require(run == a->run, XYL_ESTATE,
+            "stale adjoint run: another xyl_adjoint_forward replaced its checkpoints on this lattice");
+    require(h->k == a->k0 + a->N && h->version == a->version, XYL_ESTATE,
+            "lattice was stepped, reset or reconfigured after xyl_adjoint_forward");
+    require(h->p.model == kModelXY, XYL_EUNSUPPORTED, "the adjoint supports the XY model only");
+}
+
+int xyl_adjoint_backward(xyl_lattice* h, uint64_t run, double* grad, double* dtheta0, double* domega0) {
     return guarded([&] {
-        require_init(h);
-        AdjState* a = static_cast<AdjState*>(h->adj);
-        require(a != nullptr && a->valid, XYL_ESTATE, "no adjoint forward run to differentiate");
-        require(h->k == a->k0 + a->N, XYL_ESTATE, "lattice was stepped or reset after xyl_adjoint_forward");
-        require(h->p.model == kModelXY, XYL_EUNSUPPORTED, "the adjoint supports the XY model only");
+        require_adjoint_run(h, run);
         DeviceGuard g(h->device);
-        if (h->dtype == XYL_F64) adjoint_backward_impl<double>(h, grad, dtheta0, domega0);
-        else adjoint_backward_impl<float>(h, grad, dtheta0, domega0);
+        if (h->dtype == XYL_F64) adjoint_backward_impl<double>(h, grad, dtheta0, domega0, false, 1, 1.0);
+        else adjoint_backward_impl<float>(h, grad, dtheta0, domega0, false, 1, 1.0);
+    });
+}
+
+int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, double* grad, void* dtheta0,
+                                void* domega0, int32_t dtype) {
+    return guarded([&] {
+        require_adjoint_run(h, run);
+        require(dtype == XYL_F32 || dtype == XYL_F64, XYL_EINVAL, "dtype must be XYL_F32 or XYL_F64");
+        require(std::isfinite(scale), XYL_EINVAL, "scale must be finite");
+        DeviceGuard g(h->device);
+        const int of64 = dtype == XYL_F64 ? 1 : 0;
+        if (h->dtype == XYL_F64) adjoint_backward_impl<double>(h, grad, dtheta0, domega0, true, of64, scale);
+        else adjoint_backward_impl<float>(h, grad, dtheta0, domega0, true, of64, scale);
     });
 }
 

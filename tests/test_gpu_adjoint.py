@@ -151,3 +151,120 @@ def test_repeated_gradients_reuse_state_correctly(xyl):
         np.testing.assert_array_equal(got[2], want[2])
         np.testing.assert_array_equal(got[3], want[3])
     shared.close()
+
+
+def test_stale_adjoint_runs_are_rejected(xyl):
+    """A second forward run on a lattice replaces the first one's checkpoints:
+    differentiating the first then fails (XYL_ESTATE) instead of returning
+    the second run's gradients; so does a run after the lattice was stepped,
+    re-initialised or given other parameters.  The latest run may be
+    differentiated repeatedly, with the same result."""
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=5, replica=0)
+    lat = xyl.Lattice(64, 32, dtype="f64", **spec)
+    lat.init_random()
+    lat.adjoint_forward(60, 20, 10)
+    first = lat.adjoint_run
+    lat.init_random()
+    lat.set_params(1.1, -0.1, 0.5, 1.0, 0.01)
+    lat.adjoint_forward(60, 20, 10)
+    second = lat.adjoint_run
+    assert second != first
+    with pytest.raises(xyl.XylError) as e:
+        lat.adjoint_backward(run=first)
+    assert e.value.code == -4 and "stale" in str(e.value)
+    g1 = lat.adjoint_backward(run=second)
+    g2 = lat.adjoint_backward(run=second)
+    for a, b in zip(g1, g2):
+        np.testing.assert_array_equal(a, b)
+    lat.set_params(1.0, -0.1, 0.5, 1.0, 0.01)
+    with pytest.raises(xyl.XylError) as e:
+        lat.adjoint_backward(run=second)
+    assert e.value.code == -4
+    lat.close()
+
+
+def test_stale_run_through_autograd(xyl):
+    """Two losses evaluated on one lattice before their backward: the first
+    loss's backward refuses (the lattice holds the second run), rather than
+    differentiating the wrong trajectory."""
+    import torch
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=5, replica=0)
+    lat = xyl.Lattice(64, 32, dtype="f64", **spec)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    th = torch.tensor(th0, device="cuda", requires_grad=True)
+    om = torch.tensor(om0, device="cuda", requires_grad=True)
+    p1 = torch.tensor([1.0, -0.1, 0.5, 1.0], dtype=torch.float64, requires_grad=True)
+    p2 = torch.tensor([1.1, -0.1, 0.5, 1.0], dtype=torch.float64, requires_grad=True)
+    L1 = xyl.langevin_loss(p1, th, om, lat, 60, 20, 10)
+    L2 = xyl.langevin_loss(p2, th, om, lat, 60, 20, 10)
+    L2.backward()
+    assert p2.grad is not None
+    with pytest.raises(xyl.XylError):
+        L1.backward()
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_device_outputs_equal_host_outputs(xyl, dtype):
+    """xyl_adjoint_backward_device writes the host path's state adjoints
+    (times a scale) into device buffers of either precision."""
+    import torch
+    spec = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=2, replica=1)
+    lat = xyl.Lattice(72, 20, dtype=dtype, **spec)
+    lat.init_random()
+    lat.adjoint_forward(80, 20, 16)
+    g, dth, dom = lat.adjoint_backward()
+    scale = -2.5
+    for tdt in (torch.float64, torch.float32):
+        gth = torch.full((20 * 72,), 7.0, dtype=tdt, device="cuda")
+        gom = torch.full((20 * 72,), 7.0, dtype=tdt, device="cuda")
+        gd = lat.adjoint_backward_device(gth, gom, scale=scale)
+        np.testing.assert_allclose(gd, scale * g, rtol=1e-15, atol=0)
+        want_th = (scale * dth.ravel()).astype(tdt == torch.float32 and np.float32 or np.float64)
+        want_om = (scale * dom.ravel()).astype(tdt == torch.float32 and np.float32 or np.float64)
+        np.testing.assert_array_equal(gth.cpu().numpy(), want_th)
+        np.testing.assert_array_equal(gom.cpu().numpy(), want_om)
+    lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_set_state_device(xyl, dtype):
+    """The device setter equals the host setter from float32 and float64
+    tensors, and rejects what the host setter rejects, leaving the lattice
+    as it was."""
+    import torch
+    Lx, Ly = 40, 12
+    rng = np.random.default_rng(4)
+    th = rng.uniform(-np.pi, np.pi, (Ly, Lx))
+    om = rng.standard_normal((Ly, Lx))
+    a = xyl.Lattice(Lx, Ly, dtype=dtype, schedule=[(0, 0.5)], seed=3)
+    b = xyl.Lattice(Lx, Ly, dtype=dtype, schedule=[(0, 0.5)], seed=3)
+    for tdt in (torch.float64, torch.float32):
+        src_th = th.astype(np.float32).astype(np.float64) if tdt == torch.float32 else th
+        src_om = om.astype(np.float32).astype(np.float64) if tdt == torch.float32 else om
+        a.set_state(src_th, src_om, 5)
+        b.set_state_device(torch.tensor(th, dtype=tdt, device="cuda").view(-1),
+                           torch.tensor(om, dtype=tdt, device="cuda").view(-1), 5)
+        a.step(7)
+        b.step(7)
+        for x, y in zip(a.get_state(), b.get_state()):
+            np.testing.assert_array_equal(x, y)
+    before = b.get_state()
+    bad = torch.tensor(th, dtype=torch.float64, device="cuda").view(-1)
+    okw = torch.tensor(om, dtype=torch.float64, device="cuda").view(-1)
+    for i, v in ((3, float("nan")), (100, 3.0 * np.pi + 1e-6)):
+        t = bad.clone()
+        t[i] = v
+        with pytest.raises(xyl.XylError) as e:
+            b.set_state_device(t, okw, 0)
+        assert e.value.code == -1
+    w = okw.clone()
+    w[7] = float("inf")
+    with pytest.raises(xyl.XylError):
+        b.set_state_device(bad, w, 0)
+    after = b.get_state()
+    for x, y in zip(before, after):
+        np.testing.assert_array_equal(x, y)
+    a.close()
+    b.close()
