@@ -221,6 +221,17 @@ int xyl_structure_factor(xyl_lattice* h, int32_t axis, int32_t kmax, double* S);
  * n_domains and max_size are nullable.  Synchronises. */
 int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
                 uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): xyl_domains
+ * with the same arguments and results, run without any device or host heap
+ * allocation.  Its working memory is a static device array of the library,
+ * one per device (about 48 MiB, held until the process ends), which limits
+ * the lattice to at most 2^22 sites (e.g. 2048 x 2048; EINVAL beyond).  Calls
+ * in one process are serialised by the library, since they all share the
+ * device's array (each process has its own); a call synchronises the
+ * handle's stream before it returns. */
+int xyl_domains_noalloc(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
+                        uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size);
 /* Blocks until all work issued on the handle's stream has finished. */
 int xyl_sync(xyl_lattice* h);
 

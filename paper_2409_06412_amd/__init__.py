@@ -123,6 +123,7 @@ _SIGS = {
     "xyl_adjoint_backward": (_i32, [_vp, _u64, P(_d), P(_d), P(_d)]),
     "xyl_adjoint_backward_device": (_i32, [_vp, _u64, _d, P(_d), _vp, _vp, _i32]),
     "xyl_set_state_device": (_i32, [_vp, _vp, _vp, _i32, _u64]),
+    "xyl_domains_noalloc": (_i32, [_vp, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
 }
 
 
@@ -370,6 +371,11 @@ class Lattice:
     def domains(self, want_labels: bool = True):
         """Returns (labels or None, sizes, counts, n_domains, max_size)."""
         return _domains(lambda *a: load().xyl_domains(self._h, *a), self.N, (self.Ly, self.Lx), want_labels)
+
+    def domains_noalloc(self, want_labels: bool = True):
+        """``domains`` through the library's allocation-free entry point (lattices
+        of at most 2^22 sites)."""
+        return _domains(lambda *a: load().xyl_domains_noalloc(self._h, *a), self.N, (self.Ly, self.Lx), want_labels)
 
     def noise(self, k: int) -> np.ndarray:
         out = np.empty((self.Ly, self.Lx))

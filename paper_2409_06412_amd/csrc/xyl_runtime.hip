@@ -1282,6 +1282,106 @@ int xyl_domains(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* coun
     });
 }
 
+}  // extern "C"
+
+// ----------------------------------------------- allocation-free domains
+// Scratch of xyl_domains_noalloc, the domain labelling for callers that cannot
+// allocate device memory: the union-find's parent, cluster-size and histogram
+// arrays and its (size, count) pair list for lattices of up to
+// kNoAllocMaxSites sites, 3 * 4 * 2^22 + 4 * (5 + 2 * 4096) bytes (about
+// 48 MiB).  Each device the library runs on holds one copy until the process
+// ends.  Host code never names the array itself (there it is a host-side
+// stand-in): it uses the device address hipGetSymbolAddress returns, looked up
+// once per device with that device current.
+constexpr size_t kNoAllocMaxSites = size_t(1) << 22;
+constexpr size_t kNoAllocMaxPairs = 4096;
+constexpr size_t kNoAllocWords = 3 * kNoAllocMaxSites + 1 + kDomainPairs + 2 * kNoAllocMaxPairs;
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;                         // one call at a time in this process
+static uint32_t* g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current); g_scratch_mu held.
+static uint32_t* scratch_address(int dev) {
+    require(dev >= 0 && dev < kNoAllocMaxDevices, XYL_EUNSUPPORTED, "device index beyond the scratch table");
+    if (!g_scratch_dev[dev]) {
+        uint32_t* ptr = nullptr;
+        check_hip(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        require(ptr != nullptr, XYL_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
+
+// xyl_domains on the static scratch: zeroed by kernels (no memset), results
+// read back into the caller's arrays and a fixed stack buffer (no heap).
+template <typename R>
+static void domains_noalloc(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
+                            uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size) {
+    const size_t N = h->N;
+    const uint32_t pcap = domain_size_cap(N);
+    require(pcap <= kNoAllocMaxPairs, XYL_EDEVICE, "size-distribution bound exceeds the scratch");
+    hipStream_t s = h->stream;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    uint32_t* base = scratch_address(h->device);
+    int32_t* parent = reinterpret_cast<int32_t*>(base);
+    uint32_t* usz = base + N;
+    uint32_t* hist = base + 2 * N;
+    uint32_t* stats = base + 3 * N + 1;
+    // the previous call's contents stay in the array: clear what must start at 0
+    launch_fill_u32(hist, N + 1, 0u, s);
+    launch_fill_u32(stats, kDomainPairs, 0u, s);
+    const int sx = h->p.Jx > 0.0, sy = h->p.Jy > 0.0;
+    launch_domains<R>(static_cast<const R*>(h->cur_theta()), h->Lx, h->Ly, sx, sy, h->p.model, parent, usz, hist,
+                      stats, s);
+    uint32_t head[kDomainPairs];
+    check_hip(hipMemcpyAsync(head, stats, sizeof(head), hipMemcpyDeviceToHost, s), "D2H");
+    if (labels) check_hip(hipMemcpyAsync(labels, parent, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s), "D2H");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const uint64_t ns = head[0];
+    require(ns >= 1 && ns <= pcap, XYL_EDEVICE, "domain size distribution overflowed its bound");
+    if (sizes || counts) require(cap >= ns, XYL_EINVAL, "size-distribution capacity too small");
+    // (size, count) pairs as two 32-bit words each; sorted by size as 64-bit
+    // keys size << 32 | count (sizes are distinct)
+    uint64_t pairs[kNoAllocMaxPairs];
+    check_hip(hipMemcpyAsync(pairs, stats + kDomainPairs, sizeof(uint32_t) * 2 * ns, hipMemcpyDeviceToHost, s),
+              "D2H");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (uint64_t j = 0; j < ns; ++j) {
+        uint32_t w[2];
+        std::memcpy(w, &pairs[j], sizeof(w));
+        pairs[j] = ((uint64_t)w[0] << 32) | (uint64_t)w[1];
+    }
+    std::sort(pairs, pairs + ns);
+    uint64_t nd = 0, covered = 0;
+    for (uint64_t j = 0; j < ns; ++j) {
+        const uint64_t sz = pairs[j] >> 32, ct = pairs[j] & 0xFFFFFFFFull;
+        if (sizes) sizes[j] = sz;
+        if (counts) counts[j] = ct;
+        nd += ct;
+        covered += sz * ct;
+    }
+    require(covered == N, XYL_EDEVICE, "domain sizes do not cover the lattice");
+    if (n_sizes) *n_sizes = ns;
+    if (n_domains) *n_domains = nd;
+    if (max_size) *max_size = pairs[ns - 1] >> 32;
+}
+
+extern "C" {
+
+int xyl_domains_noalloc(xyl_lattice* h, int32_t* labels, uint64_t* sizes, uint64_t* counts, uint64_t cap,
+                        uint64_t* n_sizes, uint64_t* n_domains, uint64_t* max_size) {
+    return guarded([&] {
+        require_init(h);
+        require(h->N <= kNoAllocMaxSites, XYL_EINVAL,
+                "xyl_domains_noalloc takes lattices of at most 2^22 sites (its static scratch)");
+        DeviceGuard g(h->device);
+        if (h->dtype == XYL_F64) domains_noalloc<double>(h, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+        else domains_noalloc<float>(h, labels, sizes, counts, cap, n_sizes, n_domains, max_size);
+    });
+}
+
 int xyl_sync(xyl_lattice* h) {
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");
