@@ -3,7 +3,8 @@
 Run ``python -m paper_2409_06412_amd.build`` (or ``__graft_entry__.build()``).
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
 selection disabled and without floating-point contraction (explicit fma calls
-fix the rounding order where it matters).
+fix the rounding order where it matters); the pure-host estimators are plain
+C++ built by the host compiler.
 """
 from __future__ import annotations
 
@@ -16,7 +17,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxyl.so")
 SOURCES = ["xyl_step.hip", "xyl_obs.hip", "xyl_adjoint.hip", "xyl_state.hip", "xyl_runtime.hip"]
+# pure-host C++ (no HIP header), compiled by the host compiler
+HOST_SOURCES = ["xyl_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-I", os.path.join(ROOT, "include"),
+              "-I", CSRC]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -33,6 +39,13 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))
+        objs.append(obj)
+    for src in HOST_SOURCES:
+        obj = os.path.join(bdir, src.replace(".cpp", ".o"))
+        cmd = [CXX, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))

@@ -6,6 +6,8 @@
 #include <stdexcept>
 #include <string>
 
+#include "xyl_error.hpp"
+
 namespace xyl {
 
 constexpr int kWave = 64;                  // CDNA wavefront width
@@ -200,11 +202,6 @@ void launch_check_state(const void* th, const void* om, int src_f64, size_t n, i
 void launch_convert(const void* in, int in_f64, void* out, int out_f64, size_t n, double scale, bool scaled,
                     hipStream_t s);
 void launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-
-struct Error : std::runtime_error {
-    int code;
-    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
 
 void check_hip(hipError_t e, const char* what);
 
