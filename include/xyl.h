@@ -165,6 +165,16 @@ int xyl_set_state_device(xyl_lattice* h, const void* theta, const void* omega, i
 /* Copies the synchronized state (th^k, w^k) at the current step to host
  * float64 arrays (either may be NULL) and the step index (may be NULL). */
 int xyl_get_state(xyl_lattice* h, double* theta, double* omega, uint64_t* step);
+/* The integrator's own state (App. A.1): the angles th^k, the velocity buffer
+ * u (w^{k-1/2}, the first half-kick's result, or w^k itself when *fresh is 1,
+ * i.e. right after an init or set_state call) and the step index, as float64
+ * host arrays (either may be NULL).  Restoring it with xyl_set_raw_state on a
+ * lattice of the same configuration continues the run bit for bit: this is
+ * the pair to checkpoint with.  (xyl_set_state with xyl_get_state's
+ * synchronized w^k restarts from a fresh state, which agrees only to
+ * rounding.)  The entries are checked as by xyl_set_state. */
+int xyl_get_raw_state(xyl_lattice* h, double* theta, double* u, uint64_t* step, int32_t* fresh);
+int xyl_set_raw_state(xyl_lattice* h, const double* theta, const double* u, uint64_t step, int32_t fresh);
 /* Device pointers of the current angle buffer and of the velocity buffer and
  * whether the velocity buffer holds w^k ("fresh", 1) or w^{k-1/2} (0). */
 int xyl_state_buffers(xyl_lattice* h, void** theta, void** vel, int32_t* fresh);

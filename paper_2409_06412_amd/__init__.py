@@ -124,6 +124,8 @@ _SIGS = {
     "xyl_adjoint_backward_device": (_i32, [_vp, _u64, _d, P(_d), _vp, _vp, _i32]),
     "xyl_set_state_device": (_i32, [_vp, _vp, _vp, _i32, _u64]),
     "xyl_domains_noalloc": (_i32, [_vp, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
+    "xyl_get_raw_state": (_i32, [_vp, P(_d), P(_d), P(_u64), P(_i32)]),
+    "xyl_set_raw_state": (_i32, [_vp, P(_d), P(_d), _u64, _i32]),
 }
 
 
@@ -307,6 +309,21 @@ class Lattice:
         _check(load().xyl_get_state(self._h, _pd(th), _pd(om), ctypes.byref(k)))
         return th, om, k.value
 
+    def get_raw_state(self):
+        """(theta, u, step, fresh): the integrator's own state, u being the
+        half-step velocity (or w^k when fresh); set_raw_state continues from it
+        bit for bit."""
+        th = np.empty((self.Ly, self.Lx))
+        u = np.empty((self.Ly, self.Lx))
+        k, f = _u64(), _i32()
+        _check(load().xyl_get_raw_state(self._h, _pd(th), _pd(u), ctypes.byref(k), ctypes.byref(f)))
+        return th, u, k.value, bool(f.value)
+
+    def set_raw_state(self, theta, u, step: int, fresh: bool):
+        th = _f64(theta, (self.Ly, self.Lx))
+        uu = _f64(u, (self.Ly, self.Lx))
+        _check(load().xyl_set_raw_state(self._h, _pd(th), _pd(uu), int(step), 1 if fresh else 0))
+
     @property
     def step_index(self) -> int:
         k = _u64()
@@ -387,10 +404,14 @@ class Lattice:
 
     # -- checkpoint --------------------------------------------------------------------
     def save(self, path: str):
-        """Writes the synchronized state, step index, parameters, schedule and noise key to an
-        .npz file with a checksum of the state; resuming from it continues bit for bit."""
-        th, om, k = self.get_state()
-        payload = dict(theta=th, omega=om, step=np.uint64(k), Lx=self.Lx, Ly=self.Ly, dtype=self.dtype,
+        """Writes the integrator's state (angles, stored velocities and whether
+        they are synchronized), the synchronized velocities for reference, the
+        step index, parameters, schedule and noise key to an .npz file with a
+        checksum; resuming from it continues bit for bit."""
+        th, u, k, fresh = self.get_raw_state()
+        _, om, _ = self.get_state()
+        payload = dict(theta=th, u=u, fresh=np.int32(fresh), omega=om, step=np.uint64(k), Lx=self.Lx, Ly=self.Ly,
+                       dtype=self.dtype,
                        params=np.array([self.params[n] for n in ("Jx", "Jy", "h", "gamma", "dt")]),
                        model=np.int32(self.model), p=np.float64(self.p),
                        schedule=np.array(self._schedule, dtype=np.float64),
@@ -410,7 +431,7 @@ class Lattice:
         lat = cls(int(d["Lx"]), int(d["Ly"]), dtype=int(d["dtype"]), device=device, Jx=p[0], Jy=p[1], h=p[2],
                   gamma=p[3], dt=p[4], schedule=sched, seed=seed, replica=rep, stream=stream,
                   model=int(d["model"]), p=float(d["p"]))
-        lat.set_state(d["theta"], d["omega"], int(d["step"]))
+        lat.set_raw_state(d["theta"], d["u"], int(d["step"]), bool(d["fresh"]))
         return lat
 
     # -- gradients ---------------------------------------------------------------------

@@ -258,16 +258,20 @@ __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n
                                             R& thnew) {
     if constexpr (sizeof(R) == 4) {
         // FP32: f arrives as the kick g = hdt F + hs n (site_force), used by
-        // both halves.  The fresh-step choice is folded into two step-uniform
-        // coefficients: c (u + g) on ordinary steps (fma(1, g, u) = u + g
-        // exactly), u itself on the fresh step.
+        // both halves.  With sum = u + g (fma(1, g, u), exact rounding of the
+        // sum) on ordinary steps and sum = u on the fresh step, w^k = c sum
+        // and u' = a w^k + g; the kick takes u' = fma(a c, sum, g) with a c
+        // rounded once, so w^k itself (one more product) is formed only where
+        // it is used (measurements and the velocity read-out).
         (void)hs;
         (void)n;
         const R g = f;
-        const R cf = fresh ? R(1) : v.c, gf = fresh ? R(0) : R(1);
-        const R ww = cf * Prec<R>::fma(gf, g, u);
-        w = ww;
-        unew = Prec<R>::fma(v.a, ww, g);
+        const R gf = fresh ? R(0) : R(1);
+        const R cf = fresh ? R(1) : v.c;
+        const R acf = fresh ? v.a : v.ac;
+        const R sum = Prec<R>::fma(gf, g, u);
+        w = cf * sum;
+        unew = Prec<R>::fma(acf, sum, g);
     } else {
         R ww;
         if (fresh) {
@@ -338,6 +342,24 @@ __device__ __forceinline__ void store4(R* p, const R o[4]) {
     v.z = o[2];
     v.w = o[3];
     *reinterpret_cast<typename Vec4<R>::T*>(p) = v;
+}
+
+// Element addresses as a wave-uniform base plus a lane's byte offset: the
+// base (a row's start) stays in scalar registers and the offset in one 32-bit
+// vector register, the operand form of global loads and stores with a scalar
+// base, so no per-lane 64-bit address arithmetic is needed per row.
+template <typename T>
+__device__ __forceinline__ T* at_byte(T* base, uint32_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ const T* at_byte(const T* base, uint32_t off) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+// Start of row y of an Lx-wide array (wave-uniform).
+template <typename T>
+__device__ __forceinline__ T* row_start(T* base, int y, int Lx) {
+    return base + (size_t)((uint32_t)y * (uint32_t)Lx);
 }
 
 // Bijective remap of workgroup ids so that each of the eight XCDs (which

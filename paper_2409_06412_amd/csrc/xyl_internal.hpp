@@ -43,6 +43,7 @@ struct Lat {
     // FP32, p in FP64)
     R Jx, Jy, h4, ph, pf, a, c, hdt, dt;
     R kJx, kJy, kh4, kph;  // FP32 kick: hdt q Jx, hdt q Jy, hdt 4h, hdt p h
+    R ac;                  // FP32 kick: a c, rounded once from FP64
     double Jxd, Jyd, hd, pd;       // FP64 copies for the energy
     double gamma, dtd;             // FP64 for the noise amplitude
     Schedule sched;

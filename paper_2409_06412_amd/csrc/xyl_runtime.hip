@@ -162,6 +162,7 @@ static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule&
     v.pd = p.p;
     v.a = (R)(1.0 - 0.5 * p.gamma * p.dt);
     v.c = (R)(1.0 / (1.0 + 0.5 * p.gamma * p.dt));
+    v.ac = (R)((1.0 - 0.5 * p.gamma * p.dt) / (1.0 + 0.5 * p.gamma * p.dt));
     v.hdt = (R)(0.5 * p.dt);
     v.dt = (R)p.dt;
     v.kJx = (R)(0.5 * p.dt * q * p.Jx);
@@ -826,23 +827,29 @@ int xyl_init_random(xyl_lattice* h) {
     });
 }
 
+// Host values for the state precision: finite, |th| <= 3 pi, and for the half
+// circle inside [-pi_p/2, pi_p/2) after rounding to the state precision.
+static void validate_host_state(const xyl_lattice* h, const double* theta, const double* vel, const char* vname) {
+    const bool si = h->p.model == kModelSI;
+    const double wp = h->dtype == XYL_F64 ? Prec<double>::kHalfPi : (double)Prec<float>::kHalfPi;
+    for (size_t i = 0; i < h->N; ++i) {
+        require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI, XYL_EINVAL,
+                "theta entries must be finite with |theta| <= 3 pi");
+        if (si) {
+            const double t = h->dtype == XYL_F64 ? theta[i] : (double)(float)theta[i];
+            require(t >= -wp && t < wp, XYL_EINVAL, "theta entries must lie in [-pi/2, pi/2) for the SI model");
+        }
+        require(std::isfinite(vel[i]), XYL_EINVAL, std::string(vname) + " entries must be finite");
+    }
+}
+
 int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint64_t step) {
     return guarded([&] {
         require(h != nullptr, XYL_EINVAL, "NULL handle");
         require(theta != nullptr && omega != nullptr, XYL_EINVAL, "theta/omega are NULL");
         // SI: the field is evaluated on the raw angle, so the state must already
         // lie in the half circle [-pi_p/2, pi_p/2) of the state precision
-        const bool si = h->p.model == kModelSI;
-        const double wp = h->dtype == XYL_F64 ? Prec<double>::kHalfPi : (double)Prec<float>::kHalfPi;
-        for (size_t i = 0; i < h->N; ++i) {
-            require(std::isfinite(theta[i]) && std::fabs(theta[i]) <= 3.0 * M_PI, XYL_EINVAL,
-                    "theta entries must be finite with |theta| <= 3 pi");
-            if (si) {
-                const double t = h->dtype == XYL_F64 ? theta[i] : (double)(float)theta[i];
-                require(t >= -wp && t < wp, XYL_EINVAL, "theta entries must lie in [-pi/2, pi/2) for the SI model");
-            }
-            require(std::isfinite(omega[i]), XYL_EINVAL, "omega entries must be finite");
-        }
+        validate_host_state(h, theta, omega, "omega");
         DeviceGuard g(h->device);
         h->k = step;
         h->fresh_k = step;
@@ -854,6 +861,48 @@ int xyl_set_state(xyl_lattice* h, const double* theta, const double* omega, uint
         } else {
             to_device<float>(h->cur_theta(), theta, h->N, h->stream);
             to_device<float>(h->u, omega, h->N, h->stream);
+        }
+        h->initialized = true;
+    });
+}
+
+int xyl_get_raw_state(xyl_lattice* h, double* theta, double* u, uint64_t* step, int32_t* fresh) {
+    return guarded([&] {
+        require_init(h);
+        DeviceGuard g(h->device);
+        if (theta) {
+            if (h->dtype == XYL_F64) to_host<double>(h->cur_theta(), theta, h->N, h->stream);
+            else to_host<float>(h->cur_theta(), theta, h->N, h->stream);
+        }
+        if (u) {
+            if (h->dtype == XYL_F64) to_host<double>(h->u, u, h->N, h->stream);
+            else to_host<float>(h->u, u, h->N, h->stream);
+        }
+        if (step) *step = h->k;
+        if (fresh) *fresh = h->k == h->fresh_k ? 1 : 0;
+        if (theta) require_finite(theta, h->N, "angles");
+        if (u) require_finite(u, h->N, "velocities");
+    });
+}
+
+int xyl_set_raw_state(xyl_lattice* h, const double* theta, const double* u, uint64_t step, int32_t fresh) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(theta != nullptr && u != nullptr, XYL_EINVAL, "theta/u are NULL");
+        require(fresh == 0 || fresh == 1, XYL_EINVAL, "fresh must be 0 or 1");
+        validate_host_state(h, theta, u, "u");
+        DeviceGuard g(h->device);
+        h->k = step;
+        // a stored half-step velocity is never the synchronized one again
+        h->fresh_k = fresh ? step : ~(uint64_t)0;
+        h->counter_valid = false;
+        h->touch();
+        if (h->dtype == XYL_F64) {
+            to_device<double>(h->cur_theta(), theta, h->N, h->stream);
+            to_device<double>(h->u, u, h->N, h->stream);
+        } else {
+            to_device<float>(h->cur_theta(), theta, h->N, h->stream);
+            to_device<float>(h->u, u, h->N, h->stream);
         }
         h->initialized = true;
     });

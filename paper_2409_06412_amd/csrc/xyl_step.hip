@@ -61,12 +61,15 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const R hs = noise_coeff<R>(v, k);   // FP32: -2 ln 2 hs^2; FP64: hs
     const bool fresh = (k == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
+    // byte offsets of the lane's quad and of its two outer neighbours in a row
+    const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
+    const uint32_t xmb = (uint32_t)xm * (uint32_t)sizeof(R), xpb = (uint32_t)xp * (uint32_t)sizeof(R);
 
     auto load_theta = [&](RowSet<R>& S, int y) {
-        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-        if (act) load4(thi + row + x, S.th);
-        if (edgeL) S.eL = thi[row + xm];
-        if (edgeR) S.eR = thi[row + xp];
+        const R* r = row_start(thi, y, Lx);
+        if (act) load4(at_byte(r, xb), S.th);
+        if (edgeL) S.eL = *at_byte(r, xmb);
+        if (edgeR) S.eR = *at_byte(r, xpb);
     };
     auto trig = [&](RowSet<R>& S) {
 #pragma unroll
@@ -79,13 +82,12 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     // (dead since row y-1 was stored; P's sin/cos, still needed here, are not
     // touched) and of the velocities of row y+2 into F.
     auto do_row = [&](RowSet<R>& P, RowSet<R>& C, RowSet<R>& N, RowSet<R>& F, int y) {
-        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
         trig(N);
         if (y + 3 <= y1) {   // row y+2 will be processed: it needs row y+3 and its velocities
             int y3 = y + 3;
             if (y3 >= Ly) y3 -= Ly;
             load_theta(P, y3);
-            if (act) load4(uu + row + 2u * (uint32_t)Lx + x, F.u);
+            if (act) load4(at_byte(row_start(uu, y + 2, Lx), xb), F.u);
         }
         // x-neighbours of the lane's first and last site
         // (the wave's first lane takes its left neighbour, the last active lane
@@ -121,10 +123,10 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
         }
         if ((MODE & kStore) && act) {
-            store4(tho + row + x, tho4);
-            store4(uw + row + x, uo4);
+            store4(at_byte(row_start(tho, y, Lx), xb), tho4);
+            store4(at_byte(row_start(uw, y, Lx), xb), uo4);
         }
-        if ((MODE & kOmega) && act) store4(v.omega_out + row + x, w);
+        if ((MODE & kOmega) && act) store4(at_byte(row_start(v.omega_out, y, Lx), xb), w);
 
         if (MODE & kMeasure) {
             double acc[kNPart];
@@ -188,8 +190,8 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     load_theta(C, y0 + 1 >= Ly ? y0 + 1 - Ly : y0 + 1);
     load_theta(D, y0 + 2 >= Ly ? y0 + 2 - Ly : y0 + 2);
     if (act) {
-        load4(uu + (uint32_t)y0 * (uint32_t)Lx + x, B.u);
-        if (y0 + 1 < y1) load4(uu + (uint32_t)(y0 + 1) * (uint32_t)Lx + x, C.u);
+        load4(at_byte(row_start(uu, y0, Lx), xb), B.u);
+        if (y0 + 1 < y1) load4(at_byte(row_start(uu, y0 + 1, Lx), xb), C.u);
     }
     trig(A);
     trig(B);
@@ -380,11 +382,12 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
     auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
     auto slot = [&](int it) { return rot + (size_t)(it & (kStep2Slots - 1)) * 2 * Wd; };
 
-    auto load_th = [&](TRow<R>& T, int y) { load4(B.th_in + (uint32_t)y * (uint32_t)Lx + gx, T.th); };
+    // byte offsets of the lane's quad and of its outer neighbour in a row
+    const uint32_t gxb = (uint32_t)gx * 4u, xeb = (uint32_t)xe * 4u;
+    auto load_th = [&](TRow<R>& T, int y) { load4(at_byte(row_start(B.th_in, y, Lx), gxb), T.th); };
     auto load_u = [&](URow<R>& U, int y) {
-        const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-        load4(B.u_in + row + gx, U.u);
-        U.e = B.th_in[row + xe];
+        load4(at_byte(row_start(B.u_in, y, Lx), gxb), U.u);
+        U.e = *at_byte(row_start(B.th_in, y, Lx), xeb);
     };
     auto trig = [&](TRow<R>& T) {
 #pragma unroll
@@ -448,9 +451,8 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
             site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
         if (store_b) {
-            const uint32_t row = (uint32_t)y * (uint32_t)Lx;
-            store4(B.th_out + row + gx, tho);
-            store4(B.u_out + row + gx, uo);
+            store4(at_byte(row_start(B.th_out, y, Lx), gxb), tho);
+            store4(at_byte(row_start(B.u_out, y, Lx), gxb), uo);
         }
     };
 

@@ -89,31 +89,38 @@ def test_fused_run_from_a_fresh_state_matches_oracle(xyl):
     assert d <= 1e-4
 
 
-@pytest.mark.parametrize("Lx,Ly,model", [(8200, 6, "xy"), (4100, 9, "xy"), (448, 33, "xy")])
+@pytest.mark.parametrize("Lx,Ly,model", [(8200, 6, "xy"), (4100, 9, "xy"), (448, 33, "xy"),
+                                         (8200, 6, "si"), (4100, 9, "si"), (448, 33, "si")])
 def test_fused_tiles_and_partial_waves_match_oracle(xyl, Lx, Ly, model):
     """Column tiles (8200 and 4100 wide) and a partial last wave (448) in the
-    two-step pass against the FP64 oracle over 100 steps from the same
-    FP32-representable start, to the FP32 bar at every site.  (The Si model's
-    tiles are held bitwise to single steps above; its field has a cusp at the
-    half-circle wrap, where a site FP32 puts on the other side of the cusp may
-    leave this bar, so its per-site bar is the fraction test at full size.)"""
+    two-step pass against the FP64 oracle from the same FP32-representable
+    start, to the FP32 bar.  XY: 100 steps from random angles and velocities,
+    1e-4 at every site.  Si: 20 steps from the random start at T_c (zero
+    velocities), with the bar of the small Si lattices (at most 1% of the
+    sites beyond 1e-4, median within 1e-5): its field has a cusp at the
+    half-circle wrap, across which one ulp of rounding per step can move a
+    site within 20 steps (tests/test_oracle_sensitivity.py)."""
     if model == "si":
         spec = workloads.si_lattice(Lx, Ly, seed=9, replica=4)
-        th, om = workloads.half_circle_state(Lx, Ly, seed=21, omega_scale=0.5)
-        period = np.pi
+        th, om = oracle.Oracle(**spec.oracle_kwargs()).init_random()
+        period, nsteps = np.pi, 20
     else:
         spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.7), (50, 0.3)), seed=9, replica=4)
         th, om = workloads.random_state(Lx, Ly, seed=21, omega_scale=0.5)
-        period = 2 * np.pi
+        period, nsteps = 2 * np.pi, 100
     th = th.astype(np.float32).astype(np.float64)
     om = om.astype(np.float32).astype(np.float64)
     say("fused vs oracle", Lx, Ly, model)
-    got = run(xyl, spec, 2, [100], 32, state=(th, om))
+    got = run(xyl, spec, 2, [nsteps], 32, state=(th, om))
     o = oracle.Oracle(**spec.oracle_kwargs())
-    tr, _ = o.run(th, om, 0, 100)
-    d = np.abs(np.remainder(got[0] - tr + period / 2, period) - period / 2).max()
-    say("max|dtheta|", d)
-    assert d <= 1e-4
+    tr, _ = o.run(th, om, 0, nsteps)
+    d = np.abs(np.remainder(got[0] - tr + period / 2, period) - period / 2)
+    say("max|dtheta|", d.max(), "sites beyond 1e-4", int(np.count_nonzero(d > 1e-4)))
+    if model == "xy":
+        assert d.max() <= 1e-4
+    else:
+        assert np.count_nonzero(d > 1e-4) <= 0.01 * Lx * Ly
+        assert np.median(d) <= 1e-5
 
 
 def test_fusion_keeps_measurement_and_state_buffers(xyl):

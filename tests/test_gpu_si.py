@@ -2,7 +2,9 @@
 angles; Sec. III.C) against the FP64 oracle, through the C-ABI.
 
 Bit-exact initial states, domain labels and ensemble states; observables of
-an FP64 state within 1e-10; FP32 trajectories within 1e-4 over 100 steps.  FP64
+an FP64 state within 1e-10; FP32 trajectories over 100 steps with at most 1%
+of the sites beyond 1e-4 and a median within 1e-5 (sites that rounding puts
+across the half-circle cusp; tests/test_oracle_sensitivity.py).  FP64
 trajectories: within 1e-12 over 100 steps; over longer runs the bar follows the
 trajectory's own sensitivity to rounding, which at the paper's couplings
 (|Jx| = 10) is about a thousand times that of the XY model: two oracle runs
@@ -86,15 +88,22 @@ def test_fp64_parity(xyl, Lx, Ly, nsteps, rows, wpb, tol):
 
 @pytest.mark.parametrize("Lx,Ly", [(64, 64), (300, 20)])
 def test_fp32_parity(xyl, Lx, Ly):
+    """100 FP32 steps at T_c against the FP64 oracle from the same start.  A
+    site that FP32 rounding puts on the other side of the half-circle cusp
+    than FP64 takes a different kick, and the oracle itself does that under
+    one ulp of rounding noise per step (tests/test_oracle_sensitivity.py): the
+    bar is at most 1% of the sites beyond 1e-4 and a median within 1e-5."""
     lat, o = make_pair(xyl, Lx, Ly, "f32", seed=3)
     lat.init_random()
     th0, om0, _ = lat.get_state()
     lat.step(100)
     th, om, _ = lat.get_state()
     tr, wr = o.run(th0, om0, 0, 100)
-    dth = half_circle_diff(th, tr).max()
-    say("si fp32 parity", Lx, Ly, "max|dtheta|", dth, "max|domega|", np.abs(om - wr).max())
-    assert dth <= 1e-4
+    d = half_circle_diff(th, tr)
+    n_out = int(np.count_nonzero(d > 1e-4))
+    say("si fp32 parity", Lx, Ly, "max|dtheta|", d.max(), "median", np.median(d), "sites beyond 1e-4", n_out)
+    assert n_out <= 0.01 * Lx * Ly
+    assert np.median(d) <= 1e-5
     lat.close()
 
 

@@ -138,14 +138,20 @@ def test_graph_replays_across_state_resets(xyl):
 
 
 def test_checkpoint_resume_is_bitwise(xyl, tmp_path):
-    """get_state/set_state (and save/load) at step k, then continuing, equals the
-    uninterrupted run bit for bit; a corrupted checkpoint is rejected."""
+    """The integrator's own state (get_raw_state/set_raw_state, and save/load,
+    which use them) at step k, then continuing, equals the uninterrupted run
+    bit for bit; a restart from the synchronized state (get_state/set_state: a
+    fresh start at step k) agrees to rounding; a corrupted checkpoint is
+    rejected."""
     for dtype in ("f32", "f64"):
         kw = dict(Jx=1.0, Jy=-0.1, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 1.0), (300, 0.2)], seed=9, replica=4)
         a = xyl.Lattice(96, 40, dtype=dtype, **kw)
         a.init_random()
         a.step(150)
         a.save(str(tmp_path / "ck.npz"))
+        sync = a.get_state()
+        raw = a.get_raw_state()
+        assert raw[2] == 150 and not raw[3]
         a.step(100)
         ref = a.get_state()
         b = xyl.Lattice.load(str(tmp_path / "ck.npz"))
@@ -154,6 +160,16 @@ def test_checkpoint_resume_is_bitwise(xyl, tmp_path):
         np.testing.assert_array_equal(got[0], ref[0])
         np.testing.assert_array_equal(got[1], ref[1])
         assert got[2] == ref[2] == 250
+        b.set_raw_state(*raw)
+        b.step(100)
+        for x, y in zip(b.get_state(), ref):
+            np.testing.assert_array_equal(x, y)
+        b.set_state(sync[0], sync[1], sync[2])
+        assert b.get_raw_state()[3]
+        b.step(100)
+        th = b.get_state()[0]
+        d = np.abs(np.remainder(th - ref[0] + np.pi, 2 * np.pi) - np.pi).max()
+        assert d <= (1e-4 if dtype == "f32" else 1e-12)
         a.close()
         b.close()
     z = dict(np.load(str(tmp_path / "ck.npz")))

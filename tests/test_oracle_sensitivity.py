@@ -16,6 +16,14 @@ kick, and its neighbourhood follows.
   below it.  That is the bar tests/test_gpu_fullsize.py applies to the Si model
   (the XY model, whose field is 2 pi-periodic, keeps 1e-4 at every site: the
   same experiment at 2048^2 stays below 2e-6).
+* FP32 arithmetic.  The same with one to four ulps of random relative error
+  added to every angle and velocity after each step (the size of an FP32
+  kernel's rounding), on the small lattices of tests/test_gpu_si.py, 100
+  steps: some noise streams cross the cusp (at 64^2 the 1-ulp ones reproduce
+  the GPU's 5.6e-3 at 6 sites), but none moves more than 1% of the sites
+  beyond 1e-4 or the median beyond 1e-5 (it stays near 1e-6).  That is the
+  FP32 bar of the small Si tests; a wrong force, draw or index moves most
+  sites by far more.
 * FP64 rounding.  Starts that differ by one ulp at every site (random
   direction) end 0.8-2e-10 apart after the 1000-step Si schedule of
   tests/test_gpu_si.py at 64^2 (3-5e-12 after 200 steps), while the XY model's
@@ -80,6 +88,40 @@ def test_xy_fp32_storage_keeps_the_strict_bar():
     a, _ = o.run(th0, om0, 0, nsteps)
     b, _ = run_f32_storage(o, th0, om0, nsteps, si=False)
     assert wrapped(a, b, 2 * np.pi).max() <= 1e-5
+
+
+def run_with_arithmetic_noise(o, th, om, nsteps, ulps, rng):
+    """The oracle's steps with the state perturbed by up to `ulps` binary32
+    ulps (random relative error, uniform) and rounded to binary32 after each
+    step, mapped back onto the half circle."""
+    half, full = np.float64(np.float32(np.pi / 2)), np.float64(np.float32(np.pi))
+    for k in range(nsteps):
+        th, om = o.run(th, om, k, 1)
+        th = to_f32(th * (1.0 + ulps * 2.0 ** -24 * rng.uniform(-1.0, 1.0, th.shape)))
+        om = to_f32(om * (1.0 + ulps * 2.0 ** -24 * rng.uniform(-1.0, 1.0, om.shape)))
+        th = np.where(th >= half, th - full, np.where(th < -half, th + full, th))
+    return th, om
+
+
+@pytest.mark.parametrize("Lx,Ly", [(64, 64), (300, 20)])
+def test_si_fp32_arithmetic_noise_small_lattices(Lx, Ly):
+    """The start of tests/test_gpu_si.py::test_fp32_parity, 100 steps."""
+    spec = workloads.si_lattice(Lx, Ly, seed=3)
+    o = oracle.Oracle(**spec.oracle_kwargs())
+    th0, om0 = o.init_random()
+    th0 = to_f32(th0)
+    ref, _ = o.run(th0, om0, 0, 100)
+    crossed = 0
+    for ulps in (1, 4):
+        for s in range(6):
+            b, _ = run_with_arithmetic_noise(o, th0, om0, 100, ulps, np.random.default_rng(100 + s))
+            d = wrapped(ref, b, np.pi)
+            n_out = int(np.count_nonzero(d > 1e-4))
+            crossed += n_out > 0
+            assert n_out <= 0.01 * Lx * Ly
+            assert np.median(d) <= 1e-5
+    # a per-site 1e-4 bar over 100 steps is out of reach of FP32 rounding here
+    assert crossed >= 2
 
 
 def ulp_spread(o, th0, om0, nsteps, period, seeds=(0, 1, 2, 3)):
