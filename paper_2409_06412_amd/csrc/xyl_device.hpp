@@ -115,10 +115,15 @@ struct Prec<float> {
     // kk = -2 ln 2, or -2 ln 2 scale^2 to scale both draws by `scale` inside
     // the square root), angle 2 pi u2 (native sine/cosine in revolutions, no
     // multiplication).
+    // The angle's uniform may be taken half a revolution on (c2 = 1/2 - 2^-24
+    // instead of 1 - 2^-24 below, no extra instruction), which negates both
+    // draws: cos(2 pi (u + 1/2)) = -cos(2 pi u), likewise the sine.
     static constexpr float kMinus2Ln2 = -1.38629436111989062f;
+    static constexpr float kU2 = 0x1.fffffep-1f, kU2Half = 0x1.fffffcp-2f;
     __device__ static __forceinline__ void box_muller(uint32_t r1, uint32_t r2, float& nc, float& ns,
-                                                      float kk = kMinus2Ln2) {
-        const float u1 = uniform(r1), u2 = uniform(r2);
+                                                      float kk = kMinus2Ln2, float c2 = kU2) {
+        const float u1 = uniform(r1);
+        const float u2 = __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, r2, 9u)) - c2;
         const float rad = __builtin_amdgcn_sqrtf(kk * __builtin_amdgcn_logf(u1));
         nc = rad * __builtin_amdgcn_cosf(u2);
         ns = rad * __builtin_amdgcn_sinf(u2);
@@ -175,28 +180,45 @@ __device__ __forceinline__ void noise4(uint32_t q, uint32_t replica, uint64_t k,
 
 // The noise coefficient of step k as noise4_kick and site_update take it:
 // FP32 -2 ln 2 hs^2 (the draws' scale inside the Box-Muller square root, from
-// the FP64 amplitude hs); FP64 hs itself.
-template <typename R>
+// the FP64 amplitude hs; for the factored kick F, divided by (hdt q Jx)^2 so
+// that the draws come out divided by hdt q Jx); FP64 hs itself.
+template <typename R, bool F = false>
 __device__ __forceinline__ R noise_coeff(const Lat<R>& v, uint64_t k) {
     const double hs = half_sigma(v.sched, v.gamma, v.dtd, k);
-    if constexpr (sizeof(R) == 4) return (R)(-1.38629436111989062 * hs * hs);
-    else return hs;
+    if constexpr (sizeof(R) == 4) {
+        if constexpr (F) return (R)(-1.38629436111989062 * hs * hs * v.fnoise);
+        else return (R)(-1.38629436111989062 * hs * hs);
+    } else {
+        return hs;
+    }
 }
 
 // The draws as site_force takes them: FP32 scales them by the half-kick noise
 // amplitude through the coefficient kk = noise_coeff (the same for every site
 // of a step); FP64 returns the plain draws and site_update applies hs in the
 // oracle's order.
+// c2: the angle uniform's constant (Prec<float>::box_muller): kU2Half
+// negates the draws, which the factored kick needs when hdt q Jx < 0 (its
+// scale enters through the square root, which keeps the sign positive).
 template <typename R>
 __device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64_t k, uint32_t s0, uint32_t s1, R kk,
-                                            R n[4]) {
+                                            R n[4], R c2) {
     if constexpr (sizeof(R) == 4) {
         const U32x4 r = philox4x32_10(q, replica, (uint32_t)k, (uint32_t)(k >> 32), s0, s1);
-        Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1], kk);
-        Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3], kk);
+        Prec<R>::box_muller(r.v[0], r.v[1], n[0], n[1], kk, c2);
+        Prec<R>::box_muller(r.v[2], r.v[3], n[2], n[3], kk, c2);
     } else {
+        (void)c2;
         noise4<R>(q, replica, k, s0, s1, n);
     }
+}
+
+// The draws' angle constant of a lattice's form of the FP32 kick.
+template <typename R, bool F>
+__device__ __forceinline__ R noise_u2(const Lat<R>& v) {
+    if constexpr (sizeof(R) == 4 && F) return v.fu2;
+    else if constexpr (sizeof(R) == 4) return Prec<float>::kU2;
+    else return R(0);
 }
 
 // ------------------------------------------------------ per-site BBK math
@@ -209,10 +231,27 @@ __device__ __forceinline__ void noise4_kick(uint32_t q, uint32_t replica, uint64
 // (n the scaled draw), with hdt folded into the couplings so that the draw
 // enters the last two fused multiply-adds; FP64 returns F in the oracle's
 // order and site_update adds the rest.
-template <typename R, int M>
+// FP32 with F (the factored kick, where the lattice's `fact` is set): the
+// kick divided by kx = hdt q Jx,
+//   g / kx = s (Cx + r Cy - rh c) - c (Sx + r Sy) + n / kx    (XY)
+//          = s (Cx + r Cy) - c (Sx + r Sy) - rph sin(p th) + n / kx   (SI)
+// with r = Jy/Jx, rh = 4h/(q Jx), rph = p h/(q Jx) and the draw already
+// divided by kx (noise_coeff<R, true>): the y sums enter through one fused
+// multiply-add each and the scale kx moves into site_update's coefficients.
+template <typename R, int M, bool F = false>
 __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm, R sxp, R cxp, R sym, R cym, R syp,
                                         R cyp, R th, R n) {
-    if constexpr (sizeof(R) == 4) {
+    if constexpr (sizeof(R) == 4 && F) {
+        const R X = Prec<R>::fma(v.fr, cyp + cym, cxp + cxm);
+        const R Y = Prec<R>::fma(v.fr, syp + sym, sxp + sxm);
+        const R cq = Prec<R>::fma(-c, Y, n);
+        if constexpr (M == kModelSI) {
+            const R sp = Prec<R>::sin_scaled(th, v.pf);
+            return Prec<R>::fma(-v.fph, sp, Prec<R>::fma(s, X, cq));
+        } else {
+            return Prec<R>::fma(s, Prec<R>::fma(-v.fh, c, X), cq);
+        }
+    } else if constexpr (sizeof(R) == 4) {
         // couplings scaled by hdt on the host (kJx = hdt q Jx, ...)
         const R P0 = Prec<R>::fma(v.kJx, cxp + cxm, v.kJy * (cyp + cym));
         const R Q = Prec<R>::fma(v.kJx, sxp + sxm, v.kJy * (syp + sym));
@@ -253,10 +292,22 @@ __device__ __forceinline__ double onsite_cos(const Lat<R>& v, R th, double s, do
 // step, where u already holds w^k), then the next first half-kick, the drift
 // and the wrap (App. A.1, Eqs. BBK-2 and BBK-1), with the fma order the
 // oracle uses.
-template <typename R, int M>
+template <typename R, int M, bool F = false>
 __device__ __forceinline__ void site_update(const Lat<R>& v, R f, R u, R th, R n, R hs, bool fresh, R& w, R& unew,
                                             R& thnew) {
-    if constexpr (sizeof(R) == 4) {
+    if constexpr (sizeof(R) == 4 && F) {
+        // f = g / kx (the factored kick): u' = a w^k + g with w^k = c (u + g)
+        // is ac u + kx (1 + ac) f on ordinary steps and a u + kx f on the
+        // fresh one (w^k = u); w^k itself only where it is used
+        (void)hs;
+        (void)n;
+        const R acf = fresh ? v.a : v.ac;
+        const R c1 = fresh ? v.kJx : v.fc1;
+        const R kf = fresh ? R(0) : v.kJx;
+        const R cf = fresh ? R(1) : v.c;
+        unew = Prec<R>::fma(acf, u, c1 * f);
+        w = cf * Prec<R>::fma(kf, f, u);
+    } else if constexpr (sizeof(R) == 4) {
         // FP32: f arrives as the kick g = hdt F + hs n (site_force), used by
         // both halves.  With sum = u + g (fma(1, g, u), exact rounding of the
         // sum) on ordinary steps and sum = u on the fresh step, w^k = c sum

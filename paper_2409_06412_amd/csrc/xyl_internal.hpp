@@ -44,6 +44,12 @@ struct Lat {
     R Jx, Jy, h4, ph, pf, a, c, hdt, dt;
     R kJx, kJy, kh4, kph;  // FP32 kick: hdt q Jx, hdt q Jy, hdt 4h, hdt p h
     R ac;                  // FP32 kick: a c, rounded once from FP64
+    // FP32 kick factored by the x coupling (fact = 1; see site_force): the
+    // ratios Jy/Jx, 4h/(q Jx) and p h/(q Jx), and c1 = hdt q Jx (1 + a c)
+    int32_t fact;
+    R fr, fh, fph, fc1;
+    R fu2;                 // the draws' angle constant: negates them when hdt q Jx < 0
+    double fnoise;         // 1 / (hdt q Jx)^2, the draws' extra scale
     double Jxd, Jyd, hd, pd;       // FP64 copies for the energy
     double gamma, dtd;             // FP64 for the noise amplitude
     Schedule sched;
@@ -189,8 +195,9 @@ struct LdsJobHost {
     double* obs;
 };
 int lds_threads(int N);
+// Every job of one launch is a replica whose `fact` equals `factored`.
 void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites, int model,
-                         uint64_t j0, hipStream_t s);
+                         bool factored, uint64_t j0, hipStream_t s);
 
 // State transfer between caller device buffers and a lattice (xyl_state.hip).
 // launch_check_state ORs kStateBad* bits into *flag (which must start at 0)

@@ -144,6 +144,18 @@ static Schedule make_schedule(const uint64_t* ks, const double* Ts, int32_t n, c
     return s;
 }
 
+// Whether the FP32 kick may be factored by the x coupling: it divides by
+// hdt q Jx, so that and the ratios it creates must stay well inside binary32's
+// range.  The two-step passes need it (their kernels are compiled for that
+// form only); other lattices keep the unfactored kick in every kernel.
+static bool kick_factored(const Params& p) {
+    if (p.Jx == 0.0) return false;
+    const double q = p.model == kModelSI ? 2.0 : 1.0;
+    const double kjx = 0.5 * p.dt * q * p.Jx, big = 1048576.0;
+    return std::fabs(p.Jy / p.Jx) <= big && std::fabs(4.0 * p.h / (q * p.Jx)) <= big &&
+           std::fabs(p.p * p.h / (q * p.Jx)) <= big && std::fabs(kjx) >= 1e-12 && std::fabs(kjx) <= big;
+}
+
 template <typename R>
 static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule& s, uint64_t seed, uint32_t replica) {
     v.Lx = Lx;
@@ -162,7 +174,19 @@ static void fill_lat(Lat<R>& v, int Lx, int Ly, const Params& p, const Schedule&
     v.pd = p.p;
     v.a = (R)(1.0 - 0.5 * p.gamma * p.dt);
     v.c = (R)(1.0 / (1.0 + 0.5 * p.gamma * p.dt));
-    v.ac = (R)((1.0 - 0.5 * p.gamma * p.dt) / (1.0 + 0.5 * p.gamma * p.dt));
+    const double acd = (1.0 - 0.5 * p.gamma * p.dt) / (1.0 + 0.5 * p.gamma * p.dt);
+    v.ac = (R)acd;
+    // the FP32 kick factored by the x coupling (site_force)
+    v.fact = (sizeof(R) == 4 && kick_factored(p)) ? 1 : 0;
+    const double kjx = 0.5 * p.dt * q * p.Jx;
+    v.fr = v.fact ? (R)(p.Jy / p.Jx) : R(0);
+    v.fh = v.fact ? (R)(4.0 * p.h / (q * p.Jx)) : R(0);
+    v.fph = v.fact ? (R)(p.p * p.h / (q * p.Jx)) : R(0);
+    v.fc1 = (R)(kjx * (1.0 + acd));
+    v.fnoise = v.fact ? 1.0 / (kjx * kjx) : 1.0;
+    // the draws divided by hdt q Jx: their scale goes through the Box-Muller
+    // square root, so a negative divisor flips the angle by half a turn
+    v.fu2 = (R)(v.fact && kjx < 0.0 ? 0.5 - 0x1p-24 : 1.0 - 0x1p-24);
     v.hdt = (R)(0.5 * p.dt);
     v.dt = (R)p.dt;
     v.kJx = (R)(0.5 * p.dt * q * p.Jx);
@@ -387,7 +411,7 @@ static bool step2_lattice_shape(int Lx, int Ly) {
     return Ly >= 4 && (step2_width_ok(Lx) || step2_tiles(Lx, &t));
 }
 static bool step2_eligible(const xyl_lattice* h) {
-    return h->dtype == XYL_F32 && h->fusion == 2 && step2_lattice_shape(h->Lx, h->Ly);
+    return h->dtype == XYL_F32 && h->fusion == 2 && kick_factored(h->p) && step2_lattice_shape(h->Lx, h->Ly);
 }
 
 // Rows per strip of the two-step kernel.  A workgroup spans the row (Lx / 256
@@ -1405,7 +1429,7 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
     *fusion = 1;
     *rows2 = 0;
     if constexpr (std::is_same<R, float>::value) {
-        if (step2_lattice_shape(h->Lx, h->Ly)) {
+        if (step2_lattice_shape(h->Lx, h->Ly) && kick_factored(h->p)) {
             const int reps4 = (reps + 3) / 4 * 4;
             float* A = v.th[0];
             float* B = v.th[1];
@@ -1711,7 +1735,8 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
         std::vector<std::vector<int>> byw(17);
         for (int r : active) {
             const xyl_replica_desc& d = e->desc[r];
-            if (step2_shape(d.Lx, d.Ly)) byw[(d.Lx + kWaveSites - 1) / kWaveSites].push_back(r);
+            if (step2_shape(d.Lx, d.Ly) && kick_factored(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p}))
+                byw[(d.Lx + kWaveSites - 1) / kWaveSites].push_back(r);
             else
                 for (const Task& t : tk)
                     if (t.rep == r) rest.push_back(t);
@@ -1898,10 +1923,19 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
         smp.reserve(nmeas);
         // small replicas: one launch for the whole chunk
         if (!lds_set.empty()) {
+            // replicas with the factored FP32 kick first, then the others: one
+            // launch per form of the kick
             e->lds_jobs_host.clear();
-            for (int r : lds_set)
-                e->lds_jobs_host.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
-                                                      meas[r] ? smp.take(r) : nullptr});
+            int nfact = 0;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int r : lds_set) {
+                    const xyl_replica_desc& d = e->desc[r];
+                    const bool f = kick_factored(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p});
+                    if (f != (pass == 0)) continue;
+                    nfact += f ? 1 : 0;
+                    e->lds_jobs_host.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
+                                                          meas[r] ? smp.take(r) : nullptr});
+                }
             e->lds_jobs.reserve(e->lds_jobs_host.size());
             // the previous chunk's launch must have read its job table before it is rewritten
             check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
@@ -1915,8 +1949,13 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                                      e->side),
                       "H2D");
             check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
-            launch_ensemble_lds(reinterpret_cast<const Lat<float>*>(e->lds_reps.p), e->lds_jobs.p,
-                                (int)lds_set.size(), e->lds_threads, e->lds_max_sites, e->model(), e->j, e->side);
+            const Lat<float>* lreps = reinterpret_cast<const Lat<float>*>(e->lds_reps.p);
+            if (nfact)
+                launch_ensemble_lds(lreps, e->lds_jobs.p, nfact, e->lds_threads, e->lds_max_sites, e->model(), true,
+                                    e->j, e->side);
+            if ((int)lds_set.size() > nfact)
+                launch_ensemble_lds(lreps, e->lds_jobs.p + nfact, (int)lds_set.size() - nfact, e->lds_threads,
+                                    e->lds_max_sites, e->model(), false, e->j, e->side);
         }
         // large replicas
         if (!active_g.empty()) {

@@ -36,7 +36,7 @@ struct RowSet {
     R u[4];
 };
 
-template <typename R, int MODE, int M>
+template <typename R, int MODE, int M, bool FK>
 __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
     const int Lx = v.Lx, Ly = v.Ly;
     const uint64_t k = v.k_base + j;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     R* __restrict__ tho = v.pingpong ? v.th[par ^ 1] : v.th[1];
     const R* uu = v.u;
     R* uw = v.u_out ? v.u_out : v.u;
-    const R hs = noise_coeff<R>(v, k);   // FP32: -2 ln 2 hs^2; FP64: hs
+    const R hs = noise_coeff<R, FK>(v, k);   // FP32: -2 ln 2 hs^2 (/ kx^2 if FK); FP64: hs
     const bool fresh = (k == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
     // byte offsets of the lane's quad and of its two outer neighbours in a row
@@ -111,16 +111,17 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         }
 
         R n[4];
-        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hs, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(x >> 2), v.replica, k, v.seed_lo, v.seed_hi, hs, n,
+                       noise_u2<R, FK>(v));
 
         R tho4[4], uo4[4], w[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            const R f =
-                site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q], n[q]);
-            site_update<R, M>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
+            const R f = site_force<R, M, FK>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q],
+                                             C.th[q], n[q]);
+            site_update<R, M, FK>(v, f, C.u[q], C.th[q], n[q], hs, fresh, w[q], uo4[q], tho4[q]);
         }
         if ((MODE & kStore) && act) {
             store4(at_byte(row_start(tho, y, Lx), xb), tho4);
@@ -212,6 +213,19 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     }
 }
 
+// The strip with the lattice's form of the FP32 kick (factored by the x
+// coupling where its `fact` is set, which the two-step passes require, so the
+// two agree bit for bit); FP64 has one form.
+template <typename R, int MODE, int M>
+__device__ __forceinline__ void run_strip_any(const Lat<R>& v, int xw, int strip, int rows, uint64_t j, int lane) {
+    if constexpr (sizeof(R) == 4) {
+        if (v.fact) run_strip<R, MODE, M, true>(v, xw, strip, rows, j, lane);
+        else run_strip<R, MODE, M, false>(v, xw, strip, rows, j, lane);
+    } else {
+        run_strip<R, MODE, M, false>(v, xw, strip, rows, j, lane);
+    }
+}
+
 template <typename R, int MODE, int M>
 __global__ __launch_bounds__(512) void k_step(Lat<R> v, const uint64_t* kdev, uint64_t j0, int rows, int ntasks) {
     const int wpb = blockDim.x / kWave;
@@ -221,7 +235,7 @@ __global__ __launch_bounds__(512) void k_step(Lat<R> v, const uint64_t* kdev, ui
     const int t = b * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (t >= ntasks) return;
     const uint64_t j = j0 + (kdev ? *kdev : 0);
-    run_strip<R, MODE, M>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
+    run_strip_any<R, MODE, M>(v, t % v.nxw, t / v.nxw, rows, j, threadIdx.x & (kWave - 1));
 }
 
 template <typename R, int MODE, int M>
@@ -233,7 +247,7 @@ __global__ __launch_bounds__(512) void k_ensemble_step(const Lat<R>* __restrict_
     if (t >= ntasks) return;
     const Task task = tasks[t];
     const uint64_t j = j0 + (kdev ? *kdev : 0);
-    run_strip<R, MODE, M>(reps[task.rep], task.xw, task.strip, rows, j, threadIdx.x & (kWave - 1));
+    run_strip_any<R, MODE, M>(reps[task.rep], task.xw, task.strip, rows, j, threadIdx.x & (kWave - 1));
 }
 
 template <typename R, int M>
@@ -375,8 +389,9 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         const float r = from_lane_above(v_above, edge);
         return (PARTIAL || TILE) ? (edgeR ? edge : r) : r;
     };
-    const R hsA = noise_coeff<R>(v, k);
-    const R hsB = noise_coeff<R>(v, k + 1);
+    // the two-step passes take lattices with the factored FP32 kick only
+    const R hsA = noise_coeff<R, true>(v, k);
+    const R hsB = noise_coeff<R, true>(v, k + 1);
     const bool freshA = (k == v.fresh_k), freshB = (k + 1 == v.fresh_k);
     const uint32_t qrow = (uint32_t)(Lx >> 2);
     auto wrap_y = [&](int y) { return y < 0 ? y + Ly : (y >= Ly ? y - Ly : y); };
@@ -403,16 +418,17 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         const R sL = from_lane_below(C.s[3], se), cL = from_lane_below(C.c[3], ce);
         const R sR = right_of(C.s[0], se), cR = right_of(C.c[0], ce);
         R n[4];
-        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k, v.seed_lo, v.seed_hi, hsA, n,
+                       noise_u2<R, true>(v));
         R s1[4], c1[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1];
-            const R f = site_force<R, M>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q], C.th[q],
-                                         n[q]);
+            const R f = site_force<R, M, true>(v, C.s[q], C.c[q], sxm, cxm, sxp, cxp, P.s[q], P.c[q], N.s[q], N.c[q],
+                                               C.th[q], n[q]);
             R w;
-            site_update<R, M>(v, f, U.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
+            site_update<R, M, true>(v, f, U.u[q], C.th[q], n[q], hsA, freshA, w, out.u[q], out.t[q]);
             rotor<R, M>(out.t[q], s1[q], c1[q]);
         }
         if (valid) {
@@ -440,15 +456,17 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
         load4(rn + x, sn);
         load4(rn + Wd + x, cn);
         R n[4];
-        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n);
+        noise4_kick<R>((uint32_t)y * qrow + (uint32_t)(gx >> 2), v.replica, k + 1, v.seed_lo, v.seed_hi, hsB, n,
+                       noise_u2<R, true>(v));
         R tho[4], uo[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const R sxm = q == 0 ? sL : sc[q - 1], cxm = q == 0 ? cL : cc[q - 1];
             const R sxp = q == 3 ? sR : sc[q + 1], cxp = q == 3 ? cR : cc[q + 1];
-            const R f = site_force<R, M>(v, sc[q], cc[q], sxm, cxm, sxp, cxp, sp[q], cp[q], sn[q], cn[q], C.t[q], n[q]);
+            const R f =
+                site_force<R, M, true>(v, sc[q], cc[q], sxm, cxm, sxp, cxp, sp[q], cp[q], sn[q], cn[q], C.t[q], n[q]);
             R w;
-            site_update<R, M>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
+            site_update<R, M, true>(v, f, C.u[q], C.t[q], n[q], hsB, freshB, w, uo[q], tho[q]);
         }
         if (store_b) {
             store4(at_byte(row_start(B.th_out, y, Lx), gxb), tho);
@@ -680,13 +698,9 @@ struct LdsJob {
     double* obs;        // 6 doubles
 };
 
-template <int M>
-__global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restrict__ reps,
-                                                       const LdsJob* __restrict__ jobs, uint64_t j0) {
-    extern __shared__ float lds[];
-    __shared__ double red[16][kNPart];
-    const LdsJob job = jobs[blockIdx.x];
-    const Lat<float>& v = reps[job.rep];
+template <int M, bool F>
+__device__ __forceinline__ void lds_replica(const Lat<float>& v, const LdsJob& job, uint64_t j0, float* lds,
+                                            double (*red)[kNPart]) {
     const int Lx = v.Lx, Ly = v.Ly;
     const int N = Lx * Ly, ng = N >> 2;
     float* S = lds;
@@ -744,7 +758,8 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
         for (int e = 0; e < 4; ++e) {
             const float sxm = e == 0 ? sL : s4[e - 1], cxm = e == 0 ? cL : c4[e - 1];
             const float sxp = e == 3 ? sR : s4[e + 1], cxp = e == 3 ? cR : c4[e + 1];
-            f[e] = site_force<float, M>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e], t4[e], n[e]);
+            f[e] = site_force<float, M, F>(v, s4[e], c4[e], sxm, cxm, sxp, cxp, su[e], cu[e], sd[e], cd[e], t4[e],
+                                           n[e]);
         }
     };
 
@@ -752,7 +767,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
     __syncthreads();
     if (job.measure) {
         // observables of the synchronized state at k0 (same sums as the strip kernel)
-        const float hs = noise_coeff<float>(v, k0);
+        const float hs = noise_coeff<float, F>(v, k0);
         const bool fresh = (k0 == v.fresh_k);
         double acc[kNPart];
 #pragma unroll
@@ -762,7 +777,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                noise4_kick<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, hs, n);
+                noise4_kick<float>((uint32_t)g, v.replica, k0, v.seed_lo, v.seed_hi, hs, n, noise_u2<float, F>(v));
                 forces(g, th[q], n, f, s4, c4, sR, cR, sd, cd);
                 const int i0 = 4 * g;
                 const int y = i0 / Lx, x = i0 - y * Lx;
@@ -771,7 +786,7 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w, un, tn;
-                    site_update<float, M>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, un, tn);
+                    site_update<float, M, F>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, un, tn);
                     const double sv = (double)s4[e], cv = (double)c4[e];
                     const double sxp = (double)(e == 3 ? sR : s4[e + 1]);
                     const double cxp = (double)(e == 3 ? cR : c4[e + 1]);
@@ -826,19 +841,19 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
             tables();
             __syncthreads();
         }
-        const float hs = noise_coeff<float>(v, k);
+        const float hs = noise_coeff<float, F>(v, k);
         const bool fresh = (k == v.fresh_k);
 #pragma unroll
         for (int q = 0; q < kLdsMaxGroups; ++q) {
             const int g = tid + q * nt;
             if (g < ng) {
                 float f[4], s4[4], c4[4], sd[4], cd[4], sR, cR, n[4];
-                noise4_kick<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, hs, n);
+                noise4_kick<float>((uint32_t)g, v.replica, k, v.seed_lo, v.seed_hi, hs, n, noise_u2<float, F>(v));
                 forces(g, th[q], n, f, s4, c4, sR, cR, sd, cd);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w;
-                    site_update<float, M>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, u[q][e], th[q][e]);
+                    site_update<float, M, F>(v, f[e], u[q][e], th[q][e], n[e], hs, fresh, w, u[q][e], th[q][e]);
                 }
             }
         }
@@ -856,6 +871,17 @@ __global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restr
     }
 }
 
+// One launch takes replicas of one form of the FP32 kick (F: factored, the
+// lattice's `fact`); the host launches each form's jobs separately.
+template <int M, bool F>
+__global__ __launch_bounds__(1024) void k_ensemble_lds(const Lat<float>* __restrict__ reps,
+                                                       const LdsJob* __restrict__ jobs, uint64_t j0) {
+    extern __shared__ float lds[];
+    __shared__ double red[16][kNPart];
+    const LdsJob job = jobs[blockIdx.x];
+    lds_replica<M, F>(reps[job.rep], job, j0, lds, red);
+}
+
 int lds_threads(int N) {
     const int ng = N / 4;
     int t = (ng + kLdsMaxGroups - 1) / kLdsMaxGroups;
@@ -863,21 +889,26 @@ int lds_threads(int N) {
     return t < kWave ? kWave : t;
 }
 
-template <int M>
+template <int M, bool F>
 static void dispatch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, size_t lds,
                                   uint64_t j0, hipStream_t s) {
-    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble_lds<M>),
+    check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ensemble_lds<M, F>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute");
-    k_ensemble_lds<M><<<njobs, threads, lds, s>>>(reps, reinterpret_cast<const LdsJob*>(jobs), j0);
+    k_ensemble_lds<M, F><<<njobs, threads, lds, s>>>(reps, reinterpret_cast<const LdsJob*>(jobs), j0);
     check_hip(hipGetLastError(), "LDS ensemble kernel launch");
 }
 
 void launch_ensemble_lds(const Lat<float>* reps, const void* jobs, int njobs, int threads, int max_sites, int model,
-                         uint64_t j0, hipStream_t s) {
+                         bool factored, uint64_t j0, hipStream_t s) {
     const size_t lds = 2 * sizeof(float) * (size_t)max_sites;
-    if (model == kModelSI) dispatch_ensemble_lds<kModelSI>(reps, jobs, njobs, threads, lds, j0, s);
-    else dispatch_ensemble_lds<kModelXY>(reps, jobs, njobs, threads, lds, j0, s);
+    if (model == kModelSI) {
+        if (factored) dispatch_ensemble_lds<kModelSI, true>(reps, jobs, njobs, threads, lds, j0, s);
+        else dispatch_ensemble_lds<kModelSI, false>(reps, jobs, njobs, threads, lds, j0, s);
+    } else {
+        if (factored) dispatch_ensemble_lds<kModelXY, true>(reps, jobs, njobs, threads, lds, j0, s);
+        else dispatch_ensemble_lds<kModelXY, false>(reps, jobs, njobs, threads, lds, j0, s);
+    }
 }
 
 // ------------------------------------------------------------------ init
