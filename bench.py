@@ -730,7 +730,10 @@ def main():
     fusion = lat.fusion()
     log("single-step launch shape (rows per strip, waves per workgroup):", launch,
         "; steps per pass, rows per strip of the two-step pass:", fusion)
-    lat.step(args.warmup)
+    # the warm-up runs the timed path itself (samples and stepping), so that no
+    # kernel is loaded or launched for the first time inside the timed region
+    if args.warmup:
+        lat.step_measured(args.warmup, args.every)
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()

@@ -252,9 +252,10 @@ int xyl_sync(xyl_lattice* h);
  * graphs on scratch copies of the state, which it leaves untouched) and keeps
  * the fastest; for FP32 lattices that two steps per pass apply to, it also
  * times that pass at several strip heights and sets the steps per pass
- * (xyl_set_fusion) to whichever of 1 and 2 is faster per step.  The choices
- * are cached per (shape, precision) for the process and applied to lattices
- * created later. */
+ * (xyl_set_fusion) to whichever of 1 and 2 is faster per step; it also picks
+ * the launch shape of the measurements that sampled runs take (results do
+ * not depend on it either).  The choices are cached per (shape, precision)
+ * for the process and applied to lattices created later. */
 int xyl_set_launch(xyl_lattice* h, int32_t rows_per_strip, int32_t waves_per_block);
 int xyl_get_launch(xyl_lattice* h, int32_t* rows_per_strip, int32_t* waves_per_block);
 int xyl_autotune(xyl_lattice* h);

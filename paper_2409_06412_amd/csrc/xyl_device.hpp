@@ -366,6 +366,37 @@ __device__ __forceinline__ double from_lane_above(double v, double old = 0.0) {
     return __hiloint2double(hi, lo);
 }
 
+// Sums of eight FP64 values over the 64 lanes of a wave, in a fixed pattern:
+// a reduce-scatter in which every exchange halves the values a lane carries
+// (lanes with bit 5 set keep values 4..7 and send 0..3 to their partner, and
+// so on for bits 4 and 3), then a butterfly over the last three bits.  Ten
+// exchanges instead of the 48 of eight separate butterflies.  Lane L returns
+// the total of value L >> 3; the eight lanes of a group return the same bits.
+__device__ __forceinline__ double wave_sum8(const double a[8], int lane) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+    double k4[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double keep = b5 ? a[j + 4] : a[j], send = b5 ? a[j] : a[j + 4];
+        k4[j] = keep + __shfl_xor(send, 32, kWave);
+    }
+    double k2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double keep = b4 ? k4[j + 2] : k4[j], send = b4 ? k4[j] : k4[j + 2];
+        k2[j] = keep + __shfl_xor(send, 16, kWave);
+    }
+    double k1;
+    {
+        const double keep = b3 ? k2[1] : k2[0], send = b3 ? k2[0] : k2[1];
+        k1 = keep + __shfl_xor(send, 8, kWave);
+    }
+    k1 += __shfl_xor(k1, 4, kWave);
+    k1 += __shfl_xor(k1, 2, kWave);
+    k1 += __shfl_xor(k1, 1, kWave);
+    return k1;
+}
+
 template <typename R>
 struct Vec4;
 template <>

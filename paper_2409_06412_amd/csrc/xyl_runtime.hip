@@ -218,6 +218,8 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Launch> g_tuned;
 // steps per pass and rows per strip of the two-step pass, chosen by xyl_autotune
 static std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tuned2;
+// launch shape of measurements without a step, chosen by xyl_autotune
+static std::map<std::tuple<int, int, int>, Launch> g_tunedm;
 
 // Launch shape before any autotuning: enough waves to occupy every SIMD of
 // the 256 CUs (strips of up to 16 rows while there are >= 4096 wave-rows,
@@ -261,6 +263,10 @@ struct xyl_lattice {
     uint64_t fresh_k = 0;
     bool initialized = false;
     Launch launch;
+    // launch shape of measurements without a step (xyl_autotune's choice;
+    // otherwise the stepping shape)
+    Launch mlaunch;
+    bool mlaunch_tuned = false;
     int graph_steps = 32;
     // captured step sequences, keyed by what their kernel arguments bake in
     struct GraphEntry {
@@ -378,7 +384,8 @@ static void destroy_graph(xyl_lattice* h) {
 template <typename R>
 static void lattice_launch_one(xyl_lattice* h, int mode) {
     Lat<R> v = h->view<R>();
-    launch_step<R>(v, mode, h->launch, nullptr, h->k, h->stream);
+    const Launch& l = (mode == kMeasure && h->mlaunch_tuned) ? h->mlaunch : h->launch;
+    launch_step<R>(v, mode, l, nullptr, h->k, h->stream);
 }
 
 // Captures S consecutive steps whose step index comes from the device counter
@@ -605,6 +612,22 @@ static void lattice_measure_into(xyl_lattice* h, bool advance, double* obs_dev) 
     }
 }
 
+// Observables of the current step into obs_dev, then `span` >= 1 steps.
+// Where two steps per pass apply and the span holds at least one pair of
+// passes, the sample is a measurement without a step (the same partial sums as
+// a measured step) and every step of the span goes through the two-step
+// passes; otherwise the measured step advances one step and the rest follow.
+template <typename R>
+static void lattice_sample_and_advance(xyl_lattice* h, uint64_t span, double* obs_dev) {
+    if (span >= 4 && step2_eligible(h)) {
+        lattice_measure_into<R>(h, false, obs_dev);
+        lattice_steps<R>(h, span);
+        return;
+    }
+    lattice_measure_into<R>(h, true, obs_dev);
+    lattice_steps<R>(h, span - 1);
+}
+
 // A blown-up integration (dt far too large, say) shows up as non-finite
 // values; calls that bring results to the host report it as XYL_ENUMERIC
 // (the copied values are still written).
@@ -737,6 +760,11 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find({Lx, Ly, dtype});
             if (it != g_tuned.end()) h->launch = it->second;
+            auto itm = g_tunedm.find({Lx, Ly, dtype});
+            if (itm != g_tunedm.end()) {
+                h->mlaunch = itm->second;
+                h->mlaunch_tuned = true;
+            }
             auto it2 = g_tuned2.find({Lx, Ly, dtype});
             if (it2 != g_tuned2.end()) {
                 h->fusion = it2->second.first;
@@ -1027,21 +1055,16 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
         DeviceGuard g(h->device);
         h->obs.reserve(6 * ns);
         for (uint64_t j = 0; j < ns; ++j) {
-            const bool last = j * every == nsteps;
-            if (h->dtype == XYL_F64) lattice_measure_into<double>(h, !last, h->obs.p + 6 * j);
-            else lattice_measure_into<float>(h, !last, h->obs.p + 6 * j);
-            if (!last) {
-                const uint64_t rest = std::min<uint64_t>(every - 1, nsteps - j * every - 1);
-                if (h->dtype == XYL_F64) lattice_steps<double>(h, rest);
-                else lattice_steps<float>(h, rest);
-                if (j + 1 == ns) {
-                    // nsteps not a multiple of every: finish the remaining steps
-                    const uint64_t done = j * every + 1 + rest;
-                    if (done < nsteps) {
-                        if (h->dtype == XYL_F64) lattice_steps<double>(h, nsteps - done);
-                        else lattice_steps<float>(h, nsteps - done);
-                    }
-                }
+            double* o = h->obs.p + 6 * j;
+            if (j * every == nsteps) {
+                // a sample at the last step: measured without stepping
+                if (h->dtype == XYL_F64) lattice_measure_into<double>(h, false, o);
+                else lattice_measure_into<float>(h, false, o);
+            } else {
+                // up to the next sample, or to the end (nsteps not a multiple of every)
+                const uint64_t span = std::min<uint64_t>(every, nsteps - j * every);
+                if (h->dtype == XYL_F64) lattice_sample_and_advance<double>(h, span, o);
+                else lattice_sample_and_advance<float>(h, span, o);
             }
         }
         check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6 * ns, hipMemcpyDeviceToHost, h->stream), "D2H");
@@ -1355,7 +1378,7 @@ int xyl_get_launch(xyl_lattice* h, int32_t* rows, int32_t* wpb) {
 // the best single-step shape and sets *fusion (1 or 2, whichever is faster
 // per step) and *rows2 (rows per strip of the best two-step pass, 0 if none).
 template <typename R>
-static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
+static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, Launch* mlaunch) {
     // time candidates on scratch copies so the lattice state is untouched;
     // each candidate runs as a captured graph of back-to-back steps, so the
     // host's launch overhead does not mask kernel time on small lattices
@@ -1381,11 +1404,11 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
     const int wpb_c[] = {1, 2, 4, 8};
     // about 2 ms of work per timing (at least 16 steps)
     const int reps = (int)std::max<double>(16.0, std::min<double>(512.0, 2.0e11 * 2e-3 / (double)h->N));
-    auto time_graph = [&](const Launch& l, int repeats) {
+    auto time_graph = [&](const Launch& l, int repeats, int mode = kStore) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ex = nullptr;
         check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        for (int i = 0; i < reps; ++i) launch_step<R>(v, kStore, l, kc.p, (uint64_t)i, h->cap_stream);
+        for (int i = 0; i < reps; ++i) launch_step<R>(v, mode, l, kc.p, (uint64_t)i, h->cap_stream);
         check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
         hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -1423,6 +1446,30 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2) {
         if (t < best_ms) {
             best_ms = t;
             best = scores[i].second;
+        }
+    }
+    // measurements without a step (the samples of a run): the same timing
+    // over the shapes, the partial sums written to the lattice's own buffer
+    {
+        std::vector<std::pair<float, Launch>> ms;
+        for (int r : rows_c) {
+            if (r > h->Ly) continue;
+            for (int w : wpb_c) {
+                Launch l;
+                l.rows = r;
+                l.wpb = w;
+                ms.push_back({time_graph(l, 1, kMeasure), l});
+            }
+        }
+        std::sort(ms.begin(), ms.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        *mlaunch = ms.front().second;
+        float mbest = 1e30f;
+        for (size_t i = 0; i < std::min<size_t>(3, ms.size()); ++i) {
+            const float t = time_graph(ms[i].second, 3, kMeasure);
+            if (t < mbest) {
+                mbest = t;
+                *mlaunch = ms[i].second;
+            }
         }
     }
     // two steps per pass: the same timing over a multiple of 4 steps, per step
@@ -1493,9 +1540,12 @@ int xyl_autotune(xyl_lattice* h) {
         require_init(h);
         DeviceGuard g(h->device);
         int fusion = 1, rows2 = 0;
-        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h, &fusion, &rows2)
-                                       : autotune_impl<float>(h, &fusion, &rows2);
+        Launch lm;
+        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h, &fusion, &rows2, &lm)
+                                       : autotune_impl<float>(h, &fusion, &rows2, &lm);
         h->launch = l;
+        h->mlaunch = lm;
+        h->mlaunch_tuned = true;
         if (h->dtype == XYL_F32) {
             h->fusion = fusion;
             h->step2_rows_tuned = rows2;
@@ -1503,6 +1553,7 @@ int xyl_autotune(xyl_lattice* h) {
         h->touch();
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[{h->Lx, h->Ly, h->dtype}] = l;
+        g_tunedm[{h->Lx, h->Ly, h->dtype}] = lm;
         if (h->dtype == XYL_F32) g_tuned2[{h->Lx, h->Ly, h->dtype}] = {fusion, rows2};
     });
 }

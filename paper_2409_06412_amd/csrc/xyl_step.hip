@@ -64,6 +64,13 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     // byte offsets of the lane's quad and of its two outer neighbours in a row
     const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
     const uint32_t xmb = (uint32_t)xm * (uint32_t)sizeof(R), xpb = (uint32_t)xp * (uint32_t)sizeof(R);
+    // measurement: the phases e^{-2 pi i x / Lx} of the lane's four columns
+    // (FP64; the same on every row, so evaluated once per strip)
+    double pxs[4], pxc[4];
+    if constexpr ((MODE & kMeasure) != 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sincospi(2.0 * (double)(x + q) / (double)Lx, &pxs[q], &pxc[q]);
+    }
 
     auto load_theta = [&](RowSet<R>& S, int y) {
         const R* r = row_start(thi, y, Lx);
@@ -130,11 +137,12 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
         if ((MODE & kOmega) && act) store4(at_byte(row_start(v.omega_out, y, Lx), xb), w);
 
         if (MODE & kMeasure) {
-            double acc[kNPart];
+            // per lane: energy terms, the order parameter's two components
+            // and their x modes; the y modes are the row's phase times the
+            // row's totals of the two components
+            double acc[8];
 #pragma unroll
-            for (int p = 0; p < kNPart; ++p) acc[p] = 0.0;
-            double rps, rpc;
-            sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
+            for (int p = 0; p < 8; ++p) acc[p] = 0.0;
             if (act) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -151,28 +159,25 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                     const double ec = e * (M == kModelSI ? s : c), es = e * (M == kModelSI ? c : s);
                     acc[2] += ec;
                     acc[3] += es;
-                    double pxs, pxc;
-                    sincospi(2.0 * (double)xs / (double)Lx, &pxs, &pxc);
-                    acc[4] += ec * pxc;
-                    acc[5] -= ec * pxs;
-                    acc[6] += es * pxc;
-                    acc[7] -= es * pxs;
-                    acc[8] += ec * rpc;
-                    acc[9] -= ec * rps;
-                    acc[10] += es * rpc;
-                    acc[11] -= es * rps;
+                    acc[4] += ec * pxc[q];
+                    acc[5] -= ec * pxs[q];
+                    acc[6] += es * pxc[q];
+                    acc[7] -= es * pxs[q];
                 }
             }
-#pragma unroll
-            for (int p = 0; p < kNPart; ++p) {
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) acc[p] += __shfl_xor(acc[p], off, kWave);
-            }
-            if (lane == 0) {
-                double* base = v.part + (v.part_stride ? (k - v.part_k0) * v.part_stride : 0);
-                double* dst = base + ((size_t)y * v.nxw + xw) * kNPart;
-#pragma unroll
-                for (int p = 0; p < kNPart; ++p) dst[p] = acc[p];
+            // lane 8p holds the wave's total of value p
+            const double tot = wave_sum8(acc, lane);
+            double* base = v.part + (v.part_stride ? (k - v.part_k0) * v.part_stride : 0);
+            double* dst = base + ((size_t)y * v.nxw + xw) * kNPart;
+            if ((lane & 7) == 0) dst[lane >> 3] = tot;
+            if (lane == 16 || lane == 24) {
+                // y modes of the row: e^{-2 pi i y / Ly} times the totals of
+                // the components (values 2 and 3)
+                double rps, rpc;
+                sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
+                const int o = lane == 16 ? 8 : 10;
+                dst[o] = tot * rpc;
+                dst[o + 1] = -(tot * rps);
             }
         }
     };

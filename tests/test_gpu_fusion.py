@@ -254,3 +254,31 @@ def test_autotune_picks_steps_per_pass_and_leaves_results_alone(xyl):
     np.testing.assert_array_equal(ta[1], tb[1])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("Lx,Ly,model", [(448, 33, "xy"), (768, 20, "si"), (256, 8, "xy"), (4096, 12, "xy")])
+def test_sampled_runs_on_two_step_passes_equal_single_steps(xyl, Lx, Ly, model):
+    """Sampled runs whose spans between samples go through two-step passes (a
+    measurement without a step, then the span's steps) equal, bit for bit,
+    those of measured single steps and the same steps one at a time; sample
+    spans of 4 (one pair of passes), 5 and 10 steps, a partial last wave, the
+    Si model, and the trailing sample at the run's last step."""
+    if model == "si":
+        spec = workloads.si_lattice(Lx, Ly, seed=6, replica=2)
+    else:
+        spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.9), (30, 0.4)), seed=6, replica=2)
+    res = []
+    for fusion in (1, 2):
+        lat = xyl.Lattice(Lx, Ly, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
+                          **spec.params())
+        lat.set_fusion(fusion)
+        if fusion == 2:
+            assert lat.fusion()[1] > 0, "the two-step pass applies to this shape"
+        lat.init_random()
+        s = [lat.step_measured(8, 4), lat.step_measured(23, 5), lat.step_measured(40, 10)]
+        res.append((s, lat.get_state()))
+        lat.close()
+    for a, b in zip(res[0][0], res[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(res[0][1], res[1][1]):
+        np.testing.assert_array_equal(a, b)
