@@ -120,7 +120,9 @@ def step_kernels(torch, lat, L, nsteps):
         ms = time_steps(torch, lat, nsteps)
         us = 2e3 * ms
         gbs = BYTES_PER_SITE_F32 * L * L / (us * 1e-6) / 1e9
-        out["two_step"] = {"kernel": "k_step2_tiled" if L > 4096 else "k_step2", "rows_per_strip": rows,
+        _, tile_waves, tiles = lat.step2_shape()
+        out["two_step"] = {"kernel": "k_step2_tiled" if tiles > 1 else "k_step2", "rows_per_strip": rows,
+                           "tiles": tiles, "tile_waves": tile_waves,
                            "avg_kernel_us": us,
                            "us_per_step": 1e3 * ms, "site_updates_per_s": L * L / (ms * 1e-3),
                            "algorithmic_GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}

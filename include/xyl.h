@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define XYL_ABI_VERSION 4
+#define XYL_ABI_VERSION 5
 
 enum {
     XYL_OK = 0,
@@ -282,6 +282,20 @@ int xyl_set_fusion(xyl_lattice* h, int32_t steps_per_pass);
  * per pass do not apply (shape, FP64, or steps_per_pass 1).  Either pointer
  * may be NULL. */
 int xyl_get_fusion(const xyl_lattice* h, int32_t* steps_per_pass, int32_t* rows);
+/* Shape of the two-step pass (App. B's data-parallel sweep, two BBK steps of
+ * App. A.1 per pass): rows per strip (2 to 64) and, for widths above 4096,
+ * the most waves (of 256 sites) a column tile may span (2 to 16: narrower
+ * tiles mean more of them, and up to eight workgroups per CU; below the
+ * row's own waves it splits rows up to 4096 sites wide as well, into at least
+ * two tiles); 0 keeps the current value.  A tile width no split fits falls
+ * back to whole rows (up to 4096 sites) or the fewest tiles.
+ * Results do not depend on it.  xyl_autotune sets both.  EINVAL outside the
+ * ranges. */
+int xyl_set_step2_shape(xyl_lattice* h, int32_t rows, int32_t tile_waves);
+/* The shape in effect: rows per strip, most waves per tile and the number of
+ * column tiles (whole rows: the row's waves and 1); zeros where two steps
+ * per pass do not apply.  Any pointer may be NULL. */
+int xyl_get_step2_shape(const xyl_lattice* h, int32_t* rows, int32_t* tile_waves, int32_t* tiles);
 
 /* -------------------------------------------------------------- test hooks */
 /* Raw Philox4x32-10 blocks computed on the device: for j < n, counter
@@ -424,6 +438,15 @@ int xyl_adjoint_forward(xyl_lattice* h, uint64_t nsteps, uint64_t ckpt_every, ui
 int xyl_adjoint_backward(xyl_lattice* h, uint64_t run, double* grad, double* dtheta0, double* domega0);
 int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, double* grad, void* dtheta0,
                                 void* domega0, int32_t dtype);
+/* Reverse steps per pass of xyl_adjoint_backward (App. A.1's step, run
+ * backwards): 2 (the default) takes two reverse steps per pass over the state
+ * where a row fits one workgroup (Lx at most 1024 sites in FP32, 640 in FP64,
+ * and Ly >= 4), one site per lane; 1 keeps one reverse step per pass.
+ * rows: rows per strip of the two-step pass (1, 2 or 4; 0 keeps the current
+ * value, initially 2).  dL/dth and dL/dw are bitwise
+ * the same either way; the parameter gradients are sums taken in another
+ * order.  EINVAL outside the ranges. */
+int xyl_set_adjoint_fusion(xyl_lattice* h, int32_t steps_per_pass, int32_t rows);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,8 @@ _SIGS = {
     "xyl_set_model": (_i32, [_vp, _i32, _d]),
     "xyl_set_fusion": (_i32, [_vp, _i32]),
     "xyl_get_fusion": (_i32, [_vp, P(_i32), P(_i32)]),
+    "xyl_set_step2_shape": (_i32, [_vp, _i32, _i32]),
+    "xyl_get_step2_shape": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
     "xyl_ensemble_set_fusion": (_i32, [_vp, _i32]),
     "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
@@ -122,6 +124,7 @@ _SIGS = {
     "xyl_adjoint_forward": (_i32, [_vp, _u64, _u64, _u64, P(_d), P(_u64)]),
     "xyl_adjoint_backward": (_i32, [_vp, _u64, P(_d), P(_d), P(_d)]),
     "xyl_adjoint_backward_device": (_i32, [_vp, _u64, _d, P(_d), _vp, _vp, _i32]),
+    "xyl_set_adjoint_fusion": (_i32, [_vp, _i32, _i32]),
     "xyl_set_state_device": (_i32, [_vp, _vp, _vp, _i32, _u64]),
     "xyl_domains_noalloc": (_i32, [_vp, P(_i32), P(_u64), P(_u64), _u64, P(_u64), P(_u64), P(_u64)]),
     "xyl_get_raw_state": (_i32, [_vp, P(_d), P(_d), P(_u64), P(_i32)]),
@@ -266,6 +269,18 @@ class Lattice:
         sp, rows = _i32(), _i32()
         _check(load().xyl_get_fusion(self._h, ctypes.byref(sp), ctypes.byref(rows)))
         return sp.value, rows.value
+
+    def set_step2_shape(self, rows=0, tile_waves=0):
+        """Rows per strip of the two-step pass and, for widths above 4096, the
+        most waves per column tile (0 keeps the current value)."""
+        _check(load().xyl_set_step2_shape(self._h, int(rows), int(tile_waves)))
+
+    def step2_shape(self):
+        """(rows per strip, most waves per tile, number of column tiles) of
+        the two-step pass; zeros where it does not apply."""
+        r, w, t = _i32(), _i32(), _i32()
+        _check(load().xyl_get_step2_shape(self._h, ctypes.byref(r), ctypes.byref(w), ctypes.byref(t)))
+        return r.value, w.value, t.value
 
     def set_launch(self, rows_per_strip=0, waves_per_block=0):
         _check(load().xyl_set_launch(self._h, int(rows_per_strip), int(waves_per_block)))
@@ -443,6 +458,12 @@ class Lattice:
                                           ctypes.byref(run)))
         self.adjoint_run = run.value
         return L.value
+
+    def set_adjoint_fusion(self, steps_per_pass: int, rows: int = 0):
+        """Reverse steps per pass of the backward sweep (2 where a row fits a
+        workgroup, else 1) and rows per strip of the two-step pass (0 keeps
+        it); dL/dtheta0 and dL/domega0 are identical either way."""
+        _check(load().xyl_set_adjoint_fusion(self._h, int(steps_per_pass), int(rows)))
 
     def adjoint_backward(self, run: Optional[int] = None):
         """(dL/d[Jx, Jy, h, gamma], dL/dtheta0, dL/domega0) as host arrays, of

@@ -22,6 +22,9 @@
 // (a = 1 - gamma dt/2, c = 1/(1 + gamma dt/2), hs_k = sqrt(2 gamma T_k dt)/2).
 // Every lF_j of a neighbour is recomputed from that neighbour's (lt', lu'),
 // so one pass per step reads th, u, lt', lu' and writes lt, lu.
+#include <mutex>
+#include <set>
+
 #include "xyl_device.hpp"
 
 namespace xyl {
@@ -39,6 +42,69 @@ struct AdjArgs {
     uint64_t cm_base;
     double* gacc;             // per-task parameter adjoints [ntasks][4], accumulated
 };
+
+// Coefficients of reverse step k (the same for every site).
+template <typename R>
+struct AdjStep {
+    R kap;        // lF = kap (lu' + dt lt')
+    R lu_fac;     // lu = lu_fac (lu' + dt lt')
+    R cm;         // direct loss coefficient of step k
+    R hs, ghs, ga, gc;
+    bool fresh;
+};
+
+template <typename R>
+__device__ __forceinline__ AdjStep<R> adj_step_coef(const AdjArgs<R>& A, uint64_t k) {
+    const Lat<R>& v = A.v;
+    AdjStep<R> K;
+    const double hsd = half_sigma(v.sched, v.gamma, v.dtd, k);
+    K.hs = (R)hsd;
+    K.fresh = (k == v.fresh_k);
+    const R ca = v.c * v.a;
+    K.kap = K.fresh ? v.hdt : v.hdt * (R(1) + ca);
+    K.lu_fac = K.fresh ? v.a : ca;
+    K.cm = (R)A.cm[k - A.cm_base];
+    K.ghs = v.gamma > 0.0 ? (R)(hsd / (2.0 * v.gamma)) : R(0);
+    K.ga = (R)(-0.5 * v.dtd);
+    K.gc = (R)(-0.5 * v.dtd * (double)v.c * (double)v.c);
+    return K;
+}
+
+// The reverse step at one site.  In: (s, c) of its angle th^k, (sin, cos, lF)
+// of its x- and y-neighbours (m = -1, p = +1), its own lF, lt', lu', u^k,
+// draw n^k and staggering sign eps.  Out: lt, lu; its parameter adjoints are
+// added to (rx, ry, rh, rg).
+template <typename R>
+__device__ __forceinline__ void adj_site(const Lat<R>& v, const AdjStep<R>& K, R s, R c, R sxm, R cxm, R fxm, R sxp,
+                                         R cxp, R fxp, R sym, R cym, R fym, R syp, R cyp, R fyp, R lf, R lt, R lu, R u,
+                                         R n, R eps, R& lto, R& luo, R& rx, R& ry, R& rh, R& rg) {
+    // force and its parameter derivatives
+    const R dFx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
+    const R dFy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
+    const R dFh = R(-4) * s * c;
+    const R F = Prec<R>::fma(v.Jx, dFx, Prec<R>::fma(v.Jy, dFy, (R)v.hd * dFh));
+    // J lF with cos(th_i - th_j) = c c_j + s s_j
+    const R jx = (c * cxp + s * sxp) * (lf - fxp) + (c * cxm + s * sxm) * (lf - fxm);
+    const R jy = (c * cyp + s * syp) * (lf - fyp) + (c * cym + s * sym) * (lf - fym);
+    const R jh = (c * c - s * s) * lf;
+    const R Jl = Prec<R>::fma(v.Jx, jx, Prec<R>::fma(v.Jy, jy, -v.h4 * jh));
+    const R g = Prec<R>::fma(v.dt, lt, lu);
+    lto = lt + Jl + K.cm * (-eps * s);
+    luo = K.lu_fac * g;
+    // parameter adjoints
+    rx = Prec<R>::fma(lf, dFx, rx);
+    ry = Prec<R>::fma(lf, dFy, ry);
+    rh = Prec<R>::fma(lf, dFh, rh);
+    const R lw = v.a * g;
+    if (K.fresh) {
+        rg += K.ga * g * u + K.ghs * n * g;
+    } else {
+        const R Av = Prec<R>::fma(K.hs, n, Prec<R>::fma(v.hdt, F, u));
+        const R w = v.c * Av;
+        const R lA = v.c * lw;
+        rg += K.ga * g * w + K.gc * lw * Av + K.ghs * n * (g + lA);
+    }
+}
 
 template <typename R>
 struct AdjRow {
@@ -63,16 +129,8 @@ __device__ __forceinline__ void adj_strip(const AdjArgs<R>& A, int task, int xw,
     const int x = x0 + kLaneSites * lane;
     const int xm = x == 0 ? Lx - 1 : x - 1;
     const int xp = x + 4 == Lx ? 0 : x + 4;
-    const double hsd = half_sigma(v.sched, v.gamma, v.dtd, k);
-    const R hs = (R)hsd;
-    const bool fresh = (k == v.fresh_k);
-    const R ca = v.c * v.a;
-    const R kap = fresh ? v.hdt : v.hdt * (R(1) + ca);    // lF = kap (lu' + dt lt')
-    const R lu_fac = fresh ? v.a : ca;                    // lu = lu_fac (lu' + dt lt')
-    const R cm = (R)A.cm[k - A.cm_base];
-    const R ghs = v.gamma > 0.0 ? (R)(hsd / (2.0 * v.gamma)) : R(0);
-    const R ga = (R)(-0.5 * v.dtd);
-    const R gc = (R)(-0.5 * v.dtd * (double)v.c * (double)v.c);
+    const AdjStep<R> K = adj_step_coef(A, k);
+    const R kap = K.kap;
     const uint32_t qrow = (uint32_t)(Lx >> 2);
 
     auto load_row = [&](AdjRow<R>& S, int y) {
@@ -131,41 +189,12 @@ __device__ __forceinline__ void adj_strip(const AdjArgs<R>& A, int task, int xw,
         R rx = 0, ry = 0, rh = 0, rg = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const R s = C.s[q], c = C.c[q];
             const R sxm = q == 0 ? sL : C.s[q - 1], cxm = q == 0 ? cL : C.c[q - 1], fxm = q == 0 ? fL : C.lF[q - 1];
             const R sxp = q == 3 ? sR : C.s[q + 1], cxp = q == 3 ? cR : C.c[q + 1], fxp = q == 3 ? fR : C.lF[q + 1];
-            const R sym = P.s[q], cym = P.c[q], fym = P.lF[q];
-            const R syp = N.s[q], cyp = N.c[q], fyp = N.lF[q];
-            // force and its parameter derivatives
-            const R dFx = Prec<R>::fma(s, cxp + cxm, -(c * (sxp + sxm)));
-            const R dFy = Prec<R>::fma(s, cyp + cym, -(c * (syp + sym)));
-            const R dFh = R(-4) * s * c;
-            const R F = Prec<R>::fma(v.Jx, dFx, Prec<R>::fma(v.Jy, dFy, (R)v.hd * dFh));
-            // J lF with cos(th_i - th_j) = c c_j + s s_j
-            const R lf = C.lF[q];
-            const R jx = (c * cxp + s * sxp) * (lf - fxp) + (c * cxm + s * sxm) * (lf - fxm);
-            const R jy = (c * cyp + s * syp) * (lf - fyp) + (c * cym + s * sym) * (lf - fym);
-            const R jh = (c * c - s * s) * lf;
-            const R Jl = Prec<R>::fma(v.Jx, jx, Prec<R>::fma(v.Jy, jy, -v.h4 * jh));
-            const R g = Prec<R>::fma(v.dt, C.lt[q], C.lu[q]);
             const int xs = x + q;
             const R eps = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? R(-1) : R(1);
-            lto[q] = C.lt[q] + Jl + cm * (-eps * s);
-            luo[q] = lu_fac * g;
-            // parameter adjoints
-            rx = Prec<R>::fma(lf, dFx, rx);
-            ry = Prec<R>::fma(lf, dFy, ry);
-            rh = Prec<R>::fma(lf, dFh, rh);
-            const R lw = v.a * g;
-            if (fresh) {
-                const R w = uc[q];
-                rg += ga * g * w + ghs * n[q] * g;
-            } else {
-                const R Av = Prec<R>::fma(hs, n[q], Prec<R>::fma(v.hdt, F, uc[q]));
-                const R w = v.c * Av;
-                const R lA = v.c * lw;
-                rg += ga * g * w + gc * lw * Av + ghs * n[q] * (g + lA);
-            }
+            adj_site(v, K, C.s[q], C.c[q], sxm, cxm, fxm, sxp, cxp, fxp, P.s[q], P.c[q], P.lF[q], N.s[q], N.c[q],
+                     N.lF[q], C.lF[q], C.lt[q], C.lu[q], uc[q], n[q], eps, lto[q], luo[q], rx, ry, rh, rg);
         }
         if (act) {
             store4(A.lt_out + row + x, lto);
@@ -226,6 +255,137 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<R> A, const uint64_t* k
     adj_strip<R>(A, t, t % A.v.nxw, t / A.v.nxw, rows, k, threadIdx.x & (kWave - 1));
 }
 
+// Two reverse steps per pass, k + 1 then k, for rows up to kAdj2MaxLx sites:
+// one site per lane, a workgroup per strip of rows across the whole width.
+// Stage A (reverse step k+1: th^{k+1}, u^{k+1}, lt^{k+2}, lu^{k+2}) runs two
+// rows ahead of stage B (reverse step k: th^k, u^k and stage A's lt^{k+1},
+// lu^{k+1}, which never leave the workgroup).  Each stage takes its
+// neighbours from an LDS ring of four rows holding (sin, cos, lt', lu') per
+// site; a row enters ring A two iterations before stage A uses it and ring B
+// (from stage A) two before stage B does, so one barrier per iteration
+// separates every write from its reads, and four slots keep the row being
+// written apart from the three being read.  Stage A also covers one halo row
+// on each side of the strip, which the neighbouring strips compute with the
+// same arithmetic.  Every site takes the arithmetic of adj_site with the
+// same inputs as in two single reverse steps, so lt^k and lu^k are bitwise
+// those; the parameter adjoints are summed in another order.
+template <typename R>
+struct Adj2Args {
+    AdjArgs<R> a;       // th, u: th^k, u^k; lt_in, lu_in: step k+2; lt_out, lu_out: step k
+    const R* th1;       // th^{k+1}
+    const R* u1;        // u^{k+1}
+};
+
+constexpr int kAdj2MaxLx = 1024;
+
+template <typename R, int ROWS>
+__global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const uint64_t* kdev, uint64_t koff) {
+    const AdjArgs<R>& A = A2.a;
+    const Lat<R>& v = A.v;
+    const int Lx = v.Lx, Ly = v.Ly;
+    extern __shared__ unsigned char adj2_lds[];
+    R* ringA = reinterpret_cast<R*>(adj2_lds);             // [slot][s, c, lt, lu][Lx]
+    R* ringB = ringA + (size_t)kStep2Slots * 4 * Lx;
+    auto slot = [&](R* ring, int r) { return ring + (size_t)(r & (kStep2Slots - 1)) * 4 * Lx; };
+    const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int y0 = strip * ROWS;
+    const int y1 = min(y0 + ROWS, Ly);
+    const int x = threadIdx.x;
+    const bool act = x < Lx;
+    const int xa = act ? x : 0;
+    const int xm = xa == 0 ? Lx - 1 : xa - 1, xp = xa + 1 == Lx ? 0 : xa + 1;
+    auto wrap = [&](int r) { return r < 0 ? r + Ly : (r >= Ly ? r - Ly : r); };
+    auto at = [&](int r) { return (size_t)wrap(r) * (size_t)Lx + (size_t)xa; };
+    // Every input of the strip is loaded up front, in the order of first use
+    // (the strip's loads then wait on one memory latency, not one per row):
+    // ring A rows y0-2 .. y0+ROWS+1 (th^{k+1}, lt'', lu''), stage A rows
+    // y0-1 .. y0+ROWS (u^{k+1}, th^k), stage B rows y0 .. y0+ROWS-1 (u^k).
+    // Rows past a ragged last strip's end are loaded (wrapped) and not used.
+    constexpr int NT = ROWS + 6;
+    R th1[ROWS + 4], lt2[ROWS + 4], lu2[ROWS + 4], u1[ROWS + 2], th0[ROWS + 2], u0[ROWS];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        if (i < ROWS + 4) {
+            th1[i] = A2.th1[at(y0 - 2 + i)];
+            lt2[i] = A.lt_in[at(y0 - 2 + i)];
+            lu2[i] = A.lu_in[at(y0 - 2 + i)];
+        }
+        if (i >= 3 && i - 3 < ROWS + 2) {
+            u1[i - 3] = A2.u1[at(y0 - 1 + i - 3)];
+            th0[i - 3] = A.th[at(y0 - 1 + i - 3)];
+        }
+        if (i >= 5 && i - 5 < ROWS) u0[i - 5] = A.u[at(y0 + i - 5)];
+    }
+    const uint64_t k = koff + (kdev ? *kdev : 0);
+    const AdjStep<R> KA = adj_step_coef(A, k + 1);
+    const AdjStep<R> KB = adj_step_coef(A, k);
+    auto lf_of = [&](const R* sl, int i, R kap) { return kap * Prec<R>::fma(v.dt, sl[2 * Lx + i], sl[3 * Lx + i]); };
+    // the stage's reverse step at row r from its ring (rows r-1, r, r+1 in
+    // slots r-1, r, r+1) with coefficients K, returning lt, lu
+    auto stage = [&](R* ring, const AdjStep<R>& K, int r, R u, uint64_t ks, R& lto, R& luo, double g[4]) {
+        const R* C = slot(ring, r);
+        const R* Pm = slot(ring, r - 1);
+        const R* Np = slot(ring, r + 1);
+        const int y = wrap(r);
+        R n4[4];
+        noise4<R>((uint32_t)y * (uint32_t)(Lx >> 2) + (uint32_t)(xa >> 2), v.replica, ks, v.seed_lo, v.seed_hi, n4);
+        const R eps = (((xa * v.stag_x) + (y * v.stag_y)) & 1) ? R(-1) : R(1);
+        R rx = 0, ry = 0, rh = 0, rg = 0;
+        adj_site(v, K, C[xa], C[Lx + xa], C[xm], C[Lx + xm], lf_of(C, xm, K.kap), C[xp], C[Lx + xp],
+                 lf_of(C, xp, K.kap), Pm[xa], Pm[Lx + xa], lf_of(Pm, xa, K.kap), Np[xa], Np[Lx + xa],
+                 lf_of(Np, xa, K.kap), lf_of(C, xa, K.kap), C[2 * Lx + xa], C[3 * Lx + xa], u, n4[xa & 3], eps, lto,
+                 luo, rx, ry, rh, rg);
+        if (r >= y0 && r < y1) {
+            g[0] += (double)rx;
+            g[1] += (double)ry;
+            g[2] += (double)rh;
+            g[3] += (double)rg;
+        }
+    };
+
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    // iteration i (row t = y0 - 2 + i): ring A takes row t, stage A does row
+    // t - 2 into ring B, stage B row t - 4 to memory; then one barrier
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int t = y0 - 2 + i;
+        if (i < ROWS + 4 && t <= y1 + 1 && act) {
+            R* w = slot(ringA, t);
+            R sn, cs;
+            Prec<R>::sincos(th1[i], sn, cs);
+            w[xa] = sn;
+            w[Lx + xa] = cs;
+            w[2 * Lx + xa] = lt2[i];
+            w[3 * Lx + xa] = lu2[i];
+        }
+        const int ra = t - 2;
+        if (i >= 3 && i - 3 < ROWS + 2 && ra <= y1 && act) {
+            R lto, luo;
+            stage(ringA, KA, ra, u1[i - 3], k + 1, lto, luo, g);
+            R* w = slot(ringB, ra);
+            R sn, cs;
+            Prec<R>::sincos(th0[i - 3], sn, cs);
+            w[xa] = sn;
+            w[Lx + xa] = cs;
+            w[2 * Lx + xa] = lto;
+            w[3 * Lx + xa] = luo;
+        }
+        const int rb = t - 4;
+        if (i >= 6 && i - 6 < ROWS && rb < y1 && act) {
+            R lto, luo;
+            stage(ringB, KB, rb, u0[i - 6], k, lto, luo, g);
+            A.lt_out[at(rb)] = lto;
+            A.lu_out[at(rb)] = luo;
+        }
+        if (i + 1 < NT) __syncthreads();
+    }
+    // wave totals, lane 16p holding value p; one slot per wave
+    const int lane = x & (kWave - 1);
+    const double tot = wave_sum4(g, lane);
+    const size_t wave = (size_t)strip * (blockDim.x / kWave) + (size_t)(x / kWave);
+    if ((lane & 15) == 0) A.gacc[wave * 4 + (lane >> 4)] += tot;
+}
+
 // Seed of the reverse sweep at the last step N: lt = direct loss term, lu = 0.
 template <typename R>
 __global__ void k_adj_seed(Lat<R> v, const R* th, R* lt, R* lu, double cmN) {
@@ -241,8 +401,16 @@ __global__ void k_adj_seed(Lat<R> v, const R* th, R* lt, R* lu, double cmN) {
 }
 
 template <typename R>
-int adjoint_tasks(const Lat<R>& v, int rows) {
-    return ((v.Ly + rows - 1) / rows) * v.nxw;
+bool adjoint2_fits(const Lat<R>& v) {
+    return v.Lx <= kAdj2MaxLx && v.Ly >= 4 && adjoint2_lds<R>(v.Lx) <= 160 * 1024;
+}
+
+template <typename R>
+int adjoint_tasks(const Lat<R>& v, int rows, int rows2) {
+    const int single = ((v.Ly + rows - 1) / rows) * v.nxw;
+    if (!adjoint2_fits(v) || rows2 < 1) return single;
+    const int fused = ((v.Ly + rows2 - 1) / rows2) * ((v.Lx + kWave - 1) / kWave);
+    return std::max(single, fused);
 }
 
 template <typename R>
@@ -261,10 +429,60 @@ void launch_adjoint_step(const Lat<R>& v, const R* th, const R* u, const R* lt_i
     A.cm_base = cm_base;
     A.gacc = gacc;
     const int wpb = std::min(l.wpb, 4);
-    const int ntasks = adjoint_tasks(v, l.rows);
+    const int ntasks = ((v.Ly + l.rows - 1) / l.rows) * v.nxw;
     const int nblocks = (ntasks + wpb - 1) / wpb;
     k_adjoint<R><<<nblocks, wpb * kWave, 0, s>>>(A, kdev, koff, l.rows, ntasks);
     check_hip(hipGetLastError(), "adjoint kernel launch");
+}
+
+// the LDS above the default limit is allowed once per device and instance
+template <typename R, int ROWS>
+static void launch_adjoint2(const Adj2Args<R>& A2, int nstrips, int threads, size_t lds, const uint64_t* kdev,
+                            uint64_t koff, hipStream_t s) {
+    static std::mutex mu;
+    static std::set<int> allowed;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!allowed.count(dev)) {
+            check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_adjoint2<R, ROWS>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024),
+                      "hipFuncSetAttribute");
+            allowed.insert(dev);
+        }
+    }
+    k_adjoint2<R, ROWS><<<nstrips, threads, lds, s>>>(A2, kdev, koff);
+    check_hip(hipGetLastError(), "two-step reverse kernel launch");
+}
+
+template <typename R>
+void launch_adjoint_step2(const Lat<R>& v, const R* th0, const R* u0, const R* th1, const R* u1, const R* lt_in,
+                          const R* lu_in, R* lt_out, R* lu_out, const double* cm, uint64_t cm_base, double* gacc,
+                          const uint64_t* kdev, uint64_t koff, int rows, hipStream_t s) {
+    if (!adjoint2_fits(v) || rows < 1) throw Error(-5, "two-step reverse pass: shape not supported");
+    Adj2Args<R> A2;
+    A2.a.v = v;
+    A2.a.th = th0;
+    A2.a.u = u0;
+    A2.a.lt_in = lt_in;
+    A2.a.lu_in = lu_in;
+    A2.a.lt_out = lt_out;
+    A2.a.lu_out = lu_out;
+    A2.a.cm = cm;
+    A2.a.cm_base = cm_base;
+    A2.a.gacc = gacc;
+    A2.th1 = th1;
+    A2.u1 = u1;
+    const int nstrips = (v.Ly + rows - 1) / rows;
+    const int threads = (v.Lx + kWave - 1) / kWave * kWave;
+    const size_t lds = adjoint2_lds<R>(v.Lx);
+    switch (rows) {
+        case 1: launch_adjoint2<R, 1>(A2, nstrips, threads, lds, kdev, koff, s); break;
+        case 2: launch_adjoint2<R, 2>(A2, nstrips, threads, lds, kdev, koff, s); break;
+        case 4: launch_adjoint2<R, 4>(A2, nstrips, threads, lds, kdev, koff, s); break;
+        default: throw Error(-5, "two-step reverse pass: rows per strip must be 1, 2 or 4");
+    }
 }
 
 template <typename R>
@@ -274,8 +492,17 @@ void launch_adjoint_seed(const Lat<R>& v, const R* th, R* lt, R* lu, double cmN,
     check_hip(hipGetLastError(), "adjoint seed launch");
 }
 
-template int adjoint_tasks<float>(const Lat<float>&, int);
-template int adjoint_tasks<double>(const Lat<double>&, int);
+template bool adjoint2_fits<float>(const Lat<float>&);
+template bool adjoint2_fits<double>(const Lat<double>&);
+template int adjoint_tasks<float>(const Lat<float>&, int, int);
+template int adjoint_tasks<double>(const Lat<double>&, int, int);
+template void launch_adjoint_step2<float>(const Lat<float>&, const float*, const float*, const float*, const float*,
+                                          const float*, const float*, float*, float*, const double*, uint64_t,
+                                          double*, const uint64_t*, uint64_t, int, hipStream_t);
+template void launch_adjoint_step2<double>(const Lat<double>&, const double*, const double*, const double*,
+                                           const double*, const double*, const double*, double*, double*,
+                                           const double*, uint64_t, double*, const uint64_t*, uint64_t, int,
+                                           hipStream_t);
 template void launch_adjoint_step<float>(const Lat<float>&, const float*, const float*, const float*, const float*,
                                          float*, float*, const double*, uint64_t, double*, const uint64_t*, uint64_t,
                                          const Launch&, hipStream_t);

@@ -397,6 +397,25 @@ __device__ __forceinline__ double wave_sum8(const double a[8], int lane) {
     return k1;
 }
 
+// The same for four FP64 values: lane L returns the total of value L >> 4.
+__device__ __forceinline__ double wave_sum4(const double a[4], int lane) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+    double k2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double keep = b5 ? a[j + 2] : a[j], send = b5 ? a[j] : a[j + 2];
+        k2[j] = keep + __shfl_xor(send, 32, kWave);
+    }
+    double k1;
+    {
+        const double keep = b4 ? k2[1] : k2[0], send = b4 ? k2[0] : k2[1];
+        k1 = keep + __shfl_xor(send, 16, kWave);
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) k1 += __shfl_xor(k1, off, kWave);
+    return k1;
+}
+
 template <typename R>
 struct Vec4;
 template <>

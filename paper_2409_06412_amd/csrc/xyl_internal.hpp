@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include <stdexcept>
 #include <string>
 
@@ -102,19 +104,26 @@ struct Task2 {
 // take the row's two outer neighbours.
 // A width wider than one workgroup's 16 waves is split into the fewest column
 // tiles ntx of w columns (the last takes the rest), each workgroup covering
-// its tile and one quad on each side (w + 8 <= 4096 sites).  No tile may leave
-// a single lane in its last wave.  Returns false if Lx needs no tiles or none
-// fit.  Tiles of up to kStep2SmallTileWaves waves run in a kernel instance
-// bounded to that many (so the compiler may use more registers per lane).
-constexpr int kStep2SmallTileWaves = 11;
+// its tile and one quad on each side (w + 8 sites, at most max_waves waves).
+// A width that fits one workgroup is split as well when max_waves is below
+// its waves (at least two tiles).  No tile may leave a single lane in its
+// last wave.  Returns false if the width needs no tiles or none fit.
+// Narrower tiles trade lanes left idle in a partial last wave, and the halo
+// quads, for more workgroups per CU (each holds a 32 (w + 8) B LDS ring, and
+// a barrier holds fewer waves); the kernel instance is chosen by the tile's
+// waves (step2_tile_bound).
+// Rows of sine/cosine in the two-step pass's LDS ring (8 B per site per row).
+constexpr int kStep2Slots = 4;
+
 struct Step2Tiles {
     int ntx = 0, w = 0;
 };
-inline bool step2_tiles(int Lx, Step2Tiles* t) {
-    constexpr int kMax = 16 * kWaveSites;
-    if (Lx <= kMax || Lx % 4 != 0) return false;
+inline bool step2_tiles(int Lx, Step2Tiles* t, int max_waves = 16) {
+    if (Lx % 4 != 0 || max_waves < 2 || max_waves > 16) return false;
+    if (Lx <= max_waves * kWaveSites && Lx <= 16 * kWaveSites) return false;
+    const int kMax = max_waves * kWaveSites;
     auto lanes_ok = [](int W) { return W % kWaveSites == 0 || W % kWaveSites >= 2 * kLaneSites; };
-    for (int ntx = (Lx + kMax - 9) / (kMax - 8); ntx <= 64; ++ntx) {
+    for (int ntx = std::max(2, (Lx + kMax - 9) / (kMax - 8)); ntx <= 64; ++ntx) {
         const int w = ((Lx + ntx - 1) / ntx + 3) / 4 * 4;
         const int wl = Lx - (ntx - 1) * w;
         if (w + 8 <= kMax && wl >= 4 && lanes_ok(w + 8) && lanes_ok(wl + 8)) {
@@ -125,6 +134,10 @@ inline bool step2_tiles(int Lx, Step2Tiles* t) {
     }
     return false;
 }
+// Waves of the kernel instance that runs tiles of `waves` waves: 4 and 8 (at
+// most 128 VGPRs, so that 4 and 2 workgroups share a CU), 11 (one workgroup
+// per CU with room for more registers) and 16.
+inline int step2_tile_bound(int waves) { return waves <= 4 ? 4 : waves <= 8 ? 8 : waves <= 11 ? 11 : 16; }
 
 inline bool step2_width_ok(int Lx) {
     if (Lx % 4 != 0 || Lx > 16 * kWaveSites) return false;
@@ -143,9 +156,15 @@ void launch_ensemble_step(const Lat<R>* reps, const Task* tasks, int ntasks, int
 // Two steps per pass (FP32; Lx up to 4096 with step2_width_ok, Ly >= 4): angles
 // and velocities at step k are read from th_in / u_in and those at k+2
 // written to th_out / u_out (distinct buffers); k = v.k_base + j (+ *kdev).
-// Widths above 4096 run as column tiles (step2_tiles); rows per strip as given.
+// Widths above 4096 run as column tiles (step2_tiles) of at most tile_waves
+// waves (0: 16, the fewest tiles; a value no tiling fits falls back to 16);
+// rows per strip as given.
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
-                  const uint64_t* kdev, uint64_t j, hipStream_t s);
+                  const uint64_t* kdev, uint64_t j, hipStream_t s, int tile_waves = 0);
+// The same for XY lattices whose rows one workgroup takes whole, also storing
+// the state after the first of the two steps into (th_mid, u_mid).
+void launch_step2_mid(const Lat<float>& v, const float* th_in, const float* u_in, float* th_mid, float* u_mid,
+                      float* th_out, float* u_out, int rows, const uint64_t* kdev, uint64_t j, hipStream_t s);
 // Two steps per pass of many FP32 replicas (reps: the table of their views,
 // k = k_base + j (+ *kdev)): one workgroup per task, every task's replica
 // spanning `waves` waves (partial: some width not a multiple of 256), max_lx
@@ -178,8 +197,25 @@ template <typename R>
 void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent, uint32_t* size,
                     uint32_t* hist, uint32_t* stats, hipStream_t s);
 
+// Slots of parameter adjoints the reverse kernels use (rows per strip of
+// the single and of the two-step reverse pass).
 template <typename R>
-int adjoint_tasks(const Lat<R>& v, int rows);
+int adjoint_tasks(const Lat<R>& v, int rows, int rows2);
+// LDS of the two-step reverse pass: two rings of 4 rows of (sin, cos, lt', lu').
+template <typename R>
+constexpr size_t adjoint2_lds(int Lx) {
+    return sizeof(R) * 2 * (size_t)kStep2Slots * 4 * (size_t)Lx;
+}
+// Whether the two-step reverse pass takes this lattice (rows up to 1024
+// sites, Ly >= 4, its LDS within a CU's).
+template <typename R>
+bool adjoint2_fits(const Lat<R>& v);
+// Reverse steps k+1 and k in one pass (k = koff + *kdev): th0, u0 the state at
+// k, th1, u1 at k+1, (lt_in, lu_in) the adjoint at k+2, (lt_out, lu_out) at k.
+template <typename R>
+void launch_adjoint_step2(const Lat<R>& v, const R* th0, const R* u0, const R* th1, const R* u1, const R* lt_in,
+                          const R* lu_in, R* lt_out, R* lu_out, const double* cm, uint64_t cm_base, double* gacc,
+                          const uint64_t* kdev, uint64_t koff, int rows, hipStream_t s);
 template <typename R>
 void launch_adjoint_step(const Lat<R>& v, const R* th, const R* u, const R* lt_in, const R* lu_in, R* lt_out,
                          R* lu_out, const double* cm, uint64_t cm_base, double* gacc, const uint64_t* kdev,

@@ -216,8 +216,12 @@ static size_t elem_size(int dtype) { return dtype == XYL_F64 ? sizeof(double) : 
 // -------------------------------------------------------- launch tuning
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Launch> g_tuned;
-// steps per pass and rows per strip of the two-step pass, chosen by xyl_autotune
-static std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tuned2;
+// steps per pass, rows per strip and waves per column tile of the two-step
+// pass, chosen by xyl_autotune
+struct Tuned2 {
+    int fusion, rows, tile_waves;
+};
+static std::map<std::tuple<int, int, int>, Tuned2> g_tuned2;
 // launch shape of measurements without a step, chosen by xyl_autotune
 static std::map<std::tuple<int, int, int>, Launch> g_tunedm;
 
@@ -282,6 +286,9 @@ struct xyl_lattice {
     int fusion = 2;                // steps per pass of plain FP32 stepping where the shape allows (1 or 2)
     int cus = 256;                 // compute units of the device
     int step2_rows_tuned = 0;      // rows per strip of the two-step pass from xyl_autotune (0: the size rule)
+    int step2_tw_tuned = 0;        // most waves per column tile (widths above 4096) from xyl_autotune (0: the rule)
+    int adj2_rows = 0;             // rows per strip of the two-step reverse pass (0: the rule)
+    int adj_fusion = 2;            // reverse steps per pass of the adjoint sweep (1 or 2)
     DevBuf<char> u2;               // second velocity buffer of the two-step passes
     // device scratch
     DevBuf<uint64_t> kdev;
@@ -421,6 +428,19 @@ static bool step2_eligible(const xyl_lattice* h) {
     return h->dtype == XYL_F32 && h->fusion == 2 && kick_factored(h->p) && step2_lattice_shape(h->Lx, h->Ly);
 }
 
+// Waves per column tile of the two-step pass when not tuned: rows up to 4096
+// sites wide run whole (one workgroup per strip); wider ones as tiles of at
+// most 4 waves, four workgroups per CU (8192^2: 9 tiles, 119 against 143 us
+// per step with the fewest tiles, 3 of 11 waves; 6144^2, 12288 x 4096 and
+// 16384 x 2048 gain 14-18% the same way), where such a tiling exists.
+static int step2_tile_waves(int Lx) {
+    Step2Tiles t;
+    return Lx > 16 * kWaveSites && step2_tiles(Lx, &t, 4) ? 4 : 16;
+}
+static int step2_tile_waves(const xyl_lattice* h) {
+    return h->step2_tw_tuned ? h->step2_tw_tuned : step2_tile_waves(h->Lx);
+}
+
 // Rows per strip of the two-step kernel.  A workgroup spans the row (Lx / 256
 // waves of up to 128 VGPRs, 32 Lx bytes of LDS), so a CU holds
 // per_cu = min(16 / waves, 160 KiB / LDS) of them.  The strip count aims at
@@ -429,14 +449,21 @@ static bool step2_eligible(const xyl_lattice* h) {
 // rows of the first step), 2 to 16 rows.  Measured best over 512^2 .. 4096^2,
 // 4096 x 1024, 1024 x 4096 and 256 x 8192 (strip counts off a multiple of the
 // CU count leave a partial last round of workgroups).
-static int step2_rows(int Lx, int Ly, int cus) {
+static int step2_rows(int Lx, int Ly, int cus, int tile_waves) {
     Step2Tiles t;
-    if (step2_tiles(Lx, &t)) {
-        // column tiles (one workgroup of up to 11 waves per CU at a time): the
-        // workgroup count is large, so the last round of workgroups matters.
-        // Score = rows / (rows + 1) (the halo rows' share of the work) times
-        // the fraction of the last round that is filled; strips of up to 32
-        // rows (8192^2: 146 against 150 us per step with 16).
+    if (step2_tiles(Lx, &t, tile_waves) || step2_tiles(Lx, &t)) {
+        // column tiles.  Several workgroups per CU (tiles of at most 8 waves:
+        // as many as 16 waves of 128 VGPRs and the 160 KiB of LDS allow):
+        // 16-row strips, measured best at 8192^2, 6144^2 and 16384 x 2048
+        // with 2- to 4-wave tiles (8-row strips 6-7% slower, 32-row 0-10%).
+        const int W = t.w + 2 * kLaneSites;
+        const int waves = (W + kWaveSites - 1) / kWaveSites;
+        const int per_cu =
+            waves > 8 ? 1 : std::max(1, std::min(16 / waves, (160 * 1024) / (int)(sizeof(float) * 2 * kStep2Slots * W)));
+        if (per_cu >= 2) return 16;
+        // One workgroup per CU: the last round of workgroups matters.  Score =
+        // rows / (rows + 1) (the halo rows' share of the work) times the
+        // fraction of the last round that is filled; strips of up to 32 rows.
         int best = 32;
         double best_score = -1.0;
         for (int rows = 32; rows >= 2; rows /= 2) {
@@ -456,7 +483,7 @@ static int step2_rows(int Lx, int Ly, int cus) {
     return std::max(2, std::min(16, Ly / strips));
 }
 static int step2_rows(const xyl_lattice* h) {
-    return h->step2_rows_tuned ? h->step2_rows_tuned : step2_rows(h->Lx, h->Ly, h->cus);
+    return h->step2_rows_tuned ? h->step2_rows_tuned : step2_rows(h->Lx, h->Ly, h->cus, step2_tile_waves(h));
 }
 
 // Launches for 4m steps from the current step: pairs of two-step passes,
@@ -469,10 +496,10 @@ static void step2_launches(xyl_lattice* h, const Lat<float>& v, uint64_t nsteps,
     float* Bb = static_cast<float*>(h->th[parity ^ 1]);
     float* u = static_cast<float*>(h->u);
     float* u2 = reinterpret_cast<float*>(h->u2.p);
-    const int rows = step2_rows(h);
+    const int rows = step2_rows(h), tw = step2_tile_waves(h);
     for (uint64_t i = 0; i < nsteps; i += 4) {
-        launch_step2(v, A, u, Bb, u2, rows, kdev, j + i, s);
-        launch_step2(v, Bb, u2, A, u, rows, kdev, j + i + 2, s);
+        launch_step2(v, A, u, Bb, u2, rows, kdev, j + i, s, tw);
+        launch_step2(v, Bb, u2, A, u, rows, kdev, j + i + 2, s, tw);
     }
 }
 
@@ -767,8 +794,9 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
             }
             auto it2 = g_tuned2.find({Lx, Ly, dtype});
             if (it2 != g_tuned2.end()) {
-                h->fusion = it2->second.first;
-                h->step2_rows_tuned = it2->second.second;
+                h->fusion = it2->second.fusion;
+                h->step2_rows_tuned = it2->second.rows;
+                h->step2_tw_tuned = it2->second.tile_waves;
             }
         }
         *out = h.release();
@@ -1378,7 +1406,7 @@ int xyl_get_launch(xyl_lattice* h, int32_t* rows, int32_t* wpb) {
 // the best single-step shape and sets *fusion (1 or 2, whichever is faster
 // per step) and *rows2 (rows per strip of the best two-step pass, 0 if none).
 template <typename R>
-static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, Launch* mlaunch) {
+static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, int* tw2, Launch* mlaunch) {
     // time candidates on scratch copies so the lattice state is untouched;
     // each candidate runs as a captured graph of back-to-back steps, so the
     // host's launch overhead does not mask kernel time on small lattices
@@ -1475,6 +1503,7 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, Launch* mla
     // two steps per pass: the same timing over a multiple of 4 steps, per step
     *fusion = 1;
     *rows2 = 0;
+    *tw2 = 0;
     if constexpr (std::is_same<R, float>::value) {
         if (step2_lattice_shape(h->Lx, h->Ly) && kick_factored(h->p)) {
             const int reps4 = (reps + 3) / 4 * 4;
@@ -1483,14 +1512,14 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, Launch* mla
             float* u = v.u;
             float* u2 = reinterpret_cast<float*>(tmp.p + 3 * bytes);
             check_hip(hipMemcpyAsync(u2, v.u, bytes, hipMemcpyDeviceToDevice, h->stream), "D2D");
-            auto time_step2 = [&](int rows, int repeats) {
+            auto time_step2 = [&](int rows, int tw, int repeats) {
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ex = nullptr;
                 check_hip(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal),
                           "hipStreamBeginCapture");
                 for (int i = 0; i < reps4; i += 4) {
-                    launch_step2(v, A, u, B, u2, rows, kc.p, (uint64_t)i, h->cap_stream);
-                    launch_step2(v, B, u2, A, u, rows, kc.p, (uint64_t)i + 2, h->cap_stream);
+                    launch_step2(v, A, u, B, u2, rows, kc.p, (uint64_t)i, h->cap_stream, tw);
+                    launch_step2(v, B, u2, A, u, rows, kc.p, (uint64_t)i + 2, h->cap_stream, tw);
                 }
                 check_hip(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
                 hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -1510,21 +1539,46 @@ static Launch autotune_impl(xyl_lattice* h, int* fusion, int* rows2, Launch* mla
                 (void)hipGraphExecDestroy(ex);
                 return best_t / (float)reps4;
             };
-            std::vector<int> rows_c2 = {2, 4, 8, 16, step2_rows(h->Lx, h->Ly, h->cus)};
+            // the tile width first (whole rows or the fewest tiles, and
+            // narrower tiles; each at the rule's strip height for it), then
+            // the strip height at the best width
+            int tw = 16;
+            {
+                std::vector<std::pair<float, int>> st;
+                std::vector<std::pair<int, int>> seen;   // (tiles, width) of the candidates timed
+                for (int c : {16, 11, 8, 4, 3, 2}) {
+                    Step2Tiles t;
+                    if (!step2_tiles(h->Lx, &t, c)) {
+                        if (c != 16) continue;
+                        t.ntx = 1;             // whole rows
+                        t.w = h->Lx;
+                    }
+                    if (std::find(seen.begin(), seen.end(), std::make_pair(t.ntx, t.w)) != seen.end()) continue;
+                    seen.push_back({t.ntx, t.w});
+                    st.push_back({time_step2(step2_rows(h->Lx, h->Ly, h->cus, c), c, 2), c});
+                }
+                std::sort(st.begin(), st.end());
+                tw = st.front().second;
+            }
+            Step2Tiles t0;
+            const bool tiled = step2_tiles(h->Lx, &t0, tw);
+            std::vector<int> rows_c2 = {2, 4, 8, 16, step2_rows(h->Lx, h->Ly, h->cus, tw)};
+            if (tiled) rows_c2.push_back(32);
             std::sort(rows_c2.begin(), rows_c2.end());
             rows_c2.erase(std::unique(rows_c2.begin(), rows_c2.end()), rows_c2.end());
             std::vector<std::pair<float, int>> s2;
             for (int r : rows_c2)
-                if (r <= h->Ly) s2.push_back({time_step2(r, 1), r});
+                if (r <= h->Ly) s2.push_back({time_step2(r, tw, 1), r});
             std::sort(s2.begin(), s2.end());
             float best2 = 1e30f;
             for (size_t i = 0; i < std::min<size_t>(2, s2.size()); ++i) {
-                const float t = time_step2(s2[i].second, 3);
+                const float t = time_step2(s2[i].second, tw, 3);
                 if (t < best2) {
                     best2 = t;
                     *rows2 = s2[i].second;
                 }
             }
+            *tw2 = tw;
             if (best2 < best_ms / (float)reps) *fusion = 2;
         }
     }
@@ -1539,22 +1593,23 @@ int xyl_autotune(xyl_lattice* h) {
     return guarded([&] {
         require_init(h);
         DeviceGuard g(h->device);
-        int fusion = 1, rows2 = 0;
+        int fusion = 1, rows2 = 0, tw2 = 0;
         Launch lm;
-        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h, &fusion, &rows2, &lm)
-                                       : autotune_impl<float>(h, &fusion, &rows2, &lm);
+        Launch l = h->dtype == XYL_F64 ? autotune_impl<double>(h, &fusion, &rows2, &tw2, &lm)
+                                       : autotune_impl<float>(h, &fusion, &rows2, &tw2, &lm);
         h->launch = l;
         h->mlaunch = lm;
         h->mlaunch_tuned = true;
         if (h->dtype == XYL_F32) {
             h->fusion = fusion;
             h->step2_rows_tuned = rows2;
+            h->step2_tw_tuned = tw2;
         }
         h->touch();
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[{h->Lx, h->Ly, h->dtype}] = l;
         g_tunedm[{h->Lx, h->Ly, h->dtype}] = lm;
-        if (h->dtype == XYL_F32) g_tuned2[{h->Lx, h->Ly, h->dtype}] = {fusion, rows2};
+        if (h->dtype == XYL_F32) g_tuned2[{h->Lx, h->Ly, h->dtype}] = {fusion, rows2, tw2};
     });
 }
 
@@ -1571,6 +1626,40 @@ int xyl_get_fusion(const xyl_lattice* h, int32_t* steps_per_pass, int32_t* rows)
         require(h != nullptr, XYL_EINVAL, "NULL handle");
         if (steps_per_pass) *steps_per_pass = h->fusion;
         if (rows) *rows = step2_eligible(h) ? step2_rows(h) : 0;
+    });
+}
+
+int xyl_set_step2_shape(xyl_lattice* h, int32_t rows, int32_t tile_waves) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(rows == 0 || (rows >= 2 && rows <= 64), XYL_EINVAL, "rows per strip must be 0 or in [2, 64]");
+        require(tile_waves == 0 || (tile_waves >= 2 && tile_waves <= 16), XYL_EINVAL,
+                "waves per tile must be 0 or in [2, 16]");
+        if (rows) h->step2_rows_tuned = rows;
+        if (tile_waves) h->step2_tw_tuned = tile_waves;
+        h->touch();
+    });
+}
+
+int xyl_get_step2_shape(const xyl_lattice* h, int32_t* rows, int32_t* tile_waves, int32_t* tiles) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        const bool on = step2_eligible(h);
+        int tw = 0, ntx = 0;
+        if (on) {
+            Step2Tiles t;
+            const int want = step2_tile_waves(h);
+            if (step2_tiles(h->Lx, &t, want) || step2_tiles(h->Lx, &t)) {
+                tw = want;
+                ntx = t.ntx;
+            } else {
+                tw = (h->Lx + kWaveSites - 1) / kWaveSites;   // whole rows
+                ntx = 1;
+            }
+        }
+        if (rows) *rows = on ? step2_rows(h) : 0;
+        if (tile_waves) *tile_waves = tw;
+        if (tiles) *tiles = ntx;
     });
 }
 
@@ -2482,6 +2571,10 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
 // dL/dw^{k0}: host float64 arrays (dth0, dom0) or, with dev_out, caller
 // device buffers of precision out_f64 (written on the lattice's stream, times
 // `scale`).
+// Rows per strip of the two-step reverse pass (1, 2 or 4): 2 (512^2: 6.9
+// against 7.2 us per step with 1 and 8.6 with 4).
+static int adjoint2_rows(const xyl_lattice* h) { return h->adj2_rows ? h->adj2_rows : 2; }
+
 template <typename R>
 static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void* dom0, bool dev_out, int out_f64,
                                   double scale) {
@@ -2497,7 +2590,10 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
     Launch l = h->launch;
     l.wpb = std::min(l.wpb, 4);
     Lat<R> v = h->view<R>();
-    const int ntasks = adjoint_tasks<R>(v, l.rows);
+    // two reverse steps per pass where the rows fit one workgroup's LDS rings
+    const bool fuse = h->adj_fusion == 2 && adjoint2_fits<R>(v);
+    const int rows2 = adjoint2_rows(h);
+    const int ntasks = adjoint_tasks<R>(v, l.rows, fuse ? rows2 : 0);
     a->gacc.reserve((size_t)ntasks * 4);
     check_hip(hipMemsetAsync(a->gacc.p, 0, sizeof(double) * ntasks * 4, h->stream), "hipMemsetAsync");
     a->lam.reserve(4 * bytes);
@@ -2529,9 +2625,55 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
         w.u_out = slot_u(b, j + 1);
         launch_step<R>(w, kStore, h->launch, kdev, kj, st);
     };
+    // two recompute steps per pass (storing the state after each) where the
+    // forward's two-step pass takes the lattice whole-row: the same states
+    bool rec2 = false;
+    if constexpr (std::is_same<R, float>::value)
+        rec2 = h->adj_fusion == 2 && v.fact == 1 && v.model == kModelXY && step2_shape(h->Lx, h->Ly);
+    const int rows_rec2 = rec2 ? step2_rows(h) : 0;
+    auto recompute_run = [&](int b, uint64_t len, const uint64_t* kdev, uint64_t kbase, hipStream_t st) {
+        uint64_t j = 0;
+        if constexpr (std::is_same<R, float>::value) {
+            if (rec2)
+                for (; j + 2 <= len; j += 2)
+                    launch_step2_mid(v, slot_th(b, j), slot_u(b, j), slot_th(b, j + 1), slot_u(b, j + 1),
+                                     slot_th(b, j + 2), slot_u(b, j + 2), rows_rec2, kdev, kbase + j, st);
+        }
+        for (; j < len; ++j) recompute_node(b, j, kdev, kbase + j, st);
+    };
     auto reverse_node = [&](int b, uint64_t j, int parity, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
         launch_adjoint_step<R>(v, slot_th(b, j), slot_u(b, j), lt[parity], lu[parity], lt[parity ^ 1],
                                lu[parity ^ 1], a->cm.p, k0, a->gacc.p, kdev, kj, l, st);
+    };
+    // reverse steps j+1 and j of the segment in one pass
+    auto reverse2_node = [&](int b, uint64_t j, int parity, const uint64_t* kdev, uint64_t kj, hipStream_t st) {
+        launch_adjoint_step2<R>(v, slot_th(b, j), slot_u(b, j), slot_th(b, j + 1), slot_u(b, j + 1), lt[parity],
+                                lu[parity], lt[parity ^ 1], lu[parity ^ 1], a->cm.p, k0, a->gacc.p, kdev, kj, rows2,
+                                st);
+    };
+    // the reverse steps len-1 .. 0 of a segment from adjoint buffer `parity`
+    // (an odd one first, then pairs); returns the buffer they end in
+    auto reverse_segment = [&](int b, uint64_t len, int parity, const uint64_t* kdev, uint64_t kbase,
+                               hipStream_t st) {
+        uint64_t j = len;
+        if (fuse) {
+            if (j % 2 == 1) {
+                --j;
+                reverse_node(b, j, parity, kdev, kbase + j, st);
+                parity ^= 1;
+            }
+            while (j >= 2) {
+                j -= 2;
+                reverse2_node(b, j, parity, kdev, kbase + j, st);
+                parity ^= 1;
+            }
+        } else {
+            while (j-- > 0) {
+                reverse_node(b, j, parity, kdev, kbase + j, st);
+                parity ^= 1;
+            }
+        }
+        return parity;
     };
     // Full segments of even length replay captured graphs whose step indices
     // come from device counters set to the segment's first step: one graph
@@ -2542,7 +2684,8 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
     // the buffers, the step base and the launch shapes)
     std::vector<uint64_t> key = {K, (uint64_t)(uintptr_t)a->seg.p, (uint64_t)(uintptr_t)a->lam.p,
                                  (uint64_t)(uintptr_t)a->cm.p, (uint64_t)(uintptr_t)a->gacc.p,
-                                 (uint64_t)(uintptr_t)a->kseg.p, (uint64_t)l.rows, (uint64_t)l.wpb,
+                                 (uint64_t)(uintptr_t)a->kseg.p, (uint64_t)l.rows, (uint64_t)l.wpb, (uint64_t)rows2,
+                                 (uint64_t)fuse, (uint64_t)rec2, (uint64_t)rows_rec2,
                                  (uint64_t)h->launch.rows, (uint64_t)h->launch.wpb, (uint64_t)ntasks, k0};
     {
         Lat<R> vz{};
@@ -2584,12 +2727,12 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
         if (use_graph && len == K) {
             if (!a->rec_graph[b])
                 a->rec_graph[b] = capture([&] {
-                    for (uint64_t j = 0; j < K; ++j) recompute_node(b, j, a->kseg.p + 1, j, h->cap_stream);
+                    recompute_run(b, K, a->kseg.p + 1, 0, h->cap_stream);
                 });
             launch_set_counter(a->kseg.p + 1, ks, a->side);
             check_hip(hipGraphLaunch(a->rec_graph[b], a->side), "hipGraphLaunch");
         } else {
-            for (uint64_t j = 0; j < len; ++j) recompute_node(b, j, nullptr, ks + j, a->side);
+            recompute_run(b, len, nullptr, ks, a->side);
         }
         check_hip(hipEventRecord(a->ev_rec[b], a->side), "hipEventRecord");
     };
@@ -2608,22 +2751,16 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
         const uint64_t ks = k0 + s * K;
         const uint64_t len = std::min<uint64_t>(K, k0 + N - ks);
         if (use_graph && len == K) {
+            int end = li;
             if (!a->rev_graph[b][li])
-                a->rev_graph[b][li] = capture([&] {
-                    int p = li;
-                    for (uint64_t j = K; j-- > 0;) {
-                        reverse_node(b, j, p, a->kseg.p, j, h->cap_stream);
-                        p ^= 1;
-                    }
-                });
+                a->rev_graph[b][li] = capture([&] { end = reverse_segment(b, K, li, a->kseg.p, 0, h->cap_stream); });
+            else
+                end = fuse ? li ^ (int)((K / 2) & 1) : li;   // K even
             launch_set_counter(a->kseg.p, ks, h->stream);
             check_hip(hipGraphLaunch(a->rev_graph[b][li], h->stream), "hipGraphLaunch");
-            // K even: the adjoint state ends in the buffer it started from
+            li = end;
         } else {
-            for (uint64_t j = len; j-- > 0;) {
-                reverse_node(b, j, li, nullptr, ks + j, h->stream);
-                li ^= 1;
-            }
+            li = reverse_segment(b, len, li, nullptr, ks, h->stream);
         }
         check_hip(hipEventRecord(a->ev_rev[b], h->stream), "hipEventRecord");
     }
@@ -2689,6 +2826,16 @@ static void require_adjoint_run(xyl_lattice* h, uint64_t run) {
     require(h->k == a->k0 + a->N && h->version == a->version, XYL_ESTATE,
             "lattice was stepped, reset or reconfigured after xyl_adjoint_forward");
     require(h->p.model == kModelXY, XYL_EUNSUPPORTED, "the adjoint supports the XY model only");
+}
+
+int xyl_set_adjoint_fusion(xyl_lattice* h, int32_t steps_per_pass, int32_t rows) {
+    return guarded([&] {
+        require(h != nullptr, XYL_EINVAL, "NULL handle");
+        require(steps_per_pass == 1 || steps_per_pass == 2, XYL_EINVAL, "steps_per_pass must be 1 or 2");
+        require(rows == 0 || rows == 1 || rows == 2 || rows == 4, XYL_EINVAL, "rows per strip must be 0, 1, 2 or 4");
+        h->adj_fusion = steps_per_pass;
+        if (rows) h->adj2_rows = rows;
+    });
 }
 
 int xyl_adjoint_backward(xyl_lattice* h, uint64_t run, double* grad, double* dtheta0, double* domega0) {

@@ -331,6 +331,8 @@ struct Step2Buffers {
     const float* u_in;
     float* th_out;
     float* u_out;
+    float* th_mid = nullptr;   // with MID: the state after the first step
+    float* u_mid = nullptr;
 };
 
 template <typename R>
@@ -347,8 +349,6 @@ struct BRow {          // step-(k+1) angles and velocities of one stage-A row
     R t[4], u[4];
 };
 
-constexpr int kStep2Slots = 4;
-
 // One strip of a two-step pass: rows [y0, y1) of the lattice v, swept in
 // direction d (+1 top-down, -1 bottom-up), from step k.  rot is the LDS ring
 // (4 slots x 2 x W floats).
@@ -364,7 +364,9 @@ constexpr int kStep2Slots = 4;
 //    stores all but the two outer quads, whose second step the neighbouring
 //    tiles compute.  Every stored site so sees the same inputs as in single
 //    steps.
-template <int M, bool PARTIAL, bool TILE = false>
+//  * With MID (whole rows), stage A also stores the strip's own rows of the
+//    state after the first step (th_mid, u_mid), as a single step would.
+template <int M, bool PARTIAL, bool TILE = false, bool MID = false>
 __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buffers& B, int y0, int y1, int d,
                                             uint64_t k, float* rot, int xs = 0, int W = 0) {
     using R = float;
@@ -440,6 +442,13 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
             float* rs = slot(it);
             store4(rs + x, s1);
             store4(rs + Wd + x, c1);
+        }
+        if constexpr (MID) {
+            // the first and last iterations are the strip's halo rows
+            if (valid && it >= 1 && it <= (y1 - y0)) {
+                store4(at_byte(row_start(B.th_mid, y, Lx), gxb), out.t);
+                store4(at_byte(row_start(B.u_mid, y, Lx), gxb), out.u);
+            }
         }
     };
     // stage B on row y (stage-A values C in registers; the rotors of row y
@@ -540,7 +549,7 @@ __device__ __forceinline__ void step2_strip(const Lat<float>& v, const Step2Buff
 
 // The two-step pass of one lattice: strip b = rows [b rows, (b+1) rows), even
 // strips top-down, odd strips bottom-up.
-template <int M, bool PARTIAL>
+template <int M, bool PARTIAL, bool MID = false>
 __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, const uint64_t* kdev, uint64_t j0,
                                                 int rows) {
     extern __shared__ float rot[];   // [slot][s | c][Lx]
@@ -548,14 +557,14 @@ __global__ __launch_bounds__(1024) void k_step2(Lat<float> v, Step2Buffers B, co
     const int y0 = strip * rows;
     const int y1 = min(y0 + rows, v.Ly);
     const uint64_t k = v.k_base + j0 + (kdev ? *kdev : 0);
-    step2_strip<M, PARTIAL>(v, B, y0, y1, (strip & 1) ? -1 : 1, k, rot);
+    step2_strip<M, PARTIAL, false, MID>(v, B, y0, y1, (strip & 1) ? -1 : 1, k, rot);
 }
 
 // The two-step pass of a lattice wider than 4096: each strip is split into ntx
 // column tiles of w columns (the last takes the rest); workgroup b covers tile
 // b % ntx of strip b / ntx and one quad on each side.
 template <int M, int MAXW>
-__global__ __launch_bounds__(MAXW * kWave) void k_step2_tiled(Lat<float> v, Step2Buffers B, const uint64_t* kdev,
+__global__ __launch_bounds__(MAXW * kWave, MAXW <= 8 ? 4 : 1) void k_step2_tiled(Lat<float> v, Step2Buffers B, const uint64_t* kdev,
                                                              uint64_t j0, int rows, int ntx, int w) {
     extern __shared__ float rot[];   // [slot][s | c][w + 8]
     const int b = xcd_contiguous_block(blockIdx.x, gridDim.x);
@@ -608,41 +617,57 @@ static void allow_step2_lds(F* kernel) {
     allowed.insert({dev, reinterpret_cast<const void*>(kernel)});
 }
 
-template <int M, bool PARTIAL>
+template <int M, bool PARTIAL, bool MID = false>
 static void dispatch_step2(const Lat<float>& v, const Step2Buffers& b, int rows, const uint64_t* kdev, uint64_t j,
                            hipStream_t s) {
-    allow_step2_lds(k_step2<M, PARTIAL>);
+    allow_step2_lds(k_step2<M, PARTIAL, MID>);
     const int nstrips = (v.Ly + rows - 1) / rows;
     const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)v.Lx;
     const int waves = (v.Lx + kWaveSites - 1) / kWaveSites;
-    k_step2<M, PARTIAL><<<nstrips, waves * kWave, lds, s>>>(v, b, kdev, j, rows);
+    k_step2<M, PARTIAL, MID><<<nstrips, waves * kWave, lds, s>>>(v, b, kdev, j, rows);
     check_hip(hipGetLastError(), "two-step kernel launch");
+}
+
+void launch_step2_mid(const Lat<float>& v, const float* th_in, const float* u_in, float* th_mid, float* u_mid,
+                      float* th_out, float* u_out, int rows, const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    if (v.Ly < 4 || rows < 1 || !step2_width_ok(v.Lx) || v.model != kModelXY)
+        throw Error(-5, "two-step pass with the middle state: XY lattices of whole-row widths only");
+    Step2Buffers b{th_in, u_in, th_out, u_out};
+    b.th_mid = th_mid;
+    b.u_mid = u_mid;
+    if (v.Lx % kWaveSites != 0) dispatch_step2<kModelXY, true, true>(v, b, rows, kdev, j, s);
+    else dispatch_step2<kModelXY, false, true>(v, b, rows, kdev, j, s);
+}
+
+template <int M, int MAXW>
+static void launch_step2_tiled(const Lat<float>& v, const Step2Buffers& b, int nwg, int waves, size_t lds, int rows,
+                               const Step2Tiles& t, const uint64_t* kdev, uint64_t j, hipStream_t s) {
+    allow_step2_lds(k_step2_tiled<M, MAXW>);
+    k_step2_tiled<M, MAXW><<<nwg, waves * kWave, lds, s>>>(v, b, kdev, j, rows, t.ntx, t.w);
 }
 
 template <int M>
 static void dispatch_step2_tiled(const Lat<float>& v, const Step2Buffers& b, int rows, const Step2Tiles& t,
                                  const uint64_t* kdev, uint64_t j, hipStream_t s) {
-    const int nstrips = (v.Ly + rows - 1) / rows;
+    const int nwg = ((v.Ly + rows - 1) / rows) * t.ntx;
     const int W = t.w + 2 * kLaneSites;
     const size_t lds = sizeof(float) * 2 * (size_t)kStep2Slots * (size_t)W;
     const int waves = (W + kWaveSites - 1) / kWaveSites;
-    if (waves <= kStep2SmallTileWaves) {
-        allow_step2_lds(k_step2_tiled<M, kStep2SmallTileWaves>);
-        k_step2_tiled<M, kStep2SmallTileWaves>
-            <<<nstrips * t.ntx, waves * kWave, lds, s>>>(v, b, kdev, j, rows, t.ntx, t.w);
-    } else {
-        allow_step2_lds(k_step2_tiled<M, 16>);
-        k_step2_tiled<M, 16><<<nstrips * t.ntx, waves * kWave, lds, s>>>(v, b, kdev, j, rows, t.ntx, t.w);
+    switch (step2_tile_bound(waves)) {
+        case 4: launch_step2_tiled<M, 4>(v, b, nwg, waves, lds, rows, t, kdev, j, s); break;
+        case 8: launch_step2_tiled<M, 8>(v, b, nwg, waves, lds, rows, t, kdev, j, s); break;
+        case 11: launch_step2_tiled<M, 11>(v, b, nwg, waves, lds, rows, t, kdev, j, s); break;
+        default: launch_step2_tiled<M, 16>(v, b, nwg, waves, lds, rows, t, kdev, j, s); break;
     }
     check_hip(hipGetLastError(), "tiled two-step kernel launch");
 }
 
 void launch_step2(const Lat<float>& v, const float* th_in, const float* u_in, float* th_out, float* u_out, int rows,
-                  const uint64_t* kdev, uint64_t j, hipStream_t s) {
+                  const uint64_t* kdev, uint64_t j, hipStream_t s, int tile_waves) {
     if (v.Ly < 4 || rows < 1) throw Error(-5, "two-step kernel needs Ly >= 4");
     const Step2Buffers b{th_in, u_in, th_out, u_out};
     Step2Tiles t;
-    if (step2_tiles(v.Lx, &t)) {
+    if ((tile_waves > 0 && step2_tiles(v.Lx, &t, tile_waves)) || step2_tiles(v.Lx, &t)) {
         if (v.model == kModelSI) dispatch_step2_tiled<kModelSI>(v, b, rows, t, kdev, j, s);
         else dispatch_step2_tiled<kModelXY>(v, b, rows, t, kdev, j, s);
         return;

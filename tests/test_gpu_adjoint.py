@@ -268,3 +268,36 @@ def test_set_state_device(xyl, dtype):
         np.testing.assert_array_equal(x, y)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("Lx,Ly,dtype,K,nsteps,rows", [
+    (512, 64, "f32", 100, 400, 0),        # the rule's strips, graph-captured segments
+    (512, 42, "f32", 100, 400, 4),        # ragged strips
+    (200, 9, "f32", 7, 90, 1),            # odd segments (one single step, then pairs), a partial wave
+    (1024, 13, "f32", 20, 60, 2),         # the widest row the pass takes, a ragged strip
+    (64, 4, "f64", 10, 50, 2),            # FP64, the smallest height
+    (640, 6, "f64", 9, 45, 4),            # FP64 at its widest
+    (2048, 8, "f32", 10, 40, 0),          # too wide: one reverse step per pass either way
+])
+def test_two_reverse_steps_per_pass_equal_single_steps(xyl, Lx, Ly, dtype, K, nsteps, rows):
+    """The two-step reverse pass against one reverse step per pass: dL/dth0
+    and dL/dw0 bitwise equal, the parameter gradients equal up to the order
+    of their sums (FP32 sites summed in FP32 four at a time by the single
+    step, one at a time by the pass)."""
+    say("adjoint fusion", Lx, Ly, dtype, K, nsteps, rows)
+    spec = dict(Jx=1.0, Jy=-0.2, h=0.4, gamma=0.8, dt=0.02, schedule=[(0, 1.1), (nsteps, 0.4)], seed=5, replica=3)
+    out = []
+    for sp in (1, 2):
+        lat = xyl.Lattice(Lx, Ly, dtype=dtype, **spec)
+        lat.set_adjoint_fusion(sp, rows)
+        lat.init_random()
+        lat.step(6)
+        L = lat.adjoint_forward(nsteps, K, max(1, nsteps // 3))
+        g, dth, dom = lat.adjoint_backward()
+        out.append((L, g, dth, dom))
+        lat.close()
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    np.testing.assert_array_equal(out[0][3], out[1][3])
+    np.testing.assert_allclose(out[1][1], out[0][1], rtol=1e-5 if dtype == "f32" else 1e-12,
+                               atol=1e-9 * np.abs(out[0][1]).max())

@@ -18,11 +18,13 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None):
+def run(xyl, spec, fusion, nsteps_list, graph_steps=32, state=None, shape=None):
     lat = xyl.Lattice(spec.Lx, spec.Ly, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
                       **spec.params())
     lat.set_fusion(fusion)
     lat.set_graph_steps(graph_steps)
+    if shape is not None:
+        lat.set_step2_shape(*shape)
     if state is None:
         lat.init_random()
     else:
@@ -66,6 +68,43 @@ def test_two_steps_per_pass_equal_single_steps(xyl, Lx, Ly, model, graphs, steps
     a = run(xyl, spec, 1, steps, graphs)
     b = run(xyl, spec, 2, steps, graphs)
     assert a[2] == b[2] == sum(steps)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("Lx,Ly,model,tile_waves,rows,tiles", [
+    (8192, 12, "xy", 16, 4, 3),            # the fewest tiles: 3 of 11 waves
+    (8192, 12, "xy", 8, 4, 5),             # 5 tiles of 7 waves (the last wave 8 lanes)
+    (8192, 12, "xy", 6, 2, 6),             # 6 tiles of 6 waves
+    (8192, 12, "xy", 4, 8, 9),             # 9 tiles of 4 waves
+    (8200, 9, "si", 4, 4, 9),              # Si model, the last tile narrower
+    (6144, 7, "xy", 11, 2, 3),             # 3 tiles of 9 waves, the ninth two lanes
+    (4100, 10, "si", 8, 4, 3),             # 3 tiles of 6 waves, Si model
+    (8192, 40, "xy", 3, 32, 11),           # 11 tiles of 3 waves, a ragged second strip
+    (8192, 12, "xy", 2, 4, 17),            # 17 tiles of 2 waves
+    (4096, 12, "xy", 16, 4, 1),            # whole rows (one workgroup per strip)
+    (4096, 10, "xy", 4, 4, 5),             # a row that fits one workgroup, split: 5 tiles of 4 waves
+    (4096, 9, "si", 2, 2, 9),              # 9 tiles of 2 waves, Si model
+    (2048, 8, "xy", 3, 8, 3),              # 3 tiles of 3 waves
+    (1024, 6, "xy", 2, 2, 3),              # 3 tiles of 2 waves, the smallest height
+])
+def test_column_tile_widths_equal_single_steps(xyl, Lx, Ly, model, tile_waves, rows, tiles):
+    """Every tile width the shape setting (and the autotuner) may pick: the
+    two-step pass over narrower tiles, in the instances bounded to 4 and 8
+    waves, equals single steps bit for bit."""
+    say("tile widths", Lx, Ly, model, tile_waves, rows)
+    if model == "si":
+        spec = workloads.si_lattice(Lx, Ly, seed=5, replica=1)
+    else:
+        spec = workloads.LatticeSpec(Lx, Ly, schedule=((0, 0.8), (40, 0.3)), seed=5, replica=1)
+    lat = xyl.Lattice(Lx, Ly, dtype="f32", schedule=spec.schedule, seed=spec.seed, replica=spec.replica,
+                      **spec.params())
+    lat.set_fusion(2)
+    lat.set_step2_shape(rows, tile_waves)
+    assert lat.step2_shape() == (rows, tile_waves, tiles)
+    lat.close()
+    a = run(xyl, spec, 1, [22], 32)
+    b = run(xyl, spec, 2, [22], 32, shape=(rows, tile_waves))
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
 
