@@ -440,10 +440,13 @@ int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, doub
                                 void* domega0, int32_t dtype);
 /* Reverse steps per pass of xyl_adjoint_backward (App. A.1's step, run
  * backwards): 2 (the default) takes two reverse steps per pass over the state
- * where a row fits one workgroup (Lx at most 1024 sites in FP32, 640 in FP64,
- * and Ly >= 4), one site per lane; 1 keeps one reverse step per pass.
- * rows: rows per strip of the two-step pass (1, 2 or 4; 0 keeps the current
- * value, initially 2).  dL/dth and dL/dw are bitwise
+ * where a strip of rows fits one workgroup (one site per lane, Lx at most
+ * 1024, Ly >= 4, and 16 (2 rows + 6) Lx bytes of FP32 state, twice that in
+ * FP64, within a CU's 160 KiB of LDS), and recomputes the checkpointed
+ * segments two steps per pass too where the forward's two-step pass takes
+ * the lattice; 1 keeps one step per pass for both.  rows: rows per strip of
+ * the two-step reverse pass (1, 2 or 4; 0 keeps the current value, initially
+ * 2, or 1 where 2 does not fit).  dL/dth and dL/dw are bitwise
  * the same either way; the parameter gradients are sums taken in another
  * order.  EINVAL outside the ranges. */
 int xyl_set_adjoint_fusion(xyl_lattice* h, int32_t steps_per_pass, int32_t rows);

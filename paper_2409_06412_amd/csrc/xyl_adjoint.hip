@@ -256,19 +256,19 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<R> A, const uint64_t* k
 }
 
 // Two reverse steps per pass, k + 1 then k, for rows up to kAdj2MaxLx sites:
-// one site per lane, a workgroup per strip of rows across the whole width.
-// Stage A (reverse step k+1: th^{k+1}, u^{k+1}, lt^{k+2}, lu^{k+2}) runs two
-// rows ahead of stage B (reverse step k: th^k, u^k and stage A's lt^{k+1},
-// lu^{k+1}, which never leave the workgroup).  Each stage takes its
-// neighbours from an LDS ring of four rows holding (sin, cos, lt', lu') per
-// site; a row enters ring A two iterations before stage A uses it and ring B
-// (from stage A) two before stage B does, so one barrier per iteration
-// separates every write from its reads, and four slots keep the row being
-// written apart from the three being read.  Stage A also covers one halo row
-// on each side of the strip, which the neighbouring strips compute with the
-// same arithmetic.  Every site takes the arithmetic of adj_site with the
-// same inputs as in two single reverse steps, so lt^k and lu^k are bitwise
-// those; the parameter adjoints are summed in another order.
+// one site per lane, a workgroup per strip of ROWS rows across the whole
+// width, in three phases separated by two barriers.
+//  1. The strip's rows and two on each side enter ring A: (sin, cos) of
+//     th^{k+1} and the adjoint (lt, lu) at k+2, per site.
+//  2. Stage A, reverse step k+1, on the strip's rows and one on each side
+//     (which the neighbouring strips compute with the same arithmetic), its
+//     neighbours from ring A; its results (lt, lu at k+1) enter ring B with
+//     (sin, cos) of th^k.  They never leave the workgroup.
+//  3. Stage B, reverse step k, on the strip's rows from ring B, to memory.
+// Every input is loaded up front, so the pass waits on one memory latency.
+// Every site takes the arithmetic of adj_site with the same inputs as in two
+// single reverse steps, so lt^k and lu^k are bitwise those; the parameter
+// adjoints are summed in another order.
 template <typename R>
 struct Adj2Args {
     AdjArgs<R> a;       // th, u: th^k, u^k; lt_in, lu_in: step k+2; lt_out, lu_out: step k
@@ -284,48 +284,47 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
     const Lat<R>& v = A.v;
     const int Lx = v.Lx, Ly = v.Ly;
     extern __shared__ unsigned char adj2_lds[];
-    R* ringA = reinterpret_cast<R*>(adj2_lds);             // [slot][s, c, lt, lu][Lx]
-    R* ringB = ringA + (size_t)kStep2Slots * 4 * Lx;
-    auto slot = [&](R* ring, int r) { return ring + (size_t)(r & (kStep2Slots - 1)) * 4 * Lx; };
+    // ring A: rows y0-2 .. y0+ROWS+1, ring B: rows y0-1 .. y0+ROWS; per row
+    // [s, c, lt, lu][Lx]
+    R* ringA = reinterpret_cast<R*>(adj2_lds);
+    R* ringB = ringA + (size_t)(ROWS + 4) * 4 * Lx;
     const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int y0 = strip * ROWS;
     const int y1 = min(y0 + ROWS, Ly);
+    auto rowA = [&](int r) { return ringA + (size_t)(r - (y0 - 2)) * 4 * Lx; };
+    auto rowB = [&](int r) { return ringB + (size_t)(r - (y0 - 1)) * 4 * Lx; };
     const int x = threadIdx.x;
     const bool act = x < Lx;
     const int xa = act ? x : 0;
     const int xm = xa == 0 ? Lx - 1 : xa - 1, xp = xa + 1 == Lx ? 0 : xa + 1;
     auto wrap = [&](int r) { return r < 0 ? r + Ly : (r >= Ly ? r - Ly : r); };
     auto at = [&](int r) { return (size_t)wrap(r) * (size_t)Lx + (size_t)xa; };
-    // Every input of the strip is loaded up front, in the order of first use
-    // (the strip's loads then wait on one memory latency, not one per row):
-    // ring A rows y0-2 .. y0+ROWS+1 (th^{k+1}, lt'', lu''), stage A rows
-    // y0-1 .. y0+ROWS (u^{k+1}, th^k), stage B rows y0 .. y0+ROWS-1 (u^k).
-    // Rows past a ragged last strip's end are loaded (wrapped) and not used.
-    constexpr int NT = ROWS + 6;
+    // the strip's inputs, in the order of the phases (rows past a ragged last
+    // strip's end are loaded, wrapped, and not used)
     R th1[ROWS + 4], lt2[ROWS + 4], lu2[ROWS + 4], u1[ROWS + 2], th0[ROWS + 2], u0[ROWS];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        if (i < ROWS + 4) {
-            th1[i] = A2.th1[at(y0 - 2 + i)];
-            lt2[i] = A.lt_in[at(y0 - 2 + i)];
-            lu2[i] = A.lu_in[at(y0 - 2 + i)];
-        }
-        if (i >= 3 && i - 3 < ROWS + 2) {
-            u1[i - 3] = A2.u1[at(y0 - 1 + i - 3)];
-            th0[i - 3] = A.th[at(y0 - 1 + i - 3)];
-        }
-        if (i >= 5 && i - 5 < ROWS) u0[i - 5] = A.u[at(y0 + i - 5)];
+    for (int i = 0; i < ROWS + 4; ++i) {
+        th1[i] = A2.th1[at(y0 - 2 + i)];
+        lt2[i] = A.lt_in[at(y0 - 2 + i)];
+        lu2[i] = A.lu_in[at(y0 - 2 + i)];
     }
+#pragma unroll
+    for (int i = 0; i < ROWS + 2; ++i) {
+        u1[i] = A2.u1[at(y0 - 1 + i)];
+        th0[i] = A.th[at(y0 - 1 + i)];
+    }
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) u0[i] = A.u[at(y0 + i)];
     const uint64_t k = koff + (kdev ? *kdev : 0);
     const AdjStep<R> KA = adj_step_coef(A, k + 1);
     const AdjStep<R> KB = adj_step_coef(A, k);
     auto lf_of = [&](const R* sl, int i, R kap) { return kap * Prec<R>::fma(v.dt, sl[2 * Lx + i], sl[3 * Lx + i]); };
-    // the stage's reverse step at row r from its ring (rows r-1, r, r+1 in
-    // slots r-1, r, r+1) with coefficients K, returning lt, lu
-    auto stage = [&](R* ring, const AdjStep<R>& K, int r, R u, uint64_t ks, R& lto, R& luo, double g[4]) {
-        const R* C = slot(ring, r);
-        const R* Pm = slot(ring, r - 1);
-        const R* Np = slot(ring, r + 1);
+    // a stage's reverse step at row r, its rows r-1, r, r+1 at C - stride,
+    // C, C + stride in its ring, with coefficients K; returns lt, lu
+    auto stage = [&](const R* C, size_t stride, const AdjStep<R>& K, int r, R u, uint64_t ks, R& lto, R& luo,
+                     double g[4]) {
+        const R* Pm = C - stride;
+        const R* Np = C + stride;
         const int y = wrap(r);
         R n4[4];
         noise4<R>((uint32_t)y * (uint32_t)(Lx >> 2) + (uint32_t)(xa >> 2), v.replica, ks, v.seed_lo, v.seed_hi, n4);
@@ -342,15 +341,13 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             g[3] += (double)rg;
         }
     };
-
+    const size_t stride = (size_t)4 * Lx;
     double g[4] = {0.0, 0.0, 0.0, 0.0};
-    // iteration i (row t = y0 - 2 + i): ring A takes row t, stage A does row
-    // t - 2 into ring B, stage B row t - 4 to memory; then one barrier
+    // 1. ring A
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        const int t = y0 - 2 + i;
-        if (i < ROWS + 4 && t <= y1 + 1 && act) {
-            R* w = slot(ringA, t);
+        for (int i = 0; i < ROWS + 4; ++i) {
+            R* w = ringA + (size_t)i * stride;
             R sn, cs;
             Prec<R>::sincos(th1[i], sn, cs);
             w[xa] = sn;
@@ -358,26 +355,37 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             w[2 * Lx + xa] = lt2[i];
             w[3 * Lx + xa] = lu2[i];
         }
-        const int ra = t - 2;
-        if (i >= 3 && i - 3 < ROWS + 2 && ra <= y1 && act) {
+    }
+    __syncthreads();
+    // 2. stage A (reverse step k+1) on rows y0-1 .. y1, into ring B
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < ROWS + 2; ++i) {
+            const int r = y0 - 1 + i;
+            if (r > y1) break;
             R lto, luo;
-            stage(ringA, KA, ra, u1[i - 3], k + 1, lto, luo, g);
-            R* w = slot(ringB, ra);
+            stage(rowA(r), stride, KA, r, u1[i], k + 1, lto, luo, g);
+            R* w = rowB(r);
             R sn, cs;
-            Prec<R>::sincos(th0[i - 3], sn, cs);
+            Prec<R>::sincos(th0[i], sn, cs);
             w[xa] = sn;
             w[Lx + xa] = cs;
             w[2 * Lx + xa] = lto;
             w[3 * Lx + xa] = luo;
         }
-        const int rb = t - 4;
-        if (i >= 6 && i - 6 < ROWS && rb < y1 && act) {
+    }
+    __syncthreads();
+    // 3. stage B (reverse step k) on rows y0 .. y1-1, to memory
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+            const int r = y0 + i;
+            if (r >= y1) break;
             R lto, luo;
-            stage(ringB, KB, rb, u0[i - 6], k, lto, luo, g);
-            A.lt_out[at(rb)] = lto;
-            A.lu_out[at(rb)] = luo;
+            stage(rowB(r), stride, KB, r, u0[i], k, lto, luo, g);
+            A.lt_out[at(r)] = lto;
+            A.lu_out[at(r)] = luo;
         }
-        if (i + 1 < NT) __syncthreads();
     }
     // wave totals, lane 16p holding value p; one slot per wave
     const int lane = x & (kWave - 1);
@@ -401,14 +409,15 @@ __global__ void k_adj_seed(Lat<R> v, const R* th, R* lt, R* lu, double cmN) {
 }
 
 template <typename R>
-bool adjoint2_fits(const Lat<R>& v) {
-    return v.Lx <= kAdj2MaxLx && v.Ly >= 4 && adjoint2_lds<R>(v.Lx) <= 160 * 1024;
+bool adjoint2_fits(const Lat<R>& v, int rows) {
+    return (rows == 1 || rows == 2 || rows == 4) && v.Lx <= kAdj2MaxLx && v.Ly >= 4 &&
+           adjoint2_lds<R>(v.Lx, rows) <= 160 * 1024;
 }
 
 template <typename R>
 int adjoint_tasks(const Lat<R>& v, int rows, int rows2) {
     const int single = ((v.Ly + rows - 1) / rows) * v.nxw;
-    if (!adjoint2_fits(v) || rows2 < 1) return single;
+    if (!adjoint2_fits(v, rows2)) return single;
     const int fused = ((v.Ly + rows2 - 1) / rows2) * ((v.Lx + kWave - 1) / kWave);
     return std::max(single, fused);
 }
@@ -460,7 +469,7 @@ template <typename R>
 void launch_adjoint_step2(const Lat<R>& v, const R* th0, const R* u0, const R* th1, const R* u1, const R* lt_in,
                           const R* lu_in, R* lt_out, R* lu_out, const double* cm, uint64_t cm_base, double* gacc,
                           const uint64_t* kdev, uint64_t koff, int rows, hipStream_t s) {
-    if (!adjoint2_fits(v) || rows < 1) throw Error(-5, "two-step reverse pass: shape not supported");
+    if (!adjoint2_fits(v, rows)) throw Error(-5, "two-step reverse pass: shape not supported");
     Adj2Args<R> A2;
     A2.a.v = v;
     A2.a.th = th0;
@@ -476,7 +485,7 @@ void launch_adjoint_step2(const Lat<R>& v, const R* th0, const R* u0, const R* t
     A2.u1 = u1;
     const int nstrips = (v.Ly + rows - 1) / rows;
     const int threads = (v.Lx + kWave - 1) / kWave * kWave;
-    const size_t lds = adjoint2_lds<R>(v.Lx);
+    const size_t lds = adjoint2_lds<R>(v.Lx, rows);
     switch (rows) {
         case 1: launch_adjoint2<R, 1>(A2, nstrips, threads, lds, kdev, koff, s); break;
         case 2: launch_adjoint2<R, 2>(A2, nstrips, threads, lds, kdev, koff, s); break;
@@ -492,8 +501,8 @@ void launch_adjoint_seed(const Lat<R>& v, const R* th, R* lt, R* lu, double cmN,
     check_hip(hipGetLastError(), "adjoint seed launch");
 }
 
-template bool adjoint2_fits<float>(const Lat<float>&);
-template bool adjoint2_fits<double>(const Lat<double>&);
+template bool adjoint2_fits<float>(const Lat<float>&, int);
+template bool adjoint2_fits<double>(const Lat<double>&, int);
 template int adjoint_tasks<float>(const Lat<float>&, int, int);
 template int adjoint_tasks<double>(const Lat<double>&, int, int);
 template void launch_adjoint_step2<float>(const Lat<float>&, const float*, const float*, const float*, const float*,

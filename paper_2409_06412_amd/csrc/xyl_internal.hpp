@@ -201,15 +201,16 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
 // the single and of the two-step reverse pass).
 template <typename R>
 int adjoint_tasks(const Lat<R>& v, int rows, int rows2);
-// LDS of the two-step reverse pass: two rings of 4 rows of (sin, cos, lt', lu').
+// LDS of the two-step reverse pass with strips of `rows` rows: rows + 4 and
+// rows + 2 rows of (sin, cos, lt', lu') per site.
 template <typename R>
-constexpr size_t adjoint2_lds(int Lx) {
-    return sizeof(R) * 2 * (size_t)kStep2Slots * 4 * (size_t)Lx;
+constexpr size_t adjoint2_lds(int Lx, int rows) {
+    return sizeof(R) * 4 * (size_t)(2 * rows + 6) * (size_t)Lx;
 }
-// Whether the two-step reverse pass takes this lattice (rows up to 1024
-// sites, Ly >= 4, its LDS within a CU's).
+// Whether the two-step reverse pass takes this lattice with strips of `rows`
+// rows (1, 2 or 4; rows up to 1024 sites, Ly >= 4, its LDS within a CU's).
 template <typename R>
-bool adjoint2_fits(const Lat<R>& v);
+bool adjoint2_fits(const Lat<R>& v, int rows);
 // Reverse steps k+1 and k in one pass (k = koff + *kdev): th0, u0 the state at
 // k, th1, u1 at k+1, (lt_in, lu_in) the adjoint at k+2, (lt_out, lu_out) at k.
 template <typename R>

@@ -2591,8 +2591,9 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
     l.wpb = std::min(l.wpb, 4);
     Lat<R> v = h->view<R>();
     // two reverse steps per pass where the rows fit one workgroup's LDS rings
-    const bool fuse = h->adj_fusion == 2 && adjoint2_fits<R>(v);
-    const int rows2 = adjoint2_rows(h);
+    int rows2 = adjoint2_rows(h);
+    if (!h->adj2_rows && !adjoint2_fits<R>(v, rows2)) rows2 = 1;   // the rule's strips too tall for the LDS
+    const bool fuse = h->adj_fusion == 2 && adjoint2_fits<R>(v, rows2);
     const int ntasks = adjoint_tasks<R>(v, l.rows, fuse ? rows2 : 0);
     a->gacc.reserve((size_t)ntasks * 4);
     check_hip(hipMemsetAsync(a->gacc.p, 0, sizeof(double) * ntasks * 4, h->stream), "hipMemsetAsync");
