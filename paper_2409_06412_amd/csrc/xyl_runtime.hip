@@ -2101,15 +2101,25 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
         if (!active_g.empty()) {
             if (active_g != e->task_active || e->tables_fusion != e->fusion) ens_upload_table<R>(e, e->j, active_g);
             const Lat<R>* reps = reinterpret_cast<const Lat<R>*>(e->reps.p);
-            launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, meas_g.empty() ? kStore : (kStore | kMeasure),
-                                    e->model(), e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
-            for (int r : meas_g)
-                jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
-                                               (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
-            flush_finalize(e, jobs);
-            uint64_t c = 1;
+            uint64_t c = 0;
+            bool stepped = false;
+            if (!meas_g.empty()) {
+                // FP32 with two-step classes: the sample is a measurement
+                // without a step, and the whole chunk runs in pairs of passes;
+                // otherwise the chunk's first step carries the measurement
+                bool passes = false;
+                if constexpr (std::is_same<R, float>::value) passes = !e->s2cls.empty() && chunk >= 4;
+                stepped = !passes;
+                launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, passes ? kMeasure : (kStore | kMeasure),
+                                        e->model(), e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
+                for (int r : meas_g)
+                    jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
+                                                   (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
+                flush_finalize(e, jobs);
+                c = stepped ? 1 : 0;
+            }
             if constexpr (std::is_same<R, float>::value) {
-                const uint64_t n4 = (chunk - 1) / 4 * 4;
+                const uint64_t n4 = (chunk - c) / 4 * 4;
                 if (n4 && !e->s2cls.empty()) {
                     e->u2.reserve(sizeof(float) * e->total);
                     const float* ub = static_cast<const float*>(e->u);
@@ -2128,7 +2138,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                         for (uint64_t i = 0; i < n4; i += 4)
                             for (int ph = 0; ph < 2; ++ph)
                                 launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
-                                                      e->model(), ph, ub, u2b, nullptr, e->j + 1 + i + 2 * ph, st);
+                                                      e->model(), ph, ub, u2b, nullptr, e->j + c + i + 2 * ph, st);
                     }
                     for (size_t c2 = 1; c2 < ncls; ++c2) {
                         check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
@@ -2137,7 +2147,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                     if (e->ntasks_rest)
                         for (uint64_t i = 0; i < n4; ++i)
                             launch_ensemble_step<R>(reps, e->tasks_rest.p, e->ntasks_rest, kStore, e->model(),
-                                                    e->launch.rows, e->launch.wpb, nullptr, e->j + 1 + i, e->stream);
+                                                    e->launch.rows, e->launch.wpb, nullptr, e->j + c + i, e->stream);
                     c += n4;
                 }
             }
