@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1772,9 +1773,16 @@ struct xyl_ensemble {
     int lds_max_sites = 0, lds_threads = 0;
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
-    DevBuf<char> lds_reps;
-    DevBuf<LdsJobHost> lds_jobs;
-    std::vector<LdsJobHost> lds_jobs_host;
+    // the LDS launches' tables, double-buffered: a chunk writes table b while
+    // the previous chunk's launch may still read table b ^ 1; ev_lds[b] marks
+    // the end of the last launch that read table b (and of the copies into it)
+    DevBuf<char> lds_reps[2];
+    DevBuf<LdsJobHost> lds_jobs[2];
+    std::vector<LdsJobHost> lds_jobs_host[2];
+    std::vector<Lat<float>> lds_tab_host[2];
+    hipEvent_t ev_lds[2] = {nullptr, nullptr};
+    bool ev_lds_used[2] = {false, false};
+    int lds_buf = 0;
     // two steps per pass for FP32 replicas on the tile path: one batched launch
     // per class of replicas spanning the same number of waves, per pass; the
     // other tile-path replicas keep one tile launch per step (tasks_rest)
@@ -1932,10 +1940,20 @@ struct EnsSamples {
     std::vector<uint64_t> cnt;
     size_t nsamp = 0;
     std::vector<std::pair<size_t, size_t>> copies;   // (device slot, host index)
+    // finalize jobs of this call: each flush's list stays here (the source of
+    // its asynchronous copy) and takes the next slots of the device arena
+    std::deque<std::vector<FinalizeJobHost>> job_store;
+    size_t njobs = 0;
     EnsSamples(xyl_ensemble* e_, uint64_t every_, uint64_t cap_, const uint64_t* nout)
         : e(e_), every(every_), cap(cap_), cnt(e_->n, 0) {
         if (every && nout)
             for (int r = 0; r < e->n; ++r) cnt[r] = nout[r];
+    }
+    EnsSamples(const EnsSamples&) = delete;
+    EnsSamples& operator=(const EnsSamples&) = delete;
+    // the job lists are the sources of copies that may still be queued
+    ~EnsSamples() {
+        if (!job_store.empty()) (void)hipStreamSynchronize(e->stream);
     }
     bool wants(int r) const {
         return every && e->k[r] <= e->desc[r].nsteps && e->k[r] % every == 0 && e->last_sample[r] != e->k[r] + 1;
@@ -1976,14 +1994,24 @@ struct EnsSamples {
     }
 };
 
-static void flush_finalize(xyl_ensemble* e, std::vector<FinalizeJobHost>& jobs) {
+// Reduces the measurement partials of `jobs` into their sample slots, on the
+// ensemble's stream, without waiting for it: the job list moves into the
+// call's store and takes the next slots of the device arena (a full arena is
+// replaced, after the stream has drained, by one twice as large).
+static void flush_finalize(xyl_ensemble* e, EnsSamples& smp, std::vector<FinalizeJobHost>& jobs) {
     if (jobs.empty()) return;
-    e->jobs.reserve(jobs.size());
-    check_hip(hipMemcpyAsync(e->jobs.p, jobs.data(), sizeof(FinalizeJobHost) * jobs.size(), hipMemcpyHostToDevice,
-                             e->stream),
+    if (smp.njobs + jobs.size() > e->jobs.n || !e->jobs.p) {
+        check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+        e->jobs.reserve(std::max<size_t>(2 * e->jobs.n, std::max<size_t>(jobs.size(), 256)));
+        smp.njobs = 0;
+    }
+    smp.job_store.push_back(std::move(jobs));
+    const std::vector<FinalizeJobHost>& js = smp.job_store.back();
+    FinalizeJobHost* dst = e->jobs.p + smp.njobs;
+    check_hip(hipMemcpyAsync(dst, js.data(), sizeof(FinalizeJobHost) * js.size(), hipMemcpyHostToDevice, e->stream),
               "H2D");
-    launch_finalize_jobs(e->jobs.p, (int)jobs.size(), e->stream);
-    check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    launch_finalize_jobs(dst, (int)js.size(), e->stream);
+    smp.njobs += js.size();
     jobs.clear();
 }
 
@@ -2009,7 +2037,7 @@ static void ens_step_per_replica(xyl_ensemble* e, uint64_t nsteps, EnsSamples& s
                 jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                                (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
         }
-        flush_finalize(e, jobs);
+        flush_finalize(e, smp, jobs);
         for (int r : active) e->k[r] += 1;
         if (!active.empty()) e->j += 1;
     }
@@ -2065,7 +2093,12 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
         if (!lds_set.empty()) {
             // replicas with the factored FP32 kick first, then the others: one
             // launch per form of the kick
-            e->lds_jobs_host.clear();
+            const int b = e->lds_buf;
+            e->lds_buf ^= 1;
+            // table b was last read by the launch two chunks ago
+            if (e->ev_lds_used[b]) check_hip(hipEventSynchronize(e->ev_lds[b]), "hipEventSynchronize");
+            std::vector<LdsJobHost>& jh = e->lds_jobs_host[b];
+            jh.clear();
             int nfact = 0;
             for (int pass = 0; pass < 2; ++pass)
                 for (int r : lds_set) {
@@ -2073,29 +2106,29 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                     const bool f = kick_factored(Params{d.Jx, d.Jy, d.h, d.gamma, d.dt, d.model, d.p});
                     if (f != (pass == 0)) continue;
                     nfact += f ? 1 : 0;
-                    e->lds_jobs_host.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
-                                                          meas[r] ? smp.take(r) : nullptr});
+                    jh.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
+                                            meas[r] ? smp.take(r) : nullptr});
                 }
-            e->lds_jobs.reserve(e->lds_jobs_host.size());
-            // the previous chunk's launch must have read its job table before it is rewritten
-            check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
-            check_hip(hipMemcpyAsync(e->lds_jobs.p, e->lds_jobs_host.data(), sizeof(LdsJobHost) * lds_set.size(),
-                                     hipMemcpyHostToDevice, e->side),
-                      "H2D");
-            std::vector<Lat<float>> tab(e->n);
-            for (int r = 0; r < e->n; ++r) tab[r] = e->view<float>(r, e->j);
-            e->lds_reps.reserve(sizeof(Lat<float>) * e->n);
-            check_hip(hipMemcpyAsync(e->lds_reps.p, tab.data(), sizeof(Lat<float>) * e->n, hipMemcpyHostToDevice,
+            e->lds_jobs[b].reserve(jh.size());
+            check_hip(hipMemcpyAsync(e->lds_jobs[b].p, jh.data(), sizeof(LdsJobHost) * jh.size(), hipMemcpyHostToDevice,
                                      e->side),
                       "H2D");
-            check_hip(hipStreamSynchronize(e->side), "hipStreamSynchronize");
-            const Lat<float>* lreps = reinterpret_cast<const Lat<float>*>(e->lds_reps.p);
+            std::vector<Lat<float>>& tab = e->lds_tab_host[b];
+            tab.resize(e->n);
+            for (int r = 0; r < e->n; ++r) tab[r] = e->view<float>(r, e->j);
+            e->lds_reps[b].reserve(sizeof(Lat<float>) * e->n);
+            check_hip(hipMemcpyAsync(e->lds_reps[b].p, tab.data(), sizeof(Lat<float>) * e->n, hipMemcpyHostToDevice,
+                                     e->side),
+                      "H2D");
+            const Lat<float>* lreps = reinterpret_cast<const Lat<float>*>(e->lds_reps[b].p);
             if (nfact)
-                launch_ensemble_lds(lreps, e->lds_jobs.p, nfact, e->lds_threads, e->lds_max_sites, e->model(), true,
+                launch_ensemble_lds(lreps, e->lds_jobs[b].p, nfact, e->lds_threads, e->lds_max_sites, e->model(), true,
                                     e->j, e->side);
             if ((int)lds_set.size() > nfact)
-                launch_ensemble_lds(lreps, e->lds_jobs.p + nfact, (int)lds_set.size() - nfact, e->lds_threads,
+                launch_ensemble_lds(lreps, e->lds_jobs[b].p + nfact, (int)lds_set.size() - nfact, e->lds_threads,
                                     e->lds_max_sites, e->model(), false, e->j, e->side);
+            check_hip(hipEventRecord(e->ev_lds[b], e->side), "hipEventRecord");
+            e->ev_lds_used[b] = true;
         }
         // large replicas
         if (!active_g.empty()) {
@@ -2115,7 +2148,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                 for (int r : meas_g)
                     jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                                    (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
-                flush_finalize(e, jobs);
+                flush_finalize(e, smp, jobs);
                 c = stepped ? 1 : 0;
             }
             if constexpr (std::is_same<R, float>::value) {
@@ -2162,7 +2195,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
             jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                            (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
         }
-        flush_finalize(e, jobs);
+        flush_finalize(e, smp, jobs);
         if (!any_active) break;
         for (int r = 0; r < e->n; ++r)
             if (act[r]) e->k[r] += chunk;
@@ -2327,6 +2360,8 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
             check_hip(hipStreamCreateWithFlags(&e->side, hipStreamNonBlocking), "hipStreamCreate");
             check_hip(hipEventCreateWithFlags(&e->ev_main, hipEventDisableTiming), "hipEventCreate");
             check_hip(hipEventCreateWithFlags(&e->ev_side, hipEventDisableTiming), "hipEventCreate");
+            for (int b = 0; b < 2; ++b)
+                check_hip(hipEventCreateWithFlags(&e->ev_lds[b], hipEventDisableTiming), "hipEventCreate");
         }
         e->k.assign(n, 0);
         e->fresh_k.assign(n, 0);
@@ -2353,6 +2388,8 @@ int xyl_ensemble_destroy(xyl_ensemble* e) {
         if (e->side) (void)hipStreamDestroy(e->side);
         if (e->ev_main) (void)hipEventDestroy(e->ev_main);
         if (e->ev_side) (void)hipEventDestroy(e->ev_side);
+        for (int b = 0; b < 2; ++b)
+            if (e->ev_lds[b]) (void)hipEventDestroy(e->ev_lds[b]);
         for (hipStream_t st : e->cls_streams) (void)hipStreamDestroy(st);
         for (hipEvent_t ev : e->cls_events) (void)hipEventDestroy(ev);
         delete e;
