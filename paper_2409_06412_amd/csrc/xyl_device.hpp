@@ -155,12 +155,24 @@ struct Prec<double> {
 // "if t >= W: t -= 2W, else if t < -W: t += 2W" for every input.
 // The shift is selected first and subtracted once: t - 2W, t + 2W (both exact)
 // or t - (+0) = t, which keeps the sign of a zero.
+// FP32 XY angles take the shift as 2W times the nearest integer to t / 2W
+// (three operations instead of two compares, two selects and a subtraction):
+// the same whenever t / 2W, rounded, is not exactly +-1/2, so only angles
+// within an ulp or two of +-W may stay on the outer side of the boundary.
+// The XY model's force and observables are 2 pi-periodic, so that changes
+// nothing but the representative; the SI field is not, and keeps the exact
+// rule, as does FP64.
 template <typename R, int M>
 __device__ __forceinline__ R wrap_angle(R t) {
     constexpr R W = M == kModelSI ? Prec<R>::kHalfPi : Prec<R>::kPi;
     constexpr R W2 = M == kModelSI ? Prec<R>::kPi : Prec<R>::kTwoPi;
-    const R shift = t >= W ? W2 : (t < -W ? -W2 : R(0));
-    return t - shift;
+    if constexpr (sizeof(R) == 4 && M == kModelXY) {
+        const R r = __builtin_rintf(t * (R(1) / W2));
+        return Prec<R>::fma(-W2, r, t);
+    } else {
+        const R shift = t >= W ? W2 : (t < -W ? -W2 : R(0));
+        return t - shift;
+    }
 }
 
 // Rotor of a site, (sin q t, cos q t): q = 1 (XY) or 2 (SI).
