@@ -441,12 +441,13 @@ int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, doub
 /* Reverse steps per pass of xyl_adjoint_backward (App. A.1's step, run
  * backwards): 2 (the default) takes two reverse steps per pass over the state
  * where a strip of rows fits one workgroup (one site per lane, Lx at most
- * 1024, Ly >= 4, and 16 (2 rows + 6) Lx bytes of FP32 state, twice that in
- * FP64, within a CU's 160 KiB of LDS), and recomputes the checkpointed
+ * 1024, Ly >= 4, and (40 rows + 104) Lx bytes of FP32 state and draws, twice
+ * that in FP64, within a CU's 160 KiB of LDS), and recomputes the checkpointed
  * segments two steps per pass too where the forward's two-step pass takes
  * the lattice; 1 keeps one step per pass for both.  rows: rows per strip of
- * the two-step reverse pass (1, 2 or 4; 0 keeps the current value, initially
- * 2, or 1 where 2 does not fit).  dL/dth and dL/dw are bitwise
+ * the two-step reverse pass (1, 2 or 4; 0 keeps the current value,
+ * initially 2: where that does not fit, single reverse steps unless 1 is
+ * set).  dL/dth and dL/dw are bitwise
  * the same either way; the parameter gradients are sums taken in another
  * order.  EINVAL outside the ranges. */
 int xyl_set_adjoint_fusion(xyl_lattice* h, int32_t steps_per_pass, int32_t rows);

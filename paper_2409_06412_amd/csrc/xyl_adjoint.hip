@@ -288,6 +288,9 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
     // [s, c, lt, lu][Lx]
     R* ringA = reinterpret_cast<R*>(adj2_lds);
     R* ringB = ringA + (size_t)(ROWS + 4) * 4 * Lx;
+    // the draws of stage A's rows (step k+1) and stage B's (step k), [row][Lx]
+    R* noiseA = ringB + (size_t)(ROWS + 2) * 4 * Lx;
+    R* noiseB = noiseA + (size_t)(ROWS + 2) * Lx;
     const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int y0 = strip * ROWS;
     const int y1 = min(y0 + ROWS, Ly);
@@ -321,28 +324,45 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
     auto lf_of = [&](const R* sl, int i, R kap) { return kap * Prec<R>::fma(v.dt, sl[2 * Lx + i], sl[3 * Lx + i]); };
     // a stage's reverse step at row r, its rows r-1, r, r+1 at C - stride,
     // C, C + stride in its ring, with coefficients K; returns lt, lu
-    auto stage = [&](const R* C, size_t stride, const AdjStep<R>& K, int r, R u, uint64_t ks, R& lto, R& luo,
-                     double g[4]) {
+    // a stage's reverse step at row r, its rows r-1, r, r+1 at C - stride,
+    // C, C + stride in its ring, its draw n, with coefficients K; returns lt,
+    // lu and adds the parameter adjoints of the strip's own rows to g
+    auto stage = [&](const R* C, size_t stride, const AdjStep<R>& K, int r, R u, R n, R& lto, R& luo, R g[4]) {
         const R* Pm = C - stride;
         const R* Np = C + stride;
         const int y = wrap(r);
-        R n4[4];
-        noise4<R>((uint32_t)y * (uint32_t)(Lx >> 2) + (uint32_t)(xa >> 2), v.replica, ks, v.seed_lo, v.seed_hi, n4);
         const R eps = (((xa * v.stag_x) + (y * v.stag_y)) & 1) ? R(-1) : R(1);
         R rx = 0, ry = 0, rh = 0, rg = 0;
         adj_site(v, K, C[xa], C[Lx + xa], C[xm], C[Lx + xm], lf_of(C, xm, K.kap), C[xp], C[Lx + xp],
                  lf_of(C, xp, K.kap), Pm[xa], Pm[Lx + xa], lf_of(Pm, xa, K.kap), Np[xa], Np[Lx + xa],
-                 lf_of(Np, xa, K.kap), lf_of(C, xa, K.kap), C[2 * Lx + xa], C[3 * Lx + xa], u, n4[xa & 3], eps, lto,
-                 luo, rx, ry, rh, rg);
+                 lf_of(Np, xa, K.kap), lf_of(C, xa, K.kap), C[2 * Lx + xa], C[3 * Lx + xa], u, n, eps, lto, luo, rx,
+                 ry, rh, rg);
         if (r >= y0 && r < y1) {
-            g[0] += (double)rx;
-            g[1] += (double)ry;
-            g[2] += (double)rh;
-            g[3] += (double)rg;
+            g[0] += rx;
+            g[1] += ry;
+            g[2] += rh;
+            g[3] += rg;
         }
     };
     const size_t stride = (size_t)4 * Lx;
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    // the lane's parameter adjoints, in the state precision (at most
+    // 2 ROWS + 2 terms), then FP64 across the wave
+    R g[4] = {R(0), R(0), R(0), R(0)};
+    // the draws: one Philox block per (stage, row, quad), shared out over the
+    // workgroup's lanes instead of computed by each of a quad's four lanes
+    {
+        const int nq = Lx >> 2;
+        const int nbA = (ROWS + 2) * nq, nb = nbA + ROWS * nq;
+        for (int b = x; b < nb; b += blockDim.x) {
+            const bool a = b < nbA;
+            const int i = a ? b / nq : (b - nbA) / nq;
+            const int q = a ? b - i * nq : (b - nbA) - i * nq;
+            const int y = wrap(a ? y0 - 1 + i : y0 + i);
+            R n4[4];
+            noise4<R>((uint32_t)y * (uint32_t)nq + (uint32_t)q, v.replica, a ? k + 1 : k, v.seed_lo, v.seed_hi, n4);
+            store4((a ? noiseA : noiseB) + (size_t)i * Lx + 4 * q, n4);
+        }
+    }
     // 1. ring A
     if (act) {
 #pragma unroll
@@ -364,7 +384,7 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             const int r = y0 - 1 + i;
             if (r > y1) break;
             R lto, luo;
-            stage(rowA(r), stride, KA, r, u1[i], k + 1, lto, luo, g);
+            stage(rowA(r), stride, KA, r, u1[i], noiseA[(size_t)i * Lx + xa], lto, luo, g);
             R* w = rowB(r);
             R sn, cs;
             Prec<R>::sincos(th0[i], sn, cs);
@@ -382,14 +402,15 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             const int r = y0 + i;
             if (r >= y1) break;
             R lto, luo;
-            stage(rowB(r), stride, KB, r, u0[i], k, lto, luo, g);
+            stage(rowB(r), stride, KB, r, u0[i], noiseB[(size_t)i * Lx + xa], lto, luo, g);
             A.lt_out[at(r)] = lto;
             A.lu_out[at(r)] = luo;
         }
     }
     // wave totals, lane 16p holding value p; one slot per wave
     const int lane = x & (kWave - 1);
-    const double tot = wave_sum4(g, lane);
+    const double gd[4] = {(double)g[0], (double)g[1], (double)g[2], (double)g[3]};
+    const double tot = wave_sum4(gd, lane);
     const size_t wave = (size_t)strip * (blockDim.x / kWave) + (size_t)(x / kWave);
     if ((lane & 15) == 0) A.gacc[wave * 4 + (lane >> 4)] += tot;
 }

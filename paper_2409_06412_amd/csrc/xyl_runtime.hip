@@ -2618,8 +2618,11 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
 // dL/dw^{k0}: host float64 arrays (dth0, dom0) or, with dev_out, caller
 // device buffers of precision out_f64 (written on the lattice's stream, times
 // `scale`).
-// Rows per strip of the two-step reverse pass (1, 2 or 4): 2 (512^2: 6.9
-// against 7.2 us per step with 1 and 8.6 with 4).
+// Rows per strip of the two-step reverse pass (1, 2 or 4): 2, where its LDS
+// fits (512^2: 4.9 us per step, against 7.1 with 1-row strips and 8.2 with
+// single reverse steps); where it does not (FP32 rows above 888 sites, FP64
+// above 444), single reverse steps (1024^2: 15.1 us per step, against 20.7
+// with 1-row strips, whose stage A does three rows per row of output).
 static int adjoint2_rows(const xyl_lattice* h) { return h->adj2_rows ? h->adj2_rows : 2; }
 
 template <typename R>
@@ -2638,8 +2641,7 @@ static void adjoint_backward_impl(xyl_lattice* h, double* grad, void* dth0, void
     l.wpb = std::min(l.wpb, 4);
     Lat<R> v = h->view<R>();
     // two reverse steps per pass where the rows fit one workgroup's LDS rings
-    int rows2 = adjoint2_rows(h);
-    if (!h->adj2_rows && !adjoint2_fits<R>(v, rows2)) rows2 = 1;   // the rule's strips too tall for the LDS
+    const int rows2 = adjoint2_rows(h);
     const bool fuse = h->adj_fusion == 2 && adjoint2_fits<R>(v, rows2);
     const int ntasks = adjoint_tasks<R>(v, l.rows, fuse ? rows2 : 0);
     a->gacc.reserve((size_t)ntasks * 4);
