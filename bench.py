@@ -519,7 +519,7 @@ def host_info():
 
 # ----------------------------------------------------------- profile summaries
 STEP_KERNEL = "xyl::k_step<float, 1, 0>"   # single plain store step of the XY model
-STEP2_KERNEL = "xyl::k_step2<0, false>"    # two steps per pass of the XY model (full waves)
+STEP2_KERNEL = "xyl::k_step2<0, false, false>"    # two steps per pass of the XY model (full waves)
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
