@@ -137,6 +137,31 @@ def test_fp32_parity(xyl, Lx, Ly):
     lat.close()
 
 
+def test_fp32_xy_wrap_keeps_angles_within_an_ulp_of_the_circle(xyl):
+    """The FP32 XY kernels wrap by 2 pi_32 rint(th / 2 pi_32) (Sec. III.D's
+    modulo; the model is 2 pi-periodic): every angle ends within a few ulps of
+    [-pi_32, pi_32), at a temperature where sites cross the boundary every few
+    steps, for single steps and two steps per pass alike (bitwise equal)."""
+    pi32 = float(np.float32(np.pi))
+    ulp = float(np.spacing(np.float32(np.pi)))
+    out = []
+    for fusion in (1, 2):
+        lat = xyl.Lattice(512, 64, dtype="f32", Jx=1.0, Jy=-0.1, h=0.5, gamma=0.5, dt=0.05,
+                          schedule=[(0, 3.0)], seed=4)
+        lat.set_fusion(fusion)
+        lat.init_random()
+        lat.step(2000)
+        th, om, _ = lat.get_state()
+        out.append(th)
+        lat.close()
+    np.testing.assert_array_equal(out[0], out[1])
+    th = out[0]
+    say("wrap: max|th| - pi_32 =", np.abs(th).max() - pi32, "ulps", (np.abs(th).max() - pi32) / ulp)
+    assert np.abs(th).max() <= pi32 + 4 * ulp
+    # the circle is covered: crossings happened
+    assert np.count_nonzero(np.abs(th) > 3.0) > 100
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_set_state_fresh_velocity(xyl, dtype):
     """A state set with nonzero omega at step k0 continues exactly like the oracle."""
