@@ -152,11 +152,21 @@ def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
         ens.step(nsteps, every=every)
         ens.sync()
         out[name] = time.perf_counter() - t0
+        if mode == 0:
+            # a longer sampled run: its chunks repeat, so from the second one
+            # on they replay as captured graphs
+            t0 = time.perf_counter()
+            ens.step(10 * every, every=every)
+            ens.sync()
+            out["batched_long"] = time.perf_counter() - t0
+            out["batched_fusion"] = ens.fusion()
         ens.close()
     out.update(bench_solo_lattices(torch, xyl, specs, nsteps, every))
     sites = sum(s.Lx * s.Ly for s in specs)
     return {"replicas": len(specs), "sites": sites, "steps": nsteps, "sample_every": every,
             "batched_site_updates_per_s": sites * nsteps / out["batched"],
+            "batched_%d_steps_site_updates_per_s" % (10 * every): sites * 10 * every / out["batched_long"],
+            "batched_steps_per_pass": out["batched_fusion"],
             "per_replica_site_updates_per_s": sites * nsteps / out["per_replica"],
             "speedup": out["per_replica"] / out["batched"],
             # the replicas as separate lattices through the single-lattice path

@@ -387,6 +387,15 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
  * grid).  Mode 1: one launch per replica per step (the reference loop the
  * batched mode is measured against).  Default 0. */
 int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
+/* Graph-captured chunks in the batched mode (App. B: many subsystems run
+ * together; 1, the default, or 0): the
+ * stepping of a chunk between samples (its two-step passes on their class
+ * streams and its single tile-table steps) is captured as a graph the second
+ * time a chunk of the same shape (first step, length) is met, and replayed
+ * with the step index from a device counter after that; chunks of fewer than
+ * 8 launches stay direct.  Graphs are dropped when the task tables, the launch
+ * shape or the steps per pass change.  Results are bitwise the same. */
+int xyl_ensemble_set_graphs(xyl_ensemble* e, int32_t enable);
 /* Steps per pass for the batched mode (1 or 2; default 2).  With 2 (FP32),
  * runs of 4m steps between samples advance the replicas on the tile path
  * whose width the two-step pass takes (as for xyl_set_fusion) two steps per
@@ -396,10 +405,15 @@ int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
  * Results are bitwise identical either way.  The library allocates a second
  * velocity buffer of the ensemble's size on first use. */
 int xyl_ensemble_set_fusion(xyl_ensemble* e, int32_t steps_per_pass);
+/* The steps per pass in effect (set, or chosen by xyl_ensemble_autotune). */
+int xyl_ensemble_get_fusion(const xyl_ensemble* e, int32_t* steps_per_pass);
 /* Launch shape (rows per strip, waves per workgroup) of the tile launches:
  * xyl_ensemble_autotune times candidates on scratch copies of the replicas'
- * state (the ensemble itself is not advanced) and keeps the fastest.
- * Results do not depend on it. */
+ * state (the ensemble itself is not advanced) and keeps the fastest.  For
+ * FP32 ensembles with replicas the two-step pass takes, it then times their
+ * passes (with the other replicas' tile steps) against the best tile launch
+ * for every step and sets the steps per pass (xyl_ensemble_set_fusion) to
+ * whichever is faster.  Results do not depend on either. */
 int xyl_ensemble_autotune(xyl_ensemble* e);
 int xyl_ensemble_get_launch(xyl_ensemble* e, int32_t* rows, int32_t* wpb);
 int xyl_ensemble_get_state(xyl_ensemble* e, int32_t r, double* theta, double* omega, uint64_t* step);

@@ -81,6 +81,8 @@ _SIGS = {
     "xyl_set_step2_shape": (_i32, [_vp, _i32, _i32]),
     "xyl_get_step2_shape": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
     "xyl_ensemble_set_fusion": (_i32, [_vp, _i32]),
+    "xyl_ensemble_set_graphs": (_i32, [_vp, _i32]),
+    "xyl_ensemble_get_fusion": (_i32, [_vp, P(_i32)]),
     "xyl_stream_ceiling": (_i32, [_i32, _u64, _i32, P(_d)]),
     "xyl_set_schedule_shaped": (_i32, [_vp, P(_u64), P(_d), P(_i32), _i32]),
     "xyl_step_adaptive": (_i32, [_vp, _u64, _u64, _u64, _u64, _i32, _u64, P(_d), P(_u64), _u64, P(_u64)]),
@@ -591,6 +593,17 @@ class Ensemble:
         waves per row; 1: every step is one batched launch.  Results are
         identical."""
         _check(load().xyl_ensemble_set_fusion(self._h, int(steps_per_pass)))
+
+    def fusion(self) -> int:
+        """Steps per pass in effect for the batched mode."""
+        sp = _i32()
+        _check(load().xyl_ensemble_get_fusion(self._h, ctypes.byref(sp)))
+        return sp.value
+
+    def set_graphs(self, enable: bool):
+        """Capture repeated chunks of batched stepping as graphs (default on);
+        results are identical."""
+        _check(load().xyl_ensemble_set_graphs(self._h, int(bool(enable))))
 
     def autotune(self):
         _check(load().xyl_ensemble_autotune(self._h))

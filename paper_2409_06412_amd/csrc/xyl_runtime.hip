@@ -1805,6 +1805,24 @@ struct xyl_ensemble {
     // their own (default priority), forked from and joined to the ensemble's
     std::vector<hipStream_t> cls_streams;
     std::vector<hipEvent_t> cls_events;   // [0] fork, [1 + i] join of class i + 1
+    // Chunks of steps captured as graphs (step index from the device counter
+    // kc): keyed by (first step within the chunk, steps), captured the second
+    // time a key is met and replayed after; all dropped when a table, the
+    // launch shape or the steps per pass change (graph_version).
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    DevBuf<uint64_t> kc;
+    uint64_t graph_version = 0, graphs_built_for = ~(uint64_t)0;
+    struct ChunkGraph {
+        int seen = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<std::pair<uint64_t, uint64_t>, ChunkGraph> graphs;
+    void drop_graphs() {
+        for (auto& g : graphs)
+            if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+        graphs.clear();
+    }
     void class_streams(size_t ncls) {
         while (cls_streams.size() + 1 < ncls) {
             hipStream_t st = nullptr;
@@ -1930,6 +1948,7 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
     check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     e->task_active = active;
     e->tables_fusion = e->fusion;
+    e->graph_version += 1;
 }
 
 // Sample bookkeeping of one xyl_ensemble_step call: observables gathered in
@@ -2151,43 +2170,91 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                 flush_finalize(e, smp, jobs);
                 c = stepped ? 1 : 0;
             }
-            if constexpr (std::is_same<R, float>::value) {
-                const uint64_t n4 = (chunk - c) / 4 * 4;
-                if (n4 && !e->s2cls.empty()) {
-                    e->u2.reserve(sizeof(float) * e->total);
-                    const float* ub = static_cast<const float*>(e->u);
-                    float* u2b = reinterpret_cast<float*>(e->u2.p);
-                    const size_t ncls = e->s2cls.size();
-                    e->class_streams(ncls);
-                    if (ncls > 1) {
-                        check_hip(hipEventRecord(e->cls_events[0], e->stream), "hipEventRecord");
-                        for (size_t c2 = 1; c2 < ncls; ++c2)
-                            check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
-                                      "hipStreamWaitEvent");
+            // steps c0 .. c0 + n - 1 of the chunk, step offsets jb + c (with
+            // kdev, jb = 0 and the device counter holds e->j)
+            auto issue = [&](uint64_t c0, uint64_t n, const uint64_t* kdev, uint64_t jb, hipStream_t main) {
+                uint64_t cc = c0;
+                if constexpr (std::is_same<R, float>::value) {
+                    const uint64_t n4 = n / 4 * 4;
+                    if (n4 && !e->s2cls.empty()) {
+                        e->u2.reserve(sizeof(float) * e->total);
+                        const float* ub = static_cast<const float*>(e->u);
+                        float* u2b = reinterpret_cast<float*>(e->u2.p);
+                        const size_t ncls = e->s2cls.size();
+                        e->class_streams(ncls);
+                        if (ncls > 1) {
+                            check_hip(hipEventRecord(e->cls_events[0], main), "hipEventRecord");
+                            for (size_t c2 = 1; c2 < ncls; ++c2)
+                                check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
+                                          "hipStreamWaitEvent");
+                        }
+                        for (size_t c2 = 0; c2 < ncls; ++c2) {
+                            const auto& cl = e->s2cls[c2];
+                            hipStream_t st = c2 == 0 ? main : e->cls_streams[c2 - 1];
+                            for (uint64_t i = 0; i < n4; i += 4)
+                                for (int ph = 0; ph < 2; ++ph)
+                                    launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial,
+                                                          cl.max_lx, e->model(), ph, ub, u2b, kdev,
+                                                          jb + cc + i + 2 * ph, st);
+                        }
+                        for (size_t c2 = 1; c2 < ncls; ++c2) {
+                            check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
+                            check_hip(hipStreamWaitEvent(main, e->cls_events[c2], 0), "hipStreamWaitEvent");
+                        }
+                        if (e->ntasks_rest)
+                            for (uint64_t i = 0; i < n4; ++i)
+                                launch_ensemble_step<R>(reps, e->tasks_rest.p, e->ntasks_rest, kStore, e->model(),
+                                                        e->launch.rows, e->launch.wpb, kdev, jb + cc + i, main);
+                        cc += n4;
                     }
-                    for (size_t c2 = 0; c2 < ncls; ++c2) {
-                        const auto& cl = e->s2cls[c2];
-                        hipStream_t st = c2 == 0 ? e->stream : e->cls_streams[c2 - 1];
-                        for (uint64_t i = 0; i < n4; i += 4)
-                            for (int ph = 0; ph < 2; ++ph)
-                                launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
-                                                      e->model(), ph, ub, u2b, nullptr, e->j + c + i + 2 * ph, st);
+                }
+                for (; cc < c0 + n; ++cc)
+                    launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->model(), e->launch.rows,
+                                            e->launch.wpb, kdev, jb + cc, main);
+            };
+            const uint64_t n = chunk - c;
+            // launches the chunk's stepping takes
+            uint64_t nl = n;
+            if constexpr (std::is_same<R, float>::value)
+                if (!e->s2cls.empty()) nl = n / 4 * 2 * e->s2cls.size() + n % 4 + (e->ntasks_rest ? n / 4 * 4 : 0);
+            xyl_ensemble::ChunkGraph* cg = nullptr;
+            if (e->use_graphs && nl >= 8) {
+                if (e->graphs_built_for != e->graph_version) {
+                    e->drop_graphs();
+                    e->graphs_built_for = e->graph_version;
+                }
+                cg = &e->graphs[{c, n}];
+                if (!cg->exec && ++cg->seen >= 2) {
+                    // everything that allocates or creates happens before the capture
+                    if (!e->cap_stream)
+                        check_hip(hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+                    e->kc.reserve(1);
+                    if (!e->s2cls.empty()) {
+                        e->u2.reserve(sizeof(float) * e->total);
+                        e->class_streams(e->s2cls.size());
                     }
-                    for (size_t c2 = 1; c2 < ncls; ++c2) {
-                        check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
-                        check_hip(hipStreamWaitEvent(e->stream, e->cls_events[c2], 0), "hipStreamWaitEvent");
+                    hipGraph_t gr = nullptr;
+                    check_hip(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal),
+                              "hipStreamBeginCapture");
+                    try {
+                        issue(c, n, e->kc.p, 0, e->cap_stream);
+                    } catch (...) {
+                        (void)hipStreamEndCapture(e->cap_stream, &gr);
+                        if (gr) (void)hipGraphDestroy(gr);
+                        throw;
                     }
-                    if (e->ntasks_rest)
-                        for (uint64_t i = 0; i < n4; ++i)
-                            launch_ensemble_step<R>(reps, e->tasks_rest.p, e->ntasks_rest, kStore, e->model(),
-                                                    e->launch.rows, e->launch.wpb, nullptr, e->j + c + i, e->stream);
-                    c += n4;
+                    check_hip(hipStreamEndCapture(e->cap_stream, &gr), "hipStreamEndCapture");
+                    hipError_t err = hipGraphInstantiate(&cg->exec, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    check_hip(err, "hipGraphInstantiate");
                 }
             }
-            for (; c < chunk; ++c)
-                launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, kStore, e->model(), e->launch.rows, e->launch.wpb,
-                                        nullptr,
-                                        e->j + c, e->stream);
+            if (cg && cg->exec) {
+                launch_set_counter(e->kc.p, e->j, e->stream);
+                check_hip(hipGraphLaunch(cg->exec, e->stream), "hipGraphLaunch");
+            } else {
+                issue(c, n, nullptr, e->j, e->stream);
+            }
         }
         for (int r : only_meas_g) {
             Lat<R> v = e->view<R>(r, e->j);
@@ -2218,10 +2285,11 @@ static Launch ensemble_autotune_impl(xyl_ensemble* e) {
     if (reps.empty()) return e->launch;
     const size_t bytes = sizeof(R) * e->total;
     DevBuf<char> tmp;
-    tmp.reserve(3 * bytes);
+    tmp.reserve(4 * bytes);   // angles (2), velocities, second velocities of the two-step passes
     for (int b = 0; b < 2; ++b)
         check_hip(hipMemcpyAsync(tmp.p + b * bytes, e->th[b], bytes, hipMemcpyDeviceToDevice, e->stream), "D2D");
     check_hip(hipMemcpyAsync(tmp.p + 2 * bytes, e->u, bytes, hipMemcpyDeviceToDevice, e->stream), "D2D");
+    check_hip(hipMemcpyAsync(tmp.p + 3 * bytes, e->u, bytes, hipMemcpyDeviceToDevice, e->stream), "D2D");
     std::vector<Lat<R>> tab(e->n);
     for (int r = 0; r < e->n; ++r) {
         tab[r] = e->view<R>(r, 0);
@@ -2290,6 +2358,73 @@ static Launch ensemble_autotune_impl(xyl_ensemble* e) {
                 best.wpb = w;
             }
         }
+    }
+    // Steps per pass (FP32): the two-step classes' passes (one class after
+    // the other here) plus the tile steps of the replicas outside them,
+    // against the best tile launch for every step, over the same steps.
+    if constexpr (std::is_same<R, float>::value) {
+        std::vector<int> active;
+        for (int r : reps)
+            if (e->k[r] < e->desc[r].nsteps) active.push_back(r);
+        const int fusion0 = e->fusion;
+        const Launch launch0 = e->launch;
+        e->launch = best;
+        e->fusion = 2;
+        if (!active.empty()) ens_upload_table<R>(e, e->j, active);
+        if (!active.empty() && !e->s2cls.empty()) {
+            const int steps4 = (steps + 3) / 4 * 4;
+            const Lat<float>* dreps = reinterpret_cast<const Lat<float>*>(dtab.p);
+            const float* ub = reinterpret_cast<const float*>(tmp.p + 2 * bytes);
+            float* u2b = reinterpret_cast<float*>(tmp.p + 3 * bytes);
+            auto time_graph = [&](auto&& body, int nsteps) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ex = nullptr;
+                check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                body();
+                check_hip(hipStreamEndCapture(cap, &g), "hipStreamEndCapture");
+                hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                check_hip(err, "hipGraphInstantiate");
+                check_hip(hipGraphLaunch(ex, e->stream), "hipGraphLaunch");
+                float t = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    check_hip(hipEventRecord(e0, e->stream), "hipEventRecord");
+                    check_hip(hipGraphLaunch(ex, e->stream), "hipGraphLaunch");
+                    check_hip(hipEventRecord(e1, e->stream), "hipEventRecord");
+                    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0.f;
+                    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    t = std::min(t, ms);
+                }
+                (void)hipGraphExecDestroy(ex);
+                return t / (float)nsteps;
+            };
+            const float t2 = time_graph(
+                [&] {
+                    for (int i = 0; i < steps4; i += 4)
+                        for (int ph = 0; ph < 2; ++ph)
+                            for (const auto& cl : e->s2cls)
+                                launch_ensemble_step2(dreps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
+                                                      e->model(), ph, ub, u2b, kc.p, (uint64_t)(i + 2 * ph), cap);
+                    if (e->ntasks_rest)
+                        for (int i = 0; i < steps4; ++i)
+                            launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), e->tasks_rest.p,
+                                                    e->ntasks_rest, kStore, e->model(), best.rows, best.wpb, kc.p,
+                                                    (uint64_t)i, cap);
+                },
+                steps4);
+            const float t1 = time_graph(
+                [&] {
+                    for (int i = 0; i < steps4; ++i)
+                        launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), e->tasks.p, e->ntasks,
+                                                kStore, e->model(), best.rows, best.wpb, kc.p, (uint64_t)i, cap);
+                },
+                steps4);
+            e->fusion = t2 < t1 ? 2 : 1;
+        } else {
+            e->fusion = fusion0;
+        }
+        e->launch = launch0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2392,6 +2527,8 @@ int xyl_ensemble_destroy(xyl_ensemble* e) {
             if (e->ev_lds[b]) (void)hipEventDestroy(e->ev_lds[b]);
         for (hipStream_t st : e->cls_streams) (void)hipStreamDestroy(st);
         for (hipEvent_t ev : e->cls_events) (void)hipEventDestroy(ev);
+        e->drop_graphs();
+        if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
         delete e;
     });
 }
@@ -2400,6 +2537,21 @@ int xyl_ensemble_set_stream(xyl_ensemble* e, void* stream) {
     return guarded([&] {
         require(e != nullptr, XYL_EINVAL, "NULL handle");
         e->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int xyl_ensemble_set_graphs(xyl_ensemble* e, int32_t enable) {
+    return guarded([&] {
+        require(e != nullptr, XYL_EINVAL, "NULL handle");
+        require(enable == 0 || enable == 1, XYL_EINVAL, "enable must be 0 or 1");
+        e->use_graphs = enable != 0;
+    });
+}
+
+int xyl_ensemble_get_fusion(const xyl_ensemble* e, int32_t* steps_per_pass) {
+    return guarded([&] {
+        require(e != nullptr && steps_per_pass != nullptr, XYL_EINVAL, "NULL argument");
+        *steps_per_pass = e->fusion;
     });
 }
 

@@ -221,6 +221,68 @@ def _ensemble_run(xyl, specs, fusion, nsteps, every, states=None):
     return samples, out
 
 
+@pytest.mark.parametrize("fusion", [2, 1])
+def test_ensemble_graph_captured_chunks_equal_direct_launches(xyl, fusion):
+    """Repeated chunks of batched stepping replayed as graphs (step index from
+    a device counter; two-step classes on their streams as parallel branches)
+    against the same launches issued directly: samples and states bit for
+    bit, across a replica that ends (the tables, hence the graphs, rebuilt),
+    sampled and unsampled calls."""
+    specs = [workloads.LatticeSpec(1024, 256, schedule=((0, 0.6), (120, 0.2)), seed=8, replica=0, nsteps=10 ** 6),
+             workloads.LatticeSpec(512, 384, schedule=((0, 0.5),), seed=8, replica=1, nsteps=10 ** 6),
+             workloads.LatticeSpec(192, 192, schedule=((0, 0.8),), seed=8, replica=2, nsteps=130),
+             workloads.LatticeSpec(320, 40, schedule=((0, 0.6),), seed=8, replica=3, nsteps=10 ** 6),
+             workloads.LatticeSpec(64, 64, schedule=((0, 0.6),), seed=8, replica=4, nsteps=10 ** 6)]
+    res = []
+    for graphs in (True, False):
+        ens = xyl.Ensemble(specs, dtype="f32")
+        ens.set_fusion(fusion)
+        ens.set_graphs(graphs)
+        s1 = ens.step(203, every=25)
+        ens.step(40)
+        ens.step(40)
+        ens.step(40)
+        s2 = ens.step(60, every=20)
+        res.append((s1, s2, [ens.get_state(r) for r in range(len(specs))]))
+        ens.close()
+    say("graphs vs direct, fusion", fusion)
+    for a, b in zip(res[0][0], res[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(res[0][1], res[1][1]):
+        np.testing.assert_array_equal(a, b)
+    for (ta, wa, ka), (tb, wb, kb) in zip(res[0][2], res[1][2]):
+        assert ka == kb
+        np.testing.assert_array_equal(ta, tb)
+        np.testing.assert_array_equal(wa, wb)
+
+
+def test_ensemble_autotune_picks_steps_per_pass_without_changing_results(xyl):
+    """xyl_ensemble_autotune times the tile launch shapes on scratch copies,
+    then the two-step classes against tile steps, and keeps the faster; the
+    ensemble's own state is untouched and its results do not change."""
+    specs = [workloads.LatticeSpec(1024, 512, schedule=((0, 0.6),), seed=9, replica=0, nsteps=10 ** 6),
+             workloads.LatticeSpec(256, 256, schedule=((0, 0.4),), seed=9, replica=1, nsteps=10 ** 6),
+             workloads.LatticeSpec(320, 40, schedule=((0, 0.6),), seed=9, replica=2, nsteps=10 ** 6),
+             workloads.LatticeSpec(64, 64, schedule=((0, 0.6),), seed=9, replica=3, nsteps=10 ** 6)]
+    res = []
+    for tune in (True, False):
+        ens = xyl.Ensemble(specs, dtype="f32")
+        ens.step(5)
+        if tune:
+            rows, wpb = ens.autotune()
+            say("ensemble autotune", rows, wpb, "steps per pass", ens.fusion())
+            assert ens.fusion() in (1, 2)
+        smp = ens.step(120, every=40)
+        res.append((smp, [ens.get_state(r) for r in range(len(specs))]))
+        ens.close()
+    for a, b in zip(res[0][0], res[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for (ta, wa, ka), (tb, wb, kb) in zip(res[0][1], res[1][1]):
+        assert ka == kb
+        np.testing.assert_array_equal(ta, tb)
+        np.testing.assert_array_equal(wa, wb)
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_ensemble_two_steps_per_pass_equal_batched_single_steps(xyl, mixed):
     """FP32 replicas on the tile path whose width the two-step pass takes, of
