@@ -2223,7 +2223,20 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                     e->drop_graphs();
                     e->graphs_built_for = e->graph_version;
                 }
+                // at most kMaxChunkGraphs chunk shapes hold a graph at a time
+                // (adaptive sampling can meet many)
+                constexpr size_t kMaxChunkGraphs = 32;
+                if (!e->graphs.count({c, n}) && e->graphs.size() >= 4 * kMaxChunkGraphs) e->drop_graphs();
                 cg = &e->graphs[{c, n}];
+                if (!cg->exec && cg->seen + 1 >= 2) {
+                    size_t held = 0;
+                    for (auto& g : e->graphs) held += g.second.exec != nullptr;
+                    if (held >= kMaxChunkGraphs) {
+                        e->drop_graphs();
+                        cg = &e->graphs[{c, n}];
+                        cg->seen = 1;
+                    }
+                }
                 if (!cg->exec && ++cg->seen >= 2) {
                     // everything that allocates or creates happens before the capture
                     if (!e->cap_stream)
