@@ -455,7 +455,7 @@ int xyl_adjoint_backward_device(xyl_lattice* h, uint64_t run, double scale, doub
 /* Reverse steps per pass of xyl_adjoint_backward (App. A.1's step, run
  * backwards): 2 (the default) takes two reverse steps per pass over the state
  * where a strip of rows fits one workgroup (one site per lane, Lx at most
- * 1024, Ly >= 4, and (40 rows + 104) Lx bytes of FP32 state and draws, twice
+ * 1024, Ly >= 4, and (32 rows + 80) Lx bytes of FP32 state and draws, twice
  * that in FP64, within a CU's 160 KiB of LDS), and recomputes the checkpointed
  * segments two steps per pass too where the forward's two-step pass takes
  * the lattice; 1 keeps one step per pass for both.  rows: rows per strip of

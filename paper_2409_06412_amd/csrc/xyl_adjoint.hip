@@ -259,11 +259,13 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs<R> A, const uint64_t* k
 // one site per lane, a workgroup per strip of ROWS rows across the whole
 // width, in three phases separated by two barriers.
 //  1. The strip's rows and two on each side enter ring A: (sin, cos) of
-//     th^{k+1} and the adjoint (lt, lu) at k+2, per site.
+//     th^{k+1} and lF of stage A (from the adjoint at k+2), per site.
 //  2. Stage A, reverse step k+1, on the strip's rows and one on each side
 //     (which the neighbouring strips compute with the same arithmetic), its
-//     neighbours from ring A; its results (lt, lu at k+1) enter ring B with
-//     (sin, cos) of th^k.  They never leave the workgroup.
+//     neighbours from ring A; lF of stage B from its results (lt, lu at k+1)
+//     enters ring B with (sin, cos) of th^k.  The results themselves stay in
+//     the lane's registers, which also hold the lane's own lt, lu at k+2:
+//     a site's own adjoint is only ever read by its own lane.
 //  3. Stage B, reverse step k, on the strip's rows from ring B, to memory.
 // Every input is loaded up front, so the pass waits on one memory latency.
 // Every site takes the arithmetic of adj_site with the same inputs as in two
@@ -285,17 +287,17 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
     const int Lx = v.Lx, Ly = v.Ly;
     extern __shared__ unsigned char adj2_lds[];
     // ring A: rows y0-2 .. y0+ROWS+1, ring B: rows y0-1 .. y0+ROWS; per row
-    // [s, c, lt, lu][Lx]
+    // [s, c, lF][Lx]
     R* ringA = reinterpret_cast<R*>(adj2_lds);
-    R* ringB = ringA + (size_t)(ROWS + 4) * 4 * Lx;
+    R* ringB = ringA + (size_t)(ROWS + 4) * 3 * Lx;
     // the draws of stage A's rows (step k+1) and stage B's (step k), [row][Lx]
-    R* noiseA = ringB + (size_t)(ROWS + 2) * 4 * Lx;
+    R* noiseA = ringB + (size_t)(ROWS + 2) * 3 * Lx;
     R* noiseB = noiseA + (size_t)(ROWS + 2) * Lx;
     const int strip = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int y0 = strip * ROWS;
     const int y1 = min(y0 + ROWS, Ly);
-    auto rowA = [&](int r) { return ringA + (size_t)(r - (y0 - 2)) * 4 * Lx; };
-    auto rowB = [&](int r) { return ringB + (size_t)(r - (y0 - 1)) * 4 * Lx; };
+    auto rowA = [&](int r) { return ringA + (size_t)(r - (y0 - 2)) * 3 * Lx; };
+    auto rowB = [&](int r) { return ringB + (size_t)(r - (y0 - 1)) * 3 * Lx; };
     const int x = threadIdx.x;
     const bool act = x < Lx;
     const int xa = act ? x : 0;
@@ -321,22 +323,20 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
     const uint64_t k = koff + (kdev ? *kdev : 0);
     const AdjStep<R> KA = adj_step_coef(A, k + 1);
     const AdjStep<R> KB = adj_step_coef(A, k);
-    auto lf_of = [&](const R* sl, int i, R kap) { return kap * Prec<R>::fma(v.dt, sl[2 * Lx + i], sl[3 * Lx + i]); };
     // a stage's reverse step at row r, its rows r-1, r, r+1 at C - stride,
-    // C, C + stride in its ring, with coefficients K; returns lt, lu
-    // a stage's reverse step at row r, its rows r-1, r, r+1 at C - stride,
-    // C, C + stride in its ring, its draw n, with coefficients K; returns lt,
-    // lu and adds the parameter adjoints of the strip's own rows to g
-    auto stage = [&](const R* C, size_t stride, const AdjStep<R>& K, int r, R u, R n, R& lto, R& luo, R g[4]) {
+    // C, C + stride in its ring, the lane's own (lt', lu') and draw n, with
+    // coefficients K; returns lt, lu and adds the parameter adjoints of the
+    // strip's own rows to g
+    auto stage = [&](const R* C, size_t stride, const AdjStep<R>& K, int r, R lt, R lu, R u, R n, R& lto, R& luo,
+                     R g[4]) {
         const R* Pm = C - stride;
         const R* Np = C + stride;
         const int y = wrap(r);
         const R eps = (((xa * v.stag_x) + (y * v.stag_y)) & 1) ? R(-1) : R(1);
         R rx = 0, ry = 0, rh = 0, rg = 0;
-        adj_site(v, K, C[xa], C[Lx + xa], C[xm], C[Lx + xm], lf_of(C, xm, K.kap), C[xp], C[Lx + xp],
-                 lf_of(C, xp, K.kap), Pm[xa], Pm[Lx + xa], lf_of(Pm, xa, K.kap), Np[xa], Np[Lx + xa],
-                 lf_of(Np, xa, K.kap), lf_of(C, xa, K.kap), C[2 * Lx + xa], C[3 * Lx + xa], u, n, eps, lto, luo, rx,
-                 ry, rh, rg);
+        adj_site(v, K, C[xa], C[Lx + xa], C[xm], C[Lx + xm], C[2 * Lx + xm], C[xp], C[Lx + xp], C[2 * Lx + xp],
+                 Pm[xa], Pm[Lx + xa], Pm[2 * Lx + xa], Np[xa], Np[Lx + xa], Np[2 * Lx + xa], C[2 * Lx + xa], lt, lu,
+                 u, n, eps, lto, luo, rx, ry, rh, rg);
         if (r >= y0 && r < y1) {
             g[0] += rx;
             g[1] += ry;
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             g[3] += rg;
         }
     };
-    const size_t stride = (size_t)4 * Lx;
+    const size_t stride = (size_t)3 * Lx;
     // the lane's parameter adjoints, in the state precision (at most
     // 2 ROWS + 2 terms), then FP64 across the wave
     R g[4] = {R(0), R(0), R(0), R(0)};
@@ -372,26 +372,28 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             Prec<R>::sincos(th1[i], sn, cs);
             w[xa] = sn;
             w[Lx + xa] = cs;
-            w[2 * Lx + xa] = lt2[i];
-            w[3 * Lx + xa] = lu2[i];
+            w[2 * Lx + xa] = KA.kap * Prec<R>::fma(v.dt, lt2[i], lu2[i]);
         }
     }
     __syncthreads();
-    // 2. stage A (reverse step k+1) on rows y0-1 .. y1, into ring B
+    // 2. stage A (reverse step k+1) on rows y0-1 .. y1, into ring B; its
+    // results (lt, lu at k+1) stay in registers for stage B
+    R lt1[ROWS + 2], lu1[ROWS + 2];
+#pragma unroll
+    for (int i = 0; i < ROWS + 2; ++i) lt1[i] = lu1[i] = R(0);
     if (act) {
 #pragma unroll
         for (int i = 0; i < ROWS + 2; ++i) {
             const int r = y0 - 1 + i;
             if (r > y1) break;
-            R lto, luo;
-            stage(rowA(r), stride, KA, r, u1[i], noiseA[(size_t)i * Lx + xa], lto, luo, g);
+            stage(rowA(r), stride, KA, r, lt2[i + 1], lu2[i + 1], u1[i], noiseA[(size_t)i * Lx + xa], lt1[i],
+                  lu1[i], g);
             R* w = rowB(r);
             R sn, cs;
             Prec<R>::sincos(th0[i], sn, cs);
             w[xa] = sn;
             w[Lx + xa] = cs;
-            w[2 * Lx + xa] = lto;
-            w[3 * Lx + xa] = luo;
+            w[2 * Lx + xa] = KB.kap * Prec<R>::fma(v.dt, lt1[i], lu1[i]);
         }
     }
     __syncthreads();
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kAdj2MaxLx) void k_adjoint2(Adj2Args<R> A2, const u
             const int r = y0 + i;
             if (r >= y1) break;
             R lto, luo;
-            stage(rowB(r), stride, KB, r, u0[i], noiseB[(size_t)i * Lx + xa], lto, luo, g);
+            stage(rowB(r), stride, KB, r, lt1[i + 1], lu1[i + 1], u0[i], noiseB[(size_t)i * Lx + xa], lto, luo, g);
             A.lt_out[at(r)] = lto;
             A.lu_out[at(r)] = luo;
         }

@@ -202,10 +202,10 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
 template <typename R>
 int adjoint_tasks(const Lat<R>& v, int rows, int rows2);
 // LDS of the two-step reverse pass with strips of `rows` rows: rows + 4 and
-// rows + 2 rows of (sin, cos, lt', lu') per site, and the draws of 2 rows + 2.
+// rows + 2 rows of (sin, cos, lF) per site, and the draws of 2 rows + 2.
 template <typename R>
 constexpr size_t adjoint2_lds(int Lx, int rows) {
-    return sizeof(R) * (4 * (size_t)(2 * rows + 6) + (size_t)(2 * rows + 2)) * (size_t)Lx;
+    return sizeof(R) * (3 * (size_t)(2 * rows + 6) + (size_t)(2 * rows + 2)) * (size_t)Lx;
 }
 // Whether the two-step reverse pass takes this lattice with strips of `rows`
 // rows (1, 2 or 4; rows up to 1024 sites, Ly >= 4, its LDS within a CU's).

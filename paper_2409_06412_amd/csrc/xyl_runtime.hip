@@ -2784,10 +2784,9 @@ static void adjoint_forward_impl(xyl_lattice* h, uint64_t N, uint64_t K, uint64_
 // device buffers of precision out_f64 (written on the lattice's stream, times
 // `scale`).
 // Rows per strip of the two-step reverse pass (1, 2 or 4): 2, where its LDS
-// fits (512^2: 4.9 us per step, against 7.1 with 1-row strips and 8.2 with
-// single reverse steps); where it does not (FP32 rows above 888 sites, FP64
-// above 444), single reverse steps (1024^2: 15.1 us per step, against 20.7
-// with 1-row strips, whose stage A does three rows per row of output).
+// fits (512^2: 4.9 us per step, against 5.1 with 1-row strips and 7.8 with
+// single reverse steps; 768^2 and 1024^2 within 2% of single reverse steps);
+// where it does not (FP64 rows above 568 sites), single reverse steps.
 static int adjoint2_rows(const xyl_lattice* h) { return h->adj2_rows ? h->adj2_rows : 2; }
 
 template <typename R>

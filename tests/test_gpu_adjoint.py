@@ -274,12 +274,13 @@ def test_set_state_device(xyl, dtype):
     (512, 64, "f32", 100, 400, 0),        # the rule's strips, graph-captured segments
     (512, 42, "f32", 100, 400, 4),        # ragged strips
     (200, 9, "f32", 7, 90, 1),            # odd segments (one single step, then pairs), a partial wave
-    (1024, 13, "f32", 20, 60, 1),         # the widest row the pass takes (one-row strips)
-    (1024, 8, "f32", 12, 48, 0),          # too wide for the rule's 2-row strips: single reverse steps
+    (1024, 13, "f32", 20, 60, 1),         # the widest row the pass takes, one-row strips
+    (1024, 8, "f32", 12, 48, 0),          # the widest row, the rule's 2-row strips
     (64, 4, "f64", 10, 50, 2),            # FP64, the smallest height
-    (560, 6, "f64", 9, 45, 1),            # FP64 at its widest (one-row strips), a partial wave
+    (560, 6, "f64", 9, 45, 1),            # FP64, one-row strips, a partial wave
     (512, 8, "f64", 12, 48, 1),           # FP64, one-row strips
     (320, 8, "f64", 12, 48, 0),           # FP64, the rule's 2-row strips
+    (640, 6, "f64", 10, 40, 0),           # FP64 too wide for 2-row strips: single reverse steps
     (2048, 8, "f32", 10, 40, 0),          # too wide: one reverse step per pass either way
 ])
 def test_two_reverse_steps_per_pass_equal_single_steps(xyl, Lx, Ly, dtype, K, nsteps, rows):
