@@ -60,6 +60,10 @@ struct Lat {
     uint64_t fresh_k;      // step at which u holds w^k itself
     uint64_t k_end;        // steps while k < k_end; may be measured at k_end
     double* part;          // measurement partials [Ly][nxw][kNPart] (+ stage-1 room)
+    // phases of the structure-factor modes: sin and cos of 2 pi m / Lx at
+    // [2m], [2m + 1] (m < Lx), and of 2 pi m / Ly (m < Ly)
+    const double* xph;
+    const double* yph;
     R* omega_out;          // destination of w^k (omega mode)
     int32_t pingpong;      // 1: th[(k+cur)&1] -> th[(k+cur+1)&1]; 0: th[0] -> th[1]
     R* u_out;              // velocities written here instead of in place (or NULL)
@@ -178,6 +182,8 @@ void launch_init_random(const Lat<R>& v, hipStream_t s);
 template <typename R>
 void launch_noise(const Lat<R>& v, uint64_t k, double* out, hipStream_t s);
 void launch_finalize_obs(const double* part, int nrowparts, double N, double* out, hipStream_t s);
+// sin and cos of 2 pi m / L into t[2m], t[2m + 1] for m < L
+void launch_phase_table(double* t, int L, hipStream_t s);
 // count measurements whose partials lie stride apart: out[6 j ...] for j < count
 void launch_finalize_many(const double* part, int nrowparts, uint64_t stride, double N, double* out, int count,
                           hipStream_t s);

@@ -107,6 +107,32 @@ struct DevBuf {
     ~DevBuf() { release(); }
 };
 
+// Page-locked host memory (hipHostMalloc): device-to-host copies of samples
+// land here directly instead of through the runtime's staging of pageable
+// memory, then go to the caller's array with a plain memcpy.
+template <typename T>
+struct PinnedBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    void reserve(size_t count) {
+        if (count <= n && p) return;
+        release();
+        check_alloc(hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(T) * std::max<size_t>(count, 1),
+                                  hipHostMallocDefault),
+                    "hipHostMalloc");
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~PinnedBuf() { release(); }
+};
+
 // ------------------------------------------------------------ parameters
 struct Params {
     double Jx = 1.0, Jy = -0.1, h = 0.5, gamma = 1.0, dt = 0.01;
@@ -295,6 +321,7 @@ struct xyl_lattice {
     DevBuf<uint64_t> kdev;
     DevBuf<double> part;
     DevBuf<double> obs;
+    PinnedBuf<double> obs_host;   // host landing place of the samples' copy
     DevBuf<double> dscratch;
     DevBuf<char> omega_buf;
     DevBuf<int32_t> parent;
@@ -302,6 +329,7 @@ struct xyl_lattice {
     DevBuf<uint32_t> hist;
     DevBuf<uint32_t> stats;
     DevBuf<uint32_t> flag;        // validation result of xyl_set_state_device
+    DevBuf<double> phases;        // measurement phases: the x table (2 Lx), then the y table (2 Ly)
     // adjoint state (see xyl_adjoint.hip)
     void* adj = nullptr;
 
@@ -317,6 +345,8 @@ struct xyl_lattice {
         v.fresh_k = fresh_k;
         v.k_end = ~(uint64_t)0;
         v.part = part.p;
+        v.xph = phases.p;
+        v.yph = phases.p + 2 * (size_t)Lx;
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
         v.pingpong = 1;
         v.u_out = nullptr;
@@ -782,6 +812,10 @@ static int create_impl(xyl_lattice** out, int32_t Lx, int32_t Ly, int32_t dtype,
         check_hip(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
         h->kdev.reserve(1);
         h->part.reserve(part_elems(h->nrowparts()));
+        h->phases.reserve(2 * ((size_t)Lx + Ly));
+        launch_phase_table(h->phases.p, Lx, nullptr);
+        launch_phase_table(h->phases.p + 2 * (size_t)Lx, Ly, nullptr);
+        check_hip(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
         h->obs.reserve(16 * 6);
         h->launch = default_launch(Lx, Ly);
         {
@@ -1083,6 +1117,7 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
         require(cap >= ns, XYL_EINVAL, "sample capacity too small");
         DeviceGuard g(h->device);
         h->obs.reserve(6 * ns);
+        h->obs_host.reserve(6 * ns);
         for (uint64_t j = 0; j < ns; ++j) {
             double* o = h->obs.p + 6 * j;
             if (j * every == nsteps) {
@@ -1096,8 +1131,10 @@ int xyl_step_measured(xyl_lattice* h, uint64_t nsteps, uint64_t every, xyl_obs* 
                 else lattice_sample_and_advance<float>(h, span, o);
             }
         }
-        check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6 * ns, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipMemcpyAsync(h->obs_host.p, h->obs.p, sizeof(double) * 6 * ns, hipMemcpyDeviceToHost, h->stream),
+                  "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        std::memcpy(out, h->obs_host.p, sizeof(double) * 6 * ns);
         if (nout) *nout = ns;
         require_finite(reinterpret_cast<const double*>(out), 6 * ns, "observables");
     });
@@ -1174,10 +1211,12 @@ int xyl_measure(xyl_lattice* h, xyl_obs* out) {
         require(out != nullptr, XYL_EINVAL, "out is NULL");
         DeviceGuard g(h->device);
         h->obs.reserve(6);
+        h->obs_host.reserve(6);
         if (h->dtype == XYL_F64) lattice_measure_into<double>(h, false, h->obs.p);
         else lattice_measure_into<float>(h, false, h->obs.p);
-        check_hip(hipMemcpyAsync(out, h->obs.p, sizeof(double) * 6, hipMemcpyDeviceToHost, h->stream), "D2H");
+        check_hip(hipMemcpyAsync(h->obs_host.p, h->obs.p, sizeof(double) * 6, hipMemcpyDeviceToHost, h->stream), "D2H");
         check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        std::memcpy(out, h->obs_host.p, sizeof(double) * 6);
         require_finite(reinterpret_cast<const double*>(out), 6, "observables");
     });
 }
@@ -1762,6 +1801,8 @@ struct xyl_ensemble {
     int ntasks = 0;
     std::vector<int> task_active;   // replica ids the task list was built for
     DevBuf<double> part;
+    DevBuf<double> phases;                  // measurement phase tables, one per side length
+    std::map<int, size_t> phase_off;        // side length -> offset of its table in phases
     DevBuf<double> obs;
     DevBuf<FinalizeJobHost> jobs;
     DevBuf<double> dscratch;
@@ -1859,6 +1900,8 @@ struct xyl_ensemble {
         v.fresh_k = fresh_k[r];
         v.k_end = d.nsteps;
         v.part = part.p + poff[r];
+        v.xph = phases.p + phase_off.at(d.Lx);
+        v.yph = phases.p + phase_off.at(d.Ly);
         v.omega_out = reinterpret_cast<R*>(omega_buf.p);
         v.pingpong = 1;
         v.u_out = nullptr;
@@ -2495,6 +2538,15 @@ int xyl_ensemble_create(xyl_ensemble** out, const xyl_replica_desc* desc, int32_
         for (int b = 0; b < 2; ++b) check_alloc(hipMalloc(&e->th[b], bytes), "hipMalloc theta");
         check_alloc(hipMalloc(&e->u, bytes), "hipMalloc velocity");
         e->part.reserve(e->ptotal);
+        {
+            size_t nph = 0;
+            for (int r = 0; r < n; ++r)
+                for (int L : {desc[r].Lx, desc[r].Ly})
+                    if (e->phase_off.emplace(L, nph).second) nph += 2 * (size_t)L;
+            e->phases.reserve(nph);
+            for (const auto& t : e->phase_off) launch_phase_table(e->phases.p + t.second, t.first, nullptr);
+            check_hip(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+        }
         e->lds.assign(n, 0);
         for (int r = 0; r < n; ++r) {
             const int N = desc[r].Lx * desc[r].Ly;

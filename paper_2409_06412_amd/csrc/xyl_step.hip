@@ -65,11 +65,17 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
     const uint32_t xmb = (uint32_t)xm * (uint32_t)sizeof(R), xpb = (uint32_t)xp * (uint32_t)sizeof(R);
     // measurement: the phases e^{-2 pi i x / Lx} of the lane's four columns
-    // (FP64; the same on every row, so evaluated once per strip)
+    // (FP64, from the lattice's table; the same on every row, so read once
+    // per strip)
     double pxs[4], pxc[4];
     if constexpr ((MODE & kMeasure) != 0) {
+        const double2* ph = reinterpret_cast<const double2*>(v.xph) + x;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sincospi(2.0 * (double)(x + q) / (double)Lx, &pxs[q], &pxc[q]);
+        for (int q = 0; q < 4; ++q) {
+            const double2 e = act ? ph[q] : make_double2(0.0, 0.0);
+            pxs[q] = e.x;
+            pxc[q] = e.y;
+        }
     }
 
     auto load_theta = [&](RowSet<R>& S, int y) {
@@ -140,9 +146,14 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             // per lane: energy terms, the order parameter's two components
             // and their x modes; the y modes are the row's phase times the
             // row's totals of the two components
+            // (value 1 is the sum of w^2: the finalize halves it, which is
+            // exact, so the sums equal those of the halved terms bit for bit)
             double acc[8];
 #pragma unroll
             for (int p = 0; p < 8; ++p) acc[p] = 0.0;
+            // staggered sign: x is a multiple of 4, so site (x + q, y) has the
+            // parity of q stag_x + y stag_y (the stag flags are 0 or 1)
+            const bool odd_row = (y & v.stag_y & 1) != 0;
             if (act) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -152,11 +163,11 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                     const double syp = (double)N.s[q], cyp = (double)N.c[q];
                     acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) -
                               v.hd * onsite_cos<R, M>(v, C.th[q], s, c);
-                    acc[1] += 0.5 * (double)w[q] * (double)w[q];
-                    const int xs = x + q;
-                    const double e = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
+                    acc[1] += (double)w[q] * (double)w[q];
+                    const bool neg = ((q & 1) && v.stag_x) != odd_row;
                     // order-parameter component first: cos th (XY), sin 2th (SI)
-                    const double ec = e * (M == kModelSI ? s : c), es = e * (M == kModelSI ? c : s);
+                    const double a = M == kModelSI ? s : c, b = M == kModelSI ? c : s;
+                    const double ec = neg ? -a : a, es = neg ? -b : b;
                     acc[2] += ec;
                     acc[3] += es;
                     acc[4] += ec * pxc[q];
@@ -171,13 +182,12 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             double* dst = base + ((size_t)y * v.nxw + xw) * kNPart;
             if ((lane & 7) == 0) dst[lane >> 3] = tot;
             if (lane == 16 || lane == 24) {
-                // y modes of the row: e^{-2 pi i y / Ly} times the totals of
-                // the components (values 2 and 3)
-                double rps, rpc;
-                sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
+                // y modes of the row: e^{-2 pi i y / Ly} (the lattice's table)
+                // times the totals of the components (values 2 and 3)
+                const double2 e = reinterpret_cast<const double2*>(v.yph)[y];
                 const int o = lane == 16 ? 8 : 10;
-                dst[o] = tot * rpc;
-                dst[o + 1] = -(tot * rps);
+                dst[o] = tot * e.y;
+                dst[o + 1] = -(tot * e.x);
             }
         }
     };
@@ -811,8 +821,9 @@ __device__ __forceinline__ void lds_replica(const Lat<float>& v, const LdsJob& j
                 forces(g, th[q], n, f, s4, c4, sR, cR, sd, cd);
                 const int i0 = 4 * g;
                 const int y = i0 / Lx, x = i0 - y * Lx;
-                double rps, rpc;
-                sincospi(2.0 * (double)y / (double)Ly, &rps, &rpc);
+                const double2 ry = reinterpret_cast<const double2*>(v.yph)[y];
+                const double rps = ry.x, rpc = ry.y;
+                const bool odd_row = (y & v.stag_y & 1) != 0;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float w, un, tn;
@@ -822,14 +833,16 @@ __device__ __forceinline__ void lds_replica(const Lat<float>& v, const LdsJob& j
                     const double cxp = (double)(e == 3 ? cR : c4[e + 1]);
                     acc[0] += v.Jxd * (cv * cxp + sv * sxp) + v.Jyd * (cv * (double)cd[e] + sv * (double)sd[e]) -
                               v.hd * onsite_cos<float, M>(v, th[q][e], sv, cv);
-                    acc[1] += 0.5 * (double)w * (double)w;
+                    acc[1] += (double)w * (double)w;   // halved below
                     const int xs = x + e;
-                    const double ep = (((xs * v.stag_x) + (y * v.stag_y)) & 1) ? -1.0 : 1.0;
-                    const double ec = ep * (M == kModelSI ? sv : cv), es = ep * (M == kModelSI ? cv : sv);
+                    // staggered sign (x is a multiple of 4, the stag flags 0 or 1)
+                    const bool neg = ((e & 1) && v.stag_x) != odd_row;
+                    const double a = M == kModelSI ? sv : cv, b = M == kModelSI ? cv : sv;
+                    const double ec = neg ? -a : a, es = neg ? -b : b;
                     acc[2] += ec;
                     acc[3] += es;
-                    double pxs, pxc;
-                    sincospi(2.0 * (double)xs / (double)Lx, &pxs, &pxc);
+                    const double2 px = reinterpret_cast<const double2*>(v.xph)[xs];
+                    const double pxs = px.x, pxc = px.y;
                     acc[4] += ec * pxc;
                     acc[5] -= ec * pxs;
                     acc[6] += es * pxc;
@@ -856,7 +869,7 @@ __device__ __forceinline__ void lds_replica(const Lat<float>& v, const LdsJob& j
             }
             const double Nd = (double)N;
             job.obs[0] = P[0] / Nd;
-            job.obs[1] = P[1] / Nd;
+            job.obs[1] = (0.5 * P[1]) / Nd;
             job.obs[2] = P[2] / Nd;
             job.obs[3] = (P[2] * P[2] + P[3] * P[3]) / Nd;
             job.obs[4] = (P[4] * P[4] + P[5] * P[5] + P[6] * P[6] + P[7] * P[7]) / Nd;
@@ -1041,7 +1054,7 @@ __device__ void finalize_block(const double* part, int nrp, double N, double* ou
     if (threadIdx.x == 0) {
         const double* P = red[0];
         out[0] = P[0] / N;
-        out[1] = P[1] / N;
+        out[1] = (0.5 * P[1]) / N;   // value 1 is the sum of w^2
         out[2] = P[2] / N;
         out[3] = (P[2] * P[2] + P[3] * P[3]) / N;
         out[4] = (P[4] * P[4] + P[5] * P[5] + P[6] * P[6] + P[7] * P[7]) / N;
@@ -1087,6 +1100,19 @@ void launch_finalize_obs(const double* part, int nrowparts, double N, double* ou
         k_finalize_obs<<<1, 256, 0, s>>>(part, nrowparts, N, out);
     }
     check_hip(hipGetLastError(), "finalize kernel launch");
+}
+
+// The phases of the lowest Fourier mode of one axis (App. C): sin and cos of
+// 2 pi m / L, evaluated once per lattice shape instead of in every
+// measurement.
+__global__ __launch_bounds__(256) void k_phase_table(double* t, int L) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < L) sincospi(2.0 * (double)m / (double)L, &t[2 * m], &t[2 * m + 1]);
+}
+
+void launch_phase_table(double* t, int L, hipStream_t s) {
+    k_phase_table<<<(unsigned)((L + 255) / 256), 256, 0, s>>>(t, L);
+    check_hip(hipGetLastError(), "phase table launch");
 }
 
 __global__ __launch_bounds__(256) void k_finalize_many(const double* part, int nrp, uint64_t stride, double N,
