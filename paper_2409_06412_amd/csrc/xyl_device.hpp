@@ -378,34 +378,74 @@ __device__ __forceinline__ double from_lane_above(double v, double old = 0.0) {
     return __hiloint2double(hi, lo);
 }
 
+// A double moved between lanes by DPP (CTRL: the DPP control word; every
+// source lane of the patterns used here is inside the wave).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowRor8 = 0x128;       // within rows of 16 lanes: lane i <- lane i ^ 8
+constexpr int kDppRowHalfMirror = 0x141; // within groups of 8 lanes: lane i <- lane 7 - i
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+
+// The gfx950 lane-half swaps on a pair of doubles.  swap32: the upper 32
+// lanes of x trade places with the lower 32 lanes of y.  swap16: the odd rows
+// of 16 lanes of x (lanes 16-31, 48-63) with the even rows of y (0-15, 32-47).
+// So with x, y = values j and j' of every lane, a lane in the lower half
+// (even row) ends with its own and its partner's value j in (x, y), a lane in
+// the upper half (odd row) with its partner's and its own value j'.
+__device__ __forceinline__ void swap32_f64(double& x, double& y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                     false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16_f64(double& x, double& y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false,
+                                                     false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 // Sums of eight FP64 values over the 64 lanes of a wave, in a fixed pattern:
 // a reduce-scatter in which every exchange halves the values a lane carries
 // (lanes with bit 5 set keep values 4..7 and send 0..3 to their partner, and
-// so on for bits 4 and 3), then a butterfly over the last three bits.  Ten
-// exchanges instead of the 48 of eight separate butterflies.  Lane L returns
-// the total of value L >> 3; the eight lanes of a group return the same bits.
+// so on for bits 4 and 3), then a butterfly over the last three bits.  The
+// exchanges at bits 5 and 4 are lane-half swaps (no selects, no LDS), those
+// at bit 3 and below DPP.  Lane L returns the total of value L >> 3; the
+// eight lanes of a group return the same bits (each step adds the same two
+// numbers on both lanes of a pair).  All 64 lanes must be active.
 __device__ __forceinline__ double wave_sum8(const double a[8], int lane) {
-    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+    const bool b3 = (lane & 8) != 0;
     double k4[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const double keep = b5 ? a[j + 4] : a[j], send = b5 ? a[j] : a[j + 4];
-        k4[j] = keep + __shfl_xor(send, 32, kWave);
+        double x = a[j], y = a[j + 4];
+        swap32_f64(x, y);
+        k4[j] = x + y;
     }
     double k2[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const double keep = b4 ? k4[j + 2] : k4[j], send = b4 ? k4[j] : k4[j + 2];
-        k2[j] = keep + __shfl_xor(send, 16, kWave);
+        double x = k4[j], y = k4[j + 2];
+        swap16_f64(x, y);
+        k2[j] = x + y;
     }
     double k1;
     {
         const double keep = b3 ? k2[1] : k2[0], send = b3 ? k2[0] : k2[1];
-        k1 = keep + __shfl_xor(send, 8, kWave);
+        k1 = keep + dpp_f64<kDppRowRor8>(send);
     }
-    k1 += __shfl_xor(k1, 4, kWave);
-    k1 += __shfl_xor(k1, 2, kWave);
-    k1 += __shfl_xor(k1, 1, kWave);
+    k1 += dpp_f64<kDppRowHalfMirror>(k1);
+    k1 += dpp_f64<kDppQuadXor2>(k1);
+    k1 += dpp_f64<kDppQuadXor1>(k1);
     return k1;
 }
 
