@@ -388,13 +388,17 @@ int xyl_ensemble_step(xyl_ensemble* e, uint64_t nsteps, uint64_t every, xyl_obs*
  * batched mode is measured against).  Default 0. */
 int xyl_ensemble_set_mode(xyl_ensemble* e, int32_t mode);
 /* Graph-captured chunks in the batched mode (App. B: many subsystems run
- * together; 1, the default, or 0): the
- * stepping of a chunk between samples (its two-step passes on their class
- * streams and its single tile-table steps) is captured as a graph the second
- * time a chunk of the same shape (first step, length) is met, and replayed
- * with the step index from a device counter after that; chunks of fewer than
- * 8 launches stay direct.  Graphs are dropped when the task tables, the launch
- * shape or the steps per pass change.  Results are bitwise the same. */
+ * together).  The stepping of a chunk between samples (its two-step passes on
+ * their class streams and its single tile-table steps) is captured as a graph
+ * the second time a chunk of the same shape (first step, length) is met, and
+ * replayed with the step index from a device counter after that; chunks of
+ * fewer than 8 launches stay direct.  enable = 0: no graphs; 1 (the default):
+ * graphs for chunks with at most one class of two-step passes (a replay
+ * dispatches the parallel branches of several classes one after the other,
+ * while direct launches, issued pass by pass across the classes, let them run
+ * together); 2: graphs for every repeated chunk.  Graphs are dropped when the
+ * task tables, the launch shape or the steps per pass change.  Results are
+ * bitwise the same in every mode. */
 int xyl_ensemble_set_graphs(xyl_ensemble* e, int32_t enable);
 /* Steps per pass for the batched mode (1 or 2; default 2).  With 2 (FP32),
  * runs of 4m steps between samples advance the replicas on the tile path

@@ -600,10 +600,11 @@ class Ensemble:
         _check(load().xyl_ensemble_get_fusion(self._h, ctypes.byref(sp)))
         return sp.value
 
-    def set_graphs(self, enable: bool):
-        """Capture repeated chunks of batched stepping as graphs (default on);
-        results are identical."""
-        _check(load().xyl_ensemble_set_graphs(self._h, int(bool(enable))))
+    def set_graphs(self, enable):
+        """Capture repeated chunks of batched stepping as graphs: 0 (or False)
+        never, 1 (or True, the default) for chunks with at most one class of
+        two-step passes, 2 for every repeated chunk; results are identical."""
+        _check(load().xyl_ensemble_set_graphs(self._h, int(enable)))
 
     def autotune(self):
         _check(load().xyl_ensemble_autotune(self._h))

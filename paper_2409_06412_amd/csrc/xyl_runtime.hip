@@ -1850,7 +1850,13 @@ struct xyl_ensemble {
     // kc): keyed by (first step within the chunk, steps), captured the second
     // time a key is met and replayed after; all dropped when a table, the
     // launch shape or the steps per pass change (graph_version).
-    bool use_graphs = true;
+    // 0: no graphs; 1: graphs for chunks with at most one class of two-step
+    // passes; 2: graphs for every repeated chunk.  A replayed graph dispatches
+    // the parallel branches of several classes one after the other (one
+    // class's whole chain before the next class's first pass), so the classes
+    // barely overlap; issued directly, pass by pass across the classes, they
+    // run together.
+    int use_graphs = 1;
     hipStream_t cap_stream = nullptr;
     DevBuf<uint64_t> kc;
     uint64_t graph_version = 0, graphs_built_for = ~(uint64_t)0;
@@ -2231,15 +2237,19 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                                 check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
                                           "hipStreamWaitEvent");
                         }
-                        for (size_t c2 = 0; c2 < ncls; ++c2) {
-                            const auto& cl = e->s2cls[c2];
-                            hipStream_t st = c2 == 0 ? main : e->cls_streams[c2 - 1];
-                            for (uint64_t i = 0; i < n4; i += 4)
-                                for (int ph = 0; ph < 2; ++ph)
+                        // pass by pass across the classes: issued class by class, a
+                        // class's first pass would wait for every pass of the
+                        // classes before it to be issued (in a replayed graph,
+                        // dispatched), and the classes would hardly overlap
+                        for (uint64_t i = 0; i < n4; i += 4)
+                            for (int ph = 0; ph < 2; ++ph)
+                                for (size_t c2 = 0; c2 < ncls; ++c2) {
+                                    const auto& cl = e->s2cls[c2];
+                                    hipStream_t st = c2 == 0 ? main : e->cls_streams[c2 - 1];
                                     launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial,
                                                           cl.max_lx, e->model(), ph, ub, u2b, kdev,
                                                           jb + cc + i + 2 * ph, st);
-                        }
+                                }
                         for (size_t c2 = 1; c2 < ncls; ++c2) {
                             check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
                             check_hip(hipStreamWaitEvent(main, e->cls_events[c2], 0), "hipStreamWaitEvent");
@@ -2261,7 +2271,12 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
             if constexpr (std::is_same<R, float>::value)
                 if (!e->s2cls.empty()) nl = n / 4 * 2 * e->s2cls.size() + n % 4 + (e->ntasks_rest ? n / 4 * 4 : 0);
             xyl_ensemble::ChunkGraph* cg = nullptr;
-            if (e->use_graphs && nl >= 8) {
+            bool graphs = e->use_graphs == 2;
+            if constexpr (std::is_same<R, float>::value)
+                graphs = graphs || (e->use_graphs == 1 && e->s2cls.size() <= 1);
+            else
+                graphs = graphs || e->use_graphs == 1;
+            if (graphs && nl >= 8) {
                 if (e->graphs_built_for != e->graph_version) {
                     e->drop_graphs();
                     e->graphs_built_for = e->graph_version;
@@ -2608,8 +2623,8 @@ int xyl_ensemble_set_stream(xyl_ensemble* e, void* stream) {
 int xyl_ensemble_set_graphs(xyl_ensemble* e, int32_t enable) {
     return guarded([&] {
         require(e != nullptr, XYL_EINVAL, "NULL handle");
-        require(enable == 0 || enable == 1, XYL_EINVAL, "enable must be 0 or 1");
-        e->use_graphs = enable != 0;
+        require(enable >= 0 && enable <= 2, XYL_EINVAL, "enable must be 0, 1 or 2");
+        e->use_graphs = enable;
     });
 }
 

@@ -234,7 +234,9 @@ def test_ensemble_graph_captured_chunks_equal_direct_launches(xyl, fusion):
              workloads.LatticeSpec(320, 40, schedule=((0, 0.6),), seed=8, replica=3, nsteps=10 ** 6),
              workloads.LatticeSpec(64, 64, schedule=((0, 0.6),), seed=8, replica=4, nsteps=10 ** 6)]
     res = []
-    for graphs in (True, False):
+    # 2: every repeated chunk as a graph, so the classes' parallel branches are
+    # captured too (the default captures only chunks with at most one class)
+    for graphs in (2, 0):
         ens = xyl.Ensemble(specs, dtype="f32")
         ens.set_fusion(fusion)
         ens.set_graphs(graphs)
