@@ -147,6 +147,9 @@ def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
         if mode == 0:
             ens.autotune()
         ens.step(3)
+        if mode == 0:
+            # the timed path once (its first chunks set up what they use)
+            ens.step(every, every=every)
         ens.sync()
         t0 = time.perf_counter()
         ens.step(nsteps, every=every)

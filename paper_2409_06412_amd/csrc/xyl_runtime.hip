@@ -1993,6 +1993,12 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
                                      e->stream),
                       "H2D");
     }
+    // the second velocity buffer and the class streams now, not in the first
+    // chunk that steps through the classes
+    if (!e->s2cls.empty()) {
+        e->u2.reserve(sizeof(float) * e->total);
+        e->class_streams(e->s2cls.size());
+    }
     // the host vectors must outlive the copies
     check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     e->task_active = active;
