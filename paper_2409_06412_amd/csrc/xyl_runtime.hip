@@ -2436,9 +2436,9 @@ static Launch ensemble_autotune_impl(xyl_ensemble* e) {
             }
         }
     }
-    // Steps per pass (FP32): the two-step classes' passes (one class after
-    // the other here) plus the tile steps of the replicas outside them,
-    // against the best tile launch for every step, over the same steps.
+    // Steps per pass (FP32): the two-step classes' passes plus the tile steps
+    // of the replicas outside them, against the best tile launch for every
+    // step, over the same steps.
     if constexpr (std::is_same<R, float>::value) {
         std::vector<int> active;
         for (int r : reps)
@@ -2476,20 +2476,54 @@ static Launch ensemble_autotune_impl(xyl_ensemble* e) {
                 (void)hipGraphExecDestroy(ex);
                 return t / (float)nsteps;
             };
-            const float t2 = time_graph(
-                [&] {
-                    for (int i = 0; i < steps4; i += 4)
-                        for (int ph = 0; ph < 2; ++ph)
-                            for (const auto& cl : e->s2cls)
-                                launch_ensemble_step2(dreps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
-                                                      e->model(), ph, ub, u2b, kc.p, (uint64_t)(i + 2 * ph), cap);
-                    if (e->ntasks_rest)
-                        for (int i = 0; i < steps4; ++i)
-                            launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), e->tasks_rest.p,
-                                                    e->ntasks_rest, kStore, e->model(), best.rows, best.wpb, kc.p,
-                                                    (uint64_t)i, cap);
-                },
-                steps4);
+            // the classes' passes as the stepping issues them: on their own
+            // streams, pass by pass across the classes, where a chunk with
+            // several classes runs direct; one after the other in a graph
+            // otherwise
+            const size_t ncls = e->s2cls.size();
+            auto classes = [&](hipStream_t main, bool fork) {
+                if (fork) {
+                    e->class_streams(ncls);
+                    check_hip(hipEventRecord(e->cls_events[0], main), "hipEventRecord");
+                    for (size_t c2 = 1; c2 < ncls; ++c2)
+                        check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
+                                  "hipStreamWaitEvent");
+                }
+                for (int i = 0; i < steps4; i += 4)
+                    for (int ph = 0; ph < 2; ++ph)
+                        for (size_t c2 = 0; c2 < ncls; ++c2) {
+                            const auto& cl = e->s2cls[c2];
+                            launch_ensemble_step2(dreps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
+                                                  e->model(), ph, ub, u2b, kc.p, (uint64_t)(i + 2 * ph),
+                                                  fork && c2 > 0 ? e->cls_streams[c2 - 1] : main);
+                        }
+                if (fork)
+                    for (size_t c2 = 1; c2 < ncls; ++c2) {
+                        check_hip(hipEventRecord(e->cls_events[c2], e->cls_streams[c2 - 1]), "hipEventRecord");
+                        check_hip(hipStreamWaitEvent(main, e->cls_events[c2], 0), "hipStreamWaitEvent");
+                    }
+                if (e->ntasks_rest)
+                    for (int i = 0; i < steps4; ++i)
+                        launch_ensemble_step<R>(reinterpret_cast<const Lat<R>*>(dtab.p), e->tasks_rest.p,
+                                                e->ntasks_rest, kStore, e->model(), best.rows, best.wpb, kc.p,
+                                                (uint64_t)i, main);
+            };
+            const bool direct = e->use_graphs == 0 || (ncls > 1 && e->use_graphs == 1);
+            float t2 = 1e30f;
+            if (direct) {
+                classes(e->stream, ncls > 1);
+                for (int rep = 0; rep < 2; ++rep) {
+                    check_hip(hipEventRecord(e0, e->stream), "hipEventRecord");
+                    classes(e->stream, ncls > 1);
+                    check_hip(hipEventRecord(e1, e->stream), "hipEventRecord");
+                    check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                    float ms = 0.f;
+                    check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                    t2 = std::min(t2, ms / (float)steps4);
+                }
+            } else {
+                t2 = time_graph([&] { classes(cap, false); }, steps4);
+            }
             const float t1 = time_graph(
                 [&] {
                     for (int i = 0; i < steps4; ++i)

@@ -235,8 +235,9 @@ def test_ensemble_graph_captured_chunks_equal_direct_launches(xyl, fusion):
              workloads.LatticeSpec(64, 64, schedule=((0, 0.6),), seed=8, replica=4, nsteps=10 ** 6)]
     res = []
     # 2: every repeated chunk as a graph, so the classes' parallel branches are
-    # captured too (the default captures only chunks with at most one class)
-    for graphs in (2, 0):
+    # captured too; 1 (the default): only chunks with at most one class (all of
+    # them with fusion 1); 0: every launch direct
+    for graphs in (2, 1, 0):
         ens = xyl.Ensemble(specs, dtype="f32")
         ens.set_fusion(fusion)
         ens.set_graphs(graphs)
@@ -246,16 +247,20 @@ def test_ensemble_graph_captured_chunks_equal_direct_launches(xyl, fusion):
         ens.step(40)
         s2 = ens.step(60, every=20)
         res.append((s1, s2, [ens.get_state(r) for r in range(len(specs))]))
+        if graphs == 0:
+            with pytest.raises(xyl.XylError):
+                ens.set_graphs(3)
         ens.close()
-    say("graphs vs direct, fusion", fusion)
-    for a, b in zip(res[0][0], res[1][0]):
-        np.testing.assert_array_equal(a, b)
-    for a, b in zip(res[0][1], res[1][1]):
-        np.testing.assert_array_equal(a, b)
-    for (ta, wa, ka), (tb, wb, kb) in zip(res[0][2], res[1][2]):
-        assert ka == kb
-        np.testing.assert_array_equal(ta, tb)
-        np.testing.assert_array_equal(wa, wb)
+    say("graph modes 2 and 1 vs direct, fusion", fusion)
+    for other in res[:2]:
+        for a, b in zip(other[0], res[2][0]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(other[1], res[2][1]):
+            np.testing.assert_array_equal(a, b)
+        for (ta, wa, ka), (tb, wb, kb) in zip(other[2], res[2][2]):
+            assert ka == kb
+            np.testing.assert_array_equal(ta, tb)
+            np.testing.assert_array_equal(wa, wb)
 
 
 def test_ensemble_autotune_picks_steps_per_pass_without_changing_results(xyl):
