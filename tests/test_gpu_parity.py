@@ -234,6 +234,35 @@ def test_measured_samples_match_oracle(xyl):
     lat.close()
 
 
+@pytest.mark.parametrize("Jx,Jy", [(1.0, 0.1), (1.0, -0.1), (-1.0, 0.1), (-1.0, -0.1)])
+def test_staggered_observables_every_sign_set(xyl, Jx, Jy):
+    """The order parameter's staggering eps_i = (-1)^(x [Jx > 0] + y [Jy > 0])
+    for every sign set of the couplings, on the strip kernel (a single lattice
+    with an odd-sized last wave) and on the whole-in-LDS ensemble kernel: the
+    FP64 samples against the oracle's (rtol 1e-10).  An odd Ly along a
+    staggered axis is allowed (frustrated), so it is used here too."""
+    Lx, Ly = 68, 37
+    kw = dict(Jx=Jx, Jy=Jy, h=0.5, gamma=1.0, dt=0.01, schedule=[(0, 0.6)], seed=21, replica=3)
+    lat, o = make_pair(xyl, Lx, Ly, "f64", **kw)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    s = lat.step_measured(60, 20)
+    _, _, so = o.run(th0, om0, 0, 60, every=20)
+    np.testing.assert_allclose(s, so, rtol=1e-10, atol=1e-13)
+    lat.close()
+    # whole-in-LDS (FP32 replicas of at most 128 x 128 sites): the samples of
+    # the GPU's own states against the oracle's observables of those states
+    spec = workloads.LatticeSpec(Lx, Ly, Jx=Jx, Jy=Jy, h=0.5, gamma=1.0, dt=0.01, schedule=((0, 0.6),), seed=21,
+                                 replica=3, nsteps=10 ** 6)
+    ens = xyl.Ensemble([spec], dtype="f32")
+    s0 = ens.step(8, every=8)[0]
+    th, om, k = ens.get_state(0)
+    assert k == 8
+    r = o.observables(th, om)
+    np.testing.assert_allclose(s0[-1], r, rtol=2e-5, atol=2e-6)
+    ens.close()
+
+
 def test_measure_fp32_matches_oracle_on_same_state(xyl):
     Lx, Ly = 1024, 24
     lat, o = make_pair(xyl, Lx, Ly, "f32", schedule=[(0, 0.7)], seed=13)
