@@ -7,13 +7,16 @@
   whole-in-LDS;
 * the 60-replica 2048^2 quench batch (three ramp times, two dampings, two
   fields, five seeds), autotuned and stepped 100 steps without samples, one
-  batched two-step pass per two steps.
+  batched two-step pass per two steps;
+* the 4096^2 lattice at its eight temperatures, batched as bench.py runs it
+  (one class of 16-wave rows), sampled every 50 steps.
 
-Chosen replicas (one per side length, and the two extreme quench parameter
-sets) are compared with the FP64 oracle run from the replica's own start: the
-angles at every site after 100 steps (XY: 1e-4, the single-lattice full-size
-bar) and, for the sampled ensemble, the observables of both samples with the
-bars of the single-lattice full-size test."""
+Chosen replicas (one per side length, the two extreme quench parameter sets,
+the coldest and the hottest 4096^2 replica) are compared with the FP64 oracle
+run from the replica's own start: the angles at every site after 100 steps
+(XY: 1e-4, the single-lattice full-size bar) and, for the sampled runs, the
+observables of the samples with the bars of the single-lattice full-size
+test."""
 import sys
 
 import numpy as np
@@ -96,3 +99,20 @@ def test_quench_batch_full_size_matches_oracle(xyl):
         ens.close()
     for r in picks:
         check_replica(specs[r], start[r], end[r], nsteps, tag="quench replica %d" % r)
+
+
+def test_eight_temperatures_full_size_matches_oracle(xyl):
+    specs = [workloads.large_fp32(j) for j in range(8)]
+    nsteps, every = 100, 50
+    ens = xyl.Ensemble(specs, dtype="f32")
+    try:
+        launch = ens.autotune()
+        say("4096^2 x 8 temperatures: launch", launch, "steps per pass", ens.fusion())
+        picks = [0, len(specs) - 1]
+        start = {r: ens.get_state(r) for r in picks}
+        samples = ens.step(nsteps, every=every)
+        end = {r: ens.get_state(r) for r in picks}
+    finally:
+        ens.close()
+    for r in picks:
+        check_replica(specs[r], start[r], end[r], nsteps, samples[r], every, "4096^2 replica %d" % r)
