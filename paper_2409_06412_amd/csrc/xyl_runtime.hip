@@ -1,6 +1,17 @@
-// Host runtime behind the C-ABI of include/xyl.h: parameter validation,
-// device buffers, streams, captured step graphs, the launch-shape autotuner,
-// the batched ensemble and the host-side estimators.
+// Host runtime behind the C-ABI of include/xyl.h.  Its sections, in order:
+//   * devices, buffers (device memory and pinned host memory), parameters and
+//     their validation, the launch rules;
+//   * the lattice: creation (with its measurement phase tables), stepping
+//     through captured graphs and two-step passes, sampled runs, observables,
+//     correlation, structure factor, domains (and the allocation-free call),
+//     the autotuner;
+//   * the ensemble: replica tables, two-step classes on their own streams
+//     (issued pass by pass), whole-in-LDS replicas on a side stream, chunk
+//     graphs, samples through a finalize-job arena, its autotuner;
+//   * the adjoint: the checkpointed forward run and the reverse sweep with
+//     its recompute on a side stream.
+// The host-only estimators (Binder cumulant, errors, fits) are in
+// xyl_host.cpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
