@@ -464,24 +464,103 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
     }
 }
 
-__global__ void k_uf_init(int32_t* parent, uint32_t* size, size_t N) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
-        parent[i] = (int32_t)i;
-        size[i] = 0u;
+// The same find and union on a workgroup's LDS labels.
+__device__ __forceinline__ int32_t uf_lds_load(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t uf_lds_find(const int32_t* lab, int32_t a) {
+    int32_t p = uf_lds_load(lab + a);
+    while (p != a) {
+        a = p;
+        p = uf_lds_load(lab + a);
+    }
+    return a;
+}
+__device__ __forceinline__ void uf_lds_union(int32_t* lab, int32_t a, int32_t b) {
+    while (true) {
+        a = uf_lds_find(lab, a);
+        b = uf_lds_find(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicMin(lab + a, b);
+        if (old == a) return;
+        a = old;
     }
 }
 
+// Labelling in two levels.  First every kUfTile x kUfTile tile is labelled in
+// LDS with the bonds that lie inside it: a tile's sites in row-major order are
+// in the lattice's index order, so the smallest local index of a piece is also
+// its smallest lattice index, and parent[i] = that index keeps parent[i] <= i.
+// Then only the bonds across a tile's right and bottom edges (the periodic
+// wrap among them) are united in global memory, a few percent of all bonds
+// (every bond on the global atomics before).
+constexpr int kUfTile = 32;
+
 template <typename R>
-__global__ void k_uf_merge(const R* __restrict__ th, int Lx, int Ly, int sx, int sy, int model, int32_t* parent) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)Lx * Ly) return;
-    const int x = (int)(i % Lx), y = (int)(i / Lx);
-    const int s = spin_of(th, Lx, x, y, sx, sy, model);
-    const int xp = x + 1 == Lx ? 0 : x + 1;
-    const int yp = y + 1 == Ly ? 0 : y + 1;
-    if (spin_of(th, Lx, xp, y, sx, sy, model) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)y * Lx + xp));
-    if (spin_of(th, Lx, x, yp, sx, sy, model) == s) uf_union(parent, (int32_t)i, (int32_t)((size_t)yp * Lx + x));
+__global__ __launch_bounds__(256) void k_uf_local(const R* __restrict__ th, int Lx, int Ly, int sx, int sy,
+                                                  int model, int ntx, int32_t* parent, uint32_t* size) {
+    __shared__ int32_t lab[kUfTile * kUfTile];
+    __shared__ int8_t spin[kUfTile * kUfTile];
+    const int tx = (int)(blockIdx.x % (unsigned)ntx), ty = (int)(blockIdx.x / (unsigned)ntx);
+    const int x0 = tx * kUfTile, y0 = ty * kUfTile;
+    const int w = min(kUfTile, Lx - x0), h = min(kUfTile, Ly - y0);
+    for (int l = threadIdx.x; l < kUfTile * kUfTile; l += blockDim.x) {
+        const int ly = l / kUfTile, lx = l % kUfTile;
+        lab[l] = l;
+        spin[l] = (lx < w && ly < h) ? (int8_t)spin_of(th, Lx, x0 + lx, y0 + ly, sx, sy, model) : (int8_t)0;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < kUfTile * kUfTile; l += blockDim.x) {
+        const int ly = l / kUfTile, lx = l % kUfTile;
+        if (lx >= w || ly >= h) continue;
+        const int8_t s = spin[l];
+        if (lx + 1 < w && spin[l + 1] == s) uf_lds_union(lab, l, l + 1);
+        if (ly + 1 < h && spin[l + kUfTile] == s) uf_lds_union(lab, l, l + kUfTile);
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < kUfTile * kUfTile; l += blockDim.x) {
+        const int ly = l / kUfTile, lx = l % kUfTile;
+        if (lx >= w || ly >= h) continue;
+        const int32_t r = uf_lds_find(lab, l);
+        const size_t gi = (size_t)(y0 + ly) * Lx + (size_t)(x0 + lx);
+        parent[gi] = (int32_t)((size_t)(y0 + r / kUfTile) * Lx + (size_t)(x0 + r % kUfTile));
+        size[gi] = 0u;
+    }
+}
+
+// Bonds across tile edges: thread t < ntx Ly takes the right edge of tile
+// column t / Ly in row t % Ly (the last column's bond wraps to x = 0); the
+// next nty Lx threads take the bottom edges of the tile rows (the last row's
+// bond wraps to y = 0).
+template <typename R>
+__global__ void k_uf_boundary(const R* __restrict__ th, int Lx, int Ly, int sx, int sy, int model, int ntx, int nty,
+                              int32_t* parent) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nr = (size_t)ntx * Ly;
+    int x, y, xn, yn;
+    if (t < nr) {
+        const int tx = (int)(t / (size_t)Ly);
+        y = (int)(t % (size_t)Ly);
+        x = min((tx + 1) * kUfTile, Lx) - 1;
+        xn = x + 1 == Lx ? 0 : x + 1;
+        yn = y;
+    } else if (t < nr + (size_t)nty * Lx) {
+        const size_t u = t - nr;
+        const int ty = (int)(u / (size_t)Lx);
+        x = (int)(u % (size_t)Lx);
+        y = min((ty + 1) * kUfTile, Ly) - 1;
+        xn = x;
+        yn = y + 1 == Ly ? 0 : y + 1;
+    } else {
+        return;
+    }
+    if (spin_of(th, Lx, x, y, sx, sy, model) == spin_of(th, Lx, xn, yn, sx, sy, model))
+        uf_union(parent, (int32_t)((size_t)y * Lx + x), (int32_t)((size_t)yn * Lx + xn));
 }
 
 // Adds, for every lane with `valid`, one to base[key]: lanes of the wave with
@@ -563,10 +642,12 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
                     uint32_t* stats, hipStream_t s) {
     const size_t N = (size_t)Lx * Ly;
     const unsigned nb = (unsigned)((N + 255) / 256);
-    k_uf_init<<<nb, 256, 0, s>>>(parent, size, N);
-    check_hip(hipGetLastError(), "uf init launch");
-    k_uf_merge<R><<<nb, 256, 0, s>>>(th, Lx, Ly, sx, sy, model, parent);
-    check_hip(hipGetLastError(), "uf merge launch");
+    const int ntx = (Lx + kUfTile - 1) / kUfTile, nty = (Ly + kUfTile - 1) / kUfTile;
+    k_uf_local<R><<<(unsigned)((size_t)ntx * nty), 256, 0, s>>>(th, Lx, Ly, sx, sy, model, ntx, parent, size);
+    check_hip(hipGetLastError(), "uf local labelling launch");
+    const size_t nbond = (size_t)ntx * Ly + (size_t)nty * Lx;
+    k_uf_boundary<R><<<(unsigned)((nbond + 255) / 256), 256, 0, s>>>(th, Lx, Ly, sx, sy, model, ntx, nty, parent);
+    check_hip(hipGetLastError(), "uf boundary merge launch");
     k_uf_flatten<<<nb, 256, 0, s>>>(parent, size, N);
     check_hip(hipGetLastError(), "uf flatten launch");
     k_uf_finish<<<(unsigned)std::min<size_t>(nb, 1024), 256, 0, s>>>(parent, size, hist, N);
