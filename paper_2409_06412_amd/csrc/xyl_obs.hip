@@ -563,35 +563,66 @@ __global__ void k_uf_boundary(const R* __restrict__ th, int Lx, int Ly, int sx, 
         uf_union(parent, (int32_t)((size_t)y * Lx + x), (int32_t)((size_t)yn * Lx + xn));
 }
 
-// Adds, for every lane with `valid`, one to base[key]: lanes of the wave with
-// equal keys are counted together and their first lane adds their number, so
-// a domain spanning the wave costs one atomic, not 64 on one address.  Every
-// lane of the wave must take part (the loop runs on wave-wide ballots).
-__device__ __forceinline__ void add_grouped(uint32_t* base, uint32_t key, bool valid) {
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    uint64_t active = __ballot(valid);
-    while (active) {
-        const int leader = __ffsll((unsigned long long)active) - 1;
-        const uint32_t lk = (uint32_t)__shfl((int)key, leader);
-        const uint64_t same = __ballot(valid && key == lk) & active;
-        if (lane == leader) atomicAdd(base + lk, (uint32_t)__popcll(same));
-        active &= ~same;
+// Labels and sizes per tile, after the edge merge.  Only roots had their
+// parent changed by the merge, so a site's parent is its tile-local root or,
+// for a local root, itself or the root it was hooked under.  In LDS each site
+// points at its parent where that lies in the tile (an index no larger than
+// its own); a chain ends at a root of the whole lattice or at a site whose
+// parent lies outside the tile, which takes one find in global memory.  Every
+// site's label is its chain end's, and each chain end adds its count of
+// sites to its root's size once.  Concurrent finds from other tiles see a
+// site's old parent or its root, both ancestors, so they still end at the
+// root.
+template <int TILE>
+__global__ __launch_bounds__(256) void k_uf_flatten_tiles(int32_t* parent, uint32_t* size, int Lx, int Ly, int ntx) {
+    __shared__ int32_t nxt[TILE * TILE];
+    __shared__ int32_t fin[TILE * TILE];
+    __shared__ uint32_t cnt[TILE * TILE];
+    const int tx = (int)(blockIdx.x % (unsigned)ntx), ty = (int)(blockIdx.x / (unsigned)ntx);
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int w = min(TILE, Lx - x0), h = min(TILE, Ly - y0);
+    for (int l = threadIdx.x; l < TILE * TILE; l += blockDim.x) {
+        const int ly = l / TILE, lx = l % TILE;
+        cnt[l] = 0u;
+        nxt[l] = l;
+        if (lx >= w || ly >= h) continue;
+        const size_t gi = (size_t)(y0 + ly) * Lx + (size_t)(x0 + lx);
+        const int32_t p = uf_load(parent + gi);
+        const int py = (int)((size_t)p / (size_t)Lx), px = (int)((size_t)p % (size_t)Lx);
+        if ((size_t)p == gi) {
+            fin[l] = p;                                        // a root of the lattice
+        } else if (py >= y0 && py < y0 + h && px >= x0 && px < x0 + w) {
+            nxt[l] = (py - y0) * TILE + (px - x0);             // in the tile: at most l
+        } else {
+            nxt[l] = -1;                                       // leaves the tile
+            fin[l] = uf_find(parent, p);
+        }
     }
-}
-
-// Once the merges are done: every site's root (its label) replaces its parent,
-// and each root's cluster size is counted.  Concurrent finds see either a
-// site's old parent or its root, both ancestors, so every find still ends at
-// the root.
-__global__ void k_uf_flatten(int32_t* parent, uint32_t* size, size_t N) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < N;
-    int32_t r = 0;
-    if (valid) {
-        r = uf_find(parent, (int32_t)i);
-        __hip_atomic_store(parent + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // the chain ends of the thread's sites (nxt is not written in this phase)
+    constexpr int kPer = TILE * TILE / 256;
+    int ends[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int l = (int)threadIdx.x + 256 * k;
+        const int ly = l / TILE, lx = l % TILE;
+        ends[k] = -1;
+        if (lx >= w || ly >= h) continue;
+        int e = l;
+        while (nxt[e] >= 0 && nxt[e] != e) e = nxt[e];
+        atomicAdd(&cnt[e], 1u);
+        ends[k] = e;
     }
-    add_grouped(size, (uint32_t)r, valid);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int l = (int)threadIdx.x + 256 * k;
+        if (ends[k] < 0) continue;
+        const int ly = l / TILE, lx = l % TILE;
+        const size_t gi = (size_t)(y0 + ly) * Lx + (size_t)(x0 + lx);
+        __hip_atomic_store(parent + gi, fin[ends[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cnt[l]) atomicAdd(size + fin[l], cnt[l]);
+    }
 }
 
 // After the flatten pass every parent is a root: histogram the cluster sizes
@@ -648,7 +679,7 @@ void launch_domains(const R* th, int Lx, int Ly, int sx, int sy, int model, int3
     const size_t nbond = (size_t)ntx * Ly + (size_t)nty * Lx;
     k_uf_boundary<R><<<(unsigned)((nbond + 255) / 256), 256, 0, s>>>(th, Lx, Ly, sx, sy, model, ntx, nty, parent);
     check_hip(hipGetLastError(), "uf boundary merge launch");
-    k_uf_flatten<<<nb, 256, 0, s>>>(parent, size, N);
+    k_uf_flatten_tiles<kUfTile><<<(unsigned)((size_t)ntx * nty), 256, 0, s>>>(parent, size, Lx, Ly, ntx);
     check_hip(hipGetLastError(), "uf flatten launch");
     k_uf_finish<<<(unsigned)std::min<size_t>(nb, 1024), 256, 0, s>>>(parent, size, hist, N);
     check_hip(hipGetLastError(), "uf finish launch");
