@@ -573,8 +573,11 @@ __global__ void k_uf_boundary(const R* __restrict__ th, int Lx, int Ly, int sx, 
 // sites to its root's size once.  Concurrent finds from other tiles see a
 // site's old parent or its root, both ancestors, so they still end at the
 // root.
+// Launched with 256 threads per tile (each thread keeps the chain ends of its
+// TILE^2 / 256 sites in registers).
 template <int TILE>
 __global__ __launch_bounds__(256) void k_uf_flatten_tiles(int32_t* parent, uint32_t* size, int Lx, int Ly, int ntx) {
+    static_assert(TILE * TILE % 256 == 0, "whole sites per thread");
     __shared__ int32_t nxt[TILE * TILE];
     __shared__ int32_t fin[TILE * TILE];
     __shared__ uint32_t cnt[TILE * TILE];
