@@ -18,7 +18,6 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
-#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1816,6 +1815,7 @@ struct xyl_ensemble {
     std::map<int, size_t> phase_off;        // side length -> offset of its table in phases
     DevBuf<double> obs;
     DevBuf<FinalizeJobHost> jobs;
+    PinnedBuf<FinalizeJobHost> jobs_host;   // the source of each flush's copy into `jobs`
     DevBuf<double> dscratch;
     DevBuf<char> omega_buf;
     DevBuf<int32_t> parent;
@@ -1830,8 +1830,11 @@ struct xyl_ensemble {
     // the end of the last launch that read table b (and of the copies into it)
     DevBuf<char> lds_reps[2];
     DevBuf<LdsJobHost> lds_jobs[2];
-    std::vector<LdsJobHost> lds_jobs_host[2];
-    std::vector<Lat<float>> lds_tab_host[2];
+    // host sides of those tables in pinned memory: an asynchronous copy from
+    // pageable memory waits for its stream to drain, which left the GPU idle
+    // at every chunk boundary while the host waited
+    PinnedBuf<LdsJobHost> lds_jobs_host[2];
+    PinnedBuf<Lat<float>> lds_tab_host[2];
     hipEvent_t ev_lds[2] = {nullptr, nullptr};
     bool ev_lds_used[2] = {false, false};
     int lds_buf = 0;
@@ -2025,9 +2028,8 @@ struct EnsSamples {
     std::vector<uint64_t> cnt;
     size_t nsamp = 0;
     std::vector<std::pair<size_t, size_t>> copies;   // (device slot, host index)
-    // finalize jobs of this call: each flush's list stays here (the source of
-    // its asynchronous copy) and takes the next slots of the device arena
-    std::deque<std::vector<FinalizeJobHost>> job_store;
+    // finalize jobs of this call: each flush takes the next slots of the
+    // device arena, copied from the same slots of its pinned host mirror
     size_t njobs = 0;
     EnsSamples(xyl_ensemble* e_, uint64_t every_, uint64_t cap_, const uint64_t* nout)
         : e(e_), every(every_), cap(cap_), cnt(e_->n, 0) {
@@ -2036,9 +2038,10 @@ struct EnsSamples {
     }
     EnsSamples(const EnsSamples&) = delete;
     EnsSamples& operator=(const EnsSamples&) = delete;
-    // the job lists are the sources of copies that may still be queued
+    // the pinned job slots are the sources of copies that may still be
+    // queued; the next call writes them again
     ~EnsSamples() {
-        if (!job_store.empty()) (void)hipStreamSynchronize(e->stream);
+        if (njobs) (void)hipStreamSynchronize(e->stream);
     }
     bool wants(int r) const {
         return every && e->k[r] <= e->desc[r].nsteps && e->k[r] % every == 0 && e->last_sample[r] != e->k[r] + 1;
@@ -2085,18 +2088,20 @@ struct EnsSamples {
 // replaced, after the stream has drained, by one twice as large).
 static void flush_finalize(xyl_ensemble* e, EnsSamples& smp, std::vector<FinalizeJobHost>& jobs) {
     if (jobs.empty()) return;
-    if (smp.njobs + jobs.size() > e->jobs.n || !e->jobs.p) {
+    if (smp.njobs + jobs.size() > e->jobs.n || !e->jobs.p || e->jobs_host.n < e->jobs.n) {
         check_hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-        e->jobs.reserve(std::max<size_t>(2 * e->jobs.n, std::max<size_t>(jobs.size(), 256)));
+        const size_t cap = std::max<size_t>(2 * e->jobs.n, std::max<size_t>(jobs.size(), 256));
+        e->jobs.reserve(cap);
+        e->jobs_host.reserve(e->jobs.n);
         smp.njobs = 0;
     }
-    smp.job_store.push_back(std::move(jobs));
-    const std::vector<FinalizeJobHost>& js = smp.job_store.back();
+    FinalizeJobHost* src = e->jobs_host.p + smp.njobs;
+    std::memcpy(src, jobs.data(), sizeof(FinalizeJobHost) * jobs.size());
     FinalizeJobHost* dst = e->jobs.p + smp.njobs;
-    check_hip(hipMemcpyAsync(dst, js.data(), sizeof(FinalizeJobHost) * js.size(), hipMemcpyHostToDevice, e->stream),
+    check_hip(hipMemcpyAsync(dst, src, sizeof(FinalizeJobHost) * jobs.size(), hipMemcpyHostToDevice, e->stream),
               "H2D");
-    launch_finalize_jobs(dst, (int)js.size(), e->stream);
-    smp.njobs += js.size();
+    launch_finalize_jobs(dst, (int)jobs.size(), e->stream);
+    smp.njobs += jobs.size();
     jobs.clear();
 }
 
@@ -2182,8 +2187,8 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
             e->lds_buf ^= 1;
             // table b was last read by the launch two chunks ago
             if (e->ev_lds_used[b]) check_hip(hipEventSynchronize(e->ev_lds[b]), "hipEventSynchronize");
-            std::vector<LdsJobHost>& jh = e->lds_jobs_host[b];
-            jh.clear();
+            std::vector<LdsJobHost> jh;
+            jh.reserve(lds_set.size());
             int nfact = 0;
             for (int pass = 0; pass < 2; ++pass)
                 for (int r : lds_set) {
@@ -2194,16 +2199,18 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                     jh.push_back(LdsJobHost{r, meas[r] ? 1 : 0, act[r] ? (int32_t)chunk : 0, 0,
                                             meas[r] ? smp.take(r) : nullptr});
                 }
+            // (pinned table b's last copy went with that launch, so it is free)
             e->lds_jobs[b].reserve(jh.size());
-            check_hip(hipMemcpyAsync(e->lds_jobs[b].p, jh.data(), sizeof(LdsJobHost) * jh.size(), hipMemcpyHostToDevice,
-                                     e->side),
+            e->lds_jobs_host[b].reserve(jh.size());
+            std::memcpy(e->lds_jobs_host[b].p, jh.data(), sizeof(LdsJobHost) * jh.size());
+            check_hip(hipMemcpyAsync(e->lds_jobs[b].p, e->lds_jobs_host[b].p, sizeof(LdsJobHost) * jh.size(),
+                                     hipMemcpyHostToDevice, e->side),
                       "H2D");
-            std::vector<Lat<float>>& tab = e->lds_tab_host[b];
-            tab.resize(e->n);
+            e->lds_tab_host[b].reserve(e->n);
+            Lat<float>* tab = e->lds_tab_host[b].p;
             for (int r = 0; r < e->n; ++r) tab[r] = e->view<float>(r, e->j);
             e->lds_reps[b].reserve(sizeof(Lat<float>) * e->n);
-            check_hip(hipMemcpyAsync(e->lds_reps[b].p, tab.data(), sizeof(Lat<float>) * e->n, hipMemcpyHostToDevice,
-                                     e->side),
+            check_hip(hipMemcpyAsync(e->lds_reps[b].p, tab, sizeof(Lat<float>) * e->n, hipMemcpyHostToDevice, e->side),
                       "H2D");
             const Lat<float>* lreps = reinterpret_cast<const Lat<float>*>(e->lds_reps[b].p);
             if (nfact)
