@@ -1976,9 +1976,11 @@ static void ens_upload_table(xyl_ensemble* e, uint64_t jbase, const std::vector<
             cl.waves = w;
             // strips as tall as keep at least two waves per SIMD busy (2 to 32
             // rows; 32 for the 60 x 2048^2 quench batch: 5.83 -> 5.98e11
-            // site-updates/s against 16)
+            // site-updates/s against 16, 5.86e11 with 64).  Rows of more than
+            // 8 waves hold one workgroup per CU and go to 64 (eight 4096^2
+            // replicas: 6.05 -> 6.19e11)
             cl.rows = 2;
-            for (int rows = 32; rows >= 2; rows /= 2) {
+            for (int rows = w > 8 ? 64 : 32; rows >= 2; rows /= 2) {
                 long strips = 0;
                 for (int r : byw[w]) strips += (e->desc[r].Ly + rows - 1) / rows;
                 if (strips * w >= 8L * e->cus) {
