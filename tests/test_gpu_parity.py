@@ -263,6 +263,22 @@ def test_staggered_observables_every_sign_set(xyl, Jx, Jy):
     ens.close()
 
 
+def test_measured_samples_of_many_partial_rows_match_oracle(xyl):
+    """A lattice with more than 4096 (row, wave) partials (256 x 4100: one wave
+    per row) takes the measurement's two-stage finalize in one launch (the last
+    workgroup reduces the stage-1 rows); its FP64 samples against the
+    oracle's, several in a row so the launch's counter is reused."""
+    Lx, Ly = 256, 4100
+    lat, o = make_pair(xyl, Lx, Ly, "f64", schedule=[(0, 0.7)], seed=14)
+    lat.init_random()
+    th0, om0, _ = lat.get_state()
+    s = lat.step_measured(30, 10)
+    _, _, so = o.run(th0, om0, 0, 30, every=10)
+    assert s.shape == so.shape == (4, 6)
+    np.testing.assert_allclose(s, so, rtol=1e-10, atol=1e-13)
+    lat.close()
+
+
 def test_measure_fp32_matches_oracle_on_same_state(xyl):
     Lx, Ly = 1024, 24
     lat, o = make_pair(xyl, Lx, Ly, "f32", schedule=[(0, 0.7)], seed=13)
