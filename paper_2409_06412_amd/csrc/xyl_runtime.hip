@@ -1890,7 +1890,8 @@ struct xyl_ensemble {
             check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
             cls_streams.push_back(st);
         }
-        while (cls_events.size() < ncls) {
+        // [0] fork, [1 + i] join of class i + 1, [ncls] end of a chunk's sample
+        while (cls_events.size() < ncls + 1) {
             hipEvent_t ev = nullptr;
             check_hip(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
             cls_events.push_back(ev);
@@ -2230,6 +2231,7 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
             const Lat<R>* reps = reinterpret_cast<const Lat<R>*>(e->reps.p);
             uint64_t c = 0;
             bool stepped = false;
+            bool preforked = false;   // the later classes' first pass already issued (below)
             if (!meas_g.empty()) {
                 // FP32 with two-step classes: the sample is a measurement
                 // without a step, and the whole chunk runs in pairs of passes;
@@ -2237,8 +2239,32 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                 bool passes = false;
                 if constexpr (std::is_same<R, float>::value) passes = !e->s2cls.empty() && chunk >= 4;
                 stepped = !passes;
+                if constexpr (std::is_same<R, float>::value) {
+                    // several classes issued directly: the classes after the
+                    // first start their first pass beside the measurement (it
+                    // reads the sampled state and writes the other buffers);
+                    // their second pass, which overwrites that state, waits
+                    // for the measurement's end
+                    const size_t ncls = e->s2cls.size();
+                    if (passes && ncls > 1 && e->use_graphs != 2) {
+                        e->class_streams(ncls);
+                        const float* ub = static_cast<const float*>(e->u);
+                        float* u2b = reinterpret_cast<float*>(e->u2.p);
+                        check_hip(hipEventRecord(e->cls_events[0], e->stream), "hipEventRecord");
+                        for (size_t c2 = 1; c2 < ncls; ++c2) {
+                            const auto& cl = e->s2cls[c2];
+                            check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
+                                      "hipStreamWaitEvent");
+                            launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial, cl.max_lx,
+                                                  e->model(), 0, ub, u2b, nullptr, e->j, e->cls_streams[c2 - 1]);
+                        }
+                        preforked = true;
+                    }
+                }
                 launch_ensemble_step<R>(reps, e->tasks.p, e->ntasks, passes ? kMeasure : (kStore | kMeasure),
                                         e->model(), e->launch.rows, e->launch.wpb, nullptr, e->j, e->stream);
+                if (preforked)
+                    check_hip(hipEventRecord(e->cls_events[e->s2cls.size()], e->stream), "hipEventRecord");
                 for (int r : meas_g)
                     jobs.push_back(FinalizeJobHost{e->part.p + e->poff[r], e->nrp(r),
                                                    (double)e->desc[r].Lx * (double)e->desc[r].Ly, smp.take(r)});
@@ -2257,7 +2283,11 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                         float* u2b = reinterpret_cast<float*>(e->u2.p);
                         const size_t ncls = e->s2cls.size();
                         e->class_streams(ncls);
-                        if (ncls > 1) {
+                        // with `preforked` (a direct chunk of several classes,
+                        // from its start), the later classes are forked and their
+                        // first pass issued; their second waits for the sample
+                        const bool pre = preforked && cc == 0 && kdev == nullptr;
+                        if (ncls > 1 && !pre) {
                             check_hip(hipEventRecord(e->cls_events[0], main), "hipEventRecord");
                             for (size_t c2 = 1; c2 < ncls; ++c2)
                                 check_hip(hipStreamWaitEvent(e->cls_streams[c2 - 1], e->cls_events[0], 0),
@@ -2272,6 +2302,11 @@ static void ens_step_batched(xyl_ensemble* e, uint64_t nsteps, EnsSamples& smp) 
                                 for (size_t c2 = 0; c2 < ncls; ++c2) {
                                     const auto& cl = e->s2cls[c2];
                                     hipStream_t st = c2 == 0 ? main : e->cls_streams[c2 - 1];
+                                    if (pre && c2 > 0 && i == 0) {
+                                        if (ph == 0) continue;   // issued before the sample
+                                        check_hip(hipStreamWaitEvent(st, e->cls_events[ncls], 0),
+                                                  "hipStreamWaitEvent");
+                                    }
                                     launch_ensemble_step2(reps, cl.tasks.p, cl.ntasks, cl.waves, cl.partial,
                                                           cl.max_lx, e->model(), ph, ub, u2b, kdev,
                                                           jb + cc + i + 2 * ph, st);
