@@ -146,10 +146,10 @@ def bench_ensemble(torch, xyl, workloads, nsteps, every=100):
         ens.set_mode(mode)
         if mode == 0:
             ens.autotune()
-        ens.step(3)
-        if mode == 0:
-            # the timed path once (its first chunks set up what they use)
-            ens.step(every, every=every)
+        # the timed path once, from step 0 as the configuration runs (its
+        # first chunks set up what they use); the timed call then starts on a
+        # sample step, as every later stretch of the run does
+        ens.step(every, every=every)
         ens.sync()
         t0 = time.perf_counter()
         ens.step(nsteps, every=every)
@@ -386,7 +386,9 @@ def bench_si_fss(torch, xyl, workloads, nsteps=200, every=100):
     specs = workloads.si_fss_ensemble(nsteps=10 ** 9)
     ens = xyl.Ensemble(specs, dtype="f32", stream=torch.cuda.current_stream().cuda_stream)
     launch = ens.autotune()
-    ens.step(3)
+    # warm-up on the timed path from step 0, so the timed call starts on a
+    # sample step as the configuration's run does
+    ens.step(every, every=every)
     ens.sync()
     t0 = time.perf_counter()
     ens.step(nsteps, every=every)
