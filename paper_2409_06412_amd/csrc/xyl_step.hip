@@ -66,15 +66,20 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
     const uint32_t xmb = (uint32_t)xm * (uint32_t)sizeof(R), xpb = (uint32_t)xp * (uint32_t)sizeof(R);
     // measurement: the phases e^{-2 pi i x / Lx} of the lane's four columns
     // (FP64, from the lattice's table; the same on every row, so read once
-    // per strip)
-    double pxs[4], pxc[4];
+    // per strip), each times the column's staggered sign along x: x is a
+    // multiple of 4, so column x + q has the parity of q and the sign of the
+    // odd columns is sxo (the stag flags are 0 or 1).  mc = sign cos,
+    // ms = -sign sin, so every x-mode term is one fma.
+    double mc[4], ms[4];
+    const double sxo = v.stag_x ? -1.0 : 1.0;
     if constexpr ((MODE & kMeasure) != 0) {
         const double2* ph = reinterpret_cast<const double2*>(v.xph) + x;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double2 e = act ? ph[q] : make_double2(0.0, 0.0);
-            pxs[q] = e.x;
-            pxc[q] = e.y;
+            const double sg = (q & 1) ? sxo : 1.0;
+            mc[q] = sg * e.y;
+            ms[q] = -(sg * e.x);
         }
     }
 
@@ -148,11 +153,11 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
             // row's totals of the two components
             // (value 1 is the sum of w^2: the finalize halves it, which is
             // exact, so the sums equal those of the halved terms bit for bit)
+            // (values 2 to 7 carry the x part of the staggered sign here;
+            // the row's y part, a sign flip of the totals, is exact)
             double acc[8];
 #pragma unroll
             for (int p = 0; p < 8; ++p) acc[p] = 0.0;
-            // staggered sign: x is a multiple of 4, so site (x + q, y) has the
-            // parity of q stag_x + y stag_y (the stag flags are 0 or 1)
             const bool odd_row = (y & v.stag_y & 1) != 0;
             if (act) {
 #pragma unroll
@@ -161,23 +166,26 @@ __device__ __forceinline__ void run_strip(const Lat<R>& v, int xw, int strip, in
                     const double sxp = (double)(q == 3 ? sR : C.s[q + 1]);
                     const double cxp = (double)(q == 3 ? cR : C.c[q + 1]);
                     const double syp = (double)N.s[q], cyp = (double)N.c[q];
-                    acc[0] += v.Jxd * (c * cxp + s * sxp) + v.Jyd * (c * cyp + s * syp) -
-                              v.hd * onsite_cos<R, M>(v, C.th[q], s, c);
-                    acc[1] += (double)w[q] * (double)w[q];
-                    const bool neg = ((q & 1) && v.stag_x) != odd_row;
+                    // bonds cos(th - th') = c c' + s s', the field cos 2th = c^2 - s^2 (XY)
+                    const double bx = fma(c, cxp, s * sxp), by = fma(c, cyp, s * syp);
+                    const double fld = M == kModelSI ? onsite_cos<R, M>(v, C.th[q], s, c) : fma(c, c, -(s * s));
+                    acc[0] += fma(-v.hd, fld, fma(v.Jxd, bx, v.Jyd * by));
+                    const double wq = (double)w[q];
+                    acc[1] = fma(wq, wq, acc[1]);
                     // order-parameter component first: cos th (XY), sin 2th (SI)
                     const double a = M == kModelSI ? s : c, b = M == kModelSI ? c : s;
-                    const double ec = neg ? -a : a, es = neg ? -b : b;
-                    acc[2] += ec;
-                    acc[3] += es;
-                    acc[4] += ec * pxc[q];
-                    acc[5] -= ec * pxs[q];
-                    acc[6] += es * pxc[q];
-                    acc[7] -= es * pxs[q];
+                    acc[2] = (q & 1) ? fma(a, sxo, acc[2]) : acc[2] + a;
+                    acc[3] = (q & 1) ? fma(b, sxo, acc[3]) : acc[3] + b;
+                    acc[4] = fma(a, mc[q], acc[4]);
+                    acc[5] = fma(a, ms[q], acc[5]);
+                    acc[6] = fma(b, mc[q], acc[6]);
+                    acc[7] = fma(b, ms[q], acc[7]);
                 }
             }
-            // lane 8p holds the wave's total of value p
-            const double tot = wave_sum8(acc, lane);
+            // lane 8p holds the wave's total of value p; the row's staggered
+            // sign along y on values 2 to 7
+            double tot = wave_sum8(acc, lane);
+            if (odd_row && lane >= 16) tot = -tot;
             double* base = v.part + (v.part_stride ? (k - v.part_k0) * v.part_stride : 0);
             double* dst = base + ((size_t)y * v.nxw + xw) * kNPart;
             if ((lane & 7) == 0) dst[lane >> 3] = tot;
