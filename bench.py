@@ -708,8 +708,8 @@ def main():
         summarize_valu(a[0], a[1], a[2], args.L, a[3], args.kernel)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on a single MI355X "
+              "(sharding across GPUs is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
