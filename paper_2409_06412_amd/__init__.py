@@ -625,7 +625,8 @@ class Ensemble:
         nout = np.zeros(self.n, dtype=np.uint64)
         _check(load().xyl_ensemble_step(self._h, int(nsteps), int(every), _pd(out), cap,
                                         nout.ctypes.data_as(P(_u64))))
-        return [out[r, : int(nout[r])] for r in range(self.n)]
+        counts = nout.tolist()
+        return [out[r, : counts[r]] for r in range(self.n)]
 
     def get_state(self, r: int):
         s = self.specs[r]
