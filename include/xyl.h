@@ -349,6 +349,19 @@ int xyl_z_collapse(const double* t1, const double* U1, uint64_t n1, double L1, c
  * fit does not converge.  Pure host computation. */
 int xyl_lorentzian_xi(const double* S, int32_t L, int32_t k_first, int32_t k_last, double* xi, double* amplitude);
 
+/* Second-moment correlation length along axis 0 (x) or 1 (y) from samples
+ * s[discard..n-1] (as the measuring calls return them):
+ *   xi = sqrt(<F(0)> / <F(k_min)> - 1) / (2 sin(pi / L)),
+ * <.> the mean over the samples, F(0) = f0 and F(k_min) = fkx or fky, L the
+ * side length along the axis; the means come before the ratio.  It is exact
+ * for the lattice Lorentzian S(k) = S(0) / (1 + 4 xi^2 sin^2(pi k / L)),
+ * which is the Lorentzian of App. C (Eq. Lorentzian-Peak, wave number k / L)
+ * up to terms of relative order (k / L)^2, solved through k = 0 and k = 1
+ * (the wave number 2 pi / L).  xi = 0
+ * where <F(0)> <= <F(k_min)> (no correlation beyond the noise); XYL_ENUMERIC
+ * if <F(k_min)> is not positive and finite.  Pure host computation. */
+int xyl_xi_second_moment(const xyl_obs* s, uint64_t n, uint64_t discard, int32_t axis, int32_t L, double* xi);
+
 /* --------------------------------------------------------------- ensemble */
 /* One replica of a batched ensemble: its own lattice size, parameters,
  * schedule, noise key and number of steps to run. */

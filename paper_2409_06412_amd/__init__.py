@@ -112,6 +112,7 @@ _SIGS = {
     "xyl_noise": (_i32, [_vp, _u64, P(_d)]),
     "xyl_binder": (_i32, [P(_d), _u64, _u64, P(_d), P(_d)]),
     "xyl_mean_error": (_i32, [P(_d), _u64, _u64, P(_d), P(_d), P(_d)]),
+    "xyl_xi_second_moment": (_i32, [P(_d), _u64, _u64, _i32, _i32, P(_d)]),
     "xyl_ensemble_create": (_i32, [P(_vp), P(ReplicaDesc), _i32, _i32, _i32]),
     "xyl_ensemble_destroy": (_i32, [_vp]),
     "xyl_ensemble_set_stream": (_i32, [_vp, _vp]),
@@ -710,6 +711,18 @@ def lorentzian_xi(S, L: int, k_first: int, k_last: int):
     xi, A = _d(), _d()
     _check(load().xyl_lorentzian_xi(_pd(S), int(L), int(k_first), int(k_last), ctypes.byref(xi), ctypes.byref(A)))
     return xi.value, A.value
+
+
+def xi_second_moment(samples, L: int, axis: int = 0, discard: int = 0) -> float:
+    """Second-moment correlation length along axis 0 (x) or 1 (y) from an
+    (n, 6) array of samples as the measuring calls return them."""
+    s = np.ascontiguousarray(samples, dtype=np.float64)
+    if s.ndim != 2 or s.shape[1] != 6:
+        raise ValueError("samples must be (n, 6)")
+    xi = _d()
+    _check(load().xyl_xi_second_moment(_pd(s), s.shape[0], int(discard), int(axis),
+                                       int(L), ctypes.byref(xi)))
+    return xi.value
 
 
 def mean_error(f, discard: int = 0):

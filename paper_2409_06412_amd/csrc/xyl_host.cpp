@@ -133,6 +133,27 @@ int xyl_lorentzian_xi(const double* S, int32_t L, int32_t k_first, int32_t k_las
     });
 }
 
+int xyl_xi_second_moment(const xyl_obs* s, uint64_t n, uint64_t discard, int32_t axis, int32_t L, double* xi) {
+    return guarded([&] {
+        require(s != nullptr && xi != nullptr, XYL_EINVAL, "NULL argument");
+        require(discard < n, XYL_EINVAL, "discard must be < n");
+        require(axis == 0 || axis == 1, XYL_EINVAL, "axis must be 0 (x) or 1 (y)");
+        require(L >= 2, XYL_EINVAL, "L must be >= 2");
+        double f0 = 0.0, fk = 0.0;
+        for (uint64_t i = discard; i < n; ++i) {
+            f0 += s[i].f0;
+            fk += axis == 0 ? s[i].fkx : s[i].fky;
+        }
+        const double cnt = (double)(n - discard);
+        f0 /= cnt;
+        fk /= cnt;
+        require(std::isfinite(f0) && std::isfinite(fk) && fk > 0.0, XYL_ENUMERIC,
+                "<F(k_min)> must be positive and finite");
+        const double r = f0 / fk - 1.0;
+        *xi = r <= 0.0 ? 0.0 : std::sqrt(r) / (2.0 * std::sin(M_PI / (double)L));
+    });
+}
+
 int xyl_binder(const double* m, uint64_t n, uint64_t discard, double* U, double* U_se) {
     return guarded([&] {
         require(m != nullptr && U != nullptr, XYL_EINVAL, "NULL argument");

@@ -151,3 +151,33 @@ def test_oracle_library_is_independent_of_product():
         assert not re.search(r"^\s*(import|from)\s+paper_2409_06412_amd", src, flags=re.M), f
         assert "#include" not in src or "xyl" not in "".join(re.findall(r"#include.*", src)), f
     assert oracle.lib() is not None
+
+
+def test_second_moment_xi_matches_oracle_estimator():
+    """The library's second-moment correlation length: exact on the lattice
+    Lorentzian, the oracle estimator's value on noisy samples (means before the
+    ratio, samples before `discard` dropped, either axis), 0 where F(0) does not
+    exceed F(k_min), and bad input refused."""
+    import math
+    import paper_2409_06412_amd as xyl
+    L, xi = 64, 3.0
+    S1 = 1.0 / (1 + 4 * xi * xi * math.sin(math.pi / L) ** 2)
+    s = np.zeros((5, 6))
+    s[:, 3], s[:, 4], s[:, 5] = 1.0, S1, 0.5
+    assert xyl.xi_second_moment(s, L) == pytest.approx(xi, rel=1e-12)
+    rng = np.random.default_rng(3)
+    s = np.abs(rng.normal(1.0, 0.2, size=(40, 6)))
+    s[:, 4] *= 0.3
+    s[:, 5] *= 0.6
+    for axis in (0, 1):
+        for discard in (0, 8):
+            want = estimators.xi_second_moment(s[discard:, 3].mean(), s[discard:, 4 + axis].mean(), 48)
+            assert xyl.xi_second_moment(s, 48, axis, discard) == pytest.approx(want, rel=1e-12)
+    flat = np.ones((4, 6))
+    assert xyl.xi_second_moment(flat, 32) == 0.0
+    with pytest.raises(xyl.XylError):
+        xyl.xi_second_moment(np.zeros((4, 6)), 32)                     # <F(k_min)> = 0
+    with pytest.raises(xyl.XylError):
+        xyl.xi_second_moment(flat, 32, axis=2)
+    with pytest.raises(xyl.XylError):
+        xyl.xi_second_moment(flat, 32, discard=4)

@@ -147,6 +147,12 @@ int main() {
     CHECK(xyl_lorentzian_xi(rising.data(), L, 0, 20, &xi, &A) == XYL_ENUMERIC);
     S[3] = -1.0;
     CHECK(xyl_lorentzian_xi(S.data(), L, 0, 20, &xi, &A) == XYL_EINVAL);
+    std::vector<xyl_obs> smp(12);
+    for (size_t i = 0; i < smp.size(); ++i) smp[i] = xyl_obs{-1.0, 0.5, 0.1, 2.0 + 0.01 * i, 0.5, 1.0};
+    CHECK(xyl_xi_second_moment(smp.data(), smp.size(), 2, 0, 64, &xi) == XYL_OK && xi > 0.0);
+    CHECK(xyl_xi_second_moment(smp.data(), smp.size(), 0, 1, 64, &xi) == XYL_OK && xi > 0.0);
+    CHECK(xyl_xi_second_moment(smp.data(), smp.size(), 12, 0, 64, &xi) == XYL_EINVAL);
+    CHECK(xyl_xi_second_moment(smp.data(), smp.size(), 0, 2, 64, &xi) == XYL_EINVAL);
     if (bad) return 1;
     std::puts("ok");
     return 0;
