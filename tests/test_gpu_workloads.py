@@ -50,8 +50,9 @@ def test_quench_ensemble_domains(xyl):
 
 def test_fss_analysis_chain(xyl):
     """Three small replicas sampled every 100 steps: the host estimators of the
-    library (Binder cumulant, mean and error) agree with the oracle's on the
-    same samples, and the sample series agree with single-lattice runs."""
+    library (Binder cumulant, second-moment correlation length, mean and
+    error) agree with the oracle's on the same samples, and the sample series
+    agree with single-lattice runs."""
     specs = workloads.fss_ensemble(sizes=(32, 64), ntemps=2, seeds=(0,), nsteps=3000)
     ens = xyl.Ensemble(specs, dtype="f32")
     samples = ens.step(3000, every=100)
@@ -62,6 +63,7 @@ def test_fss_analysis_chain(xyl):
         U, U_se = xyl.binder(m, 6)
         assert U == pytest.approx(estimators.binder(m, 0.2), rel=1e-12)
         xi = estimators.xi_second_moment(s[6:, 3].mean(), s[6:, 4].mean(), sp.Lx)
+        assert xyl.xi_second_moment(s, sp.Lx, 0, 6) == pytest.approx(xi, rel=1e-12)
         say("L", sp.Lx, "T", sp.schedule[0][1], "U", U, "+-", U_se, "xi_2nd", xi)
         assert 0.9 < U < 3.1
         mu, se, tau = xyl.mean_error(s[:, 0], 6)
