@@ -292,12 +292,19 @@ __device__ __forceinline__ R site_force(const Lat<R>& v, R s, R c, R sxm, R cxm,
     }
 }
 
-// cos of the field's angle for the energy, in FP64: cos 2th = c^2 - s^2 from
-// the rotor (XY), cos(p th) of the raw angle (SI).
+// cos of the field's angle for the energy: cos 2th = c^2 - s^2 from the rotor
+// (XY); cos(p th) of the raw angle (SI), in the state's precision like the
+// rotors: the native FP32 cosine for FP32 lattices (pf = p / 2pi revolutions
+// per radian; an FP64 cosine here spilled the whole-in-LDS kernel's
+// registers), FP64 cos for FP64 lattices.
 template <typename R, int M>
 __device__ __forceinline__ double onsite_cos(const Lat<R>& v, R th, double s, double c) {
-    if constexpr (M == kModelSI) return cos(v.pd * (double)th);
-    else return c * c - s * s;
+    if constexpr (M == kModelSI) {
+        if constexpr (sizeof(R) == 4) return (double)__builtin_amdgcn_cosf(th * v.pf);
+        else return cos(v.pd * (double)th);
+    } else {
+        return c * c - s * s;
+    }
 }
 
 // Completes the previous step's second half-kick (w^k; skipped at the fresh
